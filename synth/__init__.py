@@ -1,0 +1,236 @@
+"""Seeded synthetic inputs for the KFBI workloads.
+
+This module only *generates inputs*: boundary samples of the test domains,
+manufactured exact solutions (and the right-hand sides they imply), and seeded
+densities.  It holds none of the method's arithmetic (no spline, no jump, no
+correction, no fast solve, no interpolation, no Krylov step), so both the CPU
+oracle and the HIP path may draw their inputs from it.
+
+Workloads follow the paper's numerical-results section: a Dirichlet problem
+for ``Lap u - kappa u = f`` (eq. of the modified Helmholtz problem, Sec. 2) on
+a curved domain inside the box ``[-1.2, 1.2]^2`` (Example 1), with ``f`` and
+``g`` taken from a closed-form solution.  The concrete domains (circle r=0.8,
+star ``0.6 + 0.15 sin 5 theta``, random stars) and solutions are the
+benchmark configurations this library is measured on.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+BOX_LO = -1.2
+BOX_HI = 1.2
+
+
+# --------------------------------------------------------------------------
+# boundary curves (counter-clockwise, first sample at theta = 0)
+# --------------------------------------------------------------------------
+
+def circle_points(m: int, r: float = 0.8) -> np.ndarray:
+    """``m`` equally spaced points on the circle of radius ``r``, CCW, theta_0 = 0."""
+    th = 2.0 * np.pi * np.arange(m) / m
+    return np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+
+
+def _star_speed(theta, r0, a, k):
+    r = r0 + a * np.sin(k * theta)
+    dr = a * k * np.cos(k * theta)
+    return np.sqrt(r * r + dr * dr)
+
+
+def star_points(m: int, r0: float = 0.6, a: float = 0.15, k: int = 5,
+                n_fourier: int = 8192) -> np.ndarray:
+    """``m`` points of equal arc length on ``r(theta) = r0 + a sin(k theta)``.
+
+    The arc-length function is integrated spectrally (the speed is smooth and
+    periodic, so its Fourier series converges geometrically) and inverted by
+    Newton's method.  The first point sits at ``theta = 0``.
+    """
+    th = 2.0 * np.pi * np.arange(n_fourier) / n_fourier
+    sp = _star_speed(th, r0, a, k)
+    c = np.fft.rfft(sp) / n_fourier          # speed = c0 + 2 Re sum c_j e^{ij theta}
+    c0 = c[0].real
+    jj = np.arange(1, len(c))
+    cj = c[1:]
+    if n_fourier % 2 == 0:
+        cj = cj.copy()
+        cj[-1] *= 0.5                         # Nyquist term counted once
+    perim = 2.0 * np.pi * c0
+
+    def arclen(t):
+        t = np.atleast_1d(t)
+        # integral of 2 Re(c_j e^{i j t}) from 0 to t = 2 Re(c_j (e^{ijt} - 1) / (i j))
+        e = np.exp(1j * np.outer(t, jj))
+        s = 2.0 * np.real(((e - 1.0) / (1j * jj)) @ cj)
+        return c0 * t + s
+
+    target = perim * np.arange(m) / m
+    t = 2.0 * np.pi * np.arange(m) / m       # initial guess
+    for _ in range(30):
+        f = arclen(t) - target
+        t = t - f / _star_speed(t, r0, a, k)
+        if np.max(np.abs(f)) < 1e-15 * perim:
+            break
+    t[0] = 0.0
+    r = r0 + a * np.sin(k * t)
+    return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
+
+
+def star_perimeter(r0: float, a: float, k: int, n: int = 8192) -> float:
+    th = 2.0 * np.pi * np.arange(n) / n
+    return float(np.mean(_star_speed(th, r0, a, k)) * 2.0 * np.pi)
+
+
+def star_min_radius_of_curvature(r0: float, a: float, k: int, n: int = 20000) -> float:
+    th = 2.0 * np.pi * np.arange(n) / n
+    r = r0 + a * np.sin(k * th)
+    r1 = a * k * np.cos(k * th)
+    r2 = -a * k * k * np.sin(k * th)
+    curv = np.abs(r * r + 2 * r1 * r1 - r * r2) / (r * r + r1 * r1) ** 1.5
+    return float(1.0 / np.max(curv))
+
+
+# --------------------------------------------------------------------------
+# manufactured solutions: u, and Lap u (so f = Lap u - kappa u)
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass(frozen=True)
+class Manufactured:
+    """A closed-form solution ``u`` with its Laplacian."""
+    name: str
+    u: callable
+    lap: callable
+
+    def f(self, x, y, kappa):
+        """Right-hand side of ``Lap u - kappa u = f``."""
+        return self.lap(x, y) - kappa * self.u(x, y)
+
+
+EXP_SIN = Manufactured(
+    "exp(x) sin(y)",
+    lambda x, y: np.exp(x) * np.sin(y),
+    lambda x, y: np.zeros_like(np.asarray(x, dtype=float) + np.asarray(y, dtype=float)),
+)
+
+PAPER_EX1 = Manufactured(
+    "exp(x) cos(y) + exp(y) sin(x)",
+    lambda x, y: np.exp(x) * np.cos(y) + np.exp(y) * np.sin(x),
+    lambda x, y: np.zeros_like(np.asarray(x, dtype=float) + np.asarray(y, dtype=float)),
+)
+
+SIN_COS_X2 = Manufactured(
+    "sin(pi x) cos(pi y) + x^2",
+    lambda x, y: np.sin(np.pi * x) * np.cos(np.pi * y) + x * x,
+    lambda x, y: -2.0 * np.pi ** 2 * np.sin(np.pi * x) * np.cos(np.pi * y) + 2.0,
+)
+
+
+def random_manufactured(rng: np.random.Generator) -> Manufactured:
+    """``u = A sin(w1 x + a) cos(w2 y + b) + B (x^2 - y^2)`` with seeded parameters."""
+    A, B = rng.uniform(-1.0, 1.0, size=2)
+    w1, w2 = rng.uniform(0.5, np.pi, size=2)
+    al, be = rng.uniform(0.0, 2.0 * np.pi, size=2)
+    return Manufactured(
+        f"{A:.3f} sin({w1:.3f}x+{al:.3f}) cos({w2:.3f}y+{be:.3f}) + {B:.3f}(x^2-y^2)",
+        lambda x, y: A * np.sin(w1 * x + al) * np.cos(w2 * y + be) + B * (x * x - y * y),
+        lambda x, y: -(w1 * w1 + w2 * w2) * A * np.sin(w1 * x + al) * np.cos(w2 * y + be),
+    )
+
+
+# --------------------------------------------------------------------------
+# densities for the stand-alone operator apply
+# --------------------------------------------------------------------------
+
+def smooth_density(m: int, seed: int = 1234, kmax: int = 8) -> np.ndarray:
+    """``phi_m = sum_{k<=kmax} a_k cos(k th_m) + b_k sin(k th_m)``, ``a,b ~ N(0,1)/(1+k^2)``."""
+    rng = np.random.default_rng(seed)
+    th = 2.0 * np.pi * np.arange(m) / m
+    phi = np.zeros(m)
+    for k in range(kmax + 1):
+        a, b = rng.standard_normal(2) / (1.0 + k * k)
+        phi += a * np.cos(k * th) + b * np.sin(k * th)
+    return phi
+
+
+# --------------------------------------------------------------------------
+# problem bundles
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Problem:
+    """Everything a Dirichlet solve needs, in plain host arrays.
+
+    ``xy``: (M, 2) boundary samples (CCW).  ``n``: intervals per axis.
+    ``f_grid``: (n+1, n+1) right-hand side sampled at every node, indexed
+    ``[j, i]`` (row j is the grid line ``y = lo + j h``, i runs along x).
+    ``f_gamma`` and ``g``: f and the Dirichlet data at the boundary samples.
+    """
+    name: str
+    xy: np.ndarray
+    n: int
+    kappa: float
+    lo: float
+    hi: float
+    f_grid: np.ndarray
+    f_gamma: np.ndarray
+    g: np.ndarray
+    exact: Manufactured
+
+    @property
+    def h(self):
+        return (self.hi - self.lo) / self.n
+
+    def node_coords(self):
+        k = np.arange(self.n + 1)
+        return self.lo + k * self.h
+
+
+def make_problem(name, xy, n, kappa, sol: Manufactured, lo=BOX_LO, hi=BOX_HI) -> Problem:
+    h = (hi - lo) / n
+    c = lo + np.arange(n + 1) * h
+    X, Y = np.meshgrid(c, c, indexing="xy")       # X[j, i] = x_i, Y[j, i] = y_j
+    f_grid = sol.f(X, Y, kappa)
+    f_gamma = sol.f(xy[:, 0], xy[:, 1], kappa)
+    g = sol.u(xy[:, 0], xy[:, 1])
+    return Problem(name, xy, n, kappa, lo, hi, np.ascontiguousarray(f_grid, dtype=np.float64),
+                   np.asarray(f_gamma, dtype=np.float64), np.asarray(g, dtype=np.float64), sol)
+
+
+def circle_problem(n=64, m=128, kappa=0.0, sol=EXP_SIN, r=0.8) -> Problem:
+    """Interior Dirichlet problem on the circle of radius ``r`` (``e^x sin y`` by default)."""
+    return make_problem(f"circle r={r} n={n} m={m} kappa={kappa}", circle_points(m, r), n, kappa, sol)
+
+
+def star_problem(n=512, m=None, kappa=1.0, sol=SIN_COS_X2, r0=0.6, a=0.15, k=5) -> Problem:
+    """Modified Helmholtz problem on the star ``r0 + a sin(k theta)``, ``m = n/2`` samples by default."""
+    if m is None:
+        m = n // 2
+    return make_problem(f"star {r0}+{a}sin({k}t) n={n} m={m} kappa={kappa}",
+                        star_points(m, r0, a, k), n, kappa, sol)
+
+
+def serving_request(seed: int, n: int):
+    """One request of the mixed serving stream: a random star, kappa and solution."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(0.05, 0.2)
+    k = int(rng.integers(3, 9))
+    kappa = rng.uniform(0.0, 10.0)
+    sol = random_manufactured(rng)
+    h = (BOX_HI - BOX_LO) / n
+    per = star_perimeter(0.6, a, k)
+    m = 64 * int(math.ceil(per / (64 * h)))
+    return make_problem(f"req{seed} star a={a:.3f} k={k} n={n} m={m} kappa={kappa:.3f}",
+                        star_points(m, 0.6, a, k), n, kappa, sol)
+
+
+def serving_stream(n_requests: int, seed: int = 2404, qps: float = 100.0,
+                   sizes=(256, 512, 1024, 2048), weights=(0.4, 0.3, 0.2, 0.1)):
+    """Seeded request stream: Poisson arrival times, grid sizes and per-request seeds."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / qps, size=n_requests)
+    arrivals = np.cumsum(gaps)
+    ns = rng.choice(np.asarray(sizes), size=n_requests, p=np.asarray(weights))
+    seeds = rng.integers(0, 2 ** 31 - 1, size=n_requests)
+    return [(float(t), int(n), int(s)) for t, n, s in zip(arrivals, ns, seeds)]

@@ -1,0 +1,441 @@
+"""Pins of the CPU oracle to facts that do not come from the oracle itself.
+
+Each test checks one piece of the oracle against mathematics the paper fixes
+(closed forms, invariants, textbook special cases, brute force on tiny inputs),
+so that a dropped term, a wrong sign or index, or a transposed operand in the
+oracle fails at least one of them.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kfbi_oracle as O
+
+LO, HI = synth.BOX_LO, synth.BOX_HI
+
+
+# --------------------------------------------------------------------------
+# periodic cubic spline (R-06)
+# --------------------------------------------------------------------------
+
+def test_spline_reproduces_knots_and_constants():
+    rng = np.random.default_rng(0)
+    y = rng.standard_normal(37)
+    s2 = O.spline_second_derivs(y)
+    val, _, _ = O.spline_eval(y, s2, np.arange(37.0))
+    assert np.array_equal(val, y)
+    c = np.full(20, 3.25)
+    s2c = O.spline_second_derivs(c)
+    assert np.max(np.abs(s2c)) < 1e-15
+    v, d1, d2 = O.spline_eval(c, s2c, np.linspace(0, 19.9, 50))
+    assert np.allclose(v, 3.25, atol=1e-15) and np.allclose(d1, 0, atol=1e-14)
+
+
+def test_spline_is_c1_and_c2_at_knots():
+    """Left and right derivatives at every knot agree (what defines the spline)."""
+    rng = np.random.default_rng(1)
+    y = rng.standard_normal(24)
+    s2 = O.spline_second_derivs(y)
+    dl = 1e-7
+    k = np.arange(1.0, 24.0)
+    _, d1l, d2l = O.spline_eval(y, s2, k - dl)
+    _, d1r, d2r = O.spline_eval(y, s2, k + dl)
+    assert np.max(np.abs(d1l - d1r)) < 1e-5
+    assert np.max(np.abs(d2l - d2r)) < 1e-5
+    # periodic wrap: knot 0 seen from the last segment
+    _, a, _ = O.spline_eval(y, s2, np.array([24.0 - dl]))
+    _, b, _ = O.spline_eval(y, s2, np.array([dl]))
+    assert abs(a[0] - b[0]) < 1e-5
+
+
+def test_spline_fourth_order_on_cosine():
+    errs, derrs = [], []
+    for m in (32, 64, 128):
+        t = np.arange(m)
+        y = np.cos(2 * np.pi * t / m)
+        s2 = O.spline_second_derivs(y)
+        tm = t + 0.37
+        v, d1, _ = O.spline_eval(y, s2, tm)
+        errs.append(np.max(np.abs(v - np.cos(2 * np.pi * tm / m))))
+        derrs.append(np.max(np.abs(d1 + (2 * np.pi / m) * np.sin(2 * np.pi * tm / m))) * m)
+    r = [errs[i] / errs[i + 1] for i in range(2)]
+    assert min(r) > 14.0, r                       # O(M^-4)
+    rd = [derrs[i] / derrs[i + 1] for i in range(2)]
+    assert min(rd) > 6.5, rd                      # derivative w.r.t. arc angle: O(M^-3)
+
+
+# --------------------------------------------------------------------------
+# fast solver (Alg. 4): DST-I against dense LU of the 5-point matrix
+# --------------------------------------------------------------------------
+
+def five_point_matrix(n, h, kappa):
+    """The (n-1)^2 x (n-1)^2 matrix of L_h - kappa, written out node by node."""
+    k = n - 1
+    A = np.zeros((k * k, k * k))
+    for j in range(k):
+        for i in range(k):
+            p = j * k + i
+            A[p, p] = -4.0 / h ** 2 - kappa
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                ii, jj = i + di, j + dj
+                if 0 <= ii < k and 0 <= jj < k:
+                    A[p, jj * k + ii] = 1.0 / h ** 2
+    return A
+
+
+@pytest.mark.parametrize("n,kappa", [(8, 0.0), (16, 0.0), (16, 3.0), (12, 100.0), (32, 1.0)])
+def test_dst_solve_matches_dense_lu(n, kappa):
+    rng = np.random.default_rng(n)
+    h = 2.4 / n
+    rhs = rng.standard_normal((n - 1, n - 1))
+    rhs[3, 2] = 40.0                                  # a spike
+    v = O.dst_solve(rhs, h, kappa)
+    ref = np.linalg.solve(five_point_matrix(n, h, kappa), rhs.reshape(-1)).reshape(n - 1, n - 1)
+    assert np.max(np.abs(v - ref)) <= 1e-13 * np.max(np.abs(ref)) * n
+
+
+def test_dst_solve_nonsquare_axes_not_transposed():
+    """A right-hand side that varies only along x gives a solution varying mostly along x."""
+    n, h = 16, 0.15
+    i = np.arange(1, n)
+    rhs = np.tile(np.sin(np.pi * i / n), (n - 1, 1)) * np.sin(np.pi * 2 * i / n)[:, None]
+    v = O.dst_solve(rhs, h, 0.0)
+    lam = lambda k: -(4 / h ** 2) * np.sin(np.pi * k / (2 * n)) ** 2
+    assert np.allclose(v, rhs / (lam(1) + lam(2)), rtol=1e-12, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# geometry plan: brute-force classification and crossing counts
+# --------------------------------------------------------------------------
+
+def brute_inside(n, inside_fn):
+    c = LO + np.arange(n + 1) * (HI - LO) / n
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    return inside_fn(X, Y)
+
+
+def brute_counts(mask):
+    ex = np.count_nonzero(mask[:, :-1] != mask[:, 1:])
+    ey = np.count_nonzero(mask[:-1, :] != mask[1:, :])
+    irr = np.zeros_like(mask)
+    irr[:, :-1] |= mask[:, :-1] != mask[:, 1:]
+    irr[:, 1:] |= mask[:, :-1] != mask[:, 1:]
+    irr[:-1, :] |= mask[:-1, :] != mask[1:, :]
+    irr[1:, :] |= mask[:-1, :] != mask[1:, :]
+    return ex + ey, int(irr.sum())
+
+
+def test_plan_circle_64_counts():
+    """Circle r=0.8 on the 64^2 grid: 172 crossings, 244 irregular nodes."""
+    p = synth.circle_problem(n=64, m=128)
+    plan = O.build_plan(p.xy, 64, LO, HI)
+    mask = brute_inside(64, lambda x, y: x * x + y * y < 0.64)
+    assert np.array_equal(plan.inside, mask)
+    assert len(plan.q_t) == 172 and len(plan.irr) == 244
+    assert brute_counts(mask) == (172, 244)
+    # crossings sit on their grid line, between their two nodes, on the circle
+    r = np.hypot(plan.q_xy[:, 0], plan.q_xy[:, 1])
+    assert np.max(np.abs(r - 0.8)) < 2e-7
+    for k in range(len(plan.q_t)):
+        (i0, j0), (i1, j1) = plan.q_nodes[k]
+        assert plan.inside[j0, i0] != plan.inside[j1, i1]
+        ax = plan.q_axis[k]
+        lo_c, hi_c = plan.coord((i0, j0)[ax]), plan.coord((i1, j1)[ax])
+        assert lo_c <= plan.q_xy[k, ax] <= hi_c
+        assert plan.q_xy[k, 1 - ax] == plan.coord((i0, j0)[1 - ax])
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_plan_star_matches_brute_force(n):
+    p = synth.star_problem(n=n)
+    plan = O.build_plan(p.xy, n, LO, HI)
+
+    def star_in(x, y):
+        return np.hypot(x, y) < 0.6 + 0.15 * np.sin(5 * np.arctan2(y, x))
+    mask = brute_inside(n, star_in)
+    c = LO + np.arange(n + 1) * (HI - LO) / n
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    gap = np.abs(np.hypot(X, Y) - 0.6 - 0.15 * np.sin(5 * np.arctan2(Y, X)))
+    differ = plan.inside != mask
+    # the spline curve differs from the exact star by far less than 1e-5
+    assert np.all(gap[differ] < 1e-5)
+    q, ir = brute_counts(plan.inside)
+    assert (q, ir) == (len(plan.q_t), len(plan.irr))
+    qb, irb = brute_counts(mask)
+    assert abs(q - qb) <= 4 and abs(ir - irb) <= 4
+    # survey-time brute-force counts on the exact star
+    ref = {512: (1352, 1912), 1024: (2700, 3824)}[n]
+    assert abs(q - ref[0]) <= 4 and abs(ir - ref[1]) <= 4
+
+
+def test_node_exactly_on_curve_counts_inside():
+    """R-07: a sample placed exactly on a grid node, where the curve enters Omega from the
+    left, puts that node on Gamma; it is classified inside, its arm to the outside has
+    d = 0 at the node itself, and the operator identities still hold."""
+    n, m = 64, 128
+    h = (HI - LO) / n
+    i0, j0 = 11, 29
+    th = np.pi + 2 * np.pi * np.arange(m) / m
+    xy = np.stack([0.78 * np.cos(th), 0.78 * np.sin(th)], 1)
+    xy[:, 0] += (LO + i0 * h) + 0.78                      # leftmost sample lands on node (i0, j0)
+    xy[:, 1] += (LO + j0 * h)
+    xy[0] = (LO + i0 * h, LO + j0 * h)
+    plan = O.build_plan(xy, n, LO, HI)
+    assert plan.inside[j0, i0] and not plan.inside[j0, i0 - 1]
+    k = [q for q in range(len(plan.q_t)) if plan.q_axis[q] == 0 and tuple(plan.q_nodes[q, 1]) == (i0, j0)]
+    assert len(k) == 1 and plan.q_xy[k[0], 0] == LO + i0 * h
+    assert abs(O.apply_KD(plan, np.ones(m), 0.0) - 1.0).max() < 1e-12
+
+
+def test_plan_geometry_errors():
+    with pytest.raises(O.GeometryError):
+        O.build_plan(synth.circle_points(64, 1.15), 32, LO, HI)       # within 2h of the box
+    xy = synth.star_points(400, 0.6, 0.35, 8)                           # deep, thin petals
+    with pytest.raises(O.GeometryError):
+        O.build_plan(xy, 24, LO, HI)
+
+
+# --------------------------------------------------------------------------
+# jumps (R-09): two smooth functions, one inside and one outside
+# --------------------------------------------------------------------------
+
+def _D(x, y):
+    """D = A - B for A = 1+2x-y+x^2/2+1.5xy-0.7y^2+0.3x^3-0.2xy^2, B = -0.4+x+0.3y-x^2+xy/4+y^2+0.1y^3."""
+    v = 1.4 + x - 1.3 * y + 1.5 * x * x + 1.25 * x * y - 1.7 * y * y + 0.3 * x ** 3 - 0.2 * x * y * y - 0.1 * y ** 3
+    gx = 1.0 + 3.0 * x + 1.25 * y + 0.9 * x * x - 0.2 * y * y
+    gy = -1.3 + 1.25 * x - 3.4 * y - 0.4 * x * y - 0.3 * y * y
+    hxx = 3.0 + 1.8 * x
+    hxy = 1.25 - 0.4 * y
+    hyy = -3.4 - 0.4 * x - 0.6 * y
+    return v, np.array([gx, gy]), np.array([[hxx, hxy], [hxy, hyy]])
+
+
+@pytest.mark.parametrize("shape", ["circle", "ellipse"])
+@pytest.mark.parametrize("kappa", [0.0, 2.5])
+def test_cartesian_jumps_piecewise_polynomial_truth(shape, kappa):
+    a, b = (0.8, 0.8) if shape == "circle" else (0.9, 0.5)
+    for th in np.linspace(0.1, 6.2, 17):
+        X = np.array([a * np.cos(th), b * np.sin(th)])
+        X1 = np.array([-a * np.sin(th), b * np.cos(th)])
+        X2 = np.array([-a * np.cos(th), -b * np.sin(th)])
+        sig = np.linalg.norm(X1)
+        T = X1 / sig
+        nrm = np.array([T[1], -T[0]])
+        dT = (X2 / sig - X1 * (X1 @ X2) / sig ** 3) / sig          # dT/ds
+        dn = np.array([dT[1], -dT[0]])
+        curv = (X1[0] * X2[1] - X1[1] * X2[0]) / sig ** 3
+        v, g, H = _D(*X)
+        Phi, Phi_s, Phi_ss = v, g @ T, T @ H @ T + g @ dT
+        Psi, Psi_s = g @ nrm, T @ H @ nrm + g @ dn
+        Fj = np.trace(H) - kappa * v
+        J = O.cartesian_jumps(T, nrm, curv, Phi, Phi_s, Phi_ss, Psi, Psi_s, Fj, kappa)
+        ref = np.array([v, g[0], g[1], H[0, 0], H[0, 1], H[1, 1]])
+        assert np.allclose(J, ref, rtol=0, atol=1e-12), (th, J - ref)
+
+
+def test_spline_geometry_and_jumps_on_circle():
+    """Spline tangent, normal, curvature and density derivatives converge to the analytic ones."""
+    R = 0.8
+    phi_fn = lambda s: np.cos(3 * s) + 0.5 * np.sin(s)
+    errs = []
+    for m in (128, 256, 512):
+        plan = O.build_plan(synth.circle_points(m, R), 64, LO, HI)
+        t = m * np.array([0.0, 0.0676, 0.3926, 0.7887])
+        th = 2 * np.pi * t / m
+        T, nrm, curv, sig, _ = O.local_geometry(plan, t)
+        assert np.allclose(T, np.stack([-np.sin(th), np.cos(th)], 1), atol=1e-7)
+        assert np.allclose(nrm, np.stack([np.cos(th), np.sin(th)], 1), atol=1e-7)
+        assert np.allclose(curv, 1 / R, rtol=1e-3)
+        # density = restriction of a smooth function; zero normal-derivative jump
+        phi = phi_fn(2 * np.pi * np.arange(m) / m)
+        J = O.jumps_at(plan, t, phi, None, 0.7)
+        Phi_s = (-3 * np.sin(3 * th) + 0.5 * np.cos(th)) / R
+        Phi_ss = (-9 * np.cos(3 * th) - 0.5 * np.sin(th)) / R ** 2
+        ref = O.cartesian_jumps(np.stack([-np.sin(th), np.cos(th)], 1), np.stack([np.cos(th), np.sin(th)], 1),
+                                1 / R, phi_fn(th), Phi_s, Phi_ss, 0 * th, 0 * th, 0 * th, 0.7)
+        errs.append(np.max(np.abs(J - ref)))
+    assert errs[-1] < 5e-3, errs
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5     # at least second order
+
+
+def test_spline_jumps_on_ellipse_with_uneven_speed():
+    """Uniform-angle samples of an ellipse: the speed |X'| varies along the curve, so the
+    arc-length derivatives need the X'.X'' term.  Density = trace of D, [F] = trace of a
+    smooth function; compared with the jumps from the exact geometry."""
+    a, b, kappa = 0.87, 0.53, 1.3         # not tangent to any grid line
+    F_fn = lambda x, y: np.cos(x) * (1 + y * y)
+    errs = []
+    for m in (256, 1024, 4096):
+        th_k = 2 * np.pi * np.arange(m) / m
+        xy = np.stack([a * np.cos(th_k), b * np.sin(th_k)], 1)
+        plan = O.build_plan(xy, 64, LO, HI)
+        phi = _D(xy[:, 0], xy[:, 1])[0]
+        t = m * np.array([0.03, 0.21, 0.44, 0.61, 0.87])
+        th = 2 * np.pi * t / m
+        J = O.jumps_at(plan, t, phi, F_fn(xy[:, 0], xy[:, 1]), kappa)
+        ref = []
+        for tt in th:
+            X = np.array([a * np.cos(tt), b * np.sin(tt)])
+            X1 = np.array([-a * np.sin(tt), b * np.cos(tt)])
+            X2 = -X
+            sig = np.linalg.norm(X1)
+            T = X1 / sig
+            dT = (X2 / sig - X1 * (X1 @ X2) / sig ** 3) / sig
+            v, g, H = _D(*X)
+            ref.append(O.cartesian_jumps(T, np.array([T[1], -T[0]]), (X1[0] * X2[1] - X1[1] * X2[0]) / sig ** 3,
+                                         v, g @ T, T @ H @ T + g @ dT, 0.0, 0.0, F_fn(*X), kappa))
+        errs.append(np.max(np.abs(J - np.array(ref))))
+    # second order in the sample spacing: two halvings gain well over 8x
+    assert errs[-1] < 1e-5, errs
+    assert errs[0] / errs[1] > 8.0 and errs[1] / errs[2] > 8.0, errs
+
+
+# --------------------------------------------------------------------------
+# correction + fast solve + interpolation: exact on quadratics
+# --------------------------------------------------------------------------
+
+def _quad(x, y):
+    v = 0.3 + 1.1 * x - 0.6 * y + 0.9 * x * x - 0.8 * x * y + 0.45 * y * y
+    return np.stack([v, 1.1 + 1.8 * x - 0.8 * y, -0.6 - 0.8 * x + 0.9 * y,
+                     1.8 + 0 * x, -0.8 + 0 * x, 0.9 + 0 * x], axis=-1)
+
+
+@pytest.mark.parametrize("domain", ["circle", "star"])
+@pytest.mark.parametrize("kappa", [0.0, 3.0])
+def test_quadratic_exactness(domain, kappa):
+    """With v+ = q (quadratic), v- = 0 and exact jumps, the discrete solution is q on Omega."""
+    n = 64 if domain == "circle" else 128
+    xy = synth.circle_points(128, 0.8) if domain == "circle" else synth.star_points(160)
+    plan = O.build_plan(xy, n, LO, HI)
+    c = plan.coord(np.arange(n + 1))
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    Q = _quad(X, Y)
+    F = Q[..., 3] + Q[..., 5] - kappa * Q[..., 0]
+    jq = _quad(plan.q_xy[:, 0], plan.q_xy[:, 1])
+    jz = _quad(plan.xy[:, 0], plan.xy[:, 1])
+    v, vz = O.interface_solve_with_jumps(plan, jq, jz, O.zero_extension(plan, F), kappa)
+    expect = np.where(plan.inside, Q[..., 0], 0.0)
+    assert np.max(np.abs(v - expect)) < 1e-11
+    assert np.max(np.abs(vz - jz[:, 0])) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# the whole boundary operator
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("domain", ["circle", "star"])
+def test_KD_of_one_is_one_for_laplace(domain):
+    """For kappa = 0, v = 1 in Omega / 0 outside solves the corrected system exactly."""
+    if domain == "circle":
+        p = synth.circle_problem(n=64, m=128)
+    else:
+        p = synth.star_problem(n=256)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    out = O.apply_KD(plan, np.ones(plan.M), 0.0)
+    assert np.max(np.abs(out - 1.0)) < 1e-12
+
+
+def test_KD_is_linear_and_not_identity():
+    p = synth.circle_problem(n=64, m=128, kappa=2.0)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    a, b = synth.smooth_density(128, 1), synth.smooth_density(128, 2)
+    ka, kb = O.apply_KD(plan, a, 2.0), O.apply_KD(plan, b, 2.0)
+    kab = O.apply_KD(plan, 2 * a - 3 * b, 2.0)
+    assert np.allclose(kab, 2 * ka - 3 * kb, atol=1e-12)
+    assert np.max(np.abs(ka - 0.5 * a)) > 1e-3
+
+
+def test_KD_constant_density_on_circle_modified_helmholtz():
+    """kappa > 0, phi = 1 on a circle centred in the square box: the discrete problem is
+    invariant under quarter turns and reflections of the box, so the result is too;
+    it lies strictly between 0 and 1 (the kernel decays)."""
+    m = 256
+    p = synth.circle_problem(n=128, m=m, kappa=4.0)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    out = O.apply_KD(plan, np.ones(plan.M), 4.0)
+    assert 0.0 < out.min() and out.max() < 1.0
+    k = np.arange(m)
+    assert np.max(np.abs(out - out[(k + m // 4) % m])) < 1e-10
+    assert np.max(np.abs(out - out[(m - k) % m])) < 1e-10
+
+
+def test_yf_of_zero_is_zero():
+    p = synth.circle_problem(n=32, m=64)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    v, vz = O.interface_solve(plan, np.zeros(plan.M), np.zeros((33, 33)), np.zeros(plan.M), 0.0)
+    assert not v.any() and not vz.any()
+
+
+# --------------------------------------------------------------------------
+# GMRES (Alg. 5)
+# --------------------------------------------------------------------------
+
+def test_gmres_small_nonsymmetric_matches_lu():
+    rng = np.random.default_rng(5)
+    A = np.eye(60) + 0.3 * rng.standard_normal((60, 60)) / np.sqrt(60)
+    b = rng.standard_normal(60)
+    x, it, rel = O.gmres(lambda v: A @ v, b, tol=1e-13, restart=10)
+    assert rel < 1e-13
+    assert np.allclose(x, np.linalg.solve(A, b), atol=1e-11)
+    assert it > 10                                   # exercised a restart
+
+
+def test_gmres_iterate_is_the_krylov_least_squares_minimiser():
+    """After k steps (no restart) GMRES returns argmin ||b - A x|| over span{b, ..., A^(k-1) b}."""
+    rng = np.random.default_rng(11)
+    A = np.eye(40) + 0.5 * rng.standard_normal((40, 40)) / np.sqrt(40)
+    b = rng.standard_normal(40)
+    for k in (1, 3, 7):
+        x, it, _ = O.gmres(lambda v: A @ v, b, tol=1e-30, restart=k, max_iter=k)
+        K = np.stack([np.linalg.matrix_power(A, p) @ b for p in range(k)], axis=1)
+        Qk, _ = np.linalg.qr(K)
+        c = np.linalg.lstsq(A @ Qk, b, rcond=None)[0]
+        assert it == k
+        assert np.allclose(x, Qk @ c, atol=1e-10), k
+
+
+@pytest.mark.slow
+def test_gmres_density_matches_dense_solve_c1():
+    """Assemble the 128x128 K_D on the circle config column by column and LU-solve."""
+    p = synth.circle_problem(n=64, m=128)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    K = np.stack([O.apply_KD(plan, e, 0.0) for e in np.eye(plan.M)], axis=1)
+    b = synth.smooth_density(plan.M, 7)
+    phi, it, rel = O.gmres(lambda v: O.apply_KD(plan, v, 0.0), b, tol=1e-13)
+    ref = np.linalg.solve(K, b)
+    assert np.max(np.abs(phi - ref)) < 1e-11 * np.max(np.abs(ref)) * np.linalg.cond(K)
+    assert np.linalg.cond(K) < 50.0                  # second-kind equation: well conditioned
+
+
+# --------------------------------------------------------------------------
+# end to end: second-order convergence with manufactured solutions
+# --------------------------------------------------------------------------
+
+def _solve(p, tol=1e-10):
+    s = O.solve_bvp(p.xy, p.n, p.lo, p.hi, p.kappa, p.f_grid, p.f_gamma, p.g, tol=tol)
+    return s, O.error_norms(s.plan, s.u_grid, p.exact.u)
+
+
+@pytest.mark.slow
+def test_second_order_circle_laplace():
+    errs = [_solve(synth.circle_problem(n=n, m=2 * n))[1] for n in (32, 64, 128)]
+    for k in range(2):
+        assert errs[k][0] / errs[k + 1][0] > 3.0
+        assert errs[k][1] / errs[k + 1][1] > 3.0
+    assert errs[1][0] < 2e-4
+
+
+@pytest.mark.slow
+def test_second_order_star_helmholtz():
+    errs = [_solve(synth.star_problem(n=n, kappa=1.0))[1] for n in (128, 256, 512)]
+    for k in range(2):
+        assert errs[k][1] / errs[k + 1][1] > 3.0
+    assert errs[2][0] < 2e-5
+
+
+def test_boundary_value_reproduces_g():
+    p = synth.circle_problem(n=64, m=128)
+    s, _ = _solve(p)
+    # u+ at the samples is g to the discretisation error
+    assert np.max(np.abs(s.u_gamma - p.g)) < 1e-3
+    assert s.relres < 1e-10 and 5 <= s.iters <= 40
