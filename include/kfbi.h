@@ -1,0 +1,189 @@
+/*
+ * kfbi.h -- C ABI of the MI355X (gfx950) kernel-free boundary integral library.
+ *
+ * The library solves the interior Dirichlet problem of the modified Helmholtz
+ * equation  Lap u - kappa u = f  in Omega,  u = g  on Gamma = dOmega  (kappa >= 0)
+ * by the kernel-free boundary integral (KFBI) method of Tan, Huang & Ying,
+ * "A GPU-accelerated Cartesian grid method for PDEs on irregular domain"
+ * (arXiv 2404.15249):
+ *   - Sec. 2.1 (second-kind equation): phi/2 + W phi + Y f = g on Gamma, and
+ *     u = W phi + Y f in Omega.  K_D = I/2 + W is the interior one-sided limit
+ *     of the double-layer potential.
+ *   - Sec. 2.2 (interface problem and the table under it): W phi and Y f are the
+ *     solution of  Lap v - kappa v = F  off Gamma, [v] = Phi, [d_n v] = 0,
+ *     v = 0 on the box, with (F, Phi) = (0, phi) or (f~, 0).
+ *   - Alg. 1-4: jumps, correction of the 5-point system at irregular nodes,
+ *     fast sine-transform solve, interpolation to the boundary samples.
+ *   - Alg. 5: restarted GMRES with K_D as the matrix-vector product.
+ *
+ * Conventions shared by every entry point
+ *   Box B = [lo, hi]^2 split into n intervals per axis (h = (hi-lo)/n); node
+ *   (i, j) sits at (lo + i h, lo + j h).  A "grid" array holds the (n+1)^2 node
+ *   values row by row: element j*(n+1) + i (row j is the line y = lo + j h).
+ *   Gamma is given by M >= 3 samples x_m (counter-clockwise, no repeated end
+ *   point) and represented by the periodic cubic spline through them in the
+ *   sample index; densities and f on Gamma are sampled at the same points and
+ *   splined the same way.  The samples are the GMRES unknowns (the paper's
+ *   control points).
+ *
+ *   Unless a parameter says "host", array pointers are DEVICE pointers on the
+ *   context's device, FP64, owned by the caller, and must stay valid until the
+ *   work enqueued by the call has finished on the context stream.  Calls enqueue
+ *   on the context stream and return without synchronising unless stated.
+ *   The library owns only its handles and the device workspace it allocates in
+ *   kfbi_prob_create.  A problem handle must not be used by two host threads at
+ *   the same time.
+ *
+ * Errors: every call returns a kfbi_status; on error no output is written (for
+ * enqueueing calls: nothing is enqueued) and kfbi_last_error() returns a
+ * message for the calling thread.
+ */
+#ifndef KFBI_H
+#define KFBI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int kfbi_status;
+#define KFBI_OK 0
+#define KFBI_NOT_CONVERGED 1       /* warning: outputs hold the last iterate */
+#define KFBI_ERR_ARG (-1)          /* bad argument (null pointer, size out of range) */
+#define KFBI_ERR_GEOMETRY (-2)     /* curve too close to the box, grid edge crossed twice, ... */
+#define KFBI_ERR_OOM (-3)          /* device allocation failed */
+#define KFBI_ERR_DEVICE (-4)       /* HIP runtime error */
+#define KFBI_ERR_BUDGET (-5)       /* request can never fit the batch's memory budget */
+#define KFBI_ERR_NONFINITE (-6)    /* NaN or Inf met in the data */
+#define KFBI_ERR_UNSUPPORTED (-7)  /* configuration outside what this build handles */
+
+typedef struct kfbi_ctx kfbi_ctx;
+typedef struct kfbi_prob kfbi_prob;
+
+/* Problem description (all host memory). */
+typedef struct {
+    double lo, hi;        /* box [lo, hi]^2 */
+    int n;                /* intervals per axis; power of two, 64 <= n <= 4096 */
+    double kappa;         /* >= 0, the operator is Lap - kappa (Sec. 2, modified Helmholtz) */
+    int m;                /* number of boundary samples, 3 <= m <= 65536 */
+    const double* xy;     /* host, m x 2 (x0, y0, x1, y1, ...), counter-clockwise */
+    double tol;           /* GMRES relative residual tolerance (Sec. 5 uses 1e-8); <= 0: 1e-10 */
+    int restart;          /* GMRES restart length; <= 0: 50 */
+    int max_iter;         /* cap on K_D applications inside GMRES; <= 0: 500 */
+} kfbi_desc;
+
+/* ---------------------------------------------------------------- contexts */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on (NULL: the library creates its own stream with default flags and
+ * priority).  The caller keeps ownership of a stream it passes in. */
+kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out);
+kfbi_status kfbi_ctx_destroy(kfbi_ctx* ctx);
+/* Block until all work enqueued on the context stream has finished. */
+kfbi_status kfbi_ctx_sync(kfbi_ctx* ctx);
+
+/* ---------------------------------------------------------------- problems */
+
+/* Build the geometry plan on the host (spline of Gamma, classification of the
+ * nodes by horizontal scan lines, grid-line crossings, irregular nodes and
+ * their arms, six-point interpolation stencils: Alg. 1 steps 1-3 and the
+ * Procedure 1 list of Sec. 4.2) and upload it with the workspace of the solve.
+ * Fails with KFBI_ERR_GEOMETRY when the curve comes within 2h of the box, when
+ * an edge whose end nodes differ holds other than one crossing, or when an edge
+ * is crossed twice.  Synchronous. */
+kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* desc, kfbi_prob** out);
+kfbi_status kfbi_prob_destroy(kfbi_prob* prob);
+
+/* Sizes: samples M, crossings Q, irregular nodes I, device bytes held. */
+kfbi_status kfbi_prob_info(const kfbi_prob* prob, int* m, int* q, int* n_irregular,
+                           size_t* device_bytes);
+/* host, (n+1)^2 bytes: 1 where the node lies in Omega (or on Gamma). */
+kfbi_status kfbi_prob_mask(const kfbi_prob* prob, unsigned char* inside);
+/* host, plan export: for each crossing its axis (0: on a line y = const, 1: on a
+ * line x = const), its two end nodes (i0, j0, i1, j1), its spline parameter and
+ * its position (x, y).  Any pointer may be NULL. */
+kfbi_status kfbi_prob_crossings(const kfbi_prob* prob, int* axis, int* nodes, double* t, double* xy);
+/* host, I x 2: the irregular nodes (i, j) in the library's internal order. */
+kfbi_status kfbi_prob_irregular(const kfbi_prob* prob, int* ij);
+
+/* ---------------------------------------------------------------- hot path */
+
+/* K_D phi = (I/2 + W) phi at the M samples: one interface solve with [v] = phi,
+ * F = 0 (Alg. 1 steps 4-6).  Jumps and corrections at the irregular nodes
+ * (Alg. 2), a sine-transform solve along y with a tridiagonal solve along x
+ * (Alg. 4) evaluated only where the interpolation needs it, and the
+ * interpolation (Alg. 3).  phi, out: device, M doubles. */
+kfbi_status kfbi_apply(kfbi_prob* prob, const double* phi, double* out);
+
+/* Full Dirichlet solve (Sec. 2.1): g^ = g - (Y f)^+, GMRES (Alg. 5) on
+ * K_D phi = g^ until the relative residual drops below tol, then u = W phi + Y f.
+ *   f_grid : device grid, f at every node (values outside Omega are ignored)
+ *   f_gamma: device, M: f at the samples (the jump of F across Gamma)
+ *   g      : device, M: Dirichlet data at the samples
+ *   u_grid : device grid out: u at nodes in Omega, 0 elsewhere
+ *   u_gamma: device, M out: the interior limit u+ at the samples
+ *   phi    : device, M in/out: initial guess in, density out
+ *   iters  : host out, K_D applications made by GMRES (may be NULL)
+ *   rel_res: host out, final true relative residual (may be NULL)
+ * Synchronises.  Returns KFBI_NOT_CONVERGED when max_iter was reached. */
+kfbi_status kfbi_solve(kfbi_prob* prob, const double* f_grid, const double* f_gamma,
+                       const double* g, double* u_grid, double* u_gamma, double* phi,
+                       int* iters, double* rel_res);
+
+/* Alg. 5 alone: restarted GMRES on K_D phi = rhs, fully device resident (the
+ * Hessenberg least-squares problem is solved on the device, so nothing crosses
+ * to the host inside the iteration).  rhs: device M; phi: device M, initial
+ * guess in, iterate out.  Stops when the true relative residual drops below
+ * tol, or after max_iter Arnoldi steps; tol <= 0 never stops early (fixed
+ * work, for timing).  iters: Arnoldi steps made; applies: all K_D
+ * applications (Arnoldi steps plus one residual check per restart cycle);
+ * rel_res: last relative residual (true residual at cycle ends, Givens
+ * estimate otherwise).  Host outputs may be NULL.  Synchronises. */
+kfbi_status kfbi_gmres(kfbi_prob* prob, const double* rhs, double* phi, double tol, int max_iter,
+                       int* iters, int* applies, double* rel_res);
+
+/* ---------------------------------------------------------------- steps (for tests and tools) */
+
+/* Alg. 2 alone: the correction of the right-hand side at every irregular node
+ * for [v] = phi and [F] = f_gamma (f_gamma may be NULL: [F] = 0).  corr: device,
+ * I doubles in the order of kfbi_prob_irregular. */
+kfbi_status kfbi_correct(kfbi_prob* prob, const double* phi, const double* f_gamma, double* corr);
+
+/* Alg. 4 alone: solve (L_h - kappa) v = rhs on the interior nodes with v = 0 on
+ * the box.  rhs, v: device grids (only interior nodes of rhs are read; the box
+ * rows and columns of v are written 0).  rhs and v may alias. */
+kfbi_status kfbi_fast_solve(kfbi_prob* prob, const double* rhs, double* v);
+
+/* One interface solve with the full grid: [v] = phi, F = ftilde (already zero
+ * outside Omega), [F] = f_gamma (may be NULL).  vgrid: device grid out, vz:
+ * device M out (v+ at the samples).  phi may be NULL (Phi = 0). */
+kfbi_status kfbi_interface_solve(kfbi_prob* prob, const double* phi, const double* ftilde,
+                                 const double* f_gamma, double* vgrid, double* vz);
+
+/* As kfbi_interface_solve but with the Cartesian jumps given directly:
+ * jq: device Q x 6 at the crossings, jz: device M x 6 at the samples, each row
+ * ([v], [v_x], [v_y], [v_xx], [v_xy], [v_yy]).  Used to check that correction,
+ * fast solve and interpolation are exact on quadratics. */
+kfbi_status kfbi_interface_solve_jumps(kfbi_prob* prob, const double* jq, const double* jz,
+                                       const double* ftilde, double* vgrid, double* vz);
+
+/* ---------------------------------------------------------------- diagnostics */
+
+const char* kfbi_status_str(kfbi_status s);
+const char* kfbi_last_error(void);
+/* Kernel timing of the K_D apply.  While timing is on, every apply (also the
+ * ones inside kfbi_gmres and kfbi_solve) records HIP events around its three
+ * launches on the context stream, without synchronising; kfbi_apply_timing
+ * synchronises and returns the average duration in microseconds of the
+ * correction (Alg. 2), the sparse fast solve (Alg. 4) and the interpolation
+ * (Alg. 3) launches over the applies recorded since timing was switched on
+ * (at most 4096).  kfbi_set_timing(prob, 1) also clears the record. */
+kfbi_status kfbi_set_timing(kfbi_prob* prob, int on);
+kfbi_status kfbi_apply_timing(kfbi_prob* prob, double* us_correct, double* us_modes,
+                              double* us_interp, int* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFBI_H */

@@ -1,0 +1,538 @@
+// C ABI of the KFBI library (see include/kfbi.h): contexts, problems, the
+// operator apply, the device-resident GMRES solve and the step entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/kfbi.h"
+#include "kernels.h"
+#include "plan.h"
+
+using namespace kfbi;
+
+namespace {
+
+thread_local std::string g_err;
+
+kfbi_status set_err(kfbi_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return set_err(KFBI_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
+    } while (0)
+
+}  // namespace
+
+struct kfbi_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t lds_max = 65536;
+    int num_cu = 256;
+};
+
+struct kfbi_prob {
+    kfbi_ctx* ctx = nullptr;
+    Plan plan;
+    double kappa = 0, tol = 1e-10;
+    int restart = 50, max_iter = 500;
+    int N = 0, n = 0, M = 0, Q = 0, I = 0;
+    int W = 4, G = 1;
+    DevPlan dp{};
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    // work buffers
+    double* corr = nullptr;      // I
+    double* partial = nullptr;   // G M
+    double* R = nullptr;         // N N
+    double* A = nullptr;         // N N
+    double* tmpM = nullptr;      // M
+    GmresBufs gm{};
+    // timing: four events per recorded apply, read back by kfbi_apply_timing
+    static constexpr int kMaxTimed = 4096;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    int t_count = 0;
+};
+
+namespace {
+
+template <class T>
+kfbi_status dev_alloc(kfbi_prob* p, T** out, size_t count) {
+    void* ptr = nullptr;
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    if (hipMalloc(&ptr, b) != hipSuccess) {
+        hipGetLastError();
+        return set_err(KFBI_ERR_OOM, "device allocation of " + std::to_string(b) + " bytes failed");
+    }
+    p->allocs.push_back(ptr);
+    p->bytes += b;
+    *out = static_cast<T*>(ptr);
+    return KFBI_OK;
+}
+
+template <class T>
+kfbi_status upload(kfbi_prob* p, const T** out, const std::vector<T>& v) {
+    T* d = nullptr;
+    kfbi_status s = dev_alloc(p, &d, v.size());
+    if (s) return s;
+    if (!v.empty()) HIP_TRY(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *out = d;
+    return KFBI_OK;
+}
+
+void free_prob(kfbi_prob* p) {
+    for (void* a : p->allocs) hipFree(a);
+    p->allocs.clear();
+    for (auto& e : p->ev)
+        if (e) hipEventDestroy(e);
+    p->ev.clear();
+}
+
+// Per-mode constants of the x-direction tridiagonal systems (Alg. 4), FP64.
+std::vector<ModeConst> mode_constants(int N, double h, double kappa) {
+    std::vector<ModeConst> mc(N);
+    const int C = N / 64;
+    for (int l = 1; l < N; ++l) {
+        const double s = std::sin(M_PI * l / (2.0 * N));
+        const double d = h * h * kappa + 4.0 * s * s;          // beta - 2 > 0
+        const double sq = std::sqrt(d * (4.0 + d));
+        const double r = 1.0 + 0.5 * d - 0.5 * sq;             // root of r^2 - beta r + 1 in (0, 1)
+        ModeConst& c = mc[l];
+        c.r = r;
+        c.rinv = 1.0 / r;
+        c.logr = std::log1p(0.5 * d - 0.5 * sq);
+        c.rC = std::pow(r, C);
+        const double r2N = std::exp(2.0 * N * c.logr);
+        c.smc = -r / (1.0 - r2N);
+    }
+    return mc;
+}
+
+kfbi_status check_ptr(const void* p, const char* name) {
+    if (!p) return set_err(KFBI_ERR_ARG, std::string(name) + " is NULL");
+    return KFBI_OK;
+}
+
+// Dense interface solve: R <- f~ (+ corrections), two sine products around the
+// row solves, then interpolation; the solution grid is left in R (padded
+// interior layout) and optionally written to `vgrid`.
+kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, bool mask, double* vgrid,
+                                  bool mask_out, double* vz) {
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(launch_fill_rhs(p->dp, f, mask, p->R, s));
+    HIP_TRY(launch_correct(p->dp, js, nullptr, p->R, nullptr, s));
+    HIP_TRY(launch_sine_gemm(p->dp, p->R, p->A, 1.0, s));
+    HIP_TRY(launch_rows_solve(p->dp, p->A, s));
+    HIP_TRY(launch_sine_gemm(p->dp, p->A, p->R, 2.0 / p->N, s));
+    if (vz) HIP_TRY(launch_interp(p->dp, js, nullptr, 0, p->R, vz, nullptr, s));
+    if (vgrid) HIP_TRY(launch_grid_out(p->dp, p->R, mask_out, vgrid, s));
+    return KFBI_OK;
+}
+
+kfbi_status sparse_apply(kfbi_prob* p, const double* phi, double* out, const int* skip) {
+    hipStream_t s = p->ctx->stream;
+    JumpSrc js{phi, nullptr, nullptr, nullptr};
+    hipEvent_t* ev = nullptr;
+    if (p->timing && p->t_count < kfbi_prob::kMaxTimed) {
+        if (p->ev.empty()) {
+            p->ev.assign(4 * kfbi_prob::kMaxTimed, nullptr);
+            for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
+        }
+        ev = &p->ev[4 * p->t_count++];
+    }
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(launch_correct(p->dp, js, p->corr, nullptr, skip, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(launch_modes(p->dp, p->corr, p->partial, p->G, p->W, skip, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    HIP_TRY(launch_interp(p->dp, js, p->partial, p->G, nullptr, out, skip, s));
+    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    return KFBI_OK;
+}
+
+// Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps are
+// enqueued in batches; with tol > 0 the host polls the device state after each
+// batch, with tol <= 0 the work is fixed and the host waits once at the end.
+kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_iter, GmresState* out) {
+    hipStream_t s = p->ctx->stream;
+    const int M = p->M;
+    GmresBufs b = p->gm;
+    b.tol = tol;
+    b.max_iter = max_iter;
+    HIP_TRY(hipMemcpyAsync(b.phi, phi_in, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(b.xcur, phi_in, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    static const GmresState st0 = [] {
+        GmresState g{};
+        g.first = 1;
+        return g;
+    }();
+    HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
+    const int* skip = &b.st->converged;
+    const int cycles = max_iter / std::max(1, p->restart) + 2;
+    const int max_steps = max_iter + cycles;
+    const int batch = tol > 0 ? 8 : max_steps;
+    GmresState st{};
+    for (int done = 0; done < max_steps; done += batch) {
+        const int nb = std::min(batch, max_steps - done);
+        for (int k = 0; k < nb; ++k) {
+            if (kfbi_status e = sparse_apply(p, b.xcur, b.w, skip)) return e;
+            HIP_TRY(launch_gmres_step(p->dp, b, s));
+        }
+        HIP_TRY(hipMemcpyAsync(&st, b.st, sizeof st, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (st.converged) break;
+    }
+    *out = st;
+    return KFBI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kfbi_status_str(kfbi_status s) {
+    switch (s) {
+        case KFBI_OK: return "ok";
+        case KFBI_NOT_CONVERGED: return "not converged";
+        case KFBI_ERR_ARG: return "invalid argument";
+        case KFBI_ERR_GEOMETRY: return "unsupported geometry";
+        case KFBI_ERR_OOM: return "out of device memory";
+        case KFBI_ERR_DEVICE: return "device error";
+        case KFBI_ERR_BUDGET: return "over memory budget";
+        case KFBI_ERR_NONFINITE: return "non-finite data";
+        case KFBI_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* kfbi_last_error(void) { return g_err.c_str(); }
+
+kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
+    if (!out) return set_err(KFBI_ERR_ARG, "out is NULL");
+    int count = 0;
+    HIP_TRY(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return set_err(KFBI_ERR_ARG, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    kfbi_ctx* c = new (std::nothrow) kfbi_ctx;
+    if (!c) return set_err(KFBI_ERR_ARG, "host allocation failed");
+    c->device = device;
+    c->lds_max = prop.sharedMemPerBlock;
+    c->num_cu = prop.multiProcessorCount;
+    if (hip_stream) {
+        c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return set_err(KFBI_ERR_DEVICE, hipGetErrorString(e));
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_ctx_destroy(kfbi_ctx* ctx) {
+    if (!ctx) return KFBI_OK;
+    if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_ctx_sync(kfbi_ctx* ctx) {
+    if (!ctx) return set_err(KFBI_ERR_ARG, "ctx is NULL");
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out) {
+    if (!ctx || !d || !out || !d->xy) return set_err(KFBI_ERR_ARG, "NULL argument");
+    const int n = d->n;
+    if (n < 64 || n > 4096 || (n & (n - 1))) return set_err(KFBI_ERR_UNSUPPORTED, "n must be a power of two in [64, 4096]");
+    if (d->m < 3 || d->m > 65536) return set_err(KFBI_ERR_ARG, "m must be in [3, 65536]");
+    if (!(d->hi > d->lo) || !std::isfinite(d->lo) || !std::isfinite(d->hi)) return set_err(KFBI_ERR_ARG, "bad box");
+    if (!(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return set_err(KFBI_ERR_ARG, "kappa must be finite and >= 0");
+    HIP_TRY(hipSetDevice(ctx->device));
+    kfbi_prob* p = new (std::nothrow) kfbi_prob;
+    if (!p) return set_err(KFBI_ERR_ARG, "host allocation failed");
+    p->ctx = ctx;
+    try {
+        p->plan = build_plan(d->xy, d->m, n, d->lo, d->hi);
+    } catch (const GeometryError& ge) {
+        delete p;
+        return set_err(KFBI_ERR_GEOMETRY, ge.msg);
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return set_err(KFBI_ERR_ARG, "host allocation failed");
+    }
+    const Plan& P = p->plan;
+    p->kappa = d->kappa;
+    p->tol = d->tol > 0 ? d->tol : 1e-10;
+    p->restart = d->restart > 0 ? std::min(d->restart, 120) : 50;
+    p->max_iter = d->max_iter > 0 ? d->max_iter : 500;
+    p->N = n;
+    p->n = n - 1;
+    p->M = d->m;
+    p->Q = (int)P.q_axis.size();
+    p->I = (int)P.irr_i.size();
+    if (p->M > 16384) {
+        delete p;
+        return set_err(KFBI_ERR_UNSUPPORTED, "more than 16384 samples");
+    }
+    // workgroup shape of the sparse fast solve: as many waves as the LDS allows
+    p->W = 1;
+    for (int W : {4, 2, 1}) {
+        if (modes_lds_bytes(n, p->M, W) <= ctx->lds_max) {
+            p->W = W;
+            break;
+        }
+    }
+    if (modes_lds_bytes(n, p->M, p->W) > ctx->lds_max) {
+        delete p;
+        return set_err(KFBI_ERR_UNSUPPORTED, "problem too large for the local data share");
+    }
+    p->G = std::max(1, std::min((p->n + p->W - 1) / p->W, 2 * ctx->num_cu));
+
+    kfbi_status st = KFBI_OK;
+    auto fail = [&](kfbi_status s) {
+        free_prob(p);
+        delete p;
+        return s;
+    };
+    DevPlan& dp = p->dp;
+    dp.n = p->n;
+    dp.N = n;
+    dp.M = p->M;
+    dp.Q = p->Q;
+    dp.I = p->I;
+    dp.log2N = 0;
+    while ((1 << dp.log2N) < n) dp.log2N++;
+    dp.lo = P.lo;
+    dp.h = P.h;
+    dp.h2 = P.h * P.h;
+    dp.inv_h2 = 1.0 / (P.h * P.h);
+    dp.kappa = p->kappa;
+    std::vector<int> sxy(p->M);
+    for (int k = 0; k < p->M; ++k) sxy[k] = (P.cp_sx[k] > 0 ? 1 : 0) | (P.cp_sy[k] > 0 ? 2 : 0);
+    std::vector<double> sinq(n / 2 + 1);
+    for (int k = 0; k <= n / 2; ++k) sinq[k] = std::sin(M_PI * k / n);
+    sinq[n / 2] = 1.0;
+    const int K = 30;
+    dp.K = K;
+    std::vector<int> colptr(P.col_ptr.begin(), P.col_ptr.end());
+    if ((st = upload(p, &dp.q_geo, P.q_geo)) || (st = upload(p, &dp.q_axis, P.q_axis)) ||
+        (st = upload(p, &dp.z_geo, P.z_geo)) || (st = upload(p, &dp.zx, P.px)) || (st = upload(p, &dp.zy, P.py)) ||
+        (st = upload(p, &dp.irr_i, P.irr_i)) || (st = upload(p, &dp.irr_j, P.irr_j)) ||
+        (st = upload(p, &dp.irr_s, P.irr_s)) || (st = upload(p, &dp.arm_q, P.arm_q)) ||
+        (st = upload(p, &dp.arm_d, P.arm_d)) || (st = upload(p, &dp.col_ptr, colptr)) ||
+        (st = upload(p, &dp.cp_i0, P.cp_i0)) || (st = upload(p, &dp.cp_j0, P.cp_j0)) ||
+        (st = upload(p, &dp.cp_sxy, sxy)) || (st = upload(p, &dp.cp_w, P.cp_w)) ||
+        (st = upload(p, &dp.cp_out, P.cp_out)) || (st = upload(p, &dp.inside, P.inside)) ||
+        (st = upload(p, &dp.sinq, sinq)) || (st = upload(p, &dp.modes, mode_constants(n, P.h, p->kappa))) ||
+        (st = upload(p, &dp.taps, spline_filter_taps(K))))
+        return fail(st);
+    const int M = p->M, m = p->restart;
+    if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->partial, (size_t)p->G * M)) ||
+        (st = dev_alloc(p, &p->R, (size_t)n * n)) || (st = dev_alloc(p, &p->A, (size_t)n * n)) ||
+        (st = dev_alloc(p, &p->tmpM, M)) || (st = dev_alloc(p, &p->gm.V, (size_t)(m + 1) * M)) ||
+        (st = dev_alloc(p, &p->gm.H, (size_t)(m + 1) * m)) || (st = dev_alloc(p, &p->gm.cs, m)) ||
+        (st = dev_alloc(p, &p->gm.sn, m)) || (st = dev_alloc(p, &p->gm.g, m + 1)) ||
+        (st = dev_alloc(p, &p->gm.ghat, M)) || (st = dev_alloc(p, &p->gm.phi, M)) ||
+        (st = dev_alloc(p, &p->gm.xcur, M)) || (st = dev_alloc(p, &p->gm.w, M)) ||
+        (st = dev_alloc(p, &p->gm.st, 1)))
+        return fail(st);
+    p->gm.m = m;
+    p->gm.max_iter = p->max_iter;
+    p->gm.tol = p->tol;
+    *out = p;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_destroy(kfbi_prob* p) {
+    if (!p) return KFBI_OK;
+    hipSetDevice(p->ctx->device);
+    hipStreamSynchronize(p->ctx->stream);
+    free_prob(p);
+    delete p;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_info(const kfbi_prob* p, int* m, int* q, int* ni, size_t* bytes) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (m) *m = p->M;
+    if (q) *q = p->Q;
+    if (ni) *ni = p->I;
+    if (bytes) *bytes = p->bytes;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_mask(const kfbi_prob* p, unsigned char* inside) {
+    if (!p || !inside) return set_err(KFBI_ERR_ARG, "NULL argument");
+    std::memcpy(inside, p->plan.inside.data(), p->plan.inside.size());
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_crossings(const kfbi_prob* p, int* axis, int* nodes, double* t, double* xy) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    const Plan& P = p->plan;
+    for (int k = 0; k < p->Q; ++k) {
+        if (axis) axis[k] = P.q_axis[k];
+        if (nodes)
+            for (int c = 0; c < 4; ++c) nodes[4 * k + c] = P.q_nodes[4 * k + c];
+        if (t) t[k] = P.q_t[k];
+        if (xy) {
+            xy[2 * k] = P.q_x[k];
+            xy[2 * k + 1] = P.q_y[k];
+        }
+    }
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_irregular(const kfbi_prob* p, int* ij) {
+    if (!p || !ij) return set_err(KFBI_ERR_ARG, "NULL argument");
+    for (int k = 0; k < p->I; ++k) {
+        ij[2 * k] = p->plan.irr_i[k];
+        ij[2 * k + 1] = p->plan.irr_j[k];
+    }
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status s = check_ptr(phi, "phi")) return s;
+    if (kfbi_status s = check_ptr(out, "out")) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    return sparse_apply(p, phi, out, nullptr);
+}
+
+kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status s = check_ptr(corr, "corr")) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    JumpSrc js{phi, f_gamma, nullptr, nullptr};
+    HIP_TRY(launch_correct(p->dp, js, corr, nullptr, nullptr, p->ctx->stream));
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_fast_solve(kfbi_prob* p, const double* rhs, double* v) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status s = check_ptr(rhs, "rhs")) return s;
+    if (kfbi_status s = check_ptr(v, "v")) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(launch_fill_rhs(p->dp, rhs, false, p->R, s));
+    HIP_TRY(launch_sine_gemm(p->dp, p->R, p->A, 1.0, s));
+    HIP_TRY(launch_rows_solve(p->dp, p->A, s));
+    HIP_TRY(launch_sine_gemm(p->dp, p->A, p->R, 2.0 / p->N, s));
+    HIP_TRY(launch_grid_out(p->dp, p->R, false, v, s));
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_interface_solve(kfbi_prob* p, const double* phi, const double* ftilde, const double* f_gamma,
+                                 double* vgrid, double* vz) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (!vgrid && !vz) return set_err(KFBI_ERR_ARG, "no output requested");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    JumpSrc js{phi, f_gamma, nullptr, nullptr};
+    return dense_interface_solve(p, js, ftilde, false, vgrid, false, vz);
+}
+
+kfbi_status kfbi_interface_solve_jumps(kfbi_prob* p, const double* jq, const double* jz, const double* ftilde,
+                                       double* vgrid, double* vz) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status s = check_ptr(jq, "jq")) return s;
+    if (kfbi_status s = check_ptr(jz, "jz")) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    JumpSrc js{nullptr, nullptr, jq, jz};
+    return dense_interface_solve(p, js, ftilde, false, vgrid, false, vz);
+}
+
+kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma, const double* g, double* u_grid,
+                       double* u_gamma, double* phi, int* iters, double* rel_res) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    for (auto [ptr, name] : {std::pair<const void*, const char*>{f_grid, "f_grid"}, {f_gamma, "f_gamma"}, {g, "g"},
+                             {u_grid, "u_grid"}, {u_gamma, "u_gamma"}, {phi, "phi"}})
+        if (kfbi_status s = check_ptr(ptr, name)) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    const int M = p->M;
+    // g^ = g - (Y f)^+ (Sec. 2.1)
+    JumpSrc jy{nullptr, f_gamma, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
+    GmresBufs b = p->gm;
+    HIP_TRY(launch_axpby(M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
+    // GMRES (Alg. 5): every step is one K_D apply plus one orthogonalisation
+    GmresState st{};
+    if (kfbi_status e = run_gmres(p, phi, p->tol, p->max_iter, &st)) return e;
+    // u = W phi + Y f
+    JumpSrc jf{b.phi, f_gamma, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, jf, f_grid, true, u_grid, true, u_gamma)) return e;
+    HIP_TRY(hipMemcpyAsync(phi, b.phi, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (iters) *iters = st.it;
+    if (rel_res) *rel_res = st.relres;
+    if (st.converged == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
+}
+
+kfbi_status kfbi_gmres(kfbi_prob* p, const double* rhs, double* phi, double tol, int max_iter, int* iters,
+                       int* applies, double* rel_res) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status e = check_ptr(rhs, "rhs")) return e;
+    if (kfbi_status e = check_ptr(phi, "phi")) return e;
+    if (max_iter <= 0) return set_err(KFBI_ERR_ARG, "max_iter must be positive");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(hipMemcpyAsync(p->gm.ghat, rhs, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    GmresState st{};
+    if (kfbi_status e = run_gmres(p, phi, tol, max_iter, &st)) return e;
+    HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (iters) *iters = st.it;
+    // one residual apply per cycle start, one more for the final residual check
+    if (applies) *applies = st.it + st.cycles + (st.converged ? 1 : 0);
+    if (rel_res) *rel_res = st.relres;
+    if (st.converged == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
+}
+
+kfbi_status kfbi_set_timing(kfbi_prob* p, int on) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    p->timing = on != 0;
+    if (p->timing) p->t_count = 0;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_apply_timing(kfbi_prob* p, double* a, double* b, double* c, int* count) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    double acc[3] = {0, 0, 0};
+    for (int k = 0; k < p->t_count; ++k) {
+        for (int q = 0; q < 3; ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, p->ev[4 * k + q], p->ev[4 * k + q + 1]));
+            acc[q] += 1e3 * ms;
+        }
+    }
+    const double k = p->t_count ? 1.0 / p->t_count : 0.0;
+    if (a) *a = acc[0] * k;
+    if (b) *b = acc[1] * k;
+    if (c) *c = acc[2] * k;
+    if (count) *count = p->t_count;
+    return KFBI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// Device data layouts and kernel launchers of the KFBI library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace kfbi {
+
+// Per y-mode constants of the tridiagonal solve along x (Alg. 4).  For mode l
+// the system is x[i-1] - beta x[i] + x[i+1] = e[i], beta = 2 + h^2 (kappa - lambda_l),
+// lambda_l = -(4/h^2) sin^2(pi l / 2N); r is the root of r^2 - beta r + 1 = 0 in (0, 1).
+struct ModeConst {
+    double r;      // decay root
+    double rinv;   // 1 / r
+    double logr;   // log r
+    double rC;     // r^C (C = N / 64, the chunk one lane owns)
+    double smc;    // -r / (1 - r^(2N)): scale of the rank-one boundary fix
+    double pad[3];
+};
+
+// Everything a kernel needs to read one problem's plan on the device.
+struct DevPlan {
+    int n, N, M, Q, I;
+    int log2N;
+    double lo, h, inv_h2, h2, kappa;
+    const PointGeom* q_geo;   // Q
+    const int* q_axis;        // Q
+    const PointGeom* z_geo;   // M
+    const double* zx;         // M sample positions
+    const double* zy;         // M
+    const int* irr_i;         // I
+    const int* irr_j;         // I
+    const double* irr_s;      // I
+    const int* arm_q;         // 4 I
+    const double* arm_d;      // 4 I
+    const int* col_ptr;       // N + 1 entries used (i = 0..N)
+    const int* cp_i0;         // M
+    const int* cp_j0;         // M
+    const int* cp_sxy;        // M: bit 0 sx>0, bit 1 sy>0
+    const double* cp_w;       // 6 M
+    const unsigned char* cp_out;   // 6 M
+    const unsigned char* inside;   // (n+1)^2
+    const double* sinq;       // N/2 + 1: sin(pi k / N)
+    const ModeConst* modes;   // N (index l = 1..N-1 used)
+    const double* taps;       // 2 K + 3 spline filter taps
+    int K;
+};
+
+// Source of the interface jumps: either computed from densities on the
+// spline (phi, fgam may be null) or given directly (jq / jz, 6 per point).
+struct JumpSrc {
+    const double* phi;
+    const double* fgam;
+    const double* jq;
+    const double* jz;
+};
+
+struct GmresState {
+    int mode;        // 0: residual step pending, 1: Arnoldi, 2: done
+    int j;           // Arnoldi column inside the cycle
+    int it;          // K_D applications made by the Arnoldi process
+    int first;       // 1 until r0 is known
+    int converged;   // 1 converged, -1 iteration cap, 0 running
+    int cycles;
+    double r0;
+    double relres;
+};
+
+struct GmresBufs {
+    double* V;       // (m+1) M
+    double* H;       // (m+1) m, column j at H + j (m+1)
+    double* cs;      // m
+    double* sn;      // m
+    double* g;       // m + 1
+    double* ghat;    // M
+    double* phi;     // M
+    double* xcur;    // M: input of the next K_D apply
+    double* w;       // M: output of the last K_D apply
+    GmresState* st;
+    int m;
+    int max_iter;
+    double tol;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* dense, const int* skip,
+                          hipStream_t s);
+hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int G, int W,
+                        const int* skip, hipStream_t s);
+hipError_t launch_interp(const DevPlan& p, JumpSrc js, const double* partial, int G, const double* grid,
+                         double* out, const int* skip, hipStream_t s);
+hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double* R, hipStream_t s);
+hipError_t launch_sine_gemm(const DevPlan& p, const double* B, double* Cm, double alpha, hipStream_t s);
+hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s);
+hipError_t launch_grid_out(const DevPlan& p, const double* V, bool mask, double* u, hipStream_t s);
+hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z,
+                        hipStream_t s);
+hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s);
+
+size_t modes_lds_bytes(int N, int M, int W);
+
+}  // namespace kfbi

@@ -1,0 +1,237 @@
+"""Python binding of the KFBI HIP library (``include/kfbi.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libkfbi.so``.  PyTorch supplies device memory and the stream.  There is no
+CPU fallback: importing this module fails when the library is not built.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libkfbi.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2404_15249_amd.build`")
+
+_lib = ct.CDLL(LIB_PATH)
+
+OK = 0
+NOT_CONVERGED = 1
+ERR_GEOMETRY = -2
+
+
+class KfbiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class GeometryError(KfbiError):
+    pass
+
+
+class _Desc(ct.Structure):
+    _fields_ = [("lo", ct.c_double), ("hi", ct.c_double), ("n", ct.c_int), ("kappa", ct.c_double),
+                ("m", ct.c_int), ("xy", ct.POINTER(ct.c_double)), ("tol", ct.c_double),
+                ("restart", ct.c_int), ("max_iter", ct.c_int)]
+
+
+_vp = ct.c_void_p
+_sigs = {
+    "kfbi_ctx_create": [ct.c_int, _vp, ct.POINTER(_vp)],
+    "kfbi_ctx_destroy": [_vp],
+    "kfbi_ctx_sync": [_vp],
+    "kfbi_prob_create": [_vp, ct.POINTER(_Desc), ct.POINTER(_vp)],
+    "kfbi_prob_destroy": [_vp],
+    "kfbi_prob_info": [_vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_size_t)],
+    "kfbi_prob_mask": [_vp, _vp],
+    "kfbi_prob_crossings": [_vp, _vp, _vp, _vp, _vp],
+    "kfbi_prob_irregular": [_vp, _vp],
+    "kfbi_apply": [_vp, _vp, _vp],
+    "kfbi_solve": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
+    "kfbi_gmres": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                   ct.POINTER(ct.c_double)],
+    "kfbi_correct": [_vp, _vp, _vp, _vp],
+    "kfbi_fast_solve": [_vp, _vp, _vp],
+    "kfbi_interface_solve": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi_interface_solve_jumps": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi_set_timing": [_vp, ct.c_int],
+    "kfbi_apply_timing": [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
+                          ct.POINTER(ct.c_int)],
+}
+for _name, _args in _sigs.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ct.c_int
+_lib.kfbi_status_str.argtypes = [ct.c_int]
+_lib.kfbi_status_str.restype = ct.c_char_p
+_lib.kfbi_last_error.argtypes = []
+_lib.kfbi_last_error.restype = ct.c_char_p
+
+EXPORTED = tuple(_sigs) + ("kfbi_status_str", "kfbi_last_error")
+
+
+def _check(status, allow=(OK,)):
+    if status in allow:
+        return status
+    msg = _lib.kfbi_last_error().decode() or _lib.kfbi_status_str(status).decode()
+    if status == ERR_GEOMETRY:
+        raise GeometryError(status, msg)
+    raise KfbiError(status, msg)
+
+
+def _dptr(t, name, numel=None):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return _vp(t.data_ptr())
+
+
+class Context:
+    """A device and the HIP stream the library enqueues on (torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = _vp()
+        _check(_lib.kfbi_ctx_create(device, _vp(self.stream.cuda_stream), ct.byref(h)))
+        self._h = h
+
+    def sync(self):
+        _check(_lib.kfbi_ctx_sync(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.kfbi_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+class Problem:
+    """One domain on one grid: the geometry plan and the device workspace."""
+
+    def __init__(self, ctx: Context, xy, n: int, kappa: float, lo: float = -1.2, hi: float = 1.2,
+                 tol: float = 1e-10, restart: int = 50, max_iter: int = 500):
+        self.ctx = ctx
+        xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
+        self._xy = xy
+        d = _Desc(lo, hi, int(n), float(kappa), xy.shape[0], xy.ctypes.data_as(ct.POINTER(ct.c_double)),
+                  float(tol), int(restart), int(max_iter))
+        h = _vp()
+        _check(_lib.kfbi_prob_create(ctx._h, ct.byref(d), ct.byref(h)))
+        self._h = h
+        self.n, self.kappa, self.lo, self.hi = int(n), float(kappa), lo, hi
+        m, q, ni, nb = ct.c_int(), ct.c_int(), ct.c_int(), ct.c_size_t()
+        _check(_lib.kfbi_prob_info(h, ct.byref(m), ct.byref(q), ct.byref(ni), ct.byref(nb)))
+        self.M, self.Q, self.I, self.device_bytes = m.value, q.value, ni.value, nb.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.kfbi_prob_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def grid_numel(self):
+        return (self.n + 1) ** 2
+
+    # ---- plan export (host)
+    def mask(self) -> np.ndarray:
+        out = np.zeros((self.n + 1, self.n + 1), dtype=np.uint8)
+        _check(_lib.kfbi_prob_mask(self._h, _vp(out.ctypes.data)))
+        return out.astype(bool)
+
+    def crossings(self):
+        axis = np.zeros(self.Q, dtype=np.int32)
+        nodes = np.zeros((self.Q, 4), dtype=np.int32)
+        t = np.zeros(self.Q)
+        xy = np.zeros((self.Q, 2))
+        _check(_lib.kfbi_prob_crossings(self._h, _vp(axis.ctypes.data), _vp(nodes.ctypes.data),
+                                        _vp(t.ctypes.data), _vp(xy.ctypes.data)))
+        return axis, nodes, t, xy
+
+    def irregular(self) -> np.ndarray:
+        ij = np.zeros((self.I, 2), dtype=np.int32)
+        _check(_lib.kfbi_prob_irregular(self._h, _vp(ij.ctypes.data)))
+        return ij
+
+    # ---- device work
+    def apply(self, phi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty_like(phi)
+        _check(_lib.kfbi_apply(self._h, _dptr(phi, "phi", self.M), _dptr(out, "out", self.M)))
+        return out
+
+    def correct(self, phi, f_gamma=None, out=None):
+        if out is None:
+            out = torch.empty(self.I, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        _check(_lib.kfbi_correct(self._h, _dptr(phi, "phi", self.M), _dptr(f_gamma, "f_gamma", self.M),
+                                 _dptr(out, "corr", self.I)))
+        return out
+
+    def fast_solve(self, rhs, out=None):
+        if out is None:
+            out = torch.empty_like(rhs)
+        _check(_lib.kfbi_fast_solve(self._h, _dptr(rhs, "rhs", self.grid_numel), _dptr(out, "v", self.grid_numel)))
+        return out
+
+    def interface_solve(self, phi, ftilde, f_gamma=None):
+        dev = f"cuda:{self.ctx.device}"
+        vg = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+        vz = torch.empty(self.M, dtype=torch.float64, device=dev)
+        _check(_lib.kfbi_interface_solve(self._h, _dptr(phi, "phi", self.M), _dptr(ftilde, "ftilde", self.grid_numel),
+                                         _dptr(f_gamma, "f_gamma", self.M), _dptr(vg, "vgrid"), _dptr(vz, "vz")))
+        return vg, vz
+
+    def interface_solve_jumps(self, jq, jz, ftilde):
+        dev = f"cuda:{self.ctx.device}"
+        vg = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+        vz = torch.empty(self.M, dtype=torch.float64, device=dev)
+        _check(_lib.kfbi_interface_solve_jumps(self._h, _dptr(jq, "jq", 6 * self.Q), _dptr(jz, "jz", 6 * self.M),
+                                               _dptr(ftilde, "ftilde", self.grid_numel), _dptr(vg, "vgrid"),
+                                               _dptr(vz, "vz")))
+        return vg, vz
+
+    def solve(self, f_grid, f_gamma, g, phi0=None):
+        """Dirichlet solve; returns ``(u_grid, u_gamma, phi, iters, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        u = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+        ug = torch.empty(self.M, dtype=torch.float64, device=dev)
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, rel = ct.c_int(), ct.c_double()
+        st = _check(_lib.kfbi_solve(self._h, _dptr(f_grid, "f_grid", self.grid_numel), _dptr(f_gamma, "f_gamma", self.M),
+                                    _dptr(g, "g", self.M), _dptr(u, "u_grid"), _dptr(ug, "u_gamma"), _dptr(phi, "phi"),
+                                    ct.byref(it), ct.byref(rel)), allow=(OK, NOT_CONVERGED))
+        return u, ug, phi, it.value, rel.value, st == OK
+
+    def gmres(self, rhs, phi0=None, tol=1e-10, max_iter=500):
+        """GMRES on ``K_D phi = rhs``; returns ``(phi, iters, applies, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, ap, rel = ct.c_int(), ct.c_int(), ct.c_double()
+        st = _check(_lib.kfbi_gmres(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M), float(tol),
+                                    int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
+                    allow=(OK, NOT_CONVERGED))
+        return phi, it.value, ap.value, rel.value, st == OK
+
+    # ---- timing of the three apply stages (HIP events on the context stream)
+    def set_timing(self, on: bool):
+        _check(_lib.kfbi_set_timing(self._h, 1 if on else 0))
+
+    def apply_timing(self):
+        a, b, c, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int()
+        _check(_lib.kfbi_apply_timing(self._h, ct.byref(a), ct.byref(b), ct.byref(c), ct.byref(n)))
+        return {"correct_us": a.value, "modes_us": b.value, "interp_us": c.value, "count": n.value}
