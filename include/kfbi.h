@@ -69,7 +69,7 @@ typedef struct {
     int m;                /* number of boundary samples, 3 <= m <= 65536 */
     const double* xy;     /* host, m x 2 (x0, y0, x1, y1, ...), counter-clockwise */
     double tol;           /* GMRES relative residual tolerance (Sec. 5 uses 1e-8); <= 0: 1e-10 */
-    int restart;          /* GMRES restart length; <= 0: 50 */
+    int restart;          /* GMRES restart length; <= 0: 50; capped at 64 */
     int max_iter;         /* cap on K_D applications inside GMRES; <= 0: 500 */
 } kfbi_desc;
 

@@ -9,7 +9,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/kfbi.h"
+#include "kfbi.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -53,16 +53,24 @@ struct kfbi_prob {
     size_t bytes = 0;
     // work buffers
     double* corr = nullptr;      // I
+    double* corr_il = nullptr;   // T x 64: corrections in the interleaved layout of the sparse sums
     double* partial = nullptr;   // G M
     double* R = nullptr;         // N N
     double* A = nullptr;         // N N
     double* tmpM = nullptr;      // M
+    double* s2a = nullptr;       // M: spline second derivatives (density)
+    double* s2b = nullptr;       // M: spline second derivatives (f on Gamma)
     GmresBufs gm{};
+    GmresState st_host{};        // host copy of the GMRES state (stable address for async copies)
     // timing: four events per recorded apply, read back by kfbi_apply_timing
     static constexpr int kMaxTimed = 4096;
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int t_count = 0;
+    // a captured batch of GMRES steps (apply + Arnoldi update), replayed per batch
+    static constexpr int kGraphSteps = 8;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
 };
 
 namespace {
@@ -97,6 +105,8 @@ void free_prob(kfbi_prob* p) {
     for (auto& e : p->ev)
         if (e) hipEventDestroy(e);
     p->ev.clear();
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
 }
 
 // Per-mode constants of the x-direction tridiagonal systems (Alg. 4), FP64.
@@ -130,19 +140,27 @@ kfbi_status check_ptr(const void* p, const char* name) {
 kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, bool mask, double* vgrid,
                                   bool mask_out, double* vz) {
     hipStream_t s = p->ctx->stream;
+    if (js.phi) {
+        HIP_TRY(launch_spline(p->dp, js.phi, p->s2a, nullptr, s));
+        js.phi_s2 = p->s2a;
+    }
+    if (js.fgam) {
+        HIP_TRY(launch_spline(p->dp, js.fgam, p->s2b, nullptr, s));
+        js.fgam_s2 = p->s2b;
+    }
     HIP_TRY(launch_fill_rhs(p->dp, f, mask, p->R, s));
-    HIP_TRY(launch_correct(p->dp, js, nullptr, p->R, nullptr, s));
+    HIP_TRY(launch_correct(p->dp, js, nullptr, nullptr, p->R, nullptr, s));
     HIP_TRY(launch_sine_gemm(p->dp, p->R, p->A, 1.0, s));
     HIP_TRY(launch_rows_solve(p->dp, p->A, s));
     HIP_TRY(launch_sine_gemm(p->dp, p->A, p->R, 2.0 / p->N, s));
-    if (vz) HIP_TRY(launch_interp(p->dp, js, nullptr, 0, p->R, vz, nullptr, s));
+    if (vz) HIP_TRY(launch_interp_grid(p->dp, js, p->R, vz, s));
     if (vgrid) HIP_TRY(launch_grid_out(p->dp, p->R, mask_out, vgrid, s));
     return KFBI_OK;
 }
 
-kfbi_status sparse_apply(kfbi_prob* p, const double* phi, double* out, const int* skip) {
+kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, double* out, const int* skip) {
     hipStream_t s = p->ctx->stream;
-    JumpSrc js{phi, nullptr, nullptr, nullptr};
+    JumpSrc js{phi, phi_s2, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t* ev = nullptr;
     if (p->timing && p->t_count < kfbi_prob::kMaxTimed) {
         if (p->ev.empty()) {
@@ -152,11 +170,11 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, double* out, const int
         ev = &p->ev[4 * p->t_count++];
     }
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_correct(p->dp, js, p->corr, nullptr, skip, s));
+    HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, skip, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_modes(p->dp, p->corr, p->partial, p->G, p->W, skip, s));
+    HIP_TRY(launch_modes(p->dp, p->corr_il, p->partial, p->G, p->W, skip, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_interp(p->dp, js, p->partial, p->G, nullptr, out, skip, s));
+    HIP_TRY(launch_reduce_interp(p->dp, js, p->partial, p->G, out, skip, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return KFBI_OK;
 }
@@ -164,34 +182,78 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, double* out, const int
 // Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps are
 // enqueued in batches; with tol > 0 the host polls the device state after each
 // batch, with tol <= 0 the work is fixed and the host waits once at the end.
+kfbi_status enqueue_steps(kfbi_prob* p, int nsteps) {
+    hipStream_t s = p->ctx->stream;
+    GmresBufs b = p->gm;
+    const int* skip = &b.st->converged;
+    for (int k = 0; k < nsteps; ++k) {
+        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip)) return e;
+        HIP_TRY(launch_gmres_step(p->dp, b, s));
+    }
+    return KFBI_OK;
+}
+
+// Capture kGraphSteps GMRES steps into a graph once per problem.  All launch
+// arguments are fixed device pointers and the steps read their parameters from
+// the device state, so one graph serves every call.  If capture is not possible
+// (e.g. the context stream is the null stream) the steps are launched directly.
+void ensure_graph(kfbi_prob* p) {
+    if (p->gexec || p->graph_failed) return;
+    hipStream_t s = p->ctx->stream;
+    if (s == nullptr || hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        hipGetLastError();
+        p->graph_failed = true;
+        return;
+    }
+    const bool timing = p->timing;
+    p->timing = false;
+    const kfbi_status e = enqueue_steps(p, kfbi_prob::kGraphSteps);
+    p->timing = timing;
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(s, &g);
+    if (e != KFBI_OK || ee != hipSuccess || !g || hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+        hipGetLastError();
+        p->gexec = nullptr;
+        p->graph_failed = true;
+    }
+    if (g) hipGraphDestroy(g);
+}
+
+// Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps go in
+// batches (a replayed graph unless per-launch timing is on); with tol > 0 the
+// host polls the device state after each batch, with tol <= 0 the work is fixed
+// and the host waits once at the end.
 kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_iter, GmresState* out) {
     hipStream_t s = p->ctx->stream;
     const int M = p->M;
     GmresBufs b = p->gm;
-    b.tol = tol;
-    b.max_iter = max_iter;
     HIP_TRY(hipMemcpyAsync(b.phi, phi_in, M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(b.xcur, phi_in, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    static const GmresState st0 = [] {
-        GmresState g{};
-        g.first = 1;
-        return g;
-    }();
+    GmresState& st0 = p->st_host;
+    st0 = GmresState{};
+    st0.first = 1;
+    st0.tol = tol;
+    st0.max_iter = max_iter;
     HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
-    const int* skip = &b.st->converged;
+    HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
     const int cycles = max_iter / std::max(1, p->restart) + 2;
     const int max_steps = max_iter + cycles;
-    const int batch = tol > 0 ? 8 : max_steps;
-    GmresState st{};
-    for (int done = 0; done < max_steps; done += batch) {
-        const int nb = std::min(batch, max_steps - done);
-        for (int k = 0; k < nb; ++k) {
-            if (kfbi_status e = sparse_apply(p, b.xcur, b.w, skip)) return e;
-            HIP_TRY(launch_gmres_step(p->dp, b, s));
+    const int B = kfbi_prob::kGraphSteps;
+    const bool use_graph = !p->timing;
+    if (use_graph) ensure_graph(p);
+    const int poll_every = tol > 0 ? 1 : (max_steps + B - 1) / B;   // in batches
+    GmresState& st = p->st_host;
+    for (int done = 0, nb = 0; done < max_steps; done += B) {
+        if (use_graph && p->gexec) {
+            HIP_TRY(hipGraphLaunch(p->gexec, s));
+        } else if (kfbi_status e = enqueue_steps(p, B)) {
+            return e;
         }
-        HIP_TRY(hipMemcpyAsync(&st, b.st, sizeof st, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (st.converged) break;
+        if (++nb % poll_every == 0 || done + B >= max_steps) {
+            HIP_TRY(hipMemcpyAsync(&st, b.st, sizeof st, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (st.converged) break;
+        }
     }
     *out = st;
     return KFBI_OK;
@@ -281,7 +343,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     const Plan& P = p->plan;
     p->kappa = d->kappa;
     p->tol = d->tol > 0 ? d->tol : 1e-10;
-    p->restart = d->restart > 0 ? std::min(d->restart, 120) : 50;
+    p->restart = d->restart > 0 ? std::min(d->restart, kMaxRestart) : 50;
     p->max_iter = d->max_iter > 0 ? d->max_iter : 500;
     p->N = n;
     p->n = n - 1;
@@ -293,9 +355,11 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         return set_err(KFBI_ERR_UNSUPPORTED, "more than 16384 samples");
     }
     // workgroup shape of the sparse fast solve: as many waves as the LDS allows
+    // as many waves per workgroup as the LDS allows while still giving every
+    // compute unit a workgroup
     p->W = 1;
-    for (int W : {4, 2, 1}) {
-        if (modes_lds_bytes(n, p->M, W) <= ctx->lds_max) {
+    for (int W : {8, 4, 2, 1}) {
+        if (modes_lds_bytes(n, p->M, W) <= ctx->lds_max && ((n - 1 + W - 1) / W >= ctx->num_cu || W == 1)) {
             p->W = W;
             break;
         }
@@ -333,11 +397,40 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     const int K = 30;
     dp.K = K;
     std::vector<int> colptr(P.col_ptr.begin(), P.col_ptr.end());
+    // balanced split of the irregular nodes over the 64 lanes of a wavefront,
+    // cut only at column starts so every column is summed by one lane
+    std::vector<int> laneptr(65, 0);
+    {
+        int i = 0;
+        for (int L = 1; L < 64; ++L) {
+            const long want = (long)p->I * L / 64;
+            while (i <= n && colptr[i] < want) ++i;
+            laneptr[L] = std::max(laneptr[L - 1], i <= n ? colptr[i] : p->I);
+        }
+        laneptr[64] = p->I;
+    }
+    // interleaved layout: the t-th node of lane L at slot t*64 + L
+    int T = 1;
+    for (int L = 0; L < 64; ++L) T = std::max(T, laneptr[L + 1] - laneptr[L]);
+    T = (T + kSlots - 1) / kSlots * kSlots;
+    dp.T = T;
+    std::vector<int> il_ij((size_t)T * 64, 0), il_pos(std::max(p->I, 1), 0);
+    for (int L = 0; L < 64; ++L)
+        for (int r = laneptr[L]; r < laneptr[L + 1]; ++r) {
+            const int slot = (r - laneptr[L]) * 64 + L;
+            const bool last = r + 1 == laneptr[L + 1] || P.irr_i[r + 1] != P.irr_i[r];
+            il_ij[slot] = (last ? (int)0x80000000u : 0) | (P.irr_i[r] << 16) | P.irr_j[r];
+            il_pos[r] = slot;
+        }
+    std::vector<int4> cpk(p->M);
+    for (int k = 0; k < p->M; ++k) cpk[k] = make_int4(P.cp_i0[k], P.cp_j0[k], sxy[k], 0);
     if ((st = upload(p, &dp.q_geo, P.q_geo)) || (st = upload(p, &dp.q_axis, P.q_axis)) ||
         (st = upload(p, &dp.z_geo, P.z_geo)) || (st = upload(p, &dp.zx, P.px)) || (st = upload(p, &dp.zy, P.py)) ||
         (st = upload(p, &dp.irr_i, P.irr_i)) || (st = upload(p, &dp.irr_j, P.irr_j)) ||
         (st = upload(p, &dp.irr_s, P.irr_s)) || (st = upload(p, &dp.arm_q, P.arm_q)) ||
         (st = upload(p, &dp.arm_d, P.arm_d)) || (st = upload(p, &dp.col_ptr, colptr)) ||
+        (st = upload(p, &dp.lane_ptr, laneptr)) || (st = upload(p, &dp.il_ij, il_ij)) ||
+        (st = upload(p, &dp.il_pos, il_pos)) || (st = upload(p, &dp.cp_pack, cpk)) ||
         (st = upload(p, &dp.cp_i0, P.cp_i0)) || (st = upload(p, &dp.cp_j0, P.cp_j0)) ||
         (st = upload(p, &dp.cp_sxy, sxy)) || (st = upload(p, &dp.cp_w, P.cp_w)) ||
         (st = upload(p, &dp.cp_out, P.cp_out)) || (st = upload(p, &dp.inside, P.inside)) ||
@@ -345,18 +438,19 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = upload(p, &dp.taps, spline_filter_taps(K))))
         return fail(st);
     const int M = p->M, m = p->restart;
-    if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->partial, (size_t)p->G * M)) ||
+    if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->corr_il, (size_t)dp.T * 64)) || (st = dev_alloc(p, &p->partial, (size_t)p->G * M)) ||
         (st = dev_alloc(p, &p->R, (size_t)n * n)) || (st = dev_alloc(p, &p->A, (size_t)n * n)) ||
-        (st = dev_alloc(p, &p->tmpM, M)) || (st = dev_alloc(p, &p->gm.V, (size_t)(m + 1) * M)) ||
+        (st = dev_alloc(p, &p->tmpM, M)) || (st = dev_alloc(p, &p->s2a, M)) || (st = dev_alloc(p, &p->s2b, M)) ||
+        (st = dev_alloc(p, &p->gm.s2cur, M)) || (st = dev_alloc(p, &p->gm.V, (size_t)(m + 1) * M)) ||
         (st = dev_alloc(p, &p->gm.H, (size_t)(m + 1) * m)) || (st = dev_alloc(p, &p->gm.cs, m)) ||
         (st = dev_alloc(p, &p->gm.sn, m)) || (st = dev_alloc(p, &p->gm.g, m + 1)) ||
         (st = dev_alloc(p, &p->gm.ghat, M)) || (st = dev_alloc(p, &p->gm.phi, M)) ||
         (st = dev_alloc(p, &p->gm.xcur, M)) || (st = dev_alloc(p, &p->gm.w, M)) ||
         (st = dev_alloc(p, &p->gm.st, 1)))
         return fail(st);
+    // pad slots of the interleaved corrections stay zero for the life of the problem
+    HIP_TRY(hipMemset(p->corr_il, 0, sizeof(double) * (size_t)dp.T * 64));
     p->gm.m = m;
-    p->gm.max_iter = p->max_iter;
-    p->gm.tol = p->tol;
     *out = p;
     return KFBI_OK;
 }
@@ -415,15 +509,25 @@ kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(phi, "phi")) return s;
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
-    return sparse_apply(p, phi, out, nullptr);
+    HIP_TRY(launch_spline(p->dp, phi, p->s2a, nullptr, p->ctx->stream));
+    return sparse_apply(p, phi, p->s2a, out, nullptr);
 }
 
 kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {
     if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
     if (kfbi_status s = check_ptr(corr, "corr")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
-    JumpSrc js{phi, f_gamma, nullptr, nullptr};
-    HIP_TRY(launch_correct(p->dp, js, corr, nullptr, nullptr, p->ctx->stream));
+    hipStream_t s = p->ctx->stream;
+    JumpSrc js{phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    if (phi) {
+        HIP_TRY(launch_spline(p->dp, phi, p->s2a, nullptr, s));
+        js.phi_s2 = p->s2a;
+    }
+    if (f_gamma) {
+        HIP_TRY(launch_spline(p->dp, f_gamma, p->s2b, nullptr, s));
+        js.fgam_s2 = p->s2b;
+    }
+    HIP_TRY(launch_correct(p->dp, js, corr, nullptr, nullptr, nullptr, s));
     return KFBI_OK;
 }
 
@@ -446,7 +550,7 @@ kfbi_status kfbi_interface_solve(kfbi_prob* p, const double* phi, const double* 
     if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
     if (!vgrid && !vz) return set_err(KFBI_ERR_ARG, "no output requested");
     HIP_TRY(hipSetDevice(p->ctx->device));
-    JumpSrc js{phi, f_gamma, nullptr, nullptr};
+    JumpSrc js{phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
     return dense_interface_solve(p, js, ftilde, false, vgrid, false, vz);
 }
 
@@ -456,7 +560,7 @@ kfbi_status kfbi_interface_solve_jumps(kfbi_prob* p, const double* jq, const dou
     if (kfbi_status s = check_ptr(jq, "jq")) return s;
     if (kfbi_status s = check_ptr(jz, "jz")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
-    JumpSrc js{nullptr, nullptr, jq, jz};
+    JumpSrc js{nullptr, nullptr, nullptr, nullptr, jq, jz};
     return dense_interface_solve(p, js, ftilde, false, vgrid, false, vz);
 }
 
@@ -470,7 +574,7 @@ kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma
     hipStream_t s = p->ctx->stream;
     const int M = p->M;
     // g^ = g - (Y f)^+ (Sec. 2.1)
-    JumpSrc jy{nullptr, f_gamma, nullptr, nullptr};
+    JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
     if (kfbi_status e = dense_interface_solve(p, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
     GmresBufs b = p->gm;
     HIP_TRY(launch_axpby(M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
@@ -478,7 +582,7 @@ kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma
     GmresState st{};
     if (kfbi_status e = run_gmres(p, phi, p->tol, p->max_iter, &st)) return e;
     // u = W phi + Y f
-    JumpSrc jf{b.phi, f_gamma, nullptr, nullptr};
+    JumpSrc jf{b.phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
     if (kfbi_status e = dense_interface_solve(p, jf, f_grid, true, u_grid, true, u_gamma)) return e;
     HIP_TRY(hipMemcpyAsync(phi, b.phi, M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));

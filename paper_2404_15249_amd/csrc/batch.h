@@ -1,0 +1,38 @@
+// Device descriptors of the batched KFBI steps (see batch.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace kfbi {
+
+constexpr int kBatchW = 4;          // waves (sine modes) per workgroup in the batched fast solve
+constexpr int kBatchNmax = 2048;    // largest grid a batch serves
+
+// One live problem of a batch, resident in device memory.
+struct SlotDev {
+    DevPlan p;
+    GmresBufs b;
+    double* corr_il;   // interleaved corrections (T x 64)
+    double* partial;   // M x Gs partial sums, one column per mode block
+    int Gs;            // mode blocks: ceil((n-1) / kBatchW)
+    int pad;
+};
+
+// Work lists of the batched launches, rebuilt on the host when a slot is
+// admitted or released.  counts = {correction items, mode items, sample items,
+// live slots}; items are (slot, first index) pairs.
+struct BatchWork {
+    const int* counts;
+    const int2* corr_items;   // blocks of 256 irregular nodes
+    const int2* mode_items;   // mode blocks of kBatchW modes
+    const int2* cp_items;     // blocks of 4 samples
+    const int* live;          // live slot ids
+    int max_live;
+};
+
+size_t modes_b_lds_bytes(int Nmax, int Mmax);
+hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s);
+
+}  // namespace kfbi

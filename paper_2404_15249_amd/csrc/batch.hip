@@ -1,0 +1,107 @@
+// Batched KFBI steps: many problems of uneven size advance through one launch
+// per stage of a GMRES iteration.  Every launch is persistent: a fixed grid
+// walks a device-resident work list of (slot, block) items, so the same
+// captured graph serves any mix of live slots, and a slot that has converged
+// turns its items into no-ops.  Each slot's arithmetic is split into the same
+// blocks whatever else is in the batch (one workgroup partial per mode block,
+// fixed reduction order), so its result does not depend on the mix.
+#include <hip/hip_runtime.h>
+
+#include "batch.h"
+#include "device.h"
+
+namespace kfbi {
+
+namespace {
+
+__device__ __forceinline__ bool slot_done(const SlotDev& S) { return S.b.st->converged != 0; }
+
+__global__ __launch_bounds__(256) void k_correct_b(const SlotDev* __restrict__ slots, BatchWork w) {
+    const int n_items = w.counts[0];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = w.corr_items[it];
+        const SlotDev& S = slots[item.x];
+        if (slot_done(S)) continue;
+        const int r = item.y + threadIdx.x;
+        if (r >= S.p.I) continue;
+        const JumpSrc js{S.b.xcur, S.b.s2cur, nullptr, nullptr, nullptr, nullptr};
+        S.corr_il[S.p.il_pos[r]] = correction_at(S.p, js, r);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(W * 64) void k_modes_b(const SlotDev* __restrict__ slots, BatchWork w, int Nmax,
+                                                    int Mmax) {
+    extern __shared__ double smem[];
+    const ModesLds L = modes_lds<W>(smem, Nmax, Mmax);
+    const int n_items = w.counts[1];
+    int curN = -1;
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = w.mode_items[it];
+        const SlotDev& S = slots[item.x];
+        if (slot_done(S)) continue;
+        const DevPlan& p = S.p;
+        if (p.N != curN) {
+            __syncthreads();
+            for (int k = threadIdx.x; k <= p.N / 2; k += W * 64) L.sq[k] = p.sinq[k];
+            curN = p.N;
+        }
+        double* part = S.partial;
+        const int Gs = S.Gs, row = item.y;
+        auto emit = [&](int cp, double s) { part[(size_t)cp * Gs + row] = s; };
+        const int base = row * W;
+        switch (p.N) {
+            case 64: modes_round<1, W>(p, S.corr_il, base, L, emit); break;
+            case 128: modes_round<2, W>(p, S.corr_il, base, L, emit); break;
+            case 256: modes_round<4, W>(p, S.corr_il, base, L, emit); break;
+            case 512: modes_round<8, W>(p, S.corr_il, base, L, emit); break;
+            case 1024: modes_round<16, W>(p, S.corr_il, base, L, emit); break;
+            default: modes_round<32, W>(p, S.corr_il, base, L, emit); break;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_b(const SlotDev* __restrict__ slots, BatchWork w) {
+    const int n_items = w.counts[2];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = w.cp_items[it];
+        const SlotDev& S = slots[item.x];
+        if (slot_done(S)) continue;
+        const int cp = item.y + (threadIdx.x >> 6);
+        if (cp >= S.p.M) continue;
+        const JumpSrc js{S.b.xcur, S.b.s2cur, nullptr, nullptr, nullptr, nullptr};
+        reduce_sample(S.p, js, S.partial, S.Gs, cp, S.b.w);
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_gmres_b(const SlotDev* __restrict__ slots, BatchWork w) {
+    const int n_live = w.counts[3];
+    for (int it = blockIdx.x; it < n_live; it += gridDim.x) {
+        const SlotDev& S = slots[w.live[it]];
+        gmres_step(S.p, S.b, S.p.M);
+    }
+}
+
+}  // namespace
+
+size_t modes_b_lds_bytes(int Nmax, int Mmax) {
+    return sizeof(double) * ((size_t)(Nmax / 2 + 2) + (size_t)kBatchW * (Nmax + 64) + (size_t)Mmax) +
+           (sizeof(double) + sizeof(int)) * 2 * kChunk;
+}
+
+hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s) {
+    k_correct_b<<<n_cu * 2, 256, 0, s>>>(slots, w);
+    if (hipError_t e = hipGetLastError()) return e;
+    const size_t lds = modes_b_lds_bytes(Nmax, Mmax);
+    if (hipError_t e = hipFuncSetAttribute((const void*)k_modes_b<kBatchW>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds))
+        return e;
+    k_modes_b<kBatchW><<<n_cu, kBatchW * 64, lds, s>>>(slots, w, Nmax, Mmax);
+    if (hipError_t e = hipGetLastError()) return e;
+    k_reduce_b<<<n_cu * 2, 256, 0, s>>>(slots, w);
+    if (hipError_t e = hipGetLastError()) return e;
+    k_gmres_b<<<w.max_live, 1024, 0, s>>>(slots, w);
+    return hipGetLastError();
+}
+
+}  // namespace kfbi

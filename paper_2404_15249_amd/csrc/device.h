@@ -1,0 +1,528 @@
+// Device functions shared by the single-problem and the batched kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace kfbi {
+
+// sin(pi m / N), 0 <= m < 2N, from the quarter-period table sq[0..N/2].
+__device__ __forceinline__ double sinpi_n(const double* __restrict__ sq, int m, int N) {
+    const double sgn = (m & N) ? -1.0 : 1.0;
+    m &= N - 1;
+    m = min(m, N - m);
+    return sgn * sq[m];
+}
+
+// Second derivative of the periodic spline through y at sample m: the inverse
+// of the (1, 4, 1) circulant decays like (2 - sqrt 3)^|k|, so a filter of
+// 2K+3 taps reproduces it to double precision.  Computed once per density by
+// k_spline; the kernels below read the result.
+__device__ inline double spline_s2(const double* __restrict__ y, int M, const double* __restrict__ taps, int m) {
+    constexpr int K = kSplineK;
+    double s = 0.0;
+    if (M > K + 1 && m >= K + 1 && m + K + 1 < M) {
+#pragma unroll
+        for (int q = -K - 1; q <= K + 1; ++q) s = fma(taps[q + K + 1], y[m + q], s);
+    } else {
+#pragma unroll
+        for (int q = -K - 1; q <= K + 1; ++q) {
+            int idx = (m + q) % M;
+            if (idx < 0) idx += M;
+            s = fma(taps[q + K + 1], y[idx], s);
+        }
+    }
+    return s;
+}
+
+// Value and first two parameter derivatives of the spline on segment seg at u.
+__device__ __forceinline__ void spline_at(const double* __restrict__ y, const double* __restrict__ s2,
+                                          const DevPlan& p, int seg, double u, double& v, double& d1, double& d2) {
+    const int k1 = seg + 1 == p.M ? 0 : seg + 1;
+    const double s0 = s2[seg], s1 = s2[k1];
+    const double y0 = y[seg], y1 = y[k1], w = 1.0 - u;
+    const double sixth = 1.0 / 6.0;
+    v = w * y0 + u * y1 + (w * w * w - w) * s0 * sixth + (u * u * u - u) * s1 * sixth;
+    d1 = (y1 - y0) - (3.0 * w * w - 1.0) * s0 * sixth + (3.0 * u * u - 1.0) * s1 * sixth;
+    d2 = w * s0 + u * s1;
+}
+
+struct J6 {
+    double v, gx, gy, hxx, hxy, hyy;
+};
+
+// Cartesian jumps of the interface problem at one point of Gamma.
+// [v] = Phi and [d_n v] = 0 (Sec. 2.2); differentiating along arc length gives
+// [v_tau] = Phi_s, [v_tautau] = Phi_ss, [v_taun] = -c Phi_s; the equation gives
+// [v_nn] = [F] + kappa Phi - [v_tautau].
+__device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSrc& js) {
+    double P = 0.0, P1 = 0.0, P2 = 0.0, F = 0.0, t1, t2;
+    if (js.phi) spline_at(js.phi, js.phi_s2, p, g.seg, g.u, P, P1, P2);
+    if (js.fgam) spline_at(js.fgam, js.fgam_s2, p, g.seg, g.u, F, t1, t2);
+    const double Ps = P1 * g.a1;
+    const double Pss = P2 * g.a2 - P1 * g.a3;
+    const double vtt = Pss, vtn = -g.curv * Ps, vnn = F + p.kappa * P - vtt;
+    J6 J;
+    J.v = P;
+    J.gx = Ps * g.tx;
+    J.gy = Ps * g.ty;
+    J.hxx = vtt * g.tx * g.tx + 2.0 * vtn * g.tx * g.nx + vnn * g.nx * g.nx;
+    J.hxy = vtt * g.tx * g.ty + vtn * (g.tx * g.ny + g.nx * g.ty) + vnn * g.nx * g.ny;
+    J.hyy = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
+    return J;
+}
+
+// ---------------------------------------------------------------- tridiagonal mode solve (Alg. 4)
+//
+// Solve x[i-1] - beta x[i] + x[i+1] = e[i], i = 1..N-1, x[0] = x[N] = 0, with
+// tridiag(1, -beta, 1) = -(1/r)(I - r S)(I - r S^T) - r e1 e1^T (S the down
+// shift): the forward recurrence w[i] = r (w[i-1] - e[i]), the backward one
+// y[i] = w[i] + r y[i+1], and x = y + y[1] zeta with
+// zeta[i] = -r (r^i - r^(2N-i)) / (1 - r^(2N)) from the rank-one term.
+// Lane L of the wavefront owns i = L C + 1 .. L C + C (i = N is a zero pad);
+// each recurrence runs locally per lane and the lanes are joined by a scan of
+// the carries with multiplier r^C.
+template <int C>
+__device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, int lane, int N) {
+    const double r = mc.r;
+    double w = 0.0;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        w = r * (w - e[c]);
+        e[c] = w;
+    }
+    double val = w, mul = mc.rC;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(val, off, 64);
+        if (lane >= off) val += mul * t;
+        mul *= mul;
+    }
+    double carry = __shfl_up(val, 1, 64);
+    if (lane == 0) carry = 0.0;
+    double pw = r;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        e[c] += pw * carry;
+        pw *= r;
+    }
+    if (lane == 63) e[C - 1] = 0.0;
+    double y = 0.0;
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        y = e[c] + r * y;
+        e[c] = y;
+    }
+    val = y;
+    mul = mc.rC;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_down(val, off, 64);
+        if (lane + off < 64) val += mul * t;
+        mul *= mul;
+    }
+    carry = __shfl_down(val, 1, 64);
+    if (lane == 63) carry = 0.0;
+    pw = r;
+#pragma unroll
+    for (int c = C - 1; c >= 0; --c) {
+        e[c] += pw * carry;
+        pw *= r;
+    }
+    const double y1 = __shfl(e[0], 0, 64);
+    const int is = lane * C + 1;
+    double p1 = exp((double)is * mc.logr);
+    double p2 = exp((double)(2 * N - is) * mc.logr);
+    const double coef = y1 * mc.smc;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        e[c] += coef * (p1 - p2);
+        p1 *= r;
+        p2 *= mc.rinv;
+    }
+    if (lane == 63) e[C - 1] = 0.0;
+}
+
+// Jump terms of the stencil nodes outside Omega: the far-side value is moved to
+// the Omega side with the Taylor expansion of the jumps at the sample.
+__device__ inline double outside_terms(const DevPlan& p, const JumpSrc& js, int cp, const int (&ni)[6], const int (&nj)[6],
+                                const double* __restrict__ w) {
+    const unsigned char* o6 = p.cp_out + 6 * (size_t)cp;
+    if (!(o6[0] | o6[1] | o6[2] | o6[3] | o6[4] | o6[5])) return 0.0;
+    J6 J;
+    if (js.jz) {
+        const double* q = js.jz + 6 * (size_t)cp;
+        J = {q[0], q[1], q[2], q[3], q[4], q[5]};
+    } else {
+        J = jumps_at(p, p.z_geo[cp], js);
+    }
+    const double zx = p.zx[cp], zy = p.zy[cp];
+    double s = 0.0;
+    for (int k = 0; k < 6; ++k) {
+        if (!o6[k]) continue;
+        const double dx = p.lo + ni[k] * p.h - zx, dy = p.lo + nj[k] * p.h - zy;
+        s += w[k] * (J.v + dx * J.gx + dy * J.gy + 0.5 * (dx * dx * J.hxx + 2.0 * dx * dy * J.hxy + dy * dy * J.hyy));
+    }
+    return s;
+}
+
+__device__ __forceinline__ void stencil_nodes(const DevPlan& p, int cp, int (&ni)[6], int (&nj)[6]) {
+    const int i0 = p.cp_i0[cp], j0 = p.cp_j0[cp], sxy = p.cp_sxy[cp];
+    const int sx = (sxy & 1) ? 1 : -1, sy = (sxy & 2) ? 1 : -1;
+    ni[0] = i0; nj[0] = j0;
+    ni[1] = i0 + 1; nj[1] = j0;
+    ni[2] = i0 - 1; nj[2] = j0;
+    ni[3] = i0; nj[3] = j0 + 1;
+    ni[4] = i0; nj[4] = j0 - 1;
+    ni[5] = i0 + sx; nj[5] = j0 + sy;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int k = 0; k < nw; ++k) s += red[k];
+    return s;
+}
+
+// ---------------------------------------------------------------- correction (Alg. 2)
+
+// Correction of the right-hand side at irregular node r: for each arm to a
+// neighbour across Gamma, the jump continued from the crossing along the arm by
+// its second-order Taylor expansion, times -s_r / h^2.
+__device__ inline double correction_at(const DevPlan& p, const JumpSrc& js, int r) {
+    const double s = p.irr_s[r];
+    double acc = 0.0;
+    for (int a = 0; a < 4; ++a) {
+        const int k = p.arm_q[4 * r + a];
+        if (k < 0) break;
+        const double d = p.arm_d[4 * r + a];
+        const int ax = p.q_axis[k];
+        double v, g, hh;
+        if (js.jq) {
+            const double* J = js.jq + 6 * (size_t)k;
+            v = J[0];
+            g = ax ? J[2] : J[1];
+            hh = ax ? J[5] : J[3];
+        } else {
+            const J6 J = jumps_at(p, p.q_geo[k], js);
+            v = J.v;
+            g = ax ? J.gy : J.gx;
+            hh = ax ? J.hyy : J.hxx;
+        }
+        acc -= s * (v + d * g + 0.5 * d * d * hh);
+    }
+    return acc * p.inv_h2;
+}
+
+// One wavefront per sample: the partials of the weighted sine sums added in a
+// fixed order, plus the outside-node jump terms.  Lane 0 writes out[cp].
+__device__ inline void reduce_sample(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial, int G,
+                                     int cp, double* __restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const double* row = partial + (size_t)cp * G;
+    double s = 0.0;
+#pragma unroll 8
+    for (int g = lane; g < G; g += 64) s += row[g];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) {
+        int ni[6], nj[6];
+        stencil_nodes(p, cp, ni, nj);
+        out[cp] = s * (2.0 / p.N) + outside_terms(p, js, cp, ni, nj, p.cp_w + 6 * (size_t)cp);
+    }
+}
+
+// One step of restarted GMRES, driven by a state machine in device memory so
+// that the host only polls for convergence.  Mode 0: b.w holds K_D phi; form
+// the true residual, stop or start a cycle.  Mode 1: b.w holds K_D V_j;
+// orthogonalise it (classical Gram-Schmidt applied twice), extend the
+// Hessenberg matrix, update the Givens rotations and the residual estimate;
+// at the end of a cycle solve the small triangular system and update phi.
+__device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M) {
+    __shared__ double red[16];
+    __shared__ double hs[kMaxRestart + 2];
+    __shared__ double ys[kMaxRestart + 2];
+    __shared__ int s_end;
+    GmresState* st = b.st;
+    if (st->converged) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m = b.m, mode = st->mode, j = st->j, it = st->it, first = st->first;
+    const double r0_in = st->r0, tol = st->tol;
+    const int max_iter = st->max_iter;
+    __syncthreads();
+    if (mode == 0) {
+        double part = 0.0;
+        for (int e = tid; e < M; e += 1024) {
+            const double r = b.ghat[e] - b.w[e];
+            b.V[e] = r;
+            part += r * r;
+        }
+        const double beta = sqrt(block_sum(part, red));
+        const double r0 = first ? beta : r0_in;
+        const double rel = r0 > 0.0 ? beta / r0 : 0.0;
+        const bool done = r0 == 0.0 || beta == 0.0 || rel < tol || it >= max_iter;
+        if (!done) {
+            const double ib = 1.0 / beta;
+            for (int e = tid; e < M; e += 1024) {
+                const double v = b.V[e] * ib;
+                b.V[e] = v;
+                b.xcur[e] = v;
+            }
+            __syncthreads();
+            for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(b.xcur, M, p.taps, e);
+        }
+        if (tid == 0) {
+            st->r0 = r0;
+            st->first = 0;
+            st->relres = rel;
+            if (done) {
+                st->converged = (r0 == 0.0 || beta == 0.0 || rel < tol) ? 1 : -1;
+                st->mode = 2;
+            } else {
+                b.g[0] = beta;
+                for (int k = 1; k <= m; ++k) b.g[k] = 0.0;
+                st->j = 0;
+                st->mode = 1;
+                st->cycles += 1;
+            }
+        }
+        return;
+    }
+    // mode 1: Arnoldi column j.  The column, the previous rotations and (at the
+    // end of a cycle) the Hessenberg matrix are staged in LDS so the serial
+    // Givens and back-substitution loops never wait on global memory.
+    __shared__ double col[kMaxRestart + 2];
+    __shared__ double cs_s[kMaxRestart], sn_s[kMaxRestart];
+    __shared__ double Hs[kMaxRestart * (kMaxRestart + 1)];
+    __shared__ double s_cs, s_sn;
+    double* Hj = b.H + (size_t)j * (m + 1);
+    if (tid < j) {
+        cs_s[tid] = b.cs[tid];
+        sn_s[tid] = b.sn[tid];
+    }
+    if (tid <= j) col[tid] = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = wave; i <= j; i += 16) {
+            const double* Vi = b.V + (size_t)i * M;
+            double d = 0.0;
+#pragma unroll 4
+            for (int e = lane; e < M; e += 64) d += Vi[e] * b.w[e];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
+            if (lane == 0) hs[i] = d;
+        }
+        __syncthreads();
+        for (int e = tid; e < M; e += 1024) {
+            double a = b.w[e];
+            for (int i0 = 0; i0 <= j; i0 += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
+            }
+            b.w[e] = a;
+        }
+        if (tid <= j) col[tid] += hs[tid];
+        __syncthreads();
+    }
+    double part = 0.0;
+    for (int e = tid; e < M; e += 1024) part += b.w[e] * b.w[e];
+    const double hn = sqrt(block_sum(part, red));
+    const double ihn = hn > 0.0 ? 1.0 / hn : 0.0;
+    double* Vn = b.V + (size_t)(j + 1) * M;
+    for (int e = tid; e < M; e += 1024) Vn[e] = b.w[e] * ihn;
+    if (tid == 0) {
+        // previous rotations, carried in registers down the column
+        double a = col[0];
+        for (int i = 0; i < j; ++i) {
+            const double c = col[i + 1], cc = cs_s[i], ss = sn_s[i];
+            col[i] = cc * a + ss * c;
+            a = -ss * a + cc * c;
+        }
+        const double den = hypot(a, hn);
+        const double cs = den > 0.0 ? a / den : 1.0;
+        const double sn = den > 0.0 ? hn / den : 0.0;
+        col[j] = den;
+        col[j + 1] = 0.0;
+        s_cs = cs;
+        s_sn = sn;
+        const double gj = b.g[j];
+        b.g[j + 1] = -sn * gj;
+        b.g[j] = cs * gj;
+        const int jn = j + 1, itn = it + 1;
+        const double est = fabs(sn * gj) / r0_in;
+        st->relres = est;
+        st->it = itn;
+        const bool end = est < tol || jn == m || itn >= max_iter || hn == 0.0;
+        s_end = end ? 1 : 0;
+        if (end) st->mode = 0; else st->j = jn;
+    }
+    __syncthreads();
+    if (tid <= j + 1) Hj[tid] = col[tid];
+    if (tid == 0) {
+        b.cs[j] = s_cs;
+        b.sn[j] = s_sn;
+    }
+    if (s_end) {
+        // back substitution H[0:jn, 0:jn] y = g[0:jn] from LDS
+        const int jn = j + 1;
+        for (int t = tid; t < jn * (m + 1); t += 1024) {
+            const int kc = t / (m + 1), i = t % (m + 1);
+            Hs[t] = kc == j ? col[i] : b.H[t];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = jn - 1; i >= 0; --i) {
+                double a = b.g[i];
+                for (int kk = i + 1; kk < jn; ++kk) a -= Hs[kk * (m + 1) + i] * ys[kk];
+                ys[i] = a / Hs[i * (m + 1) + i];
+            }
+        }
+    }
+    __syncthreads();
+    if (s_end) {
+        const int jn = j + 1;
+        for (int e = tid; e < M; e += 1024) {
+            double a = b.phi[e];
+            for (int i0 = 0; i0 < jn; i0 += 8) {
+                double v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a += (i0 + u < jn ? ys[i0 + u] : 0.0) * v[u];
+            }
+            b.phi[e] = a;
+            b.xcur[e] = a;
+        }
+    } else {
+        for (int e = tid; e < M; e += 1024) b.xcur[e] = Vn[e];
+    }
+    __syncthreads();
+    for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(b.xcur, M, p.taps, e);
+}
+
+// ---------------------------------------------------------------- sparse fast solve, one round of W modes
+//
+// LDS of the sparse fast solve: the quarter sine table, W padded per-wave mode
+// solutions (node i at i + (i - 1) / C, so the lanes' chunk-strided accesses
+// fall in different banks), M accumulators and a double-buffered chunk of the
+// interleaved table.  The region sizes follow the largest N and M served.
+struct ModesLds {
+    double* sq;
+    double* xs;
+    double* acc;
+    double* bcv;
+    int* bij;
+};
+
+template <int W>
+__device__ __forceinline__ ModesLds modes_lds(double* smem, int Nmax, int Mmax) {
+    ModesLds L;
+    L.sq = smem;                                        // Nmax/2 + 2
+    L.xs = L.sq + (Nmax / 2 + 2);                       // W (Nmax + 64)
+    L.acc = L.xs + W * (Nmax + 64);                     // Mmax
+    L.bcv = L.acc + Mmax;                               // 2 kChunk
+    L.bij = reinterpret_cast<int*>(L.bcv + 2 * kChunk); // 2 kChunk
+    return L;
+}
+
+// Sine modes l = base + wave + 1 (<= n), one per wave: the sparse sine sums of
+// the corrected right-hand side along y (lane L owns whole columns; its
+// irregular nodes sit at slots t*64 + L of the interleaved table, staged
+// through LDS in double-buffered chunks so all waves share one read), the
+// tridiagonal solve along x, and the weighted six-point gather at every
+// sample.  Calls emit(cp, s) for the samples cp = tid, tid + 64 W, ... with the
+// sum over the round's modes.  Must be called by the whole workgroup; L.sq must
+// hold the sine table of p.N.
+template <int C, int W, class Emit>
+__device__ __forceinline__ void modes_round(const DevPlan& p, const double* __restrict__ corr, int base,
+                                            const ModesLds& L, Emit emit) {
+    constexpr int XS = 64 * (C + 1);
+    const int N = p.N, n = p.n, M = p.M, mask2 = 2 * N - 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double* sq = L.sq;
+    double* x = L.xs + wave * XS;
+    double* bcv = L.bcv;
+    int* bij = L.bij;
+    const int nch = p.T / kSlots;                       // T is a multiple of kSlots
+    const int l = base + wave + 1;
+    const bool active = l <= n;
+#pragma unroll
+    for (int c = 0; c < C; ++c) x[lane * (C + 1) + 1 + c] = 0.0;
+    if (lane == 0) x[0] = 0.0;
+    for (int e = tid; e < kChunk; e += W * 64) {
+        bcv[e] = corr[e];
+        bij[e] = p.il_ij[e];
+    }
+    __syncthreads();
+    double run = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int cur = ch & 1;
+        if (ch + 1 < nch) {
+            const int nxt = (ch + 1) * kChunk;
+            for (int e = tid; e < kChunk; e += W * 64) {
+                bcv[(1 - cur) * kChunk + e] = corr[nxt + e];
+                bij[(1 - cur) * kChunk + e] = p.il_ij[nxt + e];
+            }
+        }
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s) {
+                const int pk = bij[cur * kChunk + s * 64 + lane];
+                const double cv = bcv[cur * kChunk + s * 64 + lane];
+                const int j = pk & 0xfff;
+                run += cv * sinpi_n(sq, (j * l) & mask2, N);
+                if (pk < 0) {                           // last node of its column
+                    const int i = (pk >> 16) & 0xfff;
+                    x[i + (i - 1) / C] = run;
+                    run = 0.0;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (active) {
+        double e[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) e[c] = x[lane * (C + 1) + 1 + c] * p.h2;
+        mode_solve<C>(e, p.modes[l], lane, N);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (lane < 63 || c < C - 1) x[lane * (C + 1) + 1 + c] = e[c];
+    }
+    __syncthreads();
+    for (int cp = tid; cp < M; cp += W * 64) {
+        const int4 pk = p.cp_pack[cp];
+        const int i0 = pk.x, j0 = pk.y, sxy = pk.z;
+        const int sx = (sxy & 1) ? 1 : -1;
+        const bool syp = (sxy & 2) != 0;
+        const double2* w2 = reinterpret_cast<const double2*>(p.cp_w + 6 * (size_t)cp);
+        const double2 wa = w2[0], wb = w2[1], wc = w2[2];
+        const double w0 = wa.x, wE = wa.y, wW = wb.x, wN = wb.y, wS = wc.x, wD = wc.y;
+        double s = 0.0;
+        for (int q = 0; q < W; ++q) {
+            const int lq = base + q + 1;
+            if (lq > n) break;
+            const double* xq = L.xs + q * XS;
+            const double s0 = sinpi_n(sq, (j0 * lq) & mask2, N);
+            const double sp = sinpi_n(sq, ((j0 + 1) * lq) & mask2, N);
+            const double sm = sinpi_n(sq, ((j0 - 1) * lq) & mask2, N);
+            const double xc = xq[i0 + (i0 - 1) / C];
+            const double xe = xq[i0 + i0 / C + 1];
+            const double xw = xq[i0 - 1 + (i0 - 2) / C];
+            const double xd = sx > 0 ? xe : xw;
+            s += s0 * (w0 * xc + wE * xe + wW * xw) + sp * wN * xc + sm * wS * xc + (syp ? sp : sm) * wD * xd;
+        }
+        emit(cp, s);
+    }
+    __syncthreads();
+}
+
+}  // namespace kfbi

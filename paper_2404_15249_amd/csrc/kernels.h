@@ -35,6 +35,13 @@ struct DevPlan {
     const int* arm_q;         // 4 I
     const double* arm_d;      // 4 I
     const int* col_ptr;       // N + 1 entries used (i = 0..N)
+    const int* lane_ptr;      // 65: irregular nodes [lane_ptr[L], lane_ptr[L+1]) feed lane L of the
+                              // sparse sine sums; the cuts fall on column starts
+    const int* il_ij;         // T x 64, slot t*64 + L: the t-th node of lane L packed as
+                              // (last-of-column << 31) | (i << 16) | j  (0: pad)
+    const int* il_pos;        // I: slot of irregular node r in the interleaved layout
+    int T;                    // slots per lane, a multiple of kSlots
+    const int4* cp_pack;      // M: (i0, j0, sxy, 0)
     const int* cp_i0;         // M
     const int* cp_j0;         // M
     const int* cp_sxy;        // M: bit 0 sx>0, bit 1 sy>0
@@ -44,14 +51,21 @@ struct DevPlan {
     const double* sinq;       // N/2 + 1: sin(pi k / N)
     const ModeConst* modes;   // N (index l = 1..N-1 used)
     const double* taps;       // 2 K + 3 spline filter taps
-    int K;
+    int K;                    // must equal kSplineK
 };
+
+constexpr int kSplineK = 30;
+constexpr int kSlots = 4;          // table slots per LDS chunk of the sparse sine sums
+constexpr int kChunk = kSlots * 64;
+constexpr int kMaxRestart = 64;   // GMRES restart length cap (LDS-resident Hessenberg)
 
 // Source of the interface jumps: either computed from densities on the
 // spline (phi, fgam may be null) or given directly (jq / jz, 6 per point).
 struct JumpSrc {
     const double* phi;
+    const double* phi_s2;    // spline second derivatives of phi (required with phi)
     const double* fgam;
+    const double* fgam_s2;   // spline second derivatives of fgam (required with fgam)
     const double* jq;
     const double* jz;
 };
@@ -65,6 +79,9 @@ struct GmresState {
     int cycles;
     double r0;
     double relres;
+    double tol;      // stop when the relative residual drops below tol (<= 0: never)
+    int max_iter;    // cap on Arnoldi steps
+    int pad;
 };
 
 struct GmresBufs {
@@ -76,20 +93,21 @@ struct GmresBufs {
     double* ghat;    // M
     double* phi;     // M
     double* xcur;    // M: input of the next K_D apply
+    double* s2cur;   // M: spline second derivatives of xcur
     double* w;       // M: output of the last K_D apply
-    GmresState* st;
+    GmresState* st;  // state machine; also holds tol and max_iter so launches are call independent
     int m;
-    int max_iter;
-    double tol;
 };
 
 // launchers (return hipError_t of the launch)
-hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* dense, const int* skip,
-                          hipStream_t s);
+hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* corr_il, double* dense,
+                          const int* skip, hipStream_t s);
 hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int G, int W,
                         const int* skip, hipStream_t s);
-hipError_t launch_interp(const DevPlan& p, JumpSrc js, const double* partial, int G, const double* grid,
-                         double* out, const int* skip, hipStream_t s);
+hipError_t launch_spline(const DevPlan& p, const double* y, double* s2, const int* skip, hipStream_t s);
+hipError_t launch_reduce_interp(const DevPlan& p, JumpSrc js, const double* partial, int G, double* out,
+                                const int* skip, hipStream_t s);
+hipError_t launch_interp_grid(const DevPlan& p, JumpSrc js, const double* R, double* out, hipStream_t s);
 hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double* R, hipStream_t s);
 hipError_t launch_sine_gemm(const DevPlan& p, const double* B, double* Cm, double alpha, hipStream_t s);
 hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s);

@@ -97,22 +97,36 @@ def _dptr(t, name, numel=None):
 
 
 class Context:
-    """A device and the HIP stream the library enqueues on (torch's current stream)."""
+    """A device and the HIP stream the library enqueues on.
+
+    By default the context owns a dedicated torch stream (default priority).
+    Every call orders itself after the caller's current stream and makes the
+    current stream wait for the library's work, so tensors flow between torch
+    and the library without explicit synchronisation.
+    """
 
     def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
         self.device = device
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = _vp()
         _check(_lib.kfbi_ctx_create(device, _vp(self.stream.cuda_stream), ct.byref(h)))
         self._h = h
+
+    def __enter__(self):
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        return self
+
+    def __exit__(self, *exc):
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return False
 
     def sync(self):
         _check(_lib.kfbi_ctx_sync(self._h))
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.kfbi_ctx_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -137,9 +151,9 @@ class Problem:
         self.M, self.Q, self.I, self.device_bytes = m.value, q.value, ni.value, nb.value
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.kfbi_prob_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -172,37 +186,43 @@ class Problem:
     def apply(self, phi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty_like(phi)
-        _check(_lib.kfbi_apply(self._h, _dptr(phi, "phi", self.M), _dptr(out, "out", self.M)))
+        with self.ctx:
+            _check(_lib.kfbi_apply(self._h, _dptr(phi, "phi", self.M), _dptr(out, "out", self.M)))
         return out
 
     def correct(self, phi, f_gamma=None, out=None):
         if out is None:
             out = torch.empty(self.I, dtype=torch.float64, device=f"cuda:{self.ctx.device}")
-        _check(_lib.kfbi_correct(self._h, _dptr(phi, "phi", self.M), _dptr(f_gamma, "f_gamma", self.M),
-                                 _dptr(out, "corr", self.I)))
+        with self.ctx:
+            _check(_lib.kfbi_correct(self._h, _dptr(phi, "phi", self.M), _dptr(f_gamma, "f_gamma", self.M),
+                                     _dptr(out, "corr", self.I)))
         return out
 
     def fast_solve(self, rhs, out=None):
         if out is None:
             out = torch.empty_like(rhs)
-        _check(_lib.kfbi_fast_solve(self._h, _dptr(rhs, "rhs", self.grid_numel), _dptr(out, "v", self.grid_numel)))
+        with self.ctx:
+            _check(_lib.kfbi_fast_solve(self._h, _dptr(rhs, "rhs", self.grid_numel), _dptr(out, "v", self.grid_numel)))
         return out
 
     def interface_solve(self, phi, ftilde, f_gamma=None):
         dev = f"cuda:{self.ctx.device}"
         vg = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
         vz = torch.empty(self.M, dtype=torch.float64, device=dev)
-        _check(_lib.kfbi_interface_solve(self._h, _dptr(phi, "phi", self.M), _dptr(ftilde, "ftilde", self.grid_numel),
-                                         _dptr(f_gamma, "f_gamma", self.M), _dptr(vg, "vgrid"), _dptr(vz, "vz")))
+        with self.ctx:
+            _check(_lib.kfbi_interface_solve(self._h, _dptr(phi, "phi", self.M),
+                                             _dptr(ftilde, "ftilde", self.grid_numel),
+                                             _dptr(f_gamma, "f_gamma", self.M), _dptr(vg, "vgrid"), _dptr(vz, "vz")))
         return vg, vz
 
     def interface_solve_jumps(self, jq, jz, ftilde):
         dev = f"cuda:{self.ctx.device}"
         vg = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
         vz = torch.empty(self.M, dtype=torch.float64, device=dev)
-        _check(_lib.kfbi_interface_solve_jumps(self._h, _dptr(jq, "jq", 6 * self.Q), _dptr(jz, "jz", 6 * self.M),
-                                               _dptr(ftilde, "ftilde", self.grid_numel), _dptr(vg, "vgrid"),
-                                               _dptr(vz, "vz")))
+        with self.ctx:
+            _check(_lib.kfbi_interface_solve_jumps(self._h, _dptr(jq, "jq", 6 * self.Q), _dptr(jz, "jz", 6 * self.M),
+                                                   _dptr(ftilde, "ftilde", self.grid_numel), _dptr(vg, "vgrid"),
+                                                   _dptr(vz, "vz")))
         return vg, vz
 
     def solve(self, f_grid, f_gamma, g, phi0=None):
@@ -212,9 +232,11 @@ class Problem:
         ug = torch.empty(self.M, dtype=torch.float64, device=dev)
         phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
         it, rel = ct.c_int(), ct.c_double()
-        st = _check(_lib.kfbi_solve(self._h, _dptr(f_grid, "f_grid", self.grid_numel), _dptr(f_gamma, "f_gamma", self.M),
-                                    _dptr(g, "g", self.M), _dptr(u, "u_grid"), _dptr(ug, "u_gamma"), _dptr(phi, "phi"),
-                                    ct.byref(it), ct.byref(rel)), allow=(OK, NOT_CONVERGED))
+        with self.ctx:
+            st = _check(_lib.kfbi_solve(self._h, _dptr(f_grid, "f_grid", self.grid_numel),
+                                        _dptr(f_gamma, "f_gamma", self.M), _dptr(g, "g", self.M), _dptr(u, "u_grid"),
+                                        _dptr(ug, "u_gamma"), _dptr(phi, "phi"), ct.byref(it), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
         return u, ug, phi, it.value, rel.value, st == OK
 
     def gmres(self, rhs, phi0=None, tol=1e-10, max_iter=500):
@@ -222,9 +244,10 @@ class Problem:
         dev = f"cuda:{self.ctx.device}"
         phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
         it, ap, rel = ct.c_int(), ct.c_int(), ct.c_double()
-        st = _check(_lib.kfbi_gmres(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M), float(tol),
-                                    int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
-                    allow=(OK, NOT_CONVERGED))
+        with self.ctx:
+            st = _check(_lib.kfbi_gmres(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M), float(tol),
+                                        int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
         return phi, it.value, ap.value, rel.value, st == OK
 
     # ---- timing of the three apply stages (HIP events on the context stream)
