@@ -9,10 +9,21 @@ One step is one GMRES iteration on the boundary density (Alg. 5): a K_D apply
 device-side Gram-Schmidt / Givens update.  The steps run back to back on the
 device with no convergence stop, so the timed work is fixed.
 
-Prints one JSON line.  The dominant kernel's duration comes from HIP events
-recorded around every launch on the library's stream inside the timed region.
+The timed region replays the captured GMRES steps (the production path).  A
+second region of the same length launches the same steps one by one with HIP
+events recorded around every launch on the library's stream: the dominant
+kernel's average duration (roofline) and the per-stage times come from there.
+
+Also reported, outside the timed region:
+  solve     one full Dirichlet solve of the workload (FP64), error vs exact;
+  mixed     the circle r = 0.8, M = 2N, kappa = 1 problem at the same grid:
+            full solves with FP64 and with FP32-refined grid solves, their
+            times and the L-infinity difference between the two;
+  serving   a seeded stream of mixed-size requests through the continuous
+            batching scheduler: solves/s at saturation and p50/p99 latency at
+            50 % and 90 % of that rate (``--mode serving`` runs a longer stream).
 The CPU baseline is the FP64 oracle timed on a bounded sample of the same
-workload (rank 0, one GPU only).
+workload (rank 0, one GPU only).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -74,6 +85,96 @@ def cpu_baseline(p, seconds: float):
                       f"{p.n}^2 star problem, {dt:.1f} s on {cpu_model()}"}
 
 
+def mixed_precision(ctx, n: int) -> dict:
+    """Full solves of the circle problem (r = 0.8, M = 2N, kappa = 1, u = e^x sin y)
+    with FP64 and with FP32-refined grid solves."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    p = synth.circle_problem(n=n, m=2 * n, kappa=1.0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    f, fg, g = dev(p.f_grid), dev(p.f_gamma), dev(p.g)
+    c = p.lo + np.arange(p.n + 1) * p.h
+    X, Y = np.meshgrid(c, c, indexing="xy")
+    exact = p.exact.u(X, Y)
+    res = {"workload": f"circle r=0.8, {n}x{n} grid, M={2 * n}, kappa=1, u=e^x sin y, GMRES tol 1e-12"}
+    base = None
+    for prec in ("fp64", "fp32"):
+        prob = kfbi.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-12, precision=prec, refine_steps=1)
+        prob.solve(f, fg, g)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = 3
+        for _ in range(reps):
+            u, ug, phi, it, rel, conv = prob.solve(f, fg, g)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t) / reps
+        # the grid solve alone (volume potential form), averaged
+        zero = torch.zeros(prob.M, dtype=torch.float64, device="cuda:0")
+        prob.interface_solve(zero, f, fg)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10):
+            prob.interface_solve(zero, f, fg)
+        torch.cuda.synchronize()
+        gs_ms = 1e3 * (time.perf_counter() - t) / 10
+        uh = u.cpu().numpy()
+        mask = prob.mask()
+        entry = {"solve_ms": ms, "interface_solve_ms": gs_ms, "gmres_iters": it, "converged": conv,
+                 "linf_err_vs_exact": float(np.max(np.abs(uh - exact)[mask]))}
+        if base is None:
+            base = uh
+        else:
+            entry["linf_diff_vs_fp64_path"] = float(np.max(np.abs(uh - base)[mask]))
+            entry["refine_steps"] = 1
+        res[prec] = entry
+        prob.close()
+    return res
+
+
+def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0):
+    import synth
+    from paper_2404_15249_amd.serving import GpuExecutor, Scheduler, summarize
+    ex = GpuExecutor(ctx, max_slots=max_slots, m_max=8192, budget_bytes=0,
+                     make_spec=lambda r: synth.serving_spec(r.seed, r.n), tol=1e-10)
+    sch = Scheduler(ex, int(budget_gib * (1 << 30)), max_slots, steps_per_poll=8, prepare_workers=8,
+                    prepare_ahead=16)
+    recs, span = sch.run(reqs, time_scale=time_scale)
+    out = summarize(recs, span)
+    out["peak_live"] = sch.peak_live
+    out["peak_reserved_gib"] = sch.peak_reserved / (1 << 30)
+    ex.batch.close()
+    return out
+
+
+def serving(ctx, n_requests: int, seed: int) -> dict:
+    """Saturation throughput, then Poisson arrivals at 50 % and 90 % of it."""
+    import synth
+    from paper_2404_15249_amd.serving import Request
+    stream = synth.serving_stream(n_requests, seed=seed, qps=1.0)
+    sat = run_stream(ctx, [Request(i, 0.0, n, s) for i, (_, n, s) in enumerate(stream)])
+    rate = sat["solves_per_s"]
+    res = {"requests": n_requests, "seed": seed, "sizes": "256/512/1024/2048 with p=.4/.3/.2/.1",
+           "tol": 1e-10, "saturation": sat}
+    for frac in (0.5, 0.9):
+        qps = frac * rate
+        # the stream's arrival times are drawn at 1 request/s: stretch them to the target rate
+        reqs = [Request(i, t, n, s) for i, (t, n, s) in enumerate(stream)]
+        res[f"at_{int(frac * 100)}pct"] = dict(run_stream(ctx, reqs, time_scale=1.0 / qps), qps=qps)
+    return res
+
+
+def serving_line(ctx, args) -> dict:
+    s = serving(ctx, args.serving_requests, args.serving_seed)
+    return {"metric": "solves/s (p99 latency beside)", "value": s["saturation"]["solves_per_s"],
+            "unit": "solves/s", "n_gpus": 1, "steps": args.serving_requests, "warmup": 0,
+            "ms_per_step": 1e3 / max(s["saturation"]["solves_per_s"], 1e-9), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"{args.serving_requests} seeded Dirichlet solve requests, random stars "
+                                   "r=0.6+a sin(k t), grids 256..2048, kappa~U(0,10), GMRES tol 1e-10"},
+            "serving": s}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +183,11 @@ def main():
     ap.add_argument("--n", type=int, default=2048, help="grid intervals per axis")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--mixed", choices=["on", "off"], default="on")
+    ap.add_argument("--serving-requests", type=int, default=300)
+    ap.add_argument("--serving-seed", type=int, default=2404)
+    ap.add_argument("--mode", choices=["apply", "serving"], default="apply",
+                    help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the KFBI path here has no multi-GPU mode "
@@ -96,25 +202,36 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    p = synth.star_problem(n=args.n, kappa=1.0)
     ctx = kfbi.Context(0)
+    if args.mode == "serving":
+        print(json.dumps(serving_line(ctx, args)), flush=True)
+        return
+    p = synth.star_problem(n=args.n, kappa=1.0)
     prob = kfbi.Problem(ctx, p.xy, p.n, p.kappa, restart=50)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
     rhs = dev(p.g)
 
-    # warm-up (untimed)
+    # warm-up (untimed): also captures the step graph
     prob.gmres(rhs, tol=0.0, max_iter=max(args.warmup, 1))
     torch.cuda.synchronize()
 
-    prob.set_timing(True)
+    # timed region: graphed steps
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     _, iters, applies, _, _ = prob.gmres(rhs, tol=0.0, max_iter=args.steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    assert iters == args.steps
+
+    # instrumented region: the same steps launched one by one with HIP events per stage
+    prob.set_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prob.gmres(rhs, tol=0.0, max_iter=args.steps)
+    torch.cuda.synchronize()
+    dt_ev = time.perf_counter() - t1
     tim = prob.apply_timing()
     prob.set_timing(False)
-    assert iters == args.steps
 
     unknowns = (p.n - 1) ** 2
     value = unknowns * args.steps / dt
@@ -133,6 +250,7 @@ def main():
     X, Y = np.meshgrid(c, c, indexing="xy")
     mask = prob_s.mask()
     err = np.max(np.abs(u.cpu().numpy() - p.exact.u(X, Y))[mask])
+    prob_s.close()
 
     out = {
         "metric": "grid unknowns/s per KFBI apply",
@@ -166,11 +284,16 @@ def main():
             "avg_us": tim["modes_us"],
         },
         "stages_us": {"correct": tim["correct_us"], "modes": tim["modes_us"], "interp": tim["interp_us"],
-                      "gmres_step_and_gaps": 1e6 * dt / args.steps - tim["correct_us"] - tim["modes_us"]
-                      - tim["interp_us"], "timed_applies": tim["count"], "all_applies": applies},
+                      "gmres_step_and_gaps": 1e6 * dt_ev / args.steps - tim["correct_us"] - tim["modes_us"]
+                      - tim["interp_us"], "timed_applies": tim["count"], "all_applies": applies,
+                      "us_per_step_ungraphed": 1e6 * dt_ev / args.steps},
         "solve": {"ms": solve_ms, "gmres_iters": it, "relres": rel, "converged": conv,
                   "linf_err_vs_exact": float(err)},
     }
+    if args.mixed == "on":
+        out["mixed"] = mixed_precision(ctx, args.n)
+    if args.serving_requests > 0:
+        out["serving"] = serving(ctx, args.serving_requests, args.serving_seed)
     if args.cpu_baseline == "on":
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -31,8 +31,11 @@
  *   work enqueued by the call has finished on the context stream.  Calls enqueue
  *   on the context stream and return without synchronising unless stated.
  *   The library owns only its handles and the device workspace it allocates in
- *   kfbi_prob_create.  A problem handle must not be used by two host threads at
- *   the same time.
+ *   kfbi_prob_create.  A problem or batch handle must not be used by two host
+ *   threads at the same time; different handles on one context may be used
+ *   from different threads (e.g. problems created by a preparation thread while
+ *   another thread steps a batch): the library captures its graphs on a private
+ *   stream, so such calls never enter a capture.
  *
  * Errors: every call returns a kfbi_status; on error no output is written (for
  * enqueueing calls: nothing is enqueued) and kfbi_last_error() returns a
@@ -66,12 +69,26 @@ typedef struct {
     double lo, hi;        /* box [lo, hi]^2 */
     int n;                /* intervals per axis; power of two, 64 <= n <= 4096 */
     double kappa;         /* >= 0, the operator is Lap - kappa (Sec. 2, modified Helmholtz) */
-    int m;                /* number of boundary samples, 3 <= m <= 65536 */
+    int m;                /* number of boundary samples, 3 <= m <= 12288 */
     const double* xy;     /* host, m x 2 (x0, y0, x1, y1, ...), counter-clockwise */
     double tol;           /* GMRES relative residual tolerance (Sec. 5 uses 1e-8); <= 0: 1e-10 */
     int restart;          /* GMRES restart length; <= 0: 50; capped at 64 */
     int max_iter;         /* cap on K_D applications inside GMRES; <= 0: 500 */
+    int precision;        /* arithmetic of the dense grid solves (volume potential,
+                             final solution, kfbi_fast_solve and the interface
+                             solves): KFBI_FP64, or KFBI_FP32_REFINED */
+    int refine_steps;     /* KFBI_FP32_REFINED only: FP64 residual corrections after
+                             the first FP32 solve, 0..4; < 0: 1 */
 } kfbi_desc;
+
+/* Precision of the dense grid solves.  KFBI_FP32_REFINED runs the two column
+ * sine transforms of Alg. 4 in FP32 arithmetic with FP32 storage between them
+ * (the tridiagonal solves along x and the transforms' running sums stay FP64),
+ * then refines: r = rhs - (L_h - kappa) v in FP64, v += FP32 solve of r, per
+ * refine step.  GMRES, the jumps, corrections and interpolation, and the
+ * K_D apply of the iteration stay FP64 in both modes. */
+#define KFBI_FP64 0
+#define KFBI_FP32_REFINED 1
 
 /* ---------------------------------------------------------------- contexts */
 
@@ -167,6 +184,70 @@ kfbi_status kfbi_interface_solve(kfbi_prob* prob, const double* phi, const doubl
  * fast solve and interpolation are exact on quadratics. */
 kfbi_status kfbi_interface_solve_jumps(kfbi_prob* prob, const double* jq, const double* jz,
                                        const double* ftilde, double* vgrid, double* vz);
+
+/* ---------------------------------------------------------------- tile shapes and the autotuner */
+
+/* Launch shapes of a problem's kernels. */
+typedef struct {
+    int modes_waves;      /* sparse fast solve: wavefronts (sine modes) per workgroup, 1/2/4/8 */
+    int modes_groups;     /* sparse fast solve: workgroups (each walks its share of the modes) */
+    int dst_cols;         /* column sine transforms: columns per workgroup, 4/8/16 */
+    double apply_us;      /* autotune output: mean K_D apply time with this shape */
+    double grid_solve_us; /* autotune output: mean dense grid solve time (transforms + row solves) */
+} kfbi_tiles;
+
+/* Time the candidate shapes on this problem (each K_D apply and grid solve
+ * candidate `reps` times, after one warm-up, with HIP events on the context
+ * stream), keep the fastest and return it in *out.  Candidates: waves 1/2/4/8
+ * whose local data share fits, workgroups n_cu/2, n_cu, 2 n_cu and one
+ * workgroup per W modes (capped by the modes and by 2 n_cu); every valid
+ * column tile.  Overwrites the problem's scratch vectors (not its results).
+ * Synchronises.  reps <= 0: 10. */
+kfbi_status kfbi_prob_autotune(kfbi_prob* prob, int reps, kfbi_tiles* out);
+/* The shapes in use (the times are those of the last autotune, else 0). */
+kfbi_status kfbi_prob_get_tiles(const kfbi_prob* prob, kfbi_tiles* out);
+/* Use the given shapes (e.g. from a cache of earlier autotune results);
+ * KFBI_ERR_ARG if a value is not a valid candidate for this problem.  The
+ * apply's result changes only by the grouping of its partial sums. */
+kfbi_status kfbi_prob_set_tiles(kfbi_prob* prob, const kfbi_tiles* tiles);
+
+/* ---------------------------------------------------------------- batches (many problems, one launch per step) */
+
+/* A batch advances the GMRES iterations of up to max_slots problems together:
+ * every stage of an iteration (correction, sparse fast solve, interpolation,
+ * Gram-Schmidt/Givens) is one persistent launch over a device-resident work
+ * list of all live problems, replayed as a captured graph.  Problems may have
+ * different grids (n <= 2048) and sample counts (m <= m_max); a problem's
+ * arithmetic is split into the same blocks whatever else is in the batch, so
+ * its result is the same alone and in the mix.  hbm_budget bounds the device
+ * bytes of the admitted problems (0: no bound).  For callers that serve solve
+ * requests: admit when a slot and memory are free, step, poll, finish. */
+typedef struct kfbi_batch kfbi_batch;
+kfbi_status kfbi_batch_create(kfbi_ctx* ctx, int max_slots, int m_max, size_t hbm_budget, kfbi_batch** out);
+/* Destroys the batch; problems still admitted are released, not destroyed. */
+kfbi_status kfbi_batch_destroy(kfbi_batch* batch);
+/* Device bytes a problem with grid n, m samples and restart length would hold
+ * once admitted to a batch (plan, workspace and batch buffers), as an upper
+ * bound computed before its plan exists: for admission control. */
+kfbi_status kfbi_batch_estimate_bytes(int n, int m, int restart, size_t* bytes);
+/* Admit a problem: enqueue its volume potential (Sec. 2.1, g^ = g - (Y f)^+)
+ * and start its GMRES iteration.  f_grid, f_gamma and g (device, as in
+ * kfbi_solve) must stay valid until kfbi_batch_finish returns.  Returns the
+ * slot id.  KFBI_ERR_BUDGET: no free slot, or the budget cannot take it now
+ * (retry after a finish); KFBI_ERR_UNSUPPORTED: it can never fit this batch. */
+kfbi_status kfbi_batch_admit(kfbi_batch* batch, kfbi_prob* prob, const double* f_grid, const double* f_gamma,
+                             const double* g, int* slot);
+/* Enqueue nsteps GMRES iterations of every live problem (no synchronisation). */
+kfbi_status kfbi_batch_step(kfbi_batch* batch, int nsteps);
+/* Synchronise and report per slot (host arrays of max_slots entries, any may be
+ * NULL): state 1 converged, -1 iteration cap reached, 0 running, -2 empty slot;
+ * Arnoldi steps made; last relative residual. */
+kfbi_status kfbi_batch_poll(kfbi_batch* batch, int* state, int* iters, double* rel_res);
+/* Final solve u = W phi + Y f of a slot (outputs as in kfbi_solve) and release
+ * the slot.  Enqueues; the outputs are ready after the next synchronisation. */
+kfbi_status kfbi_batch_finish(kfbi_batch* batch, int slot, double* u_grid, double* u_gamma, double* phi);
+/* Live problems and the device bytes they hold. */
+kfbi_status kfbi_batch_info(const kfbi_batch* batch, int* live, size_t* bytes_in_use);
 
 /* ---------------------------------------------------------------- diagnostics */
 

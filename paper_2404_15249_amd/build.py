@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libkfbi.so")
-SOURCES = ["plan.cpp", "kernels.hip", "batch.hip", "api.hip"]
+SOURCES = ["plan.cpp", "kernels.hip", "batch.hip", "dst.hip", "api.hip"]
 ARCH = "gfx950"
 
 

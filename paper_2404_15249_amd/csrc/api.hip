@@ -5,11 +5,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "kfbi.h"
+#include "batch.h"
 #include "kernels.h"
 #include "plan.h"
 
@@ -39,6 +41,11 @@ struct kfbi_ctx {
     bool own_stream = false;
     size_t lds_max = 65536;
     int num_cu = 256;
+    // Graphs are captured on a private stream (relaxed mode) under this lock:
+    // nothing else ever enqueues on it, so calls that other host threads make
+    // meanwhile (problem creation, torch work) cannot enter or break a capture.
+    hipStream_t cap_stream = nullptr;
+    std::mutex cap_mu;
 };
 
 struct kfbi_prob {
@@ -57,7 +64,15 @@ struct kfbi_prob {
     double* partial = nullptr;   // G M
     double* R = nullptr;         // N N
     double* A = nullptr;         // N N
+    int precision = KFBI_FP64, refine = 0;
+    float* X32 = nullptr;        // N N: FP32 transform storage (KFBI_FP32_REFINED)
+    int dstB = 8;                // columns per workgroup of the column transforms
+    int Gcap = 1;                // workgroups the partial buffer has room for
     double* tmpM = nullptr;      // M
+    double* partial_b = nullptr; // M x Gs: partials of the batched fast solve (allocated on first admission)
+    int Gs = 0;
+    const double* b_fgrid = nullptr;   // right-hand side of the batched request (caller owned)
+    const double* b_fgam = nullptr;
     double* s2a = nullptr;       // M: spline second derivatives (density)
     double* s2b = nullptr;       // M: spline second derivatives (f on Gamma)
     GmresBufs gm{};
@@ -67,6 +82,7 @@ struct kfbi_prob {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     int t_count = 0;
+    double tuned_apply_us = 0, tuned_grid_us = 0;
     // a captured batch of GMRES steps (apply + Arnoldi update), replayed per batch
     static constexpr int kGraphSteps = 8;
     hipGraphExec_t gexec = nullptr;
@@ -129,14 +145,40 @@ std::vector<ModeConst> mode_constants(int N, double h, double kappa) {
     return mc;
 }
 
+// bytes of one complex pair in the column transforms of a precision mode
+size_t cpx_bytes(int precision) { return precision == KFBI_FP64 ? 2 * sizeof(double) : 2 * sizeof(float); }
+
 kfbi_status check_ptr(const void* p, const char* name) {
     if (!p) return set_err(KFBI_ERR_ARG, std::string(name) + " is NULL");
     return KFBI_OK;
 }
 
-// Dense interface solve: R <- f~ (+ corrections), two sine products around the
-// row solves, then interpolation; the solution grid is left in R (padded
-// interior layout) and optionally written to `vgrid`.
+// Alg. 4 on the full grid: solve (L_h - kappa) V = R (R in the padded interior
+// layout, consumed).  FP64: in place, *V = R.  FP32 with refinement: FP32
+// column transforms around the FP64 row solves into A, then per refine step
+// the FP64 residual (into R) and an FP32 correction accumulated into A; *V = A.
+kfbi_status grid_solve(kfbi_prob* p, const double** V) {
+    hipStream_t s = p->ctx->stream;
+    const double inv = 2.0 / p->N;
+    if (p->precision == KFBI_FP64) {
+        HIP_TRY(launch_dst_cols(p->dp, p->R, p->R, 1.0, false, p->dstB, s));
+        HIP_TRY(launch_rows_solve(p->dp, p->R, s));
+        HIP_TRY(launch_dst_cols(p->dp, p->R, p->R, inv, false, p->dstB, s));
+        *V = p->R;
+        return KFBI_OK;
+    }
+    for (int k = 0; k <= p->refine; ++k) {
+        if (k > 0) HIP_TRY(launch_residual(p->dp, p->A, p->R, s));
+        HIP_TRY(launch_dst_cols_f32(p->dp, p->R, p->X32, 1.0, p->dstB, s));
+        HIP_TRY(launch_rows_solve_f32(p->dp, p->X32, s));
+        HIP_TRY(launch_dst_cols_f32_to64(p->dp, p->X32, p->A, inv, k > 0, p->dstB, s));
+    }
+    *V = p->A;
+    return KFBI_OK;
+}
+
+// Dense interface solve: R <- f~ (+ corrections), the grid solve, then
+// interpolation at the samples and, optionally, the grid written to `vgrid`.
 kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, bool mask, double* vgrid,
                                   bool mask_out, double* vz) {
     hipStream_t s = p->ctx->stream;
@@ -150,16 +192,15 @@ kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, boo
     }
     HIP_TRY(launch_fill_rhs(p->dp, f, mask, p->R, s));
     HIP_TRY(launch_correct(p->dp, js, nullptr, nullptr, p->R, nullptr, s));
-    HIP_TRY(launch_sine_gemm(p->dp, p->R, p->A, 1.0, s));
-    HIP_TRY(launch_rows_solve(p->dp, p->A, s));
-    HIP_TRY(launch_sine_gemm(p->dp, p->A, p->R, 2.0 / p->N, s));
-    if (vz) HIP_TRY(launch_interp_grid(p->dp, js, p->R, vz, s));
-    if (vgrid) HIP_TRY(launch_grid_out(p->dp, p->R, mask_out, vgrid, s));
+    const double* V = nullptr;
+    if (kfbi_status e = grid_solve(p, &V)) return e;
+    if (vz) HIP_TRY(launch_interp_grid(p->dp, js, V, vz, s));
+    if (vgrid) HIP_TRY(launch_grid_out(p->dp, V, mask_out, vgrid, s));
     return KFBI_OK;
 }
 
-kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, double* out, const int* skip) {
-    hipStream_t s = p->ctx->stream;
+kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, double* out, const int* skip,
+                         hipStream_t s) {
     JumpSrc js{phi, phi_s2, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t* ev = nullptr;
     if (p->timing && p->t_count < kfbi_prob::kMaxTimed) {
@@ -182,41 +223,52 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
 // Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps are
 // enqueued in batches; with tol > 0 the host polls the device state after each
 // batch, with tol <= 0 the work is fixed and the host waits once at the end.
-kfbi_status enqueue_steps(kfbi_prob* p, int nsteps) {
-    hipStream_t s = p->ctx->stream;
+kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
     GmresBufs b = p->gm;
     const int* skip = &b.st->converged;
     for (int k = 0; k < nsteps; ++k) {
-        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip)) return e;
+        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, s)) return e;
         HIP_TRY(launch_gmres_step(p->dp, b, s));
     }
     return KFBI_OK;
 }
 
+// Capture what `enqueue(stream)` launches into an executable graph, on the
+// context's private capture stream.  Returns false (and leaves *out null) if
+// capture or instantiation fails; the caller then launches directly.
+template <class F>
+bool capture_graph(kfbi_ctx* ctx, hipGraphExec_t* out, F enqueue) {
+    *out = nullptr;
+    if (!ctx->cap_stream) return false;
+    std::lock_guard<std::mutex> lock(ctx->cap_mu);
+    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        hipGetLastError();
+        return false;
+    }
+    const kfbi_status e = enqueue(ctx->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
+    bool ok = e == KFBI_OK && ee == hipSuccess && g != nullptr &&
+              hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        *out = nullptr;
+    }
+    if (g) hipGraphDestroy(g);
+    return ok;
+}
+
 // Capture kGraphSteps GMRES steps into a graph once per problem.  All launch
 // arguments are fixed device pointers and the steps read their parameters from
 // the device state, so one graph serves every call.  If capture is not possible
-// (e.g. the context stream is the null stream) the steps are launched directly.
+// the steps are launched directly.
 void ensure_graph(kfbi_prob* p) {
     if (p->gexec || p->graph_failed) return;
-    hipStream_t s = p->ctx->stream;
-    if (s == nullptr || hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        hipGetLastError();
-        p->graph_failed = true;
-        return;
-    }
     const bool timing = p->timing;
     p->timing = false;
-    const kfbi_status e = enqueue_steps(p, kfbi_prob::kGraphSteps);
+    p->graph_failed =
+        !capture_graph(p->ctx, &p->gexec, [&](hipStream_t cs) { return enqueue_steps(p, kfbi_prob::kGraphSteps, cs); });
     p->timing = timing;
-    hipGraph_t g = nullptr;
-    const hipError_t ee = hipStreamEndCapture(s, &g);
-    if (e != KFBI_OK || ee != hipSuccess || !g || hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
-        hipGetLastError();
-        p->gexec = nullptr;
-        p->graph_failed = true;
-    }
-    if (g) hipGraphDestroy(g);
 }
 
 // Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps go in
@@ -246,7 +298,7 @@ kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_it
     for (int done = 0, nb = 0; done < max_steps; done += B) {
         if (use_graph && p->gexec) {
             HIP_TRY(hipGraphLaunch(p->gexec, s));
-        } else if (kfbi_status e = enqueue_steps(p, B)) {
+        } else if (kfbi_status e = enqueue_steps(p, B, s)) {
             return e;
         }
         if (++nb % poll_every == 0 || done + B >= max_steps) {
@@ -303,6 +355,10 @@ kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipGetLastError();
+        c->cap_stream = nullptr;                   // no graphs: steps are launched directly
+    }
     *out = c;
     return KFBI_OK;
 }
@@ -310,6 +366,7 @@ kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
 kfbi_status kfbi_ctx_destroy(kfbi_ctx* ctx) {
     if (!ctx) return KFBI_OK;
     if (ctx->own_stream) hipStreamDestroy(ctx->stream);
+    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return KFBI_OK;
 }
@@ -324,9 +381,13 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     if (!ctx || !d || !out || !d->xy) return set_err(KFBI_ERR_ARG, "NULL argument");
     const int n = d->n;
     if (n < 64 || n > 4096 || (n & (n - 1))) return set_err(KFBI_ERR_UNSUPPORTED, "n must be a power of two in [64, 4096]");
-    if (d->m < 3 || d->m > 65536) return set_err(KFBI_ERR_ARG, "m must be in [3, 65536]");
+    if (d->m < 3 || d->m > kMaxSamples) return set_err(KFBI_ERR_ARG, "m must be in [3, 12288]");
     if (!(d->hi > d->lo) || !std::isfinite(d->lo) || !std::isfinite(d->hi)) return set_err(KFBI_ERR_ARG, "bad box");
     if (!(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return set_err(KFBI_ERR_ARG, "kappa must be finite and >= 0");
+    if (d->precision != KFBI_FP64 && d->precision != KFBI_FP32_REFINED)
+        return set_err(KFBI_ERR_ARG, "precision must be KFBI_FP64 or KFBI_FP32_REFINED");
+    if (d->precision == KFBI_FP32_REFINED && d->refine_steps > 4)
+        return set_err(KFBI_ERR_ARG, "refine_steps must be at most 4");
     HIP_TRY(hipSetDevice(ctx->device));
     kfbi_prob* p = new (std::nothrow) kfbi_prob;
     if (!p) return set_err(KFBI_ERR_ARG, "host allocation failed");
@@ -345,14 +406,16 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     p->tol = d->tol > 0 ? d->tol : 1e-10;
     p->restart = d->restart > 0 ? std::min(d->restart, kMaxRestart) : 50;
     p->max_iter = d->max_iter > 0 ? d->max_iter : 500;
+    p->precision = d->precision;
+    p->refine = d->precision == KFBI_FP32_REFINED ? (d->refine_steps < 0 ? 1 : d->refine_steps) : 0;
     p->N = n;
     p->n = n - 1;
     p->M = d->m;
     p->Q = (int)P.q_axis.size();
     p->I = (int)P.irr_i.size();
-    if (p->M > 16384) {
+    if (p->M > kMaxSamples) {
         delete p;
-        return set_err(KFBI_ERR_UNSUPPORTED, "more than 16384 samples");
+        return set_err(KFBI_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxSamples) + " samples");
     }
     // workgroup shape of the sparse fast solve: as many waves as the LDS allows
     // as many waves per workgroup as the LDS allows while still giving every
@@ -369,6 +432,12 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         return set_err(KFBI_ERR_UNSUPPORTED, "problem too large for the local data share");
     }
     p->G = std::max(1, std::min((p->n + p->W - 1) / p->W, 2 * ctx->num_cu));
+    p->Gcap = std::max(p->G, std::min(p->n, 2 * ctx->num_cu));
+    p->dstB = dst_default_tile(n, cpx_bytes(p->precision), ctx->lds_max);
+    if (p->dstB == 0) {
+        delete p;
+        return set_err(KFBI_ERR_UNSUPPORTED, "grid too large for the column transforms' local data share");
+    }
 
     kfbi_status st = KFBI_OK;
     auto fail = [&](kfbi_status s) {
@@ -438,7 +507,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = upload(p, &dp.taps, spline_filter_taps(K))))
         return fail(st);
     const int M = p->M, m = p->restart;
-    if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->corr_il, (size_t)dp.T * 64)) || (st = dev_alloc(p, &p->partial, (size_t)p->G * M)) ||
+    if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->corr_il, (size_t)dp.T * 64)) || (st = dev_alloc(p, &p->partial, (size_t)p->Gcap * M)) ||
         (st = dev_alloc(p, &p->R, (size_t)n * n)) || (st = dev_alloc(p, &p->A, (size_t)n * n)) ||
         (st = dev_alloc(p, &p->tmpM, M)) || (st = dev_alloc(p, &p->s2a, M)) || (st = dev_alloc(p, &p->s2b, M)) ||
         (st = dev_alloc(p, &p->gm.s2cur, M)) || (st = dev_alloc(p, &p->gm.V, (size_t)(m + 1) * M)) ||
@@ -448,6 +517,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = dev_alloc(p, &p->gm.xcur, M)) || (st = dev_alloc(p, &p->gm.w, M)) ||
         (st = dev_alloc(p, &p->gm.st, 1)))
         return fail(st);
+    if (p->precision == KFBI_FP32_REFINED && (st = dev_alloc(p, &p->X32, (size_t)n * n))) return fail(st);
     // pad slots of the interleaved corrections stay zero for the life of the problem
     HIP_TRY(hipMemset(p->corr_il, 0, sizeof(double) * (size_t)dp.T * 64));
     p->gm.m = m;
@@ -510,7 +580,7 @@ kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
     HIP_TRY(launch_spline(p->dp, phi, p->s2a, nullptr, p->ctx->stream));
-    return sparse_apply(p, phi, p->s2a, out, nullptr);
+    return sparse_apply(p, phi, p->s2a, out, nullptr, p->ctx->stream);
 }
 
 kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {
@@ -538,10 +608,9 @@ kfbi_status kfbi_fast_solve(kfbi_prob* p, const double* rhs, double* v) {
     HIP_TRY(hipSetDevice(p->ctx->device));
     hipStream_t s = p->ctx->stream;
     HIP_TRY(launch_fill_rhs(p->dp, rhs, false, p->R, s));
-    HIP_TRY(launch_sine_gemm(p->dp, p->R, p->A, 1.0, s));
-    HIP_TRY(launch_rows_solve(p->dp, p->A, s));
-    HIP_TRY(launch_sine_gemm(p->dp, p->A, p->R, 2.0 / p->N, s));
-    HIP_TRY(launch_grid_out(p->dp, p->R, false, v, s));
+    const double* V = nullptr;
+    if (kfbi_status e = grid_solve(p, &V)) return e;
+    HIP_TRY(launch_grid_out(p->dp, V, false, v, s));
     return KFBI_OK;
 }
 
@@ -636,6 +705,461 @@ kfbi_status kfbi_apply_timing(kfbi_prob* p, double* a, double* b, double* c, int
     if (b) *b = acc[1] * k;
     if (c) *c = acc[2] * k;
     if (count) *count = p->t_count;
+    return KFBI_OK;
+}
+
+// ---------------------------------------------------------------- tile shapes
+
+}  // extern "C"
+
+namespace {
+
+bool tiles_valid(const kfbi_prob* p, int W, int G, int B) {
+    if (W != 1 && W != 2 && W != 4 && W != 8) return false;
+    if (modes_lds_bytes(p->N, p->M, W) > p->ctx->lds_max) return false;
+    if (G < 1 || G > p->Gcap || G > (p->n + W - 1) / W) return false;
+    return dst_tile_ok(p->N, B, cpx_bytes(p->precision), p->ctx->lds_max);
+}
+
+void drop_graph(kfbi_prob* p) {
+    if (p->gexec) hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+    p->graph_failed = false;
+}
+
+// mean time in microseconds of `reps` runs of `body` (after one warm-up run)
+template <class F>
+kfbi_status time_us(hipStream_t s, int reps, double* us, F body) {
+    if (kfbi_status e = body()) return e;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return set_err(KFBI_ERR_DEVICE, "event creation failed");
+    }
+    kfbi_status st = KFBI_OK;
+    float ms = 0.f;
+    if (hipEventRecord(e0, s) != hipSuccess) st = set_err(KFBI_ERR_DEVICE, "event record failed");
+    for (int k = 0; k < reps && st == KFBI_OK; ++k) st = body();
+    if (st == KFBI_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = set_err(KFBI_ERR_DEVICE, "event timing failed");
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    *us = 1e3 * ms / reps;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+kfbi_status kfbi_prob_get_tiles(const kfbi_prob* p, kfbi_tiles* out) {
+    if (!p || !out) return set_err(KFBI_ERR_ARG, "NULL argument");
+    out->modes_waves = p->W;
+    out->modes_groups = p->G;
+    out->dst_cols = p->dstB;
+    out->apply_us = p->tuned_apply_us;
+    out->grid_solve_us = p->tuned_grid_us;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_set_tiles(kfbi_prob* p, const kfbi_tiles* t) {
+    if (!p || !t) return set_err(KFBI_ERR_ARG, "NULL argument");
+    if (!tiles_valid(p, t->modes_waves, t->modes_groups, t->dst_cols))
+        return set_err(KFBI_ERR_ARG, "tile shape not valid for this problem");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));      // a replayed graph may still use the old shape
+    p->W = t->modes_waves;
+    p->G = t->modes_groups;
+    p->dstB = t->dst_cols;
+    drop_graph(p);
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_prob_autotune(kfbi_prob* p, int reps, kfbi_tiles* out) {
+    if (!p || !out) return set_err(KFBI_ERR_ARG, "NULL argument");
+    if (reps <= 0) reps = 10;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(hipStreamSynchronize(s));
+    drop_graph(p);
+    const int ncu = p->ctx->num_cu;
+    // a zero density in tmpM with its spline in s2a: the values do not change the work
+    HIP_TRY(hipMemsetAsync(p->tmpM, 0, sizeof(double) * p->M, s));
+    HIP_TRY(hipMemsetAsync(p->s2a, 0, sizeof(double) * p->M, s));
+    double best = 1e300;
+    int bw = p->W, bg = p->G;
+    for (int W : {1, 2, 4, 8}) {
+        std::vector<int> gs = {ncu / 2, ncu, 2 * ncu, (p->n + W - 1) / W};
+        std::sort(gs.begin(), gs.end());
+        gs.erase(std::unique(gs.begin(), gs.end()), gs.end());
+        for (int G : gs) {
+            if (!tiles_valid(p, W, G, p->dstB)) continue;
+            p->W = W;
+            p->G = G;
+            double us = 0;
+            if (kfbi_status e = time_us(s, reps, &us, [&] { return sparse_apply(p, p->tmpM, p->s2a, p->s2b, nullptr, s); })) {
+                p->W = bw;
+                p->G = bg;
+                return e;
+            }
+            if (us < best) {
+                best = us;
+                bw = W;
+                bg = G;
+            }
+        }
+    }
+    p->W = bw;
+    p->G = bg;
+    p->tuned_apply_us = best;
+    double bestg = 1e300;
+    int bb = p->dstB;
+    const double* V = nullptr;
+    for (int B : {4, 8, 16}) {
+        if (!tiles_valid(p, p->W, p->G, B)) continue;
+        p->dstB = B;
+        double us = 0;
+        if (kfbi_status e = time_us(s, reps, &us, [&] {
+                HIP_TRY(launch_fill_rhs(p->dp, nullptr, false, p->R, s));
+                return grid_solve(p, &V);
+            })) {
+            p->dstB = bb;
+            return e;
+        }
+        if (us < bestg) {
+            bestg = us;
+            bb = B;
+        }
+    }
+    p->dstB = bb;
+    p->tuned_grid_us = bestg;
+    return kfbi_prob_get_tiles(p, out);
+}
+
+// ---------------------------------------------------------------- batches
+
+}  // extern "C"
+
+struct kfbi_batch {
+    kfbi_ctx* ctx = nullptr;
+    int max_slots = 0, mmax = 0;
+    size_t budget = 0, used = 0;
+    std::vector<kfbi_prob*> slot;
+    std::vector<size_t> slot_bytes;
+    std::vector<SlotDev> h_slots;
+    SlotDev* d_slots = nullptr;
+    int* d_counts = nullptr;
+    int2* d_corr = nullptr;
+    int2* d_mode = nullptr;
+    int2* d_cp = nullptr;
+    int* d_live = nullptr;
+    int cap_corr = 0, cap_mode = 0, cap_cp = 0;
+    std::vector<int2> h_corr, h_mode, h_cp;
+    std::vector<int> h_live;
+    int h_counts[4] = {0, 0, 0, 0};
+    // pinned staging of the uploads, reused once the event says the stream has
+    // consumed the previous upload
+    char* stage = nullptr;
+    size_t stage_cap = 0;
+    hipEvent_t up_ev = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool graph_failed = false;
+    static constexpr int kGraphSteps = 8;
+};
+
+namespace {
+
+void batch_free_lists(kfbi_batch* B) {
+    for (void* q : {(void*)B->d_corr, (void*)B->d_mode, (void*)B->d_cp})
+        if (q) hipFree(q);
+    B->d_corr = nullptr;
+    B->d_mode = nullptr;
+    B->d_cp = nullptr;
+    B->cap_corr = B->cap_mode = B->cap_cp = 0;
+}
+
+kfbi_status batch_grow(hipStream_t s, int2** d, int* cap, size_t need) {
+    if ((size_t)*cap >= need) return KFBI_OK;
+    size_t nc = std::max<size_t>(need, 2 * (size_t)*cap);
+    if (*d) {
+        HIP_TRY(hipStreamSynchronize(s));   // queued launches may still read the old list
+        hipFree(*d);
+    }
+    *d = nullptr;
+    if (hipMalloc((void**)d, nc * sizeof(int2)) != hipSuccess) {
+        hipGetLastError();
+        *cap = 0;
+        return set_err(KFBI_ERR_OOM, "batch work list allocation failed");
+    }
+    *cap = (int)nc;
+    return KFBI_OK;
+}
+
+// Rebuild the work lists of the live slots and upload them (stream ordered).
+kfbi_status batch_rebuild(kfbi_batch* B) {
+    B->h_corr.clear();
+    B->h_mode.clear();
+    B->h_cp.clear();
+    B->h_live.clear();
+    for (int s = 0; s < B->max_slots; ++s) {
+        kfbi_prob* p = B->slot[s];
+        if (!p) continue;
+        B->h_live.push_back(s);
+        for (int r = 0; r < p->I; r += 256) B->h_corr.push_back(make_int2(s, r));
+        for (int b = 0; b < p->Gs; ++b) B->h_mode.push_back(make_int2(s, b));
+        for (int c = 0; c < p->M; c += 4) B->h_cp.push_back(make_int2(s, c));
+    }
+    const int2* old[3] = {B->d_corr, B->d_mode, B->d_cp};
+    hipStream_t gs = B->ctx->stream;
+    if (kfbi_status e = batch_grow(gs, &B->d_corr, &B->cap_corr, std::max<size_t>(B->h_corr.size(), 1))) return e;
+    if (kfbi_status e = batch_grow(gs, &B->d_mode, &B->cap_mode, std::max<size_t>(B->h_mode.size(), 1))) return e;
+    if (kfbi_status e = batch_grow(gs, &B->d_cp, &B->cap_cp, std::max<size_t>(B->h_cp.size(), 1))) return e;
+    if (old[0] != B->d_corr || old[1] != B->d_mode || old[2] != B->d_cp) {
+        // the captured graph holds the old list addresses
+        if (B->gexec) hipGraphExecDestroy(B->gexec);
+        B->gexec = nullptr;
+    }
+    hipStream_t s = B->ctx->stream;
+    B->h_counts[0] = (int)B->h_corr.size();
+    B->h_counts[1] = (int)B->h_mode.size();
+    B->h_counts[2] = (int)B->h_cp.size();
+    B->h_counts[3] = (int)B->h_live.size();
+    const size_t nb = sizeof(int2) * (B->h_corr.size() + B->h_mode.size() + B->h_cp.size()) +
+                      sizeof(int) * (B->h_live.size() + 4) + sizeof(SlotDev) * B->max_slots;
+    HIP_TRY(hipEventSynchronize(B->up_ev));
+    if (nb > B->stage_cap) {
+        if (B->stage) hipHostFree(B->stage);
+        B->stage = nullptr;
+        B->stage_cap = 0;
+        HIP_TRY(hipHostMalloc((void**)&B->stage, 2 * nb));
+        B->stage_cap = 2 * nb;
+    }
+    // upload, ordered on the stream after the work that used the previous lists
+    char* q = B->stage;
+    auto put = [&](void* dst, const void* src, size_t bytes) -> kfbi_status {
+        if (!bytes) return KFBI_OK;
+        std::memcpy(q, src, bytes);
+        HIP_TRY(hipMemcpyAsync(dst, q, bytes, hipMemcpyHostToDevice, s));
+        q += bytes;
+        return KFBI_OK;
+    };
+    kfbi_status e = KFBI_OK;
+    if ((e = put(B->d_corr, B->h_corr.data(), B->h_corr.size() * sizeof(int2))) ||
+        (e = put(B->d_mode, B->h_mode.data(), B->h_mode.size() * sizeof(int2))) ||
+        (e = put(B->d_cp, B->h_cp.data(), B->h_cp.size() * sizeof(int2))) ||
+        (e = put(B->d_live, B->h_live.data(), B->h_live.size() * sizeof(int))) ||
+        (e = put(B->d_counts, B->h_counts, sizeof B->h_counts)) ||
+        (e = put(B->d_slots, B->h_slots.data(), sizeof(SlotDev) * B->max_slots)))
+        return e;
+    HIP_TRY(hipEventRecord(B->up_ev, s));
+    return KFBI_OK;
+}
+
+BatchWork batch_work(const kfbi_batch* B) {
+    BatchWork w;
+    w.counts = B->d_counts;
+    w.corr_items = B->d_corr;
+    w.mode_items = B->d_mode;
+    w.cp_items = B->d_cp;
+    w.live = B->d_live;
+    w.max_live = B->max_slots;
+    return w;
+}
+
+kfbi_status batch_enqueue_steps(kfbi_batch* B, int nsteps, hipStream_t s) {
+    for (int k = 0; k < nsteps; ++k)
+        HIP_TRY(launch_batch_step(B->d_slots, batch_work(B), kBatchNmax, B->mmax, B->ctx->num_cu, s));
+    return KFBI_OK;
+}
+
+void batch_ensure_graph(kfbi_batch* B) {
+    if (B->gexec || B->graph_failed) return;
+    B->graph_failed = !capture_graph(B->ctx, &B->gexec, [&](hipStream_t cs) {
+        return batch_enqueue_steps(B, kfbi_batch::kGraphSteps, cs);
+    });
+}
+
+size_t batch_extra_bytes(int n, int m) {
+    const int Gs = (n - 1 + kBatchW - 1) / kBatchW;
+    return sizeof(double) * (size_t)m * Gs;
+}
+
+}  // namespace
+
+extern "C" {
+
+kfbi_status kfbi_batch_estimate_bytes(int n, int m, int restart, size_t* bytes) {
+    if (!bytes || n < 64 || m < 3) return set_err(KFBI_ERR_ARG, "bad arguments");
+    if (restart <= 0) restart = 50;
+    restart = std::min(restart, kMaxRestart);
+    // plan: crossings and irregular nodes are O(perimeter / h); bound them by 8 n
+    const size_t nq = 8 * (size_t)n, ni = 8 * (size_t)n;
+    const size_t slots = ni + 64 * (size_t)(kSlots + 64);                  // interleaved table, padded
+    size_t b = nq * (sizeof(PointGeom) + 4) + (size_t)m * 256 + ni * 80 + slots * 12 +
+               (size_t)(n + 1) * (n + 1) + (size_t)n * (sizeof(ModeConst) + 16) + 4096;
+    b += 2 * sizeof(double) * (size_t)n * n;                                  // dense-path grids
+    b += sizeof(double) * ((size_t)(restart + 1) * (m + restart) + 16 * (size_t)m);   // GMRES
+    b += sizeof(double) * (size_t)m * 512;                                    // single-path partials
+    b += batch_extra_bytes(n, m);
+    *bytes = b;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_batch_create(kfbi_ctx* ctx, int max_slots, int m_max, size_t budget, kfbi_batch** out) {
+    if (!ctx || !out || max_slots < 1 || max_slots > 1024 || m_max < 3 || m_max > kMaxSamples)
+        return set_err(KFBI_ERR_ARG, "bad batch arguments");
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (modes_b_lds_bytes(kBatchNmax, m_max) > ctx->lds_max)
+        return set_err(KFBI_ERR_UNSUPPORTED, "m_max too large for the batched fast solve's LDS");
+    kfbi_batch* B = new (std::nothrow) kfbi_batch;
+    if (!B) return set_err(KFBI_ERR_ARG, "host allocation failed");
+    B->ctx = ctx;
+    B->max_slots = max_slots;
+    B->mmax = m_max;
+    B->budget = budget;
+    B->slot.assign(max_slots, nullptr);
+    B->slot_bytes.assign(max_slots, 0);
+    B->h_slots.resize(max_slots);
+    bool ok = hipEventCreateWithFlags(&B->up_ev, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc((void**)&B->d_slots, sizeof(SlotDev) * max_slots) == hipSuccess &&
+              hipMalloc((void**)&B->d_counts, sizeof(int) * 4) == hipSuccess &&
+              hipMalloc((void**)&B->d_live, sizeof(int) * max_slots) == hipSuccess;
+    if (!ok) {
+        hipGetLastError();
+        kfbi_batch_destroy(B);
+        return set_err(KFBI_ERR_OOM, "batch allocation failed");
+    }
+    if (kfbi_status e = batch_rebuild(B)) {
+        kfbi_batch_destroy(B);
+        return e;
+    }
+    *out = B;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_batch_destroy(kfbi_batch* B) {
+    if (!B) return KFBI_OK;
+    hipSetDevice(B->ctx->device);
+    hipStreamSynchronize(B->ctx->stream);
+    if (B->gexec) hipGraphExecDestroy(B->gexec);
+    batch_free_lists(B);
+    for (void* q : {(void*)B->d_slots, (void*)B->d_counts, (void*)B->d_live})
+        if (q) hipFree(q);
+    if (B->stage) hipHostFree(B->stage);
+    if (B->up_ev) hipEventDestroy(B->up_ev);
+    delete B;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_batch_admit(kfbi_batch* B, kfbi_prob* p, const double* f_grid, const double* f_gamma,
+                             const double* g, int* slot) {
+    if (!B || !p || !slot) return set_err(KFBI_ERR_ARG, "NULL argument");
+    for (auto [ptr, name] : {std::pair<const void*, const char*>{f_grid, "f_grid"}, {f_gamma, "f_gamma"}, {g, "g"}})
+        if (kfbi_status s = check_ptr(ptr, name)) return s;
+    if (p->ctx != B->ctx) return set_err(KFBI_ERR_ARG, "problem and batch use different contexts");
+    if (p->N > kBatchNmax || p->M > B->mmax)
+        return set_err(KFBI_ERR_UNSUPPORTED, "problem exceeds the batch's grid or sample limit");
+    for (int s = 0; s < B->max_slots; ++s)
+        if (B->slot[s] == p) return set_err(KFBI_ERR_ARG, "problem already admitted");
+    int free_slot = -1;
+    for (int s = 0; s < B->max_slots && free_slot < 0; ++s)
+        if (!B->slot[s]) free_slot = s;
+    const size_t need = p->bytes + (p->partial_b ? 0 : batch_extra_bytes(p->N, p->M));
+    if (B->budget && need > B->budget) return set_err(KFBI_ERR_UNSUPPORTED, "problem larger than the batch budget");
+    if (free_slot < 0) return set_err(KFBI_ERR_BUDGET, "no free slot");
+    if (B->budget && B->used + need > B->budget) return set_err(KFBI_ERR_BUDGET, "over the memory budget for now");
+    HIP_TRY(hipSetDevice(B->ctx->device));
+    hipStream_t s = B->ctx->stream;
+    if (!p->partial_b) {
+        p->Gs = (p->n + kBatchW - 1) / kBatchW;
+        if (kfbi_status e = dev_alloc(p, &p->partial_b, (size_t)p->M * p->Gs)) return e;
+    }
+    // g^ = g - (Y f)^+ and a fresh GMRES state (phi_0 = 0)
+    JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
+    GmresBufs b = p->gm;
+    HIP_TRY(launch_axpby(p->M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
+    HIP_TRY(launch_axpby(p->M, 0.0, b.ghat, 0.0, nullptr, b.phi, s));
+    HIP_TRY(launch_axpby(p->M, 0.0, b.ghat, 0.0, nullptr, b.xcur, s));
+    HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
+    p->st_host = GmresState{};
+    p->st_host.first = 1;
+    p->st_host.tol = p->tol;
+    p->st_host.max_iter = p->max_iter;
+    HIP_TRY(hipMemcpyAsync(b.st, &p->st_host, sizeof p->st_host, hipMemcpyHostToDevice, s));
+    SlotDev& S = B->h_slots[free_slot];
+    S.p = p->dp;
+    S.b = b;
+    S.corr_il = p->corr_il;
+    S.partial = p->partial_b;
+    S.Gs = p->Gs;
+    S.pad = 0;
+    p->b_fgrid = f_grid;
+    p->b_fgam = f_gamma;
+    B->slot[free_slot] = p;
+    B->slot_bytes[free_slot] = p->bytes;
+    B->used += p->bytes;
+    if (kfbi_status e = batch_rebuild(B)) return e;
+    *slot = free_slot;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_batch_step(kfbi_batch* B, int nsteps) {
+    if (!B || nsteps < 0) return set_err(KFBI_ERR_ARG, "bad arguments");
+    if (B->h_live.empty() || nsteps == 0) return KFBI_OK;
+    HIP_TRY(hipSetDevice(B->ctx->device));
+    batch_ensure_graph(B);
+    const int K = kfbi_batch::kGraphSteps;
+    for (int done = 0; done < nsteps; done += K) {
+        if (B->gexec) {
+            HIP_TRY(hipGraphLaunch(B->gexec, B->ctx->stream));
+        } else if (kfbi_status e = batch_enqueue_steps(B, std::min(K, nsteps - done), B->ctx->stream)) {
+            return e;
+        }
+    }
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_batch_poll(kfbi_batch* B, int* state, int* iters, double* rel_res) {
+    if (!B) return set_err(KFBI_ERR_ARG, "batch is NULL");
+    HIP_TRY(hipSetDevice(B->ctx->device));
+    hipStream_t s = B->ctx->stream;
+    for (int k = 0; k < B->max_slots; ++k)
+        if (B->slot[k]) HIP_TRY(hipMemcpyAsync(&B->slot[k]->st_host, B->slot[k]->gm.st, sizeof(GmresState),
+                                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < B->max_slots; ++k) {
+        const kfbi_prob* p = B->slot[k];
+        if (state) state[k] = p ? p->st_host.converged : -2;
+        if (iters) iters[k] = p ? p->st_host.it : 0;
+        if (rel_res) rel_res[k] = p ? p->st_host.relres : 0.0;
+    }
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_batch_finish(kfbi_batch* B, int slot, double* u_grid, double* u_gamma, double* phi) {
+    if (!B || slot < 0 || slot >= B->max_slots || !B->slot[slot]) return set_err(KFBI_ERR_ARG, "no such slot");
+    for (auto [ptr, name] : {std::pair<const void*, const char*>{u_grid, "u_grid"}, {u_gamma, "u_gamma"}, {phi, "phi"}})
+        if (kfbi_status e = check_ptr(ptr, name)) return e;
+    HIP_TRY(hipSetDevice(B->ctx->device));
+    kfbi_prob* p = B->slot[slot];
+    hipStream_t s = B->ctx->stream;
+    JumpSrc jf{p->gm.phi, nullptr, p->b_fgam, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, jf, p->b_fgrid, true, u_grid, true, u_gamma)) return e;
+    HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    B->used -= B->slot_bytes[slot];
+    B->slot[slot] = nullptr;
+    B->slot_bytes[slot] = 0;
+    p->b_fgrid = p->b_fgam = nullptr;
+    return batch_rebuild(B);
+}
+
+kfbi_status kfbi_batch_info(const kfbi_batch* B, int* live, size_t* bytes) {
+    if (!B) return set_err(KFBI_ERR_ARG, "batch is NULL");
+    if (live) *live = (int)B->h_live.size();
+    if (bytes) *bytes = B->used;
     return KFBI_OK;
 }
 

@@ -75,10 +75,12 @@ __global__ __launch_bounds__(256) void k_reduce_b(const SlotDev* __restrict__ sl
 }
 
 __global__ __launch_bounds__(1024) void k_gmres_b(const SlotDev* __restrict__ slots, BatchWork w) {
+    extern __shared__ double smem[];
     const int n_live = w.counts[3];
     for (int it = blockIdx.x; it < n_live; it += gridDim.x) {
         const SlotDev& S = slots[w.live[it]];
-        gmres_step(S.p, S.b, S.p.M);
+        gmres_step(S.p, S.b, S.p.M, smem);
+        __syncthreads();
     }
 }
 
@@ -100,7 +102,10 @@ hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mm
     if (hipError_t e = hipGetLastError()) return e;
     k_reduce_b<<<n_cu * 2, 256, 0, s>>>(slots, w);
     if (hipError_t e = hipGetLastError()) return e;
-    k_gmres_b<<<w.max_live, 1024, 0, s>>>(slots, w);
+    const size_t glds = sizeof(double) * (size_t)Mmax;
+    if (hipError_t e = hipFuncSetAttribute((const void*)k_gmres_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds))
+        return e;
+    k_gmres_b<<<w.max_live, 1024, glds, s>>>(slots, w);
     return hipGetLastError();
 }
 

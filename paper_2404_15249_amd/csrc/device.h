@@ -244,7 +244,9 @@ __device__ inline void reduce_sample(const DevPlan& p, const JumpSrc& js, const 
 // orthogonalise it (classical Gram-Schmidt applied twice), extend the
 // Hessenberg matrix, update the Givens rotations and the residual estimate;
 // at the end of a cycle solve the small triangular system and update phi.
-__device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M) {
+__device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M, double* __restrict__ ws) {
+    // ws: M doubles of LDS holding the vector being orthogonalised, then the
+    // next K_D input (whose spline is taken from LDS).
     __shared__ double red[16];
     __shared__ double hs[kMaxRestart + 2];
     __shared__ double ys[kMaxRestart + 2];
@@ -260,7 +262,7 @@ __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M) {
         double part = 0.0;
         for (int e = tid; e < M; e += 1024) {
             const double r = b.ghat[e] - b.w[e];
-            b.V[e] = r;
+            ws[e] = r;
             part += r * r;
         }
         const double beta = sqrt(block_sum(part, red));
@@ -270,12 +272,13 @@ __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M) {
         if (!done) {
             const double ib = 1.0 / beta;
             for (int e = tid; e < M; e += 1024) {
-                const double v = b.V[e] * ib;
+                const double v = ws[e] * ib;
+                ws[e] = v;
                 b.V[e] = v;
                 b.xcur[e] = v;
             }
             __syncthreads();
-            for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(b.xcur, M, p.taps, e);
+            for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(ws, M, p.taps, e);
         }
         if (tid == 0) {
             st->r0 = r0;
@@ -307,37 +310,55 @@ __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M) {
         sn_s[tid] = b.sn[tid];
     }
     if (tid <= j) col[tid] = 0.0;
+    for (int e = tid; e < M; e += 1024) ws[e] = b.w[e];
+    __syncthreads();
     for (int pass = 0; pass < 2; ++pass) {
-        for (int i = wave; i <= j; i += 16) {
-            const double* Vi = b.V + (size_t)i * M;
-            double d = 0.0;
+        // dot products with V_0..V_j: wave w takes i = w, w+16, w+32, w+48 at once
+        {
+            double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 4
-            for (int e = lane; e < M; e += 64) d += Vi[e] * b.w[e];
+            for (int e = lane; e < M; e += 64) {
+                const double we = ws[e];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) d += __shfl_xor(d, off, 64);
-            if (lane == 0) hs[i] = d;
+                for (int q = 0; q < 4; ++q) {
+                    const int i = wave + 16 * q;
+                    if (i <= j) d[q] += b.V[(size_t)i * M + e] * we;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                double v = d[q];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+                const int i = wave + 16 * q;
+                if (lane == 0 && i <= j) hs[i] = v;
+            }
         }
         __syncthreads();
         for (int e = tid; e < M; e += 1024) {
-            double a = b.w[e];
-            for (int i0 = 0; i0 <= j; i0 += 8) {
-                double v[8];
+            double a = ws[e];
+            for (int i0 = 0; i0 <= j; i0 += 16) {
+                double v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+                for (int u = 0; u < 16; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
+                for (int u = 0; u < 16; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
             }
-            b.w[e] = a;
+            ws[e] = a;
         }
         if (tid <= j) col[tid] += hs[tid];
         __syncthreads();
     }
     double part = 0.0;
-    for (int e = tid; e < M; e += 1024) part += b.w[e] * b.w[e];
+    for (int e = tid; e < M; e += 1024) part += ws[e] * ws[e];
     const double hn = sqrt(block_sum(part, red));
     const double ihn = hn > 0.0 ? 1.0 / hn : 0.0;
     double* Vn = b.V + (size_t)(j + 1) * M;
-    for (int e = tid; e < M; e += 1024) Vn[e] = b.w[e] * ihn;
+    for (int e = tid; e < M; e += 1024) {
+        const double v = ws[e] * ihn;
+        ws[e] = v;
+        Vn[e] = v;
+    }
     if (tid == 0) {
         // previous rotations, carried in registers down the column
         double a = col[0];
@@ -385,27 +406,25 @@ __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M) {
                 ys[i] = a / Hs[i * (m + 1) + i];
             }
         }
-    }
-    __syncthreads();
-    if (s_end) {
-        const int jn = j + 1;
+        __syncthreads();
         for (int e = tid; e < M; e += 1024) {
             double a = b.phi[e];
-            for (int i0 = 0; i0 < jn; i0 += 8) {
-                double v[8];
+            for (int i0 = 0; i0 < jn; i0 += 16) {
+                double v[16];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+                for (int u = 0; u < 16; ++u) v[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) a += (i0 + u < jn ? ys[i0 + u] : 0.0) * v[u];
+                for (int u = 0; u < 16; ++u) a += (i0 + u < jn ? ys[i0 + u] : 0.0) * v[u];
             }
             b.phi[e] = a;
             b.xcur[e] = a;
+            ws[e] = a;
         }
     } else {
-        for (int e = tid; e < M; e += 1024) b.xcur[e] = Vn[e];
+        for (int e = tid; e < M; e += 1024) b.xcur[e] = ws[e];
     }
     __syncthreads();
-    for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(b.xcur, M, p.taps, e);
+    for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(ws, M, p.taps, e);
 }
 
 // ---------------------------------------------------------------- sparse fast solve, one round of W modes
@@ -436,7 +455,8 @@ __device__ __forceinline__ ModesLds modes_lds(double* smem, int Nmax, int Mmax) 
 // Sine modes l = base + wave + 1 (<= n), one per wave: the sparse sine sums of
 // the corrected right-hand side along y (lane L owns whole columns; its
 // irregular nodes sit at slots t*64 + L of the interleaved table, staged
-// through LDS in double-buffered chunks so all waves share one read), the
+// through LDS in double-buffered chunks so all waves share one read, with the
+// global loads issued kDepth chunks ahead), the
 // tridiagonal solve along x, and the weighted six-point gather at every
 // sample.  Calls emit(cp, s) for the samples cp = tid, tid + 64 W, ... with the
 // sum over the round's modes.  Must be called by the whole workgroup; L.sq must
@@ -457,36 +477,67 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
 #pragma unroll
     for (int c = 0; c < C; ++c) x[lane * (C + 1) + 1 + c] = 0.0;
     if (lane == 0) x[0] = 0.0;
-    for (int e = tid; e < kChunk; e += W * 64) {
-        bcv[e] = corr[e];
-        bij[e] = p.il_ij[e];
-    }
+    // Staging pipeline: chunk c of the table travels global -> registers (slot
+    // c % kDepth, issued kDepth iterations before it is needed) -> LDS buffer
+    // c & 1 (written one iteration before it is read), so the global latency
+    // overlaps the sums of the chunks in between.
+    constexpr int NT = W * 64;
+    constexpr int E = (kChunk + NT - 1) / NT;           // table entries per thread per chunk
+    int rij[kDepth][E];
+    double rcv[kDepth][E];
+    auto gload = [&](int slot, int ch) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int e = tid + q * NT;
+            if (ch < nch && e < kChunk) {
+                rij[slot][q] = p.il_ij[(size_t)ch * kChunk + e];
+                rcv[slot][q] = corr[(size_t)ch * kChunk + e];
+            }
+        }
+    };
+    auto lstore = [&](int slot, int buf) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int e = tid + q * NT;
+            if (e < kChunk) {
+                bij[buf * kChunk + e] = rij[slot][q];
+                bcv[buf * kChunk + e] = rcv[slot][q];
+            }
+        }
+    };
+#pragma unroll
+    for (int d = 0; d < kDepth; ++d) gload(d, d);
+    lstore(0, 0);
+    gload(0, kDepth);
     __syncthreads();
     double run = 0.0;
-    for (int ch = 0; ch < nch; ++ch) {
-        const int cur = ch & 1;
-        if (ch + 1 < nch) {
-            const int nxt = (ch + 1) * kChunk;
-            for (int e = tid; e < kChunk; e += W * 64) {
-                bcv[(1 - cur) * kChunk + e] = corr[nxt + e];
-                bij[(1 - cur) * kChunk + e] = p.il_ij[nxt + e];
-            }
-        }
-        if (active) {
+    for (int ch0 = 0; ch0 < nch; ch0 += kDepth) {
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int pk = bij[cur * kChunk + s * 64 + lane];
-                const double cv = bcv[cur * kChunk + s * 64 + lane];
-                const int j = pk & 0xfff;
-                run += cv * sinpi_n(sq, (j * l) & mask2, N);
-                if (pk < 0) {                           // last node of its column
-                    const int i = (pk >> 16) & 0xfff;
-                    x[i + (i - 1) / C] = run;
-                    run = 0.0;
+        for (int d = 0; d < kDepth; ++d) {
+            const int ch = ch0 + d;
+            if (ch < nch) {
+                const int cur = ch & 1;
+                if (ch + 1 < nch) {
+                    lstore((d + 1) % kDepth, 1 - cur);
+                    gload((d + 1) % kDepth, ch + 1 + kDepth);
                 }
+                if (active) {
+#pragma unroll
+                    for (int s = 0; s < kSlots; ++s) {
+                        const int pk = bij[cur * kChunk + s * 64 + lane];
+                        const double cv = bcv[cur * kChunk + s * 64 + lane];
+                        const int j = pk & 0xfff;
+                        run += cv * sinpi_n(sq, (j * l) & mask2, N);
+                        if (pk < 0) {                   // last node of its column
+                            const int i = (pk >> 16) & 0xfff;
+                            x[i + (i - 1) / C] = run;
+                            run = 0.0;
+                        }
+                    }
+                }
+                __syncthreads();
             }
         }
-        __syncthreads();
     }
     if (active) {
         double e[C];
@@ -516,7 +567,7 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
             const double sm = sinpi_n(sq, ((j0 - 1) * lq) & mask2, N);
             const double xc = xq[i0 + (i0 - 1) / C];
             const double xe = xq[i0 + i0 / C + 1];
-            const double xw = xq[i0 - 1 + (i0 - 2) / C];
+            const double xw = i0 > 1 ? xq[i0 - 1 + (i0 - 2) / C] : 0.0;   // node 0 is on the box: zero
             const double xd = sx > 0 ? xe : xw;
             s += s0 * (w0 * xc + wE * xe + wW * xw) + sp * wN * xc + sm * wS * xc + (syp ? sp : sm) * wD * xd;
         }

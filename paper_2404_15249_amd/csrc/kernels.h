@@ -57,7 +57,9 @@ struct DevPlan {
 constexpr int kSplineK = 30;
 constexpr int kSlots = 4;          // table slots per LDS chunk of the sparse sine sums
 constexpr int kChunk = kSlots * 64;
-constexpr int kMaxRestart = 64;   // GMRES restart length cap (LDS-resident Hessenberg)
+constexpr int kDepth = 4;          // table chunks in flight (global loads issued ahead of use)
+constexpr int kMaxRestart = 64;
+constexpr int kMaxSamples = 12288; // boundary samples per problem (the GMRES step keeps one M-vector in LDS)   // GMRES restart length cap (LDS-resident Hessenberg)
 
 // Source of the interface jumps: either computed from densities on the
 // spline (phi, fgam may be null) or given directly (jq / jz, 6 per point).
@@ -109,8 +111,26 @@ hipError_t launch_reduce_interp(const DevPlan& p, JumpSrc js, const double* part
                                 const int* skip, hipStream_t s);
 hipError_t launch_interp_grid(const DevPlan& p, JumpSrc js, const double* R, double* out, hipStream_t s);
 hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double* R, hipStream_t s);
-hipError_t launch_sine_gemm(const DevPlan& p, const double* B, double* Cm, double alpha, hipStream_t s);
+// column sine transforms (dst.hip): FP64, and FP32 arithmetic reading an FP64
+// grid into FP32 storage or reading FP32 storage into an FP64 grid (written or
+// accumulated)
+// B: columns per workgroup (4, 8 or 16; see dst_tile_ok)
+hipError_t launch_dst_cols(const DevPlan& p, const double* in, double* out, double alpha, bool acc, int B,
+                           hipStream_t s);
+hipError_t launch_dst_cols_f32(const DevPlan& p, const double* in, float* out, double alpha, int B, hipStream_t s);
+hipError_t launch_dst_cols_f32_to64(const DevPlan& p, const float* in, double* out, double alpha, bool acc, int B,
+                                    hipStream_t s);
+// LDS of a column-transform workgroup with B columns whose complex pairs take
+// cpx_bytes each; whether B is a valid tile for N within lds_max; the largest
+// valid tile (0 if none).
+size_t dst_lds_bytes(int N, int B, size_t cpx_bytes);
+bool dst_tile_ok(int N, int B, size_t cpx_bytes, size_t lds_max);
+int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max);
+// tridiagonal solves along x of every sine mode (FP64 arithmetic; FP64 or FP32 storage)
 hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s);
+hipError_t launch_rows_solve_f32(const DevPlan& p, float* A, hipStream_t s);
+// R <- R - (L_h - kappa) V on the interior nodes (FP64): the refinement residual
+hipError_t launch_residual(const DevPlan& p, const double* V, double* R, hipStream_t s);
 hipError_t launch_grid_out(const DevPlan& p, const double* V, bool mask, double* u, hipStream_t s);
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z,
                         hipStream_t s);

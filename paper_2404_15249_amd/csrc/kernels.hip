@@ -21,8 +21,9 @@
 // k_spline precomputes the spline second derivatives of the density (inside the
 // GMRES step kernel when the apply runs inside GMRES).
 // The dense solve (volume potential, final solution) uses the same tridiagonal
-// solver on full rows, with the sine expansions along y done as products with
-// the sine matrix (k_sine_gemm).
+// solver on full rows (k_rows_solve), between two column sine transforms
+// (dst.hip); in the FP32 mode the transforms and the stored rows are FP32 and
+// k_residual forms the FP64 residual of the refinement step.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -115,67 +116,36 @@ __global__ __launch_bounds__(256) void k_fill_rhs(DevPlan p, const double* __res
     R[idx] = v;
 }
 
-// C = alpha S B with S[l][j] = sin(pi (l+1)(j+1) / N): the sine expansion along
-// y of every column at once (both the forward and the inverse transform).
-// 64 x 64 output tile per workgroup, 4 x 4 outputs per thread, k-tiles of 16.
-__global__ __launch_bounds__(256) void k_sine_gemm(int N, const double* __restrict__ sinq,
-                                                   const double* __restrict__ B, double* __restrict__ Cm,
-                                                   double alpha) {
-    __shared__ double sq[2050];
-    __shared__ double As[16][65];
-    __shared__ double Bs[16][64];
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    const int row0 = blockIdx.y * 64, col0 = blockIdx.x * 64;
-    const int mask2 = 2 * N - 1;
-    for (int k = tid; k <= N / 2; k += 256) sq[k] = sinq[k];
-    __syncthreads();
-    double c[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) c[a][b] = 0.0;
-    for (int k0 = 0; k0 < N; k0 += 16) {
-        for (int t = tid; t < 1024; t += 256) {
-            const int rr = t & 63, kk = t >> 6;
-            As[kk][rr] = sinpi_n(sq, ((row0 + rr + 1) * (k0 + kk + 1)) & mask2, N);
-            const int kb = t >> 6, cc = t & 63;
-            Bs[kb][cc] = B[(size_t)(k0 + kb) * N + col0 + cc];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            double a[4], b[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[q] = As[kk][ty + 16 * q];
-                b[q] = Bs[kk][tx + 16 * q];
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) c[q][r] = fma(a[q], b[r], c[q][r]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Cm[(size_t)(row0 + ty + 16 * q) * N + col0 + tx + 16 * r] = alpha * c[q][r];
-}
-
-// One wavefront per sine mode l (row l-1 of A): the tridiagonal solve along x.
-template <int C>
-__global__ __launch_bounds__(256) void k_rows_solve(DevPlan p, double* __restrict__ A) {
+// One wavefront per sine mode l (row l-1 of A): the tridiagonal solve along x,
+// in FP64 whatever the storage type T.
+template <int C, class T>
+__global__ __launch_bounds__(256) void k_rows_solve(DevPlan p, T* __restrict__ A) {
     const int lane = threadIdx.x & 63;
     const int l = blockIdx.x * 4 + (threadIdx.x >> 6) + 1;
     if (l > p.n) return;
-    double* row = A + (size_t)(l - 1) * p.N;
+    T* row = A + (size_t)(l - 1) * p.N;
     double e[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) e[c] = row[lane * C + c] * p.h2;
+    for (int c = 0; c < C; ++c) e[c] = (double)row[lane * C + c] * p.h2;
     mode_solve<C>(e, p.modes[l], lane, p.N);
 #pragma unroll
-    for (int c = 0; c < C; ++c) row[lane * C + c] = e[c];
+    for (int c = 0; c < C; ++c) row[lane * C + c] = (T)e[c];
+}
+
+// R <- R - ((V_E + V_W + V_N + V_S - 4 V) / h^2 - kappa V) at the interior nodes
+// (V = 0 on the box), both in the padded interior layout.
+__global__ __launch_bounds__(256) void k_residual(DevPlan p, const double* __restrict__ V, double* __restrict__ R) {
+    const int N = p.N;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)N * N) return;
+    const int i = (int)(idx % N) + 1, j = (int)(idx / N) + 1;
+    if (i >= N || j >= N) return;
+    const double v = V[idx];
+    const double vw = i > 1 ? V[idx - 1] : 0.0;
+    const double ve = i < N - 1 ? V[idx + 1] : 0.0;
+    const double vs = j > 1 ? V[idx - N] : 0.0;
+    const double vn = j < N - 1 ? V[idx + N] : 0.0;
+    R[idx] -= (vw + ve + vs + vn - 4.0 * v) * p.inv_h2 - p.kappa * v;
 }
 
 __global__ __launch_bounds__(256) void k_grid_out(DevPlan p, const double* __restrict__ R, int mask,
@@ -198,7 +168,10 @@ __global__ __launch_bounds__(256) void k_axpby(int n, double a, const double* __
 
 // ---------------------------------------------------------------- GMRES step (Alg. 5)
 
-__global__ __launch_bounds__(1024) void k_gmres(DevPlan p, GmresBufs b, int M) { gmres_step(p, b, M); }
+__global__ __launch_bounds__(1024) void k_gmres(DevPlan p, GmresBufs b, int M) {
+    extern __shared__ double smem[];
+    gmres_step(p, b, M, smem);
+}
 
 
 template <int C>
@@ -226,10 +199,24 @@ hipError_t modes_dispatch_w(const DevPlan& p, const double* corr, double* partia
     return hipGetLastError();
 }
 
-template <int C>
-hipError_t rows_dispatch(const DevPlan& p, double* A, hipStream_t s) {
-    k_rows_solve<C><<<(p.n + 3) / 4, 256, 0, s>>>(p, A);
+template <int C, class T>
+hipError_t rows_dispatch(const DevPlan& p, T* A, hipStream_t s) {
+    k_rows_solve<C, T><<<(p.n + 3) / 4, 256, 0, s>>>(p, A);
     return hipGetLastError();
+}
+
+template <class T>
+hipError_t rows_solve_any(const DevPlan& p, T* A, hipStream_t s) {
+    switch (p.N) {
+        case 64: return rows_dispatch<1>(p, A, s);
+        case 128: return rows_dispatch<2>(p, A, s);
+        case 256: return rows_dispatch<4>(p, A, s);
+        case 512: return rows_dispatch<8>(p, A, s);
+        case 1024: return rows_dispatch<16>(p, A, s);
+        case 2048: return rows_dispatch<32>(p, A, s);
+        case 4096: return rows_dispatch<64>(p, A, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
@@ -283,24 +270,14 @@ hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double*
     return hipGetLastError();
 }
 
-hipError_t launch_sine_gemm(const DevPlan& p, const double* B, double* Cm, double alpha, hipStream_t s) {
-    if (p.N % 64 || p.N > 4096) return hipErrorInvalidValue;
-    dim3 grid(p.N / 64, p.N / 64);
-    k_sine_gemm<<<grid, 256, 0, s>>>(p.N, p.sinq, B, Cm, alpha);
-    return hipGetLastError();
-}
+hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s) { return rows_solve_any(p, A, s); }
 
-hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s) {
-    switch (p.N) {
-        case 64: return rows_dispatch<1>(p, A, s);
-        case 128: return rows_dispatch<2>(p, A, s);
-        case 256: return rows_dispatch<4>(p, A, s);
-        case 512: return rows_dispatch<8>(p, A, s);
-        case 1024: return rows_dispatch<16>(p, A, s);
-        case 2048: return rows_dispatch<32>(p, A, s);
-        case 4096: return rows_dispatch<64>(p, A, s);
-        default: return hipErrorInvalidValue;
-    }
+hipError_t launch_rows_solve_f32(const DevPlan& p, float* A, hipStream_t s) { return rows_solve_any(p, A, s); }
+
+hipError_t launch_residual(const DevPlan& p, const double* V, double* R, hipStream_t s) {
+    const size_t tot = (size_t)p.N * p.N;
+    k_residual<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(p, V, R);
+    return hipGetLastError();
 }
 
 hipError_t launch_grid_out(const DevPlan& p, const double* R, bool mask, double* u, hipStream_t s) {
@@ -316,7 +293,10 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
 }
 
 hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s) {
-    k_gmres<<<1, 1024, 0, s>>>(p, b, p.M);
+    const size_t lds = sizeof(double) * (size_t)p.M;
+    if (hipError_t e = hipFuncSetAttribute((const void*)k_gmres, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
+        return e;
+    k_gmres<<<1, 1024, lds, s>>>(p, b, p.M);
     return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ _lib = ct.CDLL(LIB_PATH)
 OK = 0
 NOT_CONVERGED = 1
 ERR_GEOMETRY = -2
+ERR_BUDGET = -5
 
 
 class KfbiError(RuntimeError):
@@ -38,7 +39,21 @@ class GeometryError(KfbiError):
 class _Desc(ct.Structure):
     _fields_ = [("lo", ct.c_double), ("hi", ct.c_double), ("n", ct.c_int), ("kappa", ct.c_double),
                 ("m", ct.c_int), ("xy", ct.POINTER(ct.c_double)), ("tol", ct.c_double),
-                ("restart", ct.c_int), ("max_iter", ct.c_int)]
+                ("restart", ct.c_int), ("max_iter", ct.c_int), ("precision", ct.c_int),
+                ("refine_steps", ct.c_int)]
+
+FP64 = 0            # KFBI_FP64
+FP32_REFINED = 1    # KFBI_FP32_REFINED
+_PRECISION = {"fp64": FP64, "fp32": FP32_REFINED}
+
+
+class Tiles(ct.Structure):
+    """Launch shapes of a problem's kernels (``kfbi_tiles``)."""
+    _fields_ = [("modes_waves", ct.c_int), ("modes_groups", ct.c_int), ("dst_cols", ct.c_int),
+                ("apply_us", ct.c_double), ("grid_solve_us", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _vp = ct.c_void_p
@@ -60,6 +75,17 @@ _sigs = {
     "kfbi_fast_solve": [_vp, _vp, _vp],
     "kfbi_interface_solve": [_vp, _vp, _vp, _vp, _vp, _vp],
     "kfbi_interface_solve_jumps": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi_batch_create": [_vp, ct.c_int, ct.c_int, ct.c_size_t, ct.POINTER(_vp)],
+    "kfbi_batch_destroy": [_vp],
+    "kfbi_batch_estimate_bytes": [ct.c_int, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)],
+    "kfbi_batch_admit": [_vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int)],
+    "kfbi_batch_step": [_vp, ct.c_int],
+    "kfbi_batch_poll": [_vp, _vp, _vp, _vp],
+    "kfbi_batch_finish": [_vp, ct.c_int, _vp, _vp, _vp],
+    "kfbi_batch_info": [_vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_size_t)],
+    "kfbi_prob_autotune": [_vp, ct.c_int, ct.POINTER(Tiles)],
+    "kfbi_prob_get_tiles": [_vp, ct.POINTER(Tiles)],
+    "kfbi_prob_set_tiles": [_vp, ct.POINTER(Tiles)],
     "kfbi_set_timing": [_vp, ct.c_int],
     "kfbi_apply_timing": [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                           ct.POINTER(ct.c_int)],
@@ -136,12 +162,18 @@ class Problem:
     """One domain on one grid: the geometry plan and the device workspace."""
 
     def __init__(self, ctx: Context, xy, n: int, kappa: float, lo: float = -1.2, hi: float = 1.2,
-                 tol: float = 1e-10, restart: int = 50, max_iter: int = 500):
+                 tol: float = 1e-10, restart: int = 50, max_iter: int = 500, precision: str = "fp64",
+                 refine_steps: int = 1):
+        """``precision``: "fp64", or "fp32" (FP32 grid transforms with ``refine_steps``
+        FP64 residual corrections) for the dense grid solves."""
         self.ctx = ctx
         xy = np.ascontiguousarray(xy, dtype=np.float64).reshape(-1, 2)
         self._xy = xy
+        if precision not in _PRECISION:
+            raise ValueError(f"precision must be one of {sorted(_PRECISION)}")
+        self.precision, self.refine_steps = precision, int(refine_steps)
         d = _Desc(lo, hi, int(n), float(kappa), xy.shape[0], xy.ctypes.data_as(ct.POINTER(ct.c_double)),
-                  float(tol), int(restart), int(max_iter))
+                  float(tol), int(restart), int(max_iter), _PRECISION[precision], int(refine_steps))
         h = _vp()
         _check(_lib.kfbi_prob_create(ctx._h, ct.byref(d), ct.byref(h)))
         self._h = h
@@ -250,6 +282,22 @@ class Problem:
                         allow=(OK, NOT_CONVERGED))
         return phi, it.value, ap.value, rel.value, st == OK
 
+    # ---- launch shapes
+    def autotune(self, reps: int = 10) -> dict:
+        """Time the candidate shapes on this problem and keep the fastest (``kfbi_prob_autotune``)."""
+        t = Tiles()
+        _check(_lib.kfbi_prob_autotune(self._h, int(reps), ct.byref(t)))
+        return t.as_dict()
+
+    def tiles(self) -> dict:
+        t = Tiles()
+        _check(_lib.kfbi_prob_get_tiles(self._h, ct.byref(t)))
+        return t.as_dict()
+
+    def set_tiles(self, modes_waves: int, modes_groups: int, dst_cols: int):
+        t = Tiles(int(modes_waves), int(modes_groups), int(dst_cols), 0.0, 0.0)
+        _check(_lib.kfbi_prob_set_tiles(self._h, ct.byref(t)))
+
     # ---- timing of the three apply stages (HIP events on the context stream)
     def set_timing(self, on: bool):
         _check(_lib.kfbi_set_timing(self._h, 1 if on else 0))
@@ -258,3 +306,77 @@ class Problem:
         a, b, c, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int()
         _check(_lib.kfbi_apply_timing(self._h, ct.byref(a), ct.byref(b), ct.byref(c), ct.byref(n)))
         return {"correct_us": a.value, "modes_us": b.value, "interp_us": c.value, "count": n.value}
+
+
+class Batch:
+    """Many problems advancing through one launch per GMRES stage (``kfbi_batch_*``).
+
+    ``admit`` starts a problem (volume potential + GMRES state), ``step`` runs
+    iterations of every live problem, ``poll`` reports convergence per slot and
+    ``finish`` computes the final solution and frees the slot.  The tensors
+    passed to ``admit`` are kept alive until ``finish``.
+    """
+
+    def __init__(self, ctx: Context, max_slots: int = 32, m_max: int = 8192, hbm_budget: int = 0):
+        self.ctx = ctx
+        self.max_slots = int(max_slots)
+        h = _vp()
+        _check(_lib.kfbi_batch_create(ctx._h, self.max_slots, int(m_max), int(hbm_budget), ct.byref(h)))
+        self._h = h
+        self._held = {}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.kfbi_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @staticmethod
+    def estimate_bytes(n: int, m: int, restart: int = 50) -> int:
+        out = ct.c_size_t()
+        _check(_lib.kfbi_batch_estimate_bytes(int(n), int(m), int(restart), ct.byref(out)))
+        return out.value
+
+    def admit(self, prob: Problem, f_grid, f_gamma, g):
+        """Returns the slot id, or None when no slot or memory is free right now."""
+        slot = ct.c_int(-1)
+        with self.ctx:
+            st = _check(_lib.kfbi_batch_admit(self._h, prob._h, _dptr(f_grid, "f_grid", prob.grid_numel),
+                                              _dptr(f_gamma, "f_gamma", prob.M), _dptr(g, "g", prob.M),
+                                              ct.byref(slot)), allow=(OK, ERR_BUDGET))
+        if st == ERR_BUDGET:
+            return None
+        self._held[slot.value] = (prob, f_grid, f_gamma, g)
+        return slot.value
+
+    def step(self, nsteps: int):
+        with self.ctx:
+            _check(_lib.kfbi_batch_step(self._h, int(nsteps)))
+
+    def poll(self):
+        """``(state, iters, relres)`` per slot: state 1 converged, -1 cap, 0 running, -2 empty."""
+        state = np.zeros(self.max_slots, dtype=np.int32)
+        iters = np.zeros(self.max_slots, dtype=np.int32)
+        rel = np.zeros(self.max_slots)
+        _check(_lib.kfbi_batch_poll(self._h, _vp(state.ctypes.data), _vp(iters.ctypes.data), _vp(rel.ctypes.data)))
+        return state, iters, rel
+
+    def finish(self, slot: int):
+        """Final solve of a slot; returns ``(u_grid, u_gamma, phi, prob)`` and frees the slot."""
+        prob = self._held[slot][0]
+        dev = f"cuda:{self.ctx.device}"
+        u = torch.empty((prob.n + 1, prob.n + 1), dtype=torch.float64, device=dev)
+        ug = torch.empty(prob.M, dtype=torch.float64, device=dev)
+        phi = torch.empty(prob.M, dtype=torch.float64, device=dev)
+        with self.ctx:
+            _check(_lib.kfbi_batch_finish(self._h, int(slot), _dptr(u, "u_grid"), _dptr(ug, "u_gamma"),
+                                          _dptr(phi, "phi")))
+        del self._held[slot]
+        return u, ug, phi, prob
+
+    def info(self):
+        live, nb = ct.c_int(), ct.c_size_t()
+        _check(_lib.kfbi_batch_info(self._h, ct.byref(live), ct.byref(nb)))
+        return live.value, nb.value

@@ -41,38 +41,42 @@ def _star_speed(theta, r0, a, k):
 
 
 def star_points(m: int, r0: float = 0.6, a: float = 0.15, k: int = 5,
-                n_fourier: int = 8192) -> np.ndarray:
+                n_grid: int = 1 << 16) -> np.ndarray:
     """``m`` points of equal arc length on ``r(theta) = r0 + a sin(k theta)``.
 
-    The arc-length function is integrated spectrally (the speed is smooth and
-    periodic, so its Fourier series converges geometrically) and inverted by
+    The speed ``|X'(theta)|`` is smooth and periodic, so its Fourier series
+    gives the arc length in closed form; it is evaluated on a fine uniform
+    grid by one inverse FFT, and each target length is inverted on its grid
+    cell with the cubic Hermite interpolant of (arc length, speed), solved by
     Newton's method.  The first point sits at ``theta = 0``.
     """
-    th = 2.0 * np.pi * np.arange(n_fourier) / n_fourier
+    th = 2.0 * np.pi * np.arange(n_grid) / n_grid
     sp = _star_speed(th, r0, a, k)
-    c = np.fft.rfft(sp) / n_fourier          # speed = c0 + 2 Re sum c_j e^{ij theta}
+    c = np.fft.rfft(sp) / n_grid              # speed = c0 + 2 Re sum_j c_j e^{ij theta}
     c0 = c[0].real
-    jj = np.arange(1, len(c))
-    cj = c[1:]
-    if n_fourier % 2 == 0:
-        cj = cj.copy()
-        cj[-1] *= 0.5                         # Nyquist term counted once
+    d = np.zeros(n_grid // 2 + 1, dtype=complex)
+    j = np.arange(1, n_grid // 2)
+    d[1:n_grid // 2] = c[1:n_grid // 2] / (1j * j)
+    osc = np.fft.irfft(d, n=n_grid) * n_grid   # 2 Re sum_j d_j e^{ij theta}
+    s_g = c0 * th + osc - osc[0]
     perim = 2.0 * np.pi * c0
-
-    def arclen(t):
-        t = np.atleast_1d(t)
-        # integral of 2 Re(c_j e^{i j t}) from 0 to t = 2 Re(c_j (e^{ijt} - 1) / (i j))
-        e = np.exp(1j * np.outer(t, jj))
-        s = 2.0 * np.real(((e - 1.0) / (1j * jj)) @ cj)
-        return c0 * t + s
-
+    s_g = np.append(s_g, perim)
+    sp_g = np.append(sp, sp[0])
+    dth = 2.0 * np.pi / n_grid
     target = perim * np.arange(m) / m
-    t = 2.0 * np.pi * np.arange(m) / m       # initial guess
-    for _ in range(30):
-        f = arclen(t) - target
-        t = t - f / _star_speed(t, r0, a, k)
-        if np.max(np.abs(f)) < 1e-15 * perim:
-            break
+    cell = np.clip(np.searchsorted(s_g, target, side="right") - 1, 0, n_grid - 1)
+    sa, sb = s_g[cell], s_g[cell + 1]
+    da, db = sp_g[cell] * dth, sp_g[cell + 1] * dth
+    u = (target - sa) / (sb - sa)
+    for _ in range(6):
+        # Hermite cubic on the cell and its derivative in u
+        h00, h10, h01, h11 = (2 * u ** 3 - 3 * u ** 2 + 1, u ** 3 - 2 * u ** 2 + u, -2 * u ** 3 + 3 * u ** 2,
+                              u ** 3 - u ** 2)
+        H = h00 * sa + h10 * da + h01 * sb + h11 * db
+        dH = (6 * u ** 2 - 6 * u) * sa + (3 * u ** 2 - 4 * u + 1) * da + (-6 * u ** 2 + 6 * u) * sb + \
+             (3 * u ** 2 - 2 * u) * db
+        u = u - (H - target) / dH
+    t = (cell + u) * dth
     t[0] = 0.0
     r = r0 + a * np.sin(k * t)
     return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
@@ -127,15 +131,19 @@ SIN_COS_X2 = Manufactured(
 )
 
 
-def random_manufactured(rng: np.random.Generator) -> Manufactured:
-    """``u = A sin(w1 x + a) cos(w2 y + b) + B (x^2 - y^2)`` with seeded parameters."""
+def random_manufactured(rng: np.random.Generator, xp=np) -> Manufactured:
+    """``u = A sin(w1 x + a) cos(w2 y + b) + B (x^2 - y^2)`` with seeded parameters.
+
+    ``xp`` is the array module the closed forms are evaluated with (numpy, or
+    torch for inputs generated directly in device memory).
+    """
     A, B = rng.uniform(-1.0, 1.0, size=2)
     w1, w2 = rng.uniform(0.5, np.pi, size=2)
     al, be = rng.uniform(0.0, 2.0 * np.pi, size=2)
     return Manufactured(
         f"{A:.3f} sin({w1:.3f}x+{al:.3f}) cos({w2:.3f}y+{be:.3f}) + {B:.3f}(x^2-y^2)",
-        lambda x, y: A * np.sin(w1 * x + al) * np.cos(w2 * y + be) + B * (x * x - y * y),
-        lambda x, y: -(w1 * w1 + w2 * w2) * A * np.sin(w1 * x + al) * np.cos(w2 * y + be),
+        lambda x, y: A * xp.sin(w1 * x + al) * xp.cos(w2 * y + be) + B * (x * x - y * y),
+        lambda x, y: -(w1 * w1 + w2 * w2) * A * xp.sin(w1 * x + al) * xp.cos(w2 * y + be),
     )
 
 
@@ -211,18 +219,42 @@ def star_problem(n=512, m=None, kappa=1.0, sol=SIN_COS_X2, r0=0.6, a=0.15, k=5) 
                         star_points(m, r0, a, k), n, kappa, sol)
 
 
-def serving_request(seed: int, n: int):
+@dataclasses.dataclass
+class RequestSpec:
+    """Domain and data of one serving request, before any grid array exists."""
+    name: str
+    n: int
+    kappa: float
+    xy: np.ndarray
+    sol: Manufactured           # numpy closed forms
+    sol_torch: Manufactured     # the same closed forms over torch tensors
+
+
+def serving_spec(seed: int, n: int) -> RequestSpec:
     """One request of the mixed serving stream: a random star, kappa and solution."""
-    rng = np.random.default_rng(seed)
-    a = rng.uniform(0.05, 0.2)
-    k = int(rng.integers(3, 9))
-    kappa = rng.uniform(0.0, 10.0)
-    sol = random_manufactured(rng)
+    def draw(xp):
+        rng = np.random.default_rng(seed)
+        a = rng.uniform(0.05, 0.2)
+        k = int(rng.integers(3, 9))
+        kappa = rng.uniform(0.0, 10.0)
+        return a, k, kappa, random_manufactured(rng, xp)
+    a, k, kappa, sol = draw(np)
+    try:
+        import torch
+        sol_t = draw(torch)[3]
+    except ImportError:                        # CPU-only environments
+        sol_t = None
     h = (BOX_HI - BOX_LO) / n
     per = star_perimeter(0.6, a, k)
     m = 64 * int(math.ceil(per / (64 * h)))
-    return make_problem(f"req{seed} star a={a:.3f} k={k} n={n} m={m} kappa={kappa:.3f}",
-                        star_points(m, 0.6, a, k), n, kappa, sol)
+    return RequestSpec(f"req{seed} star a={a:.3f} k={k} n={n} m={m} kappa={kappa:.3f}", n, kappa,
+                       star_points(m, 0.6, a, k), sol, sol_t)
+
+
+def serving_request(seed: int, n: int):
+    """One request of the mixed serving stream as a full host-side Problem."""
+    sp = serving_spec(seed, n)
+    return make_problem(sp.name, sp.xy, n, sp.kappa, sp.sol)
 
 
 def serving_stream(n_requests: int, seed: int = 2404, qps: float = 100.0,

@@ -44,3 +44,39 @@ def test_status_strings():
     lib.kfbi_status_str.restype = ctypes.c_char_p
     assert lib.kfbi_status_str(0) == b"ok"
     assert lib.kfbi_status_str(-2) == b"unsupported geometry"
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the C layout of kfbi_desc and kfbi_tiles."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        import pytest
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "kfbi.h"\n'
+        "#define F(T, m) printf(#T \" \" #m \" %zu\\n\", offsetof(T, m))\n"
+        "int main(void) {\n"
+        '  printf("kfbi_desc size %zu\\n", sizeof(kfbi_desc));\n'
+        "  F(kfbi_desc, lo); F(kfbi_desc, hi); F(kfbi_desc, n); F(kfbi_desc, kappa); F(kfbi_desc, m);\n"
+        "  F(kfbi_desc, xy); F(kfbi_desc, tol); F(kfbi_desc, restart); F(kfbi_desc, max_iter);\n"
+        "  F(kfbi_desc, precision); F(kfbi_desc, refine_steps);\n"
+        '  printf("kfbi_tiles size %zu\\n", sizeof(kfbi_tiles));\n'
+        "  F(kfbi_tiles, modes_waves); F(kfbi_tiles, modes_groups); F(kfbi_tiles, dst_cols);\n"
+        "  F(kfbi_tiles, apply_us); F(kfbi_tiles, grid_solve_us);\n"
+        "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    lines = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    _lib_path()
+    from paper_2404_15249_amd import kfbi
+    structs = {"kfbi_desc": kfbi._Desc, "kfbi_tiles": kfbi.Tiles}
+    for line in filter(None, lines):
+        name, field, value = line.split()
+        st = structs[name]
+        if field == "size":
+            assert ctypes.sizeof(st) == int(value), line
+        else:
+            assert getattr(st, field).offset == int(value), line
