@@ -16,7 +16,7 @@ kernel's average duration (roofline) and the per-stage times come from there.
 
 Also reported, outside the timed region:
   solve     one full Dirichlet solve of the workload (FP64), error vs exact;
-  mixed     the circle r = 0.8, M = 2N, kappa = 1 problem at the same grid:
+  mixed     the circle r = 0.8, M = N, kappa = 1 problem at the same grid:
             full solves with FP64 and with FP32-refined grid solves, their
             times and the L-infinity difference between the two;
   serving   a seeded stream of mixed-size requests through the continuous
@@ -86,18 +86,18 @@ def cpu_baseline(p, seconds: float):
 
 
 def mixed_precision(ctx, n: int) -> dict:
-    """Full solves of the circle problem (r = 0.8, M = 2N, kappa = 1, u = e^x sin y)
+    """Full solves of the circle problem (r = 0.8, M = N, kappa = 1, u = e^x sin y)
     with FP64 and with FP32-refined grid solves."""
     import torch
     import synth
     from paper_2404_15249_amd import kfbi
-    p = synth.circle_problem(n=n, m=2 * n, kappa=1.0)
+    p = synth.circle_problem(n=n, m=n, kappa=1.0)
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
     f, fg, g = dev(p.f_grid), dev(p.f_gamma), dev(p.g)
     c = p.lo + np.arange(p.n + 1) * p.h
     X, Y = np.meshgrid(c, c, indexing="xy")
     exact = p.exact.u(X, Y)
-    res = {"workload": f"circle r=0.8, {n}x{n} grid, M={2 * n}, kappa=1, u=e^x sin y, GMRES tol 1e-12"}
+    res = {"workload": f"circle r=0.8, {n}x{n} grid, M={n}, kappa=1, u=e^x sin y, GMRES tol 1e-12"}
     base = None
     for prec in ("fp64", "fp32"):
         prob = kfbi.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-12, precision=prec, refine_steps=1)
@@ -138,9 +138,14 @@ def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_sc
     ex = GpuExecutor(ctx, max_slots=max_slots, m_max=8192, budget_bytes=0,
                      make_spec=lambda r: synth.serving_spec(r.seed, r.n), tol=1e-10)
     sch = Scheduler(ex, int(budget_gib * (1 << 30)), max_slots, steps_per_poll=8, prepare_workers=8,
-                    prepare_ahead=16)
+                    prepare_ahead=16, keep_results=True)
     recs, span = sch.run(reqs, time_scale=time_scale)
     out = summarize(recs, span)
+    solved = [r for r in recs if not r.rejected]
+    flagged = [r for r in solved if r.result["under_resolved"]]
+    out["under_resolved"] = len(flagged)
+    out["resolved_converged"] = sum(r.converged for r in solved if not r.result["under_resolved"])
+    out["resolved"] = len(solved) - len(flagged)
     out["peak_live"] = sch.peak_live
     out["peak_reserved_gib"] = sch.peak_reserved / (1 << 30)
     ex.batch.close()

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import os
+import re
 import shutil
 import subprocess
 import sys
@@ -34,14 +35,35 @@ def common_flags():
             "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
+def spilling_kernels(remarks: str) -> list:
+    """Kernels whose resource-usage remarks report VGPR spills to scratch memory."""
+    out, name = [], None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            name = m.group(1)
+            continue
+        m = re.search(r"VGPRs Spill: (\d+)", line)
+        if m and name is not None:
+            if int(m.group(1)) > 0:
+                out.append((name, int(m.group(1))))
+            name = None
+    return out
+
+
 def _compile(src: str, build_dir: str) -> str:
     obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + common_flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [hipcc()] + common_flags() + ["-Rpass-analysis=kernel-resource-usage", "-c",
+                                        os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stdout}\n{r.stderr}")
+    # every kernel must keep its registers: a VGPR spill to scratch is a build error
+    spills = spilling_kernels(r.stderr)
+    if spills:
+        raise RuntimeError(f"{src}: kernels spill registers to scratch memory: {spills}")
     return obj
 
 

@@ -5,17 +5,22 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "kfbi.h"
 #include "batch.h"
+#include "graph.h"
 #include "kernels.h"
 #include "plan.h"
 
 using namespace kfbi;
+
+GraphRec*& kfbi::graph_rec() {
+    static thread_local GraphRec* rec = nullptr;
+    return rec;
+}
 
 namespace {
 
@@ -41,11 +46,6 @@ struct kfbi_ctx {
     bool own_stream = false;
     size_t lds_max = 65536;
     int num_cu = 256;
-    // Graphs are captured on a private stream (relaxed mode) under this lock:
-    // nothing else ever enqueues on it, so calls that other host threads make
-    // meanwhile (problem creation, torch work) cannot enter or break a capture.
-    hipStream_t cap_stream = nullptr;
-    std::mutex cap_mu;
 };
 
 struct kfbi_prob {
@@ -66,6 +66,7 @@ struct kfbi_prob {
     double* A = nullptr;         // N N
     int precision = KFBI_FP64, refine = 0;
     float* X32 = nullptr;        // N N: FP32 transform storage (KFBI_FP32_REFINED)
+    double* D = nullptr;         // N N: a refinement correction (refine_steps >= 2)
     int dstB = 8;                // columns per workgroup of the column transforms
     int Gcap = 1;                // workgroups the partial buffer has room for
     double* tmpM = nullptr;      // M
@@ -154,9 +155,10 @@ kfbi_status check_ptr(const void* p, const char* name) {
 }
 
 // Alg. 4 on the full grid: solve (L_h - kappa) V = R (R in the padded interior
-// layout, consumed).  FP64: in place, *V = R.  FP32 with refinement: FP32
-// column transforms around the FP64 row solves into A, then per refine step
-// the FP64 residual (into R) and an FP32 correction accumulated into A; *V = A.
+// layout, consumed).  FP64: in place, *V = R.  FP32 with refinement: an FP32
+// solve (FP32 column transforms around the FP64 row solves) of R into A, then
+// per refine step: R <- R - (L_h - kappa) d for the last correction d (FP64),
+// and the FP32 solve of R as the next correction; *V = A, the sum of them.
 kfbi_status grid_solve(kfbi_prob* p, const double** V) {
     hipStream_t s = p->ctx->stream;
     const double inv = 2.0 / p->N;
@@ -167,11 +169,15 @@ kfbi_status grid_solve(kfbi_prob* p, const double** V) {
         *V = p->R;
         return KFBI_OK;
     }
+    // corrections: the first lands in A; middle ones in D (then added to A while
+    // forming the next residual); the last is accumulated into A directly
     for (int k = 0; k <= p->refine; ++k) {
-        if (k > 0) HIP_TRY(launch_residual(p->dp, p->A, p->R, s));
+        if (k == 1) HIP_TRY(launch_residual(p->dp, p->A, p->R, nullptr, s));
+        if (k >= 2) HIP_TRY(launch_residual(p->dp, p->D, p->R, p->A, s));
         HIP_TRY(launch_dst_cols_f32(p->dp, p->R, p->X32, 1.0, p->dstB, s));
         HIP_TRY(launch_rows_solve_f32(p->dp, p->X32, s));
-        HIP_TRY(launch_dst_cols_f32_to64(p->dp, p->X32, p->A, inv, k > 0, p->dstB, s));
+        const bool middle = k > 0 && k < p->refine;
+        HIP_TRY(launch_dst_cols_f32_to64(p->dp, p->X32, middle ? p->D : p->A, inv, k > 0 && !middle, p->dstB, s));
     }
     *V = p->A;
     return KFBI_OK;
@@ -233,32 +239,32 @@ kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
     return KFBI_OK;
 }
 
-// Capture what `enqueue(stream)` launches into an executable graph, on the
-// context's private capture stream.  Returns false (and leaves *out null) if
-// capture or instantiation fails; the caller then launches directly.
+// Record what `enqueue(stream)` launches as the nodes of a new graph (see
+// graph.h: no stream capture) and instantiate it.  Returns false (and leaves
+// *out null) if recording or instantiation fails; the caller then launches
+// directly.  `enqueue` must issue kernel launches only.
 template <class F>
-bool capture_graph(kfbi_ctx* ctx, hipGraphExec_t* out, F enqueue) {
+bool build_graph(kfbi_ctx* ctx, hipGraphExec_t* out, F enqueue) {
     *out = nullptr;
-    if (!ctx->cap_stream) return false;
-    std::lock_guard<std::mutex> lock(ctx->cap_mu);
-    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    GraphRec rec;
+    if (hipGraphCreate(&rec.graph, 0) != hipSuccess) {
         hipGetLastError();
         return false;
     }
-    const kfbi_status e = enqueue(ctx->cap_stream);
-    hipGraph_t g = nullptr;
-    const hipError_t ee = hipStreamEndCapture(ctx->cap_stream, &g);
-    bool ok = e == KFBI_OK && ee == hipSuccess && g != nullptr &&
-              hipGraphInstantiate(out, g, nullptr, nullptr, 0) == hipSuccess;
+    graph_rec() = &rec;
+    const kfbi_status e = enqueue(ctx->stream);
+    graph_rec() = nullptr;
+    const bool ok = e == KFBI_OK && rec.last != nullptr &&
+                    hipGraphInstantiate(out, rec.graph, nullptr, nullptr, 0) == hipSuccess;
     if (!ok) {
         hipGetLastError();
         *out = nullptr;
     }
-    if (g) hipGraphDestroy(g);
+    hipGraphDestroy(rec.graph);
     return ok;
 }
 
-// Capture kGraphSteps GMRES steps into a graph once per problem.  All launch
+// Record kGraphSteps GMRES steps into a graph once per problem.  All launch
 // arguments are fixed device pointers and the steps read their parameters from
 // the device state, so one graph serves every call.  If capture is not possible
 // the steps are launched directly.
@@ -267,7 +273,7 @@ void ensure_graph(kfbi_prob* p) {
     const bool timing = p->timing;
     p->timing = false;
     p->graph_failed =
-        !capture_graph(p->ctx, &p->gexec, [&](hipStream_t cs) { return enqueue_steps(p, kfbi_prob::kGraphSteps, cs); });
+        !build_graph(p->ctx, &p->gexec, [&](hipStream_t s) { return enqueue_steps(p, kfbi_prob::kGraphSteps, s); });
     p->timing = timing;
 }
 
@@ -355,10 +361,6 @@ kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
         }
         c->own_stream = true;
     }
-    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        hipGetLastError();
-        c->cap_stream = nullptr;                   // no graphs: steps are launched directly
-    }
     *out = c;
     return KFBI_OK;
 }
@@ -366,7 +368,6 @@ kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
 kfbi_status kfbi_ctx_destroy(kfbi_ctx* ctx) {
     if (!ctx) return KFBI_OK;
     if (ctx->own_stream) hipStreamDestroy(ctx->stream);
-    if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return KFBI_OK;
 }
@@ -518,6 +519,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = dev_alloc(p, &p->gm.st, 1)))
         return fail(st);
     if (p->precision == KFBI_FP32_REFINED && (st = dev_alloc(p, &p->X32, (size_t)n * n))) return fail(st);
+    if (p->refine >= 2 && (st = dev_alloc(p, &p->D, (size_t)n * n))) return fail(st);
     // pad slots of the interleaved corrections stay zero for the life of the problem
     HIP_TRY(hipMemset(p->corr_il, 0, sizeof(double) * (size_t)dp.T * 64));
     p->gm.m = m;
@@ -976,8 +978,8 @@ kfbi_status batch_enqueue_steps(kfbi_batch* B, int nsteps, hipStream_t s) {
 
 void batch_ensure_graph(kfbi_batch* B) {
     if (B->gexec || B->graph_failed) return;
-    B->graph_failed = !capture_graph(B->ctx, &B->gexec, [&](hipStream_t cs) {
-        return batch_enqueue_steps(B, kfbi_batch::kGraphSteps, cs);
+    B->graph_failed = !build_graph(B->ctx, &B->gexec, [&](hipStream_t s) {
+        return batch_enqueue_steps(B, kfbi_batch::kGraphSteps, s);
     });
 }
 
@@ -1113,7 +1115,7 @@ kfbi_status kfbi_batch_step(kfbi_batch* B, int nsteps) {
     batch_ensure_graph(B);
     const int K = kfbi_batch::kGraphSteps;
     for (int done = 0; done < nsteps; done += K) {
-        if (B->gexec) {
+        if (B->gexec && nsteps - done >= K) {
             HIP_TRY(hipGraphLaunch(B->gexec, B->ctx->stream));
         } else if (kfbi_status e = batch_enqueue_steps(B, std::min(K, nsteps - done), B->ctx->stream)) {
             return e;

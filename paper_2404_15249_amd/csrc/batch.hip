@@ -9,6 +9,7 @@
 
 #include "batch.h"
 #include "device.h"
+#include "graph.h"
 
 namespace kfbi {
 
@@ -74,14 +75,12 @@ __global__ __launch_bounds__(256) void k_reduce_b(const SlotDev* __restrict__ sl
     }
 }
 
+// One workgroup per live slot (the grid has max_slots workgroups).
 __global__ __launch_bounds__(1024) void k_gmres_b(const SlotDev* __restrict__ slots, BatchWork w) {
     extern __shared__ double smem[];
-    const int n_live = w.counts[3];
-    for (int it = blockIdx.x; it < n_live; it += gridDim.x) {
-        const SlotDev& S = slots[w.live[it]];
-        gmres_step(S.p, S.b, S.p.M, smem);
-        __syncthreads();
-    }
+    if ((int)blockIdx.x >= w.counts[3]) return;
+    const SlotDev& S = slots[w.live[blockIdx.x]];
+    gmres_step<8>(S.p, S.b, S.p.M, smem);        // 8-wide updates: no register spills at 1024 threads
 }
 
 }  // namespace
@@ -92,21 +91,17 @@ size_t modes_b_lds_bytes(int Nmax, int Mmax) {
 }
 
 hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s) {
-    k_correct_b<<<n_cu * 2, 256, 0, s>>>(slots, w);
-    if (hipError_t e = hipGetLastError()) return e;
-    const size_t lds = modes_b_lds_bytes(Nmax, Mmax);
+    const size_t lds = modes_b_lds_bytes(Nmax, Mmax), glds = sizeof(double) * (size_t)Mmax;
     if (hipError_t e = hipFuncSetAttribute((const void*)k_modes_b<kBatchW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds))
         return e;
-    k_modes_b<kBatchW><<<n_cu, kBatchW * 64, lds, s>>>(slots, w, Nmax, Mmax);
-    if (hipError_t e = hipGetLastError()) return e;
-    k_reduce_b<<<n_cu * 2, 256, 0, s>>>(slots, w);
-    if (hipError_t e = hipGetLastError()) return e;
-    const size_t glds = sizeof(double) * (size_t)Mmax;
     if (hipError_t e = hipFuncSetAttribute((const void*)k_gmres_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds))
         return e;
-    k_gmres_b<<<w.max_live, 1024, glds, s>>>(slots, w);
-    return hipGetLastError();
+    if (hipError_t e = klaunch(&k_correct_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
+    if (hipError_t e = klaunch(&k_modes_b<kBatchW>, dim3(n_cu), dim3(kBatchW * 64), lds, s, slots, w, Nmax, Mmax))
+        return e;
+    if (hipError_t e = klaunch(&k_reduce_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
+    return klaunch(&k_gmres_b, dim3(w.max_live), dim3(1024), glds, s, slots, w);
 }
 
 }  // namespace kfbi

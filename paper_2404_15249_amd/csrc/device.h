@@ -244,6 +244,8 @@ __device__ inline void reduce_sample(const DevPlan& p, const JumpSrc& js, const 
 // orthogonalise it (classical Gram-Schmidt applied twice), extend the
 // Hessenberg matrix, update the Givens rotations and the residual estimate;
 // at the end of a cycle solve the small triangular system and update phi.
+// U: basis vectors loaded per batch of the vector updates (register footprint).
+template <int U = 16>
 __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M, double* __restrict__ ws) {
     // ws: M doubles of LDS holding the vector being orthogonalised, then the
     // next K_D input (whose spline is taken from LDS).
@@ -337,12 +339,12 @@ __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M, d
         __syncthreads();
         for (int e = tid; e < M; e += 1024) {
             double a = ws[e];
-            for (int i0 = 0; i0 <= j; i0 += 16) {
-                double v[16];
+            for (int i0 = 0; i0 <= j; i0 += U) {
+                double v[U];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+                for (int u = 0; u < U; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 16; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
+                for (int u = 0; u < U; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
             }
             ws[e] = a;
         }
@@ -409,12 +411,12 @@ __device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M, d
         __syncthreads();
         for (int e = tid; e < M; e += 1024) {
             double a = b.phi[e];
-            for (int i0 = 0; i0 < jn; i0 += 16) {
-                double v[16];
+            for (int i0 = 0; i0 < jn; i0 += U) {
+                double v[U];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) v[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+                for (int u = 0; u < U; ++u) v[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
 #pragma unroll
-                for (int u = 0; u < 16; ++u) a += (i0 + u < jn ? ys[i0 + u] : 0.0) * v[u];
+                for (int u = 0; u < U; ++u) a += (i0 + u < jn ? ys[i0 + u] : 0.0) * v[u];
             }
             b.phi[e] = a;
             b.xcur[e] = a;

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "graph.h"
 #include "kernels.h"
 
 namespace kfbi {
@@ -163,7 +164,7 @@ hipError_t dst_launch(const DevPlan& p, const Tin* in, Tout* out, double alpha, 
     if (hipError_t e = hipFuncSetAttribute((const void*)k_dst_cols<T, Tin, Tout, B>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
         return e;
-    k_dst_cols<T, Tin, Tout, B><<<p.N / B, 256, lds, s>>>(p.N, p.log2N, p.sinq, in, out, alpha, acc ? 1 : 0);
+    if (hipError_t e_ = klaunch(&k_dst_cols<T, Tin, Tout, B>, dim3(p.N / B), dim3(256), lds, s, p.N, p.log2N, p.sinq, in, out, alpha, acc ? 1 : 0)) return e_;
     return hipGetLastError();
 }
 

@@ -129,8 +129,9 @@ int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max);
 // tridiagonal solves along x of every sine mode (FP64 arithmetic; FP64 or FP32 storage)
 hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s);
 hipError_t launch_rows_solve_f32(const DevPlan& p, float* A, hipStream_t s);
-// R <- R - (L_h - kappa) V on the interior nodes (FP64): the refinement residual
-hipError_t launch_residual(const DevPlan& p, const double* V, double* R, hipStream_t s);
+// R <- R - (L_h - kappa) V on the interior nodes (FP64): the refinement
+// residual; with A non-null also A <- A + V (V a correction being applied)
+hipError_t launch_residual(const DevPlan& p, const double* V, double* R, double* A, hipStream_t s);
 hipError_t launch_grid_out(const DevPlan& p, const double* V, bool mask, double* u, hipStream_t s);
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z,
                         hipStream_t s);

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "graph.h"
 #include "kernels.h"
 
 namespace kfbi {
@@ -133,8 +134,9 @@ __global__ __launch_bounds__(256) void k_rows_solve(DevPlan p, T* __restrict__ A
 }
 
 // R <- R - ((V_E + V_W + V_N + V_S - 4 V) / h^2 - kappa V) at the interior nodes
-// (V = 0 on the box), both in the padded interior layout.
-__global__ __launch_bounds__(256) void k_residual(DevPlan p, const double* __restrict__ V, double* __restrict__ R) {
+// (V = 0 on the box), all in the padded interior layout; with A, also A <- A + V.
+__global__ __launch_bounds__(256) void k_residual(DevPlan p, const double* __restrict__ V, double* __restrict__ R,
+                                                  double* __restrict__ A) {
     const int N = p.N;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (size_t)N * N) return;
@@ -146,6 +148,7 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan p, const double* __res
     const double vs = j > 1 ? V[idx - N] : 0.0;
     const double vn = j < N - 1 ? V[idx + N] : 0.0;
     R[idx] -= (vw + ve + vs + vn - 4.0 * v) * p.inv_h2 - p.kappa * v;
+    if (A) A[idx] += v;
 }
 
 __global__ __launch_bounds__(256) void k_grid_out(DevPlan p, const double* __restrict__ R, int mask,
@@ -180,20 +183,24 @@ hipError_t modes_dispatch_w(const DevPlan& p, const double* corr, double* partia
     const size_t lds = modes_lds_bytes(p.N, p.M, W);
     switch (W) {
         case 8:
-            if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            k_modes<C, 8><<<G, 512, lds, s>>>(p, corr, partial, G, skip);
+            if constexpr (C <= 32) {   // at N = 4096 eight mode solutions do not fit the local data share
+                if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
+                if (hipError_t e_ = klaunch(&k_modes<C, 8>, dim3(G), dim3(512), lds, s, p, corr, partial, G, skip)) return e_;
+            } else {
+                return hipErrorInvalidValue;
+            }
             break;
         case 4:
             if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            k_modes<C, 4><<<G, 256, lds, s>>>(p, corr, partial, G, skip);
+            if (hipError_t e_ = klaunch(&k_modes<C, 4>, dim3(G), dim3(256), lds, s, p, corr, partial, G, skip)) return e_;
             break;
         case 2:
             if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            k_modes<C, 2><<<G, 128, lds, s>>>(p, corr, partial, G, skip);
+            if (hipError_t e_ = klaunch(&k_modes<C, 2>, dim3(G), dim3(128), lds, s, p, corr, partial, G, skip)) return e_;
             break;
         default:
             if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            k_modes<C, 1><<<G, 64, lds, s>>>(p, corr, partial, G, skip);
+            if (hipError_t e_ = klaunch(&k_modes<C, 1>, dim3(G), dim3(64), lds, s, p, corr, partial, G, skip)) return e_;
             break;
     }
     return hipGetLastError();
@@ -201,7 +208,7 @@ hipError_t modes_dispatch_w(const DevPlan& p, const double* corr, double* partia
 
 template <int C, class T>
 hipError_t rows_dispatch(const DevPlan& p, T* A, hipStream_t s) {
-    k_rows_solve<C, T><<<(p.n + 3) / 4, 256, 0, s>>>(p, A);
+    if (hipError_t e_ = klaunch(&k_rows_solve<C, T>, dim3((p.n + 3) / 4), dim3(256), 0, s, p, A)) return e_;
     return hipGetLastError();
 }
 
@@ -230,7 +237,7 @@ size_t modes_lds_bytes(int N, int M, int W) {
 hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* corr_il, double* dense,
                           const int* skip, hipStream_t s) {
     if (p.I == 0) return hipSuccess;
-    k_correct<<<(p.I + 255) / 256, 256, 0, s>>>(p, js, corr, corr_il, dense, skip);
+    if (hipError_t e_ = klaunch(&k_correct, dim3((p.I + 255) / 256), dim3(256), 0, s, p, js, corr, corr_il, dense, skip)) return e_;
     return hipGetLastError();
 }
 
@@ -249,24 +256,24 @@ hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, i
 }
 
 hipError_t launch_spline(const DevPlan& p, const double* y, double* s2, const int* skip, hipStream_t s) {
-    k_spline<<<(p.M + 255) / 256, 256, 0, s>>>(p, y, s2, skip);
+    if (hipError_t e_ = klaunch(&k_spline, dim3((p.M + 255) / 256), dim3(256), 0, s, p, y, s2, skip)) return e_;
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_interp(const DevPlan& p, JumpSrc js, const double* partial, int G, double* out,
                                 const int* skip, hipStream_t s) {
-    k_reduce_interp<<<(p.M + 3) / 4, 256, 0, s>>>(p, js, partial, G, out, skip);
+    if (hipError_t e_ = klaunch(&k_reduce_interp, dim3((p.M + 3) / 4), dim3(256), 0, s, p, js, partial, G, out, skip)) return e_;
     return hipGetLastError();
 }
 
 hipError_t launch_interp_grid(const DevPlan& p, JumpSrc js, const double* R, double* out, hipStream_t s) {
-    k_interp_grid<<<(p.M + 255) / 256, 256, 0, s>>>(p, js, R, out);
+    if (hipError_t e_ = klaunch(&k_interp_grid, dim3((p.M + 255) / 256), dim3(256), 0, s, p, js, R, out)) return e_;
     return hipGetLastError();
 }
 
 hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double* R, hipStream_t s) {
     const size_t tot = (size_t)p.N * p.N;
-    k_fill_rhs<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(p, f, mask ? 1 : 0, R);
+    if (hipError_t e_ = klaunch(&k_fill_rhs, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p, f, mask ? 1 : 0, R)) return e_;
     return hipGetLastError();
 }
 
@@ -274,21 +281,21 @@ hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s) { retur
 
 hipError_t launch_rows_solve_f32(const DevPlan& p, float* A, hipStream_t s) { return rows_solve_any(p, A, s); }
 
-hipError_t launch_residual(const DevPlan& p, const double* V, double* R, hipStream_t s) {
+hipError_t launch_residual(const DevPlan& p, const double* V, double* R, double* A, hipStream_t s) {
     const size_t tot = (size_t)p.N * p.N;
-    k_residual<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(p, V, R);
+    if (hipError_t e_ = klaunch(&k_residual, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p, V, R, A)) return e_;
     return hipGetLastError();
 }
 
 hipError_t launch_grid_out(const DevPlan& p, const double* R, bool mask, double* u, hipStream_t s) {
     const size_t tot = (size_t)(p.N + 1) * (p.N + 1);
-    k_grid_out<<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(p, R, mask ? 1 : 0, u);
+    if (hipError_t e_ = klaunch(&k_grid_out, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, p, R, mask ? 1 : 0, u)) return e_;
     return hipGetLastError();
 }
 
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    k_axpby<<<(n + 255) / 256, 256, 0, s>>>(n, a, x, b, y, z);
+    if (hipError_t e_ = klaunch(&k_axpby, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, b, y, z)) return e_;
     return hipGetLastError();
 }
 
@@ -296,7 +303,7 @@ hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s) {
     const size_t lds = sizeof(double) * (size_t)p.M;
     if (hipError_t e = hipFuncSetAttribute((const void*)k_gmres, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
         return e;
-    k_gmres<<<1, 1024, lds, s>>>(p, b, p.M);
+    if (hipError_t e_ = klaunch(&k_gmres, dim3(1), dim3(1024), lds, s, p, b, p.M)) return e_;
     return hipGetLastError();
 }
 

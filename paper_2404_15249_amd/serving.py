@@ -46,6 +46,7 @@ class Record:
     relres: float
     converged: bool
     result: object = None
+    rejected: str = ""           # why the request was refused before admission (e.g. its geometry)
 
     @property
     def latency(self) -> float:
@@ -53,16 +54,19 @@ class Record:
 
 
 def summarize(records, makespan: float) -> dict:
-    lat = np.array([r.latency for r in records]) if records else np.zeros(1)
+    """Throughput and latency over the solved requests (refused ones are counted apart)."""
+    solved = [r for r in records if not r.rejected]
+    lat = np.array([r.latency for r in solved]) if solved else np.zeros(1)
     return {
-        "completed": len(records),
+        "completed": len(solved),
+        "rejected": len(records) - len(solved),
         "makespan_s": makespan,
-        "solves_per_s": len(records) / makespan if makespan > 0 else 0.0,
+        "solves_per_s": len(solved) / makespan if makespan > 0 else 0.0,
         "p50_ms": 1e3 * float(np.percentile(lat, 50)),
         "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "mean_ms": 1e3 * float(lat.mean()),
-        "converged": int(sum(r.converged for r in records)),
-        "mean_iters": float(np.mean([r.iters for r in records])) if records else 0.0,
+        "converged": int(sum(r.converged for r in solved)),
+        "mean_iters": float(np.mean([r.iters for r in solved])) if solved else 0.0,
     }
 
 
@@ -113,12 +117,19 @@ class Scheduler:
                     r = pending.popleft()
                     self.reserved += nb
                     self.peak_reserved = max(self.peak_reserved, self.reserved)
-                    fut = pool.submit(self.ex.prepare, r) if pool else _Done(self.ex.prepare(r))
+                    fut = pool.submit(self.ex.prepare, r) if pool else _Done.call(self.ex.prepare, r)
                     preparing.append((r, nb, fut))
                 # admit prepared requests in arrival order
                 while preparing and preparing[0][2].done():
                     r, nb, fut = preparing.popleft()
-                    handle = fut.result()
+                    try:
+                        handle = fut.result()
+                    except getattr(self.ex, "request_errors", ()) as e:   # e.g. an unsupported geometry
+                        self.reserved -= nb
+                        t = clock() - t0
+                        records.append(Record(r.rid, r.n, r.arrival * time_scale, t, t, 0, float("nan"), False,
+                                              None, rejected=str(e)))
+                        continue
                     slot = self.ex.admit(handle)
                     if slot is None:                  # cannot happen while slots are counted here
                         raise RuntimeError("executor refused an admission the scheduler had room for")
@@ -137,7 +148,7 @@ class Scheduler:
                         records.append(Record(r.rid, r.n, r.arrival * time_scale, t_adm, clock() - t0, it, rel,
                                               st == 1, res if self.keep_results else None))
                 elif preparing:
-                    preparing[0][2].result()
+                    cf.wait([preparing[0][2]])
                 elif nxt < len(reqs):
                     sleep(max(0.0, reqs[nxt].arrival * time_scale - (clock() - t0)))
         finally:
@@ -146,19 +157,24 @@ class Scheduler:
         return records, clock() - t0
 
 
-class _Done:
-    def __init__(self, v):
-        self.v = v
+class _Done(cf.Future):
+    """An already finished future (preparation without a thread pool)."""
 
-    def done(self):
-        return True
-
-    def result(self):
-        return self.v
+    @classmethod
+    def call(cls, fn, *args):
+        f = cls()
+        try:
+            f.set_result(fn(*args))
+        except Exception as e:       # delivered by result(), as from a pool
+            f.set_exception(e)
+        return f
 
 
 class GpuExecutor:
     """Runs requests through one :class:`kfbi.Batch` on the GPU.
+
+    Requests whose geometry the plan builder rejects are reported to the
+    scheduler as refused (``request_errors``).
 
     ``make_spec(request)`` returns a ``synth.RequestSpec``-like object (``n``,
     ``kappa``, ``xy``, ``sol_torch``); the right-hand sides are evaluated
@@ -177,6 +193,7 @@ class GpuExecutor:
         self.tol, self.restart = tol, restart
         self.check_error = check_error
         self._m_cache = {}
+        self.request_errors = (kfbi.GeometryError,)
 
     def estimate(self, r) -> int:
         if r.rid not in self._m_cache:
@@ -213,7 +230,7 @@ class GpuExecutor:
     def finish(self, slot, hd):
         u, ug, phi, prob = self.batch.finish(slot)
         if not self.check_error:
-            return None
+            return {"under_resolved": bool(getattr(hd["spec"], "under_resolved", False))}
         torch = self.torch
         sp = hd["spec"]
         dev = u.device
@@ -222,7 +239,8 @@ class GpuExecutor:
         Y, X = torch.meshgrid(c, c, indexing="ij")
         mask = torch.as_tensor(prob.mask(), device=dev)
         err = torch.where(mask, (u - sp.sol_torch.u(X, Y)).abs(), torch.zeros_like(u)).max()
-        return {"linf_err": float(err), "u": u, "u_gamma": ug, "phi": phi}
+        return {"linf_err": float(err), "u": u, "u_gamma": ug, "phi": phi,
+                "under_resolved": bool(getattr(sp, "under_resolved", False))}
 
     def release(self, hd):
         hd["prob"].close()

@@ -228,6 +228,12 @@ class RequestSpec:
     xy: np.ndarray
     sol: Manufactured           # numpy closed forms
     sol_torch: Manufactured     # the same closed forms over torch tensors
+    min_radius: float = float("inf")   # smallest radius of curvature of the boundary
+
+    @property
+    def under_resolved(self) -> bool:
+        """Boundary features finer than three grid spacings (served, but flagged)."""
+        return self.min_radius < 3.0 * (BOX_HI - BOX_LO) / self.n
 
 
 def serving_spec(seed: int, n: int) -> RequestSpec:
@@ -244,11 +250,12 @@ def serving_spec(seed: int, n: int) -> RequestSpec:
         sol_t = draw(torch)[3]
     except ImportError:                        # CPU-only environments
         sol_t = None
+    # samples about two grid spacings apart along the boundary, in multiples of 64
     h = (BOX_HI - BOX_LO) / n
     per = star_perimeter(0.6, a, k)
-    m = 64 * int(math.ceil(per / (64 * h)))
+    m = 64 * int(math.ceil(per / (128 * h)))
     return RequestSpec(f"req{seed} star a={a:.3f} k={k} n={n} m={m} kappa={kappa:.3f}", n, kappa,
-                       star_points(m, 0.6, a, k), sol, sol_t)
+                       star_points(m, 0.6, a, k), sol, sol_t, star_min_radius_of_curvature(0.6, a, k))
 
 
 def serving_request(seed: int, n: int):

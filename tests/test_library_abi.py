@@ -80,3 +80,14 @@ def test_struct_layouts_match_the_header(tmp_path):
             assert ctypes.sizeof(st) == int(value), line
         else:
             assert getattr(st, field).offset == int(value), line
+
+
+def test_build_flags_register_spills():
+    """The build's spill check reads the compiler's resource-usage remarks."""
+    from paper_2404_15249_amd.build import spilling_kernels
+    text = ("a.hip:1:1: remark: Function Name: k_one [-Rpass]\n"
+            "a.hip:1:1: remark:     VGPRs Spill: 0 [-Rpass]\n"
+            "a.hip:9:1: remark: Function Name: k_two [-Rpass]\n"
+            "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 48 [-Rpass]\n"
+            "a.hip:9:1: remark:     VGPRs Spill: 10 [-Rpass]\n")
+    assert spilling_kernels(text) == [("k_two", 10)]

@@ -111,3 +111,34 @@ def test_scheduler_with_thread_pool():
     reqs = stream(50, qps=2000.0, seed=3)
     recs, _ = Scheduler(ex, 10 ** 12, 8, prepare_workers=3).run(reqs, clock=clock, sleep=clock.sleep)
     assert len(recs) == 50
+
+
+class RefusingExecutor(FakeExecutor):
+    """Preparation fails for every third request (as for an unsupported geometry)."""
+
+    class Refused(Exception):
+        pass
+
+    request_errors = (Refused,)
+
+    def prepare(self, r):
+        if r.rid % 3 == 0:
+            raise self.Refused(f"request {r.rid}: edge crossed twice")
+        return super().prepare(r)
+
+
+@pytest.mark.parametrize("workers", [0, 2])
+def test_refused_requests_are_recorded_and_release_their_memory(workers):
+    clock = FakeClock()
+    ex = RefusingExecutor(clock)
+    reqs = stream(60, qps=300.0)
+    budget = 3 * 256 * 256 * 100 + 1
+    sch = Scheduler(ex, budget, 4, steps_per_poll=4, prepare_workers=workers)
+    recs, span = sch.run(reqs, clock=clock, sleep=clock.sleep)
+    assert len(recs) == len(reqs)
+    refused = [r for r in recs if r.rejected]
+    assert sorted(r.rid for r in refused) == [r.rid for r in reqs if r.rid % 3 == 0]
+    assert sch.reserved == 0                                  # every reservation was returned
+    s = summarize(recs, span)
+    assert s["rejected"] == len(refused) and s["completed"] == len(reqs) - len(refused)
+    assert all(r.converged for r in recs if not r.rejected)
