@@ -11,6 +11,7 @@
 
 #include "kfbi.h"
 #include "batch.h"
+#include "gmres.h"
 #include "graph.h"
 #include "kernels.h"
 #include "plan.h"
@@ -516,13 +517,15 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = dev_alloc(p, &p->gm.sn, m)) || (st = dev_alloc(p, &p->gm.g, m + 1)) ||
         (st = dev_alloc(p, &p->gm.ghat, M)) || (st = dev_alloc(p, &p->gm.phi, M)) ||
         (st = dev_alloc(p, &p->gm.xcur, M)) || (st = dev_alloc(p, &p->gm.w, M)) ||
-        (st = dev_alloc(p, &p->gm.st, 1)))
+        (st = dev_alloc(p, &p->gm.z, M)) || (st = dev_alloc(p, &p->gm.part, gm_part_size(m, gm_chunks(M)))) ||
+        (st = dev_alloc(p, &p->gm.y, m + 1)) || (st = dev_alloc(p, &p->gm.st, 1)))
         return fail(st);
     if (p->precision == KFBI_FP32_REFINED && (st = dev_alloc(p, &p->X32, (size_t)n * n))) return fail(st);
     if (p->refine >= 2 && (st = dev_alloc(p, &p->D, (size_t)n * n))) return fail(st);
     // pad slots of the interleaved corrections stay zero for the life of the problem
     HIP_TRY(hipMemset(p->corr_il, 0, sizeof(double) * (size_t)dp.T * 64));
     p->gm.m = m;
+    p->gm.gc = gm_chunks(M);
     *out = p;
     return KFBI_OK;
 }
@@ -856,11 +859,12 @@ struct kfbi_batch {
     int2* d_corr = nullptr;
     int2* d_mode = nullptr;
     int2* d_cp = nullptr;
+    int2* d_gm = nullptr;
     int* d_live = nullptr;
-    int cap_corr = 0, cap_mode = 0, cap_cp = 0;
-    std::vector<int2> h_corr, h_mode, h_cp;
+    int cap_corr = 0, cap_mode = 0, cap_cp = 0, cap_gm = 0;
+    std::vector<int2> h_corr, h_mode, h_cp, h_gm;
     std::vector<int> h_live;
-    int h_counts[4] = {0, 0, 0, 0};
+    int h_counts[kBatchCounts] = {0, 0, 0, 0, 0};
     // pinned staging of the uploads, reused once the event says the stream has
     // consumed the previous upload
     char* stage = nullptr;
@@ -874,12 +878,13 @@ struct kfbi_batch {
 namespace {
 
 void batch_free_lists(kfbi_batch* B) {
-    for (void* q : {(void*)B->d_corr, (void*)B->d_mode, (void*)B->d_cp})
+    for (void* q : {(void*)B->d_corr, (void*)B->d_mode, (void*)B->d_cp, (void*)B->d_gm})
         if (q) hipFree(q);
     B->d_corr = nullptr;
     B->d_mode = nullptr;
     B->d_cp = nullptr;
-    B->cap_corr = B->cap_mode = B->cap_cp = 0;
+    B->d_gm = nullptr;
+    B->cap_corr = B->cap_mode = B->cap_cp = B->cap_gm = 0;
 }
 
 kfbi_status batch_grow(hipStream_t s, int2** d, int* cap, size_t need) {
@@ -904,6 +909,7 @@ kfbi_status batch_rebuild(kfbi_batch* B) {
     B->h_corr.clear();
     B->h_mode.clear();
     B->h_cp.clear();
+    B->h_gm.clear();
     B->h_live.clear();
     for (int s = 0; s < B->max_slots; ++s) {
         kfbi_prob* p = B->slot[s];
@@ -912,13 +918,15 @@ kfbi_status batch_rebuild(kfbi_batch* B) {
         for (int r = 0; r < p->I; r += 256) B->h_corr.push_back(make_int2(s, r));
         for (int b = 0; b < p->Gs; ++b) B->h_mode.push_back(make_int2(s, b));
         for (int c = 0; c < p->M; c += 4) B->h_cp.push_back(make_int2(s, c));
+        for (int c = 0; c < p->gm.gc; ++c) B->h_gm.push_back(make_int2(s, c));
     }
-    const int2* old[3] = {B->d_corr, B->d_mode, B->d_cp};
+    const int2* old[4] = {B->d_corr, B->d_mode, B->d_cp, B->d_gm};
     hipStream_t gs = B->ctx->stream;
     if (kfbi_status e = batch_grow(gs, &B->d_corr, &B->cap_corr, std::max<size_t>(B->h_corr.size(), 1))) return e;
     if (kfbi_status e = batch_grow(gs, &B->d_mode, &B->cap_mode, std::max<size_t>(B->h_mode.size(), 1))) return e;
     if (kfbi_status e = batch_grow(gs, &B->d_cp, &B->cap_cp, std::max<size_t>(B->h_cp.size(), 1))) return e;
-    if (old[0] != B->d_corr || old[1] != B->d_mode || old[2] != B->d_cp) {
+    if (kfbi_status e = batch_grow(gs, &B->d_gm, &B->cap_gm, std::max<size_t>(B->h_gm.size(), 1))) return e;
+    if (old[0] != B->d_corr || old[1] != B->d_mode || old[2] != B->d_cp || old[3] != B->d_gm) {
         // the captured graph holds the old list addresses
         if (B->gexec) hipGraphExecDestroy(B->gexec);
         B->gexec = nullptr;
@@ -928,8 +936,9 @@ kfbi_status batch_rebuild(kfbi_batch* B) {
     B->h_counts[1] = (int)B->h_mode.size();
     B->h_counts[2] = (int)B->h_cp.size();
     B->h_counts[3] = (int)B->h_live.size();
-    const size_t nb = sizeof(int2) * (B->h_corr.size() + B->h_mode.size() + B->h_cp.size()) +
-                      sizeof(int) * (B->h_live.size() + 4) + sizeof(SlotDev) * B->max_slots;
+    B->h_counts[4] = (int)B->h_gm.size();
+    const size_t nb = sizeof(int2) * (B->h_corr.size() + B->h_mode.size() + B->h_cp.size() + B->h_gm.size()) +
+                      sizeof(int) * (B->h_live.size() + kBatchCounts) + sizeof(SlotDev) * B->max_slots;
     HIP_TRY(hipEventSynchronize(B->up_ev));
     if (nb > B->stage_cap) {
         if (B->stage) hipHostFree(B->stage);
@@ -951,6 +960,7 @@ kfbi_status batch_rebuild(kfbi_batch* B) {
     if ((e = put(B->d_corr, B->h_corr.data(), B->h_corr.size() * sizeof(int2))) ||
         (e = put(B->d_mode, B->h_mode.data(), B->h_mode.size() * sizeof(int2))) ||
         (e = put(B->d_cp, B->h_cp.data(), B->h_cp.size() * sizeof(int2))) ||
+        (e = put(B->d_gm, B->h_gm.data(), B->h_gm.size() * sizeof(int2))) ||
         (e = put(B->d_live, B->h_live.data(), B->h_live.size() * sizeof(int))) ||
         (e = put(B->d_counts, B->h_counts, sizeof B->h_counts)) ||
         (e = put(B->d_slots, B->h_slots.data(), sizeof(SlotDev) * B->max_slots)))
@@ -966,6 +976,7 @@ BatchWork batch_work(const kfbi_batch* B) {
     w.mode_items = B->d_mode;
     w.cp_items = B->d_cp;
     w.live = B->d_live;
+    w.gm_items = B->d_gm;
     w.max_live = B->max_slots;
     return w;
 }
@@ -1002,7 +1013,8 @@ kfbi_status kfbi_batch_estimate_bytes(int n, int m, int restart, size_t* bytes) 
     size_t b = nq * (sizeof(PointGeom) + 4) + (size_t)m * 256 + ni * 80 + slots * 12 +
                (size_t)(n + 1) * (n + 1) + (size_t)n * (sizeof(ModeConst) + 16) + 4096;
     b += 2 * sizeof(double) * (size_t)n * n;                                  // dense-path grids
-    b += sizeof(double) * ((size_t)(restart + 1) * (m + restart) + 16 * (size_t)m);   // GMRES
+    b += sizeof(double) * ((size_t)(restart + 1) * (m + restart) + 16 * (size_t)m +
+                           gm_part_size(restart, gm_chunks(m)) + restart + 1);      // GMRES
     b += sizeof(double) * (size_t)m * 512;                                    // single-path partials
     b += batch_extra_bytes(n, m);
     *bytes = b;
@@ -1026,7 +1038,7 @@ kfbi_status kfbi_batch_create(kfbi_ctx* ctx, int max_slots, int m_max, size_t bu
     B->h_slots.resize(max_slots);
     bool ok = hipEventCreateWithFlags(&B->up_ev, hipEventDisableTiming) == hipSuccess &&
               hipMalloc((void**)&B->d_slots, sizeof(SlotDev) * max_slots) == hipSuccess &&
-              hipMalloc((void**)&B->d_counts, sizeof(int) * 4) == hipSuccess &&
+              hipMalloc((void**)&B->d_counts, sizeof(int) * kBatchCounts) == hipSuccess &&
               hipMalloc((void**)&B->d_live, sizeof(int) * max_slots) == hipSuccess;
     if (!ok) {
         hipGetLastError();

@@ -22,15 +22,17 @@ struct SlotDev {
 
 // Work lists of the batched launches, rebuilt on the host when a slot is
 // admitted or released.  counts = {correction items, mode items, sample items,
-// live slots}; items are (slot, first index) pairs.
+// live slots, GMRES chunk items}; items are (slot, first index) pairs.
 struct BatchWork {
     const int* counts;
     const int2* corr_items;   // blocks of 256 irregular nodes
     const int2* mode_items;   // mode blocks of kBatchW modes
     const int2* cp_items;     // blocks of 4 samples
     const int* live;          // live slot ids
+    const int2* gm_items;     // (slot, chunk) of the GMRES vector launches
     int max_live;
 };
+constexpr int kBatchCounts = 5;
 
 size_t modes_b_lds_bytes(int Nmax, int Mmax);
 hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s);

@@ -9,6 +9,7 @@
 
 #include "batch.h"
 #include "device.h"
+#include "gmres.h"
 #include "graph.h"
 
 namespace kfbi {
@@ -75,12 +76,25 @@ __global__ __launch_bounds__(256) void k_reduce_b(const SlotDev* __restrict__ sl
     }
 }
 
-// One workgroup per live slot (the grid has max_slots workgroups).
-__global__ __launch_bounds__(1024) void k_gmres_b(const SlotDev* __restrict__ slots, BatchWork w) {
-    extern __shared__ double smem[];
+// GMRES (gmres.h): the vector launches walk (slot, chunk) items, the commit
+// launch has one workgroup per live slot (the grid has max_slots workgroups).
+template <int Kind>
+__global__ __launch_bounds__(kGmChunk) void k_gm_vec_b(const SlotDev* __restrict__ slots, BatchWork w) {
+    const int n_items = w.counts[4];
+    for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const int2 item = w.gm_items[it];
+        const SlotDev& S = slots[item.x];
+        if (Kind == 0) gm_dots1(S.b, S.p.M, item.y);
+        if (Kind == 1) gm_update(S.b, S.p.M, item.y, 0);
+        if (Kind == 2) gm_update(S.b, S.p.M, item.y, 1);
+        if (Kind == 3) gm_emit(S.p, S.b, S.p.M, item.y);
+        __syncthreads();                                 // the item's LDS is reused by the next item
+    }
+}
+
+__global__ __launch_bounds__(kGmChunk) void k_gm_commit_b(const SlotDev* __restrict__ slots, BatchWork w) {
     if ((int)blockIdx.x >= w.counts[3]) return;
-    const SlotDev& S = slots[w.live[blockIdx.x]];
-    gmres_step<8>(S.p, S.b, S.p.M, smem);        // 8-wide updates: no register spills at 1024 threads
+    gm_commit(slots[w.live[blockIdx.x]].b);
 }
 
 }  // namespace
@@ -91,17 +105,20 @@ size_t modes_b_lds_bytes(int Nmax, int Mmax) {
 }
 
 hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s) {
-    const size_t lds = modes_b_lds_bytes(Nmax, Mmax), glds = sizeof(double) * (size_t)Mmax;
+    const size_t lds = modes_b_lds_bytes(Nmax, Mmax);
     if (hipError_t e = hipFuncSetAttribute((const void*)k_modes_b<kBatchW>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds))
         return e;
-    if (hipError_t e = hipFuncSetAttribute((const void*)k_gmres_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)glds))
-        return e;
+    const dim3 t(kGmChunk), gv(n_cu);
     if (hipError_t e = klaunch(&k_correct_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_modes_b<kBatchW>, dim3(n_cu), dim3(kBatchW * 64), lds, s, slots, w, Nmax, Mmax))
         return e;
     if (hipError_t e = klaunch(&k_reduce_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
-    return klaunch(&k_gmres_b, dim3(w.max_live), dim3(1024), glds, s, slots, w);
+    if (hipError_t e = klaunch(&k_gm_vec_b<0>, gv, t, 0, s, slots, w)) return e;
+    if (hipError_t e = klaunch(&k_gm_vec_b<1>, gv, t, 0, s, slots, w)) return e;
+    if (hipError_t e = klaunch(&k_gm_vec_b<2>, gv, t, 0, s, slots, w)) return e;
+    if (hipError_t e = klaunch(&k_gm_commit_b, dim3(w.max_live), t, 0, s, slots, w)) return e;
+    return klaunch(&k_gm_vec_b<3>, gv, t, 0, s, slots, w);
 }
 
 }  // namespace kfbi

@@ -238,197 +238,6 @@ __device__ inline void reduce_sample(const DevPlan& p, const JumpSrc& js, const 
     }
 }
 
-// One step of restarted GMRES, driven by a state machine in device memory so
-// that the host only polls for convergence.  Mode 0: b.w holds K_D phi; form
-// the true residual, stop or start a cycle.  Mode 1: b.w holds K_D V_j;
-// orthogonalise it (classical Gram-Schmidt applied twice), extend the
-// Hessenberg matrix, update the Givens rotations and the residual estimate;
-// at the end of a cycle solve the small triangular system and update phi.
-// U: basis vectors loaded per batch of the vector updates (register footprint).
-template <int U = 16>
-__device__ inline void gmres_step(const DevPlan& p, const GmresBufs& b, int M, double* __restrict__ ws) {
-    // ws: M doubles of LDS holding the vector being orthogonalised, then the
-    // next K_D input (whose spline is taken from LDS).
-    __shared__ double red[16];
-    __shared__ double hs[kMaxRestart + 2];
-    __shared__ double ys[kMaxRestart + 2];
-    __shared__ int s_end;
-    GmresState* st = b.st;
-    if (st->converged) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = b.m, mode = st->mode, j = st->j, it = st->it, first = st->first;
-    const double r0_in = st->r0, tol = st->tol;
-    const int max_iter = st->max_iter;
-    __syncthreads();
-    if (mode == 0) {
-        double part = 0.0;
-        for (int e = tid; e < M; e += 1024) {
-            const double r = b.ghat[e] - b.w[e];
-            ws[e] = r;
-            part += r * r;
-        }
-        const double beta = sqrt(block_sum(part, red));
-        const double r0 = first ? beta : r0_in;
-        const double rel = r0 > 0.0 ? beta / r0 : 0.0;
-        const bool done = r0 == 0.0 || beta == 0.0 || rel < tol || it >= max_iter;
-        if (!done) {
-            const double ib = 1.0 / beta;
-            for (int e = tid; e < M; e += 1024) {
-                const double v = ws[e] * ib;
-                ws[e] = v;
-                b.V[e] = v;
-                b.xcur[e] = v;
-            }
-            __syncthreads();
-            for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(ws, M, p.taps, e);
-        }
-        if (tid == 0) {
-            st->r0 = r0;
-            st->first = 0;
-            st->relres = rel;
-            if (done) {
-                st->converged = (r0 == 0.0 || beta == 0.0 || rel < tol) ? 1 : -1;
-                st->mode = 2;
-            } else {
-                b.g[0] = beta;
-                for (int k = 1; k <= m; ++k) b.g[k] = 0.0;
-                st->j = 0;
-                st->mode = 1;
-                st->cycles += 1;
-            }
-        }
-        return;
-    }
-    // mode 1: Arnoldi column j.  The column, the previous rotations and (at the
-    // end of a cycle) the Hessenberg matrix are staged in LDS so the serial
-    // Givens and back-substitution loops never wait on global memory.
-    __shared__ double col[kMaxRestart + 2];
-    __shared__ double cs_s[kMaxRestart], sn_s[kMaxRestart];
-    __shared__ double Hs[kMaxRestart * (kMaxRestart + 1)];
-    __shared__ double s_cs, s_sn;
-    double* Hj = b.H + (size_t)j * (m + 1);
-    if (tid < j) {
-        cs_s[tid] = b.cs[tid];
-        sn_s[tid] = b.sn[tid];
-    }
-    if (tid <= j) col[tid] = 0.0;
-    for (int e = tid; e < M; e += 1024) ws[e] = b.w[e];
-    __syncthreads();
-    for (int pass = 0; pass < 2; ++pass) {
-        // dot products with V_0..V_j: wave w takes i = w, w+16, w+32, w+48 at once
-        {
-            double d[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-            for (int e = lane; e < M; e += 64) {
-                const double we = ws[e];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int i = wave + 16 * q;
-                    if (i <= j) d[q] += b.V[(size_t)i * M + e] * we;
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                double v = d[q];
-#pragma unroll
-                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-                const int i = wave + 16 * q;
-                if (lane == 0 && i <= j) hs[i] = v;
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < M; e += 1024) {
-            double a = ws[e];
-            for (int i0 = 0; i0 <= j; i0 += U) {
-                double v[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
-#pragma unroll
-                for (int u = 0; u < U; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
-            }
-            ws[e] = a;
-        }
-        if (tid <= j) col[tid] += hs[tid];
-        __syncthreads();
-    }
-    double part = 0.0;
-    for (int e = tid; e < M; e += 1024) part += ws[e] * ws[e];
-    const double hn = sqrt(block_sum(part, red));
-    const double ihn = hn > 0.0 ? 1.0 / hn : 0.0;
-    double* Vn = b.V + (size_t)(j + 1) * M;
-    for (int e = tid; e < M; e += 1024) {
-        const double v = ws[e] * ihn;
-        ws[e] = v;
-        Vn[e] = v;
-    }
-    if (tid == 0) {
-        // previous rotations, carried in registers down the column
-        double a = col[0];
-        for (int i = 0; i < j; ++i) {
-            const double c = col[i + 1], cc = cs_s[i], ss = sn_s[i];
-            col[i] = cc * a + ss * c;
-            a = -ss * a + cc * c;
-        }
-        const double den = hypot(a, hn);
-        const double cs = den > 0.0 ? a / den : 1.0;
-        const double sn = den > 0.0 ? hn / den : 0.0;
-        col[j] = den;
-        col[j + 1] = 0.0;
-        s_cs = cs;
-        s_sn = sn;
-        const double gj = b.g[j];
-        b.g[j + 1] = -sn * gj;
-        b.g[j] = cs * gj;
-        const int jn = j + 1, itn = it + 1;
-        const double est = fabs(sn * gj) / r0_in;
-        st->relres = est;
-        st->it = itn;
-        const bool end = est < tol || jn == m || itn >= max_iter || hn == 0.0;
-        s_end = end ? 1 : 0;
-        if (end) st->mode = 0; else st->j = jn;
-    }
-    __syncthreads();
-    if (tid <= j + 1) Hj[tid] = col[tid];
-    if (tid == 0) {
-        b.cs[j] = s_cs;
-        b.sn[j] = s_sn;
-    }
-    if (s_end) {
-        // back substitution H[0:jn, 0:jn] y = g[0:jn] from LDS
-        const int jn = j + 1;
-        for (int t = tid; t < jn * (m + 1); t += 1024) {
-            const int kc = t / (m + 1), i = t % (m + 1);
-            Hs[t] = kc == j ? col[i] : b.H[t];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int i = jn - 1; i >= 0; --i) {
-                double a = b.g[i];
-                for (int kk = i + 1; kk < jn; ++kk) a -= Hs[kk * (m + 1) + i] * ys[kk];
-                ys[i] = a / Hs[i * (m + 1) + i];
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < M; e += 1024) {
-            double a = b.phi[e];
-            for (int i0 = 0; i0 < jn; i0 += U) {
-                double v[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) v[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
-#pragma unroll
-                for (int u = 0; u < U; ++u) a += (i0 + u < jn ? ys[i0 + u] : 0.0) * v[u];
-            }
-            b.phi[e] = a;
-            b.xcur[e] = a;
-            ws[e] = a;
-        }
-    } else {
-        for (int e = tid; e < M; e += 1024) b.xcur[e] = ws[e];
-    }
-    __syncthreads();
-    for (int e = tid; e < M; e += 1024) b.s2cur[e] = spline_s2(ws, M, p.taps, e);
-}
-
 // ---------------------------------------------------------------- sparse fast solve, one round of W modes
 //
 // LDS of the sparse fast solve: the quarter sine table, W padded per-wave mode

@@ -83,7 +83,10 @@ struct GmresState {
     double relres;
     double tol;      // stop when the relative residual drops below tol (<= 0: never)
     int max_iter;    // cap on Arnoldi steps
+    int kind;        // what the last commit left for the emit launch (GmKind in gmres.h)
+    int jn;          // columns of the cycle just finished (kGmCycleEnd)
     int pad;
+    double scale;    // 1/beta (new cycle) or 1/h_{j+1,j} (next vector)
 };
 
 struct GmresBufs {
@@ -97,8 +100,12 @@ struct GmresBufs {
     double* xcur;    // M: input of the next K_D apply
     double* s2cur;   // M: spline second derivatives of xcur
     double* w;       // M: output of the last K_D apply
+    double* z;       // M: the vector being orthogonalised (or the residual)
+    double* part;    // gm_part_size(m, gc): per-chunk partial dots and norms
+    double* y;       // m + 1: solution of the cycle's triangular system
     GmresState* st;  // state machine; also holds tol and max_iter so launches are call independent
     int m;
+    int gc;          // chunks of kGmChunk elements covering the M samples
 };
 
 // launchers (return hipError_t of the launch)

@@ -18,8 +18,8 @@
 //   k_reduce_interp  one wavefront per sample: the partials summed in a fixed
 //              order plus the jump terms of the stencil nodes outside Omega
 //              (Alg. 3).
-// k_spline precomputes the spline second derivatives of the density (inside the
-// GMRES step kernel when the apply runs inside GMRES).
+// k_spline precomputes the spline second derivatives of the density (inside
+// GMRES the emit launch of gmres.h does it for the next input).
 // The dense solve (volume potential, final solution) uses the same tridiagonal
 // solver on full rows (k_rows_solve), between two column sine transforms
 // (dst.hip); in the FP32 mode the transforms and the stored rows are FP32 and
@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device.h"
+#include "gmres.h"
 #include "graph.h"
 #include "kernels.h"
 
@@ -171,10 +172,11 @@ __global__ __launch_bounds__(256) void k_axpby(int n, double a, const double* __
 
 // ---------------------------------------------------------------- GMRES step (Alg. 5)
 
-__global__ __launch_bounds__(1024) void k_gmres(DevPlan p, GmresBufs b, int M) {
-    extern __shared__ double smem[];
-    gmres_step(p, b, M, smem);
-}
+__global__ __launch_bounds__(kGmChunk) void k_gm_dots1(GmresBufs b, int M) { gm_dots1(b, M, blockIdx.x); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 0); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 1); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_commit(GmresBufs b) { gm_commit(b); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_emit(DevPlan p, GmresBufs b) { gm_emit(p, b, p.M, blockIdx.x); }
 
 
 template <int C>
@@ -300,11 +302,12 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
 }
 
 hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s) {
-    const size_t lds = sizeof(double) * (size_t)p.M;
-    if (hipError_t e = hipFuncSetAttribute((const void*)k_gmres, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
-        return e;
-    if (hipError_t e_ = klaunch(&k_gmres, dim3(1), dim3(1024), lds, s, p, b, p.M)) return e_;
-    return hipGetLastError();
+    const dim3 g(b.gc), t(kGmChunk);
+    if (hipError_t e = klaunch(&k_gm_dots1, g, t, 0, s, b, p.M)) return e;
+    if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, p.M)) return e;
+    if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, p.M)) return e;
+    if (hipError_t e = klaunch(&k_gm_commit, dim3(1), t, 0, s, b)) return e;
+    return klaunch(&k_gm_emit, g, t, 0, s, p, b);
 }
 
 }  // namespace kfbi
