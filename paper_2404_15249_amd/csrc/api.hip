@@ -207,7 +207,7 @@ kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, boo
 }
 
 kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, double* out, const int* skip,
-                         hipStream_t s) {
+                         const GmresBufs* gm, hipStream_t s) {
     JumpSrc js{phi, phi_s2, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t* ev = nullptr;
     if (p->timing && p->t_count < kfbi_prob::kMaxTimed) {
@@ -222,7 +222,7 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(launch_modes(p->dp, p->corr_il, p->partial, p->G, p->W, skip, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
-    HIP_TRY(launch_reduce_interp(p->dp, js, p->partial, p->G, out, skip, s));
+    HIP_TRY(launch_reduce_interp(p->dp, js, p->partial, p->G, out, skip, gm, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
     return KFBI_OK;
 }
@@ -234,7 +234,7 @@ kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
     GmresBufs b = p->gm;
     const int* skip = &b.st->converged;
     for (int k = 0; k < nsteps; ++k) {
-        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, s)) return e;
+        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, &p->gm, s)) return e;
         HIP_TRY(launch_gmres_step(p->dp, b, s));
     }
     return KFBI_OK;
@@ -490,7 +490,9 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         for (int r = laneptr[L]; r < laneptr[L + 1]; ++r) {
             const int slot = (r - laneptr[L]) * 64 + L;
             const bool last = r + 1 == laneptr[L + 1] || P.irr_i[r + 1] != P.irr_i[r];
-            il_ij[slot] = (last ? (int)0x80000000u : 0) | (P.irr_i[r] << 16) | P.irr_j[r];
+            // the column's place in a wavefront's padded mode-solution layout
+            const int xpos = P.irr_i[r] + (P.irr_i[r] - 1) / (n / 64);
+            il_ij[slot] = (last ? (int)0x80000000u : 0) | (xpos << 16) | P.irr_j[r];
             il_pos[r] = slot;
         }
     std::vector<int4> cpk(p->M);
@@ -517,15 +519,18 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = dev_alloc(p, &p->gm.sn, m)) || (st = dev_alloc(p, &p->gm.g, m + 1)) ||
         (st = dev_alloc(p, &p->gm.ghat, M)) || (st = dev_alloc(p, &p->gm.phi, M)) ||
         (st = dev_alloc(p, &p->gm.xcur, M)) || (st = dev_alloc(p, &p->gm.w, M)) ||
-        (st = dev_alloc(p, &p->gm.z, M)) || (st = dev_alloc(p, &p->gm.part, gm_part_size(m, gm_chunks(M)))) ||
-        (st = dev_alloc(p, &p->gm.y, m + 1)) || (st = dev_alloc(p, &p->gm.st, 1)))
+        (st = dev_alloc(p, &p->gm.z, M)) || (st = dev_alloc(p, &p->gm.part, gm_part_size(m, gm_chunks(M), gm_chunks64(M)))) ||
+        (st = dev_alloc(p, &p->gm.y, m + 1)) || (st = dev_alloc(p, &p->gm.st, 1)) ||
+        (st = dev_alloc(p, &p->gm.cnt, 1)))
         return fail(st);
+    HIP_TRY(hipMemset(p->gm.cnt, 0, sizeof(unsigned)));
     if (p->precision == KFBI_FP32_REFINED && (st = dev_alloc(p, &p->X32, (size_t)n * n))) return fail(st);
     if (p->refine >= 2 && (st = dev_alloc(p, &p->D, (size_t)n * n))) return fail(st);
     // pad slots of the interleaved corrections stay zero for the life of the problem
     HIP_TRY(hipMemset(p->corr_il, 0, sizeof(double) * (size_t)dp.T * 64));
     p->gm.m = m;
     p->gm.gc = gm_chunks(M);
+    p->gm.gc64 = gm_chunks64(M);
     *out = p;
     return KFBI_OK;
 }
@@ -585,7 +590,7 @@ kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
     HIP_TRY(launch_spline(p->dp, phi, p->s2a, nullptr, p->ctx->stream));
-    return sparse_apply(p, phi, p->s2a, out, nullptr, p->ctx->stream);
+    return sparse_apply(p, phi, p->s2a, out, nullptr, nullptr, p->ctx->stream);
 }
 
 kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {
@@ -804,7 +809,7 @@ kfbi_status kfbi_prob_autotune(kfbi_prob* p, int reps, kfbi_tiles* out) {
             p->W = W;
             p->G = G;
             double us = 0;
-            if (kfbi_status e = time_us(s, reps, &us, [&] { return sparse_apply(p, p->tmpM, p->s2a, p->s2b, nullptr, s); })) {
+            if (kfbi_status e = time_us(s, reps, &us, [&] { return sparse_apply(p, p->tmpM, p->s2a, p->s2b, nullptr, nullptr, s); })) {
                 p->W = bw;
                 p->G = bg;
                 return e;
@@ -917,7 +922,7 @@ kfbi_status batch_rebuild(kfbi_batch* B) {
         B->h_live.push_back(s);
         for (int r = 0; r < p->I; r += 256) B->h_corr.push_back(make_int2(s, r));
         for (int b = 0; b < p->Gs; ++b) B->h_mode.push_back(make_int2(s, b));
-        for (int c = 0; c < p->M; c += 4) B->h_cp.push_back(make_int2(s, c));
+        for (int c = 0; c < p->M; c += 64) B->h_cp.push_back(make_int2(s, c));
         for (int c = 0; c < p->gm.gc; ++c) B->h_gm.push_back(make_int2(s, c));
     }
     const int2* old[4] = {B->d_corr, B->d_mode, B->d_cp, B->d_gm};
@@ -1014,7 +1019,7 @@ kfbi_status kfbi_batch_estimate_bytes(int n, int m, int restart, size_t* bytes) 
                (size_t)(n + 1) * (n + 1) + (size_t)n * (sizeof(ModeConst) + 16) + 4096;
     b += 2 * sizeof(double) * (size_t)n * n;                                  // dense-path grids
     b += sizeof(double) * ((size_t)(restart + 1) * (m + restart) + 16 * (size_t)m +
-                           gm_part_size(restart, gm_chunks(m)) + restart + 1);      // GMRES
+                           gm_part_size(restart, gm_chunks(m), gm_chunks64(m)) + restart + 2);   // GMRES
     b += sizeof(double) * (size_t)m * 512;                                    // single-path partials
     b += batch_extra_bytes(n, m);
     *bytes = b;

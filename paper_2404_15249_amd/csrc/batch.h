@@ -15,7 +15,7 @@ struct SlotDev {
     DevPlan p;
     GmresBufs b;
     double* corr_il;   // interleaved corrections (T x 64)
-    double* partial;   // M x Gs partial sums, one column per mode block
+    double* partial;   // Gs x M partial sums, one row per mode block
     int Gs;            // mode blocks: ceil((n-1) / kBatchW)
     int pad;
 };
@@ -27,7 +27,7 @@ struct BatchWork {
     const int* counts;
     const int2* corr_items;   // blocks of 256 irregular nodes
     const int2* mode_items;   // mode blocks of kBatchW modes
-    const int2* cp_items;     // blocks of 4 samples
+    const int2* cp_items;     // blocks of 64 samples
     const int* live;          // live slot ids
     const int2* gm_items;     // (slot, chunk) of the GMRES vector launches
     int max_live;

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(W * 64) void k_modes_b(const SlotDev* __restrict__ 
         }
         double* part = S.partial;
         const int Gs = S.Gs, row = item.y;
-        auto emit = [&](int cp, double s) { part[(size_t)cp * Gs + row] = s; };
+        auto emit = [&](int cp, double s) { part[(size_t)row * p.M + cp] = s; };
         const int base = row * W;
         switch (p.N) {
             case 64: modes_round<1, W>(p, S.corr_il, base, L, emit); break;
@@ -63,39 +63,35 @@ __global__ __launch_bounds__(W * 64) void k_modes_b(const SlotDev* __restrict__ 
     }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_b(const SlotDev* __restrict__ slots, BatchWork w) {
+__global__ __launch_bounds__(1024) void k_reduce_b(const SlotDev* __restrict__ slots, BatchWork w) {
+    __shared__ double red[16 * 64];
     const int n_items = w.counts[2];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = w.cp_items[it];
         const SlotDev& S = slots[item.x];
         if (slot_done(S)) continue;
-        const int cp = item.y + (threadIdx.x >> 6);
-        if (cp >= S.p.M) continue;
         const JumpSrc js{S.b.xcur, S.b.s2cur, nullptr, nullptr, nullptr, nullptr};
-        reduce_sample(S.p, js, S.partial, S.Gs, cp, S.b.w);
+        reduce_samples64(S.p, js, S.partial, S.Gs, item.y, S.b.w, red);
+        gm_dots1_64(S.b, S.p.M, item.y / 64, red);
+        __syncthreads();                                 // red is reused by the next item
     }
 }
 
-// GMRES (gmres.h): the vector launches walk (slot, chunk) items, the commit
-// launch has one workgroup per live slot (the grid has max_slots workgroups).
+// GMRES (gmres.h): the update and emit launches walk (slot, chunk) items; the
+// first pass rides on k_reduce_b and the commit on the second update.
 template <int Kind>
 __global__ __launch_bounds__(kGmChunk) void k_gm_vec_b(const SlotDev* __restrict__ slots, BatchWork w) {
     const int n_items = w.counts[4];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = w.gm_items[it];
         const SlotDev& S = slots[item.x];
-        if (Kind == 0) gm_dots1(S.b, S.p.M, item.y);
         if (Kind == 1) gm_update(S.b, S.p.M, item.y, 0);
-        if (Kind == 2) gm_update(S.b, S.p.M, item.y, 1);
+        if (Kind == 2) gm_update2_commit(S.b, S.p.M, item.y);
         if (Kind == 3) gm_emit(S.p, S.b, S.p.M, item.y);
         __syncthreads();                                 // the item's LDS is reused by the next item
     }
 }
 
-__global__ __launch_bounds__(kGmChunk) void k_gm_commit_b(const SlotDev* __restrict__ slots, BatchWork w) {
-    if ((int)blockIdx.x >= w.counts[3]) return;
-    gm_commit(slots[w.live[blockIdx.x]].b);
-}
 
 }  // namespace
 
@@ -113,11 +109,9 @@ hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mm
     if (hipError_t e = klaunch(&k_correct_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_modes_b<kBatchW>, dim3(n_cu), dim3(kBatchW * 64), lds, s, slots, w, Nmax, Mmax))
         return e;
-    if (hipError_t e = klaunch(&k_reduce_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
-    if (hipError_t e = klaunch(&k_gm_vec_b<0>, gv, t, 0, s, slots, w)) return e;
+    if (hipError_t e = klaunch(&k_reduce_b, dim3(n_cu), dim3(1024), 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_gm_vec_b<1>, gv, t, 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_gm_vec_b<2>, gv, t, 0, s, slots, w)) return e;
-    if (hipError_t e = klaunch(&k_gm_commit_b, dim3(w.max_live), t, 0, s, slots, w)) return e;
     return klaunch(&k_gm_vec_b<3>, gv, t, 0, s, slots, w);
 }
 

@@ -220,22 +220,34 @@ __device__ inline double correction_at(const DevPlan& p, const JumpSrc& js, int 
     return acc * p.inv_h2;
 }
 
-// One wavefront per sample: the partials of the weighted sine sums added in a
-// fixed order, plus the outside-node jump terms.  Lane 0 writes out[cp].
-__device__ inline void reduce_sample(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial, int G,
-                                     int cp, double* __restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const double* row = partial + (size_t)cp * G;
+// Samples cp0 .. cp0 + 63 (one per lane) by a workgroup of 16 wavefronts: the
+// workgroup partials of the weighted sine sums (row g of `partial` holds
+// workgroup g's sums for all M samples) are split over the wavefronts, added in
+// a fixed order, and wavefront 0 adds the jump terms of the stencil nodes
+// outside Omega and writes out[cp] (also to red[lane], for the caller).
+// red: 16 x 64 doubles of LDS.
+__device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial,
+                                        int G, int cp0, double* __restrict__ out, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cp = cp0 + lane, M = p.M;
     double s = 0.0;
-#pragma unroll 8
-    for (int g = lane; g < G; g += 64) s += row[g];
+    if (cp < M) {
+#pragma unroll 16
+        for (int g = wave; g < G; g += 16) s += partial[(size_t)g * M + cp];
+    }
+    red[wave * 64 + lane] = s;
+    __syncthreads();
+    if (wave == 0 && cp < M) {
+        double t = 0.0;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) {
+        for (int w = 0; w < 16; ++w) t += red[w * 64 + lane];
         int ni[6], nj[6];
         stencil_nodes(p, cp, ni, nj);
-        out[cp] = s * (2.0 / p.N) + outside_terms(p, js, cp, ni, nj, p.cp_w + 6 * (size_t)cp);
+        const double v = t * (2.0 / p.N) + outside_terms(p, js, cp, ni, nj, p.cp_w + 6 * (size_t)cp);
+        out[cp] = v;
+        red[lane] = v;                                  // left in LDS for the caller
     }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- sparse fast solve, one round of W modes
@@ -333,15 +345,23 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
                     gload((d + 1) % kDepth, ch + 1 + kDepth);
                 }
                 if (active) {
+                    // all loads of the chunk first, then the sums: the LDS
+                    // latencies overlap instead of adding up slot by slot
+                    int pk[kSlots];
+                    double cv[kSlots], sv[kSlots];
 #pragma unroll
                     for (int s = 0; s < kSlots; ++s) {
-                        const int pk = bij[cur * kChunk + s * 64 + lane];
-                        const double cv = bcv[cur * kChunk + s * 64 + lane];
-                        const int j = pk & 0xfff;
-                        run += cv * sinpi_n(sq, (j * l) & mask2, N);
-                        if (pk < 0) {                   // last node of its column
-                            const int i = (pk >> 16) & 0xfff;
-                            x[i + (i - 1) / C] = run;
+                        pk[s] = bij[cur * kChunk + s * 64 + lane];
+                        cv[s] = bcv[cur * kChunk + s * 64 + lane];
+                    }
+#pragma unroll
+                    for (int s = 0; s < kSlots; ++s)
+                        sv[s] = sinpi_n(sq, (int)(__umul24((unsigned)(pk[s] & 0xfff), (unsigned)l) & mask2), N);
+#pragma unroll
+                    for (int s = 0; s < kSlots; ++s) {
+                        run += cv[s] * sv[s];
+                        if (pk[s] < 0) {                // last node of its column
+                            x[(pk[s] >> 16) & 0x7fff] = run;
                             run = 0.0;
                         }
                     }
@@ -368,19 +388,29 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
         const double2* w2 = reinterpret_cast<const double2*>(p.cp_w + 6 * (size_t)cp);
         const double2 wa = w2[0], wb = w2[1], wc = w2[2];
         const double w0 = wa.x, wE = wa.y, wW = wb.x, wN = wb.y, wS = wc.x, wD = wc.y;
+        // places of the stencil columns in the padded layout (node 0 lies on
+        // the box: zero); the sine arguments advance by j per mode
+        const int pc = i0 + (i0 - 1) / C, pe = i0 + i0 / C + 1, pw = i0 > 1 ? i0 - 1 + (i0 - 2) / C : -1;
+        const int l0 = base + 1;
+        int a0 = (int)(__umul24((unsigned)j0, (unsigned)l0) & mask2);
+        int ap = (int)(__umul24((unsigned)(j0 + 1), (unsigned)l0) & mask2);
+        int am = (int)(__umul24((unsigned)(j0 - 1), (unsigned)l0) & mask2);
         double s = 0.0;
+        // modes beyond n belong to idle wavefronts, whose solutions are zero
+#pragma unroll
         for (int q = 0; q < W; ++q) {
-            const int lq = base + q + 1;
-            if (lq > n) break;
             const double* xq = L.xs + q * XS;
-            const double s0 = sinpi_n(sq, (j0 * lq) & mask2, N);
-            const double sp = sinpi_n(sq, ((j0 + 1) * lq) & mask2, N);
-            const double sm = sinpi_n(sq, ((j0 - 1) * lq) & mask2, N);
-            const double xc = xq[i0 + (i0 - 1) / C];
-            const double xe = xq[i0 + i0 / C + 1];
-            const double xw = i0 > 1 ? xq[i0 - 1 + (i0 - 2) / C] : 0.0;   // node 0 is on the box: zero
+            const double s0 = sinpi_n(sq, a0, N);
+            const double sp = sinpi_n(sq, ap, N);
+            const double sm = sinpi_n(sq, am, N);
+            const double xc = xq[pc];
+            const double xe = xq[pe];
+            const double xw = pw >= 0 ? xq[pw] : 0.0;
             const double xd = sx > 0 ? xe : xw;
             s += s0 * (w0 * xc + wE * xe + wW * xw) + sp * wN * xc + sm * wS * xc + (syp ? sp : sm) * wD * xd;
+            a0 = (a0 + j0) & mask2;
+            ap = (ap + j0 + 1) & mask2;
+            am = (am + j0 - 1) & mask2;
         }
         emit(cp, s);
     }

@@ -45,14 +45,26 @@ __global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double
     const int col0 = blockIdx.x * B;
     const int mask2 = 2 * N - 1;
     for (int k = tid; k <= N / 2; k += 256) sq[k] = sinq[k];
-    // load: node j = r + 1 of column c at z[c/2][j] (.x even columns, .y odd)
-    for (int idx = tid; idx < N * B; idx += 256) {
-        const int r = idx / B, c = idx % B;
-        const int j = r + 1;
-        if (j < N) {
-            const T v = (T)in[(size_t)r * N + col0 + c];
-            cpx<T>& e = z[(c >> 1) * NS + j];
-            if (c & 1) e.y = v; else e.x = v;
+    // load: node j = r + 1 of column c at z[c/2][j] (.x even columns, .y odd);
+    // kLoadBatch loads per thread are issued before any is stored, so their
+    // latencies overlap
+    constexpr int kLoadBatch = 16;
+    for (int base = 0; base < N * B; base += 256 * kLoadBatch) {
+        Tin v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + tid;
+            const int r = idx / B, c = idx % B;
+            v[u] = (idx < N * B && r + 1 < N) ? in[(size_t)r * N + col0 + c] : Tin(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + tid;
+            const int r = idx / B, c = idx % B;
+            if (idx < N * B && r + 1 < N) {
+                cpx<T>& e = z[(c >> 1) * NS + r + 1];
+                if (c & 1) e.y = (T)v[u]; else e.x = (T)v[u];
+            }
         }
     }
     if (tid < P) z[tid * NS] = cpx<T>{T(0), T(0)};
@@ -144,17 +156,35 @@ __global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double
     }
     __syncthreads();
     // write: X_l to row l-1 (odd l from slot (l-1)/2, even l from slot N - l/2); row N-1 is the pad
-    for (int idx = tid; idx < N * B; idx += 256) {
-        const int r = idx / B, c = idx % B;
-        const int l = r + 1;
-        double v = 0.0;
-        if (l < N) {
-            const cpx<T>* zp = z + (c >> 1) * NS;
-            const cpx<T> e = (l & 1) ? zp[(l - 1) >> 1] : zp[N - (l >> 1)];
-            v = alpha * (double)((c & 1) ? e.y : e.x);
+    for (int base = 0; base < N * B; base += 256 * kLoadBatch) {
+        double v[kLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + tid;
+            const int r = idx / B, c = idx % B;
+            const int l = r + 1;
+            v[u] = 0.0;
+            if (idx < N * B && l < N) {
+                const cpx<T>* zp = z + (c >> 1) * NS;
+                const cpx<T> e = (l & 1) ? zp[(l - 1) >> 1] : zp[N - (l >> 1)];
+                v[u] = alpha * (double)((c & 1) ? e.y : e.x);
+            }
         }
-        Tout* o = out + (size_t)r * N + col0 + c;
-        *o = accumulate ? (Tout)((double)*o + v) : (Tout)v;
+        if (accumulate) {
+            Tout old[kLoadBatch];
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) {
+                const int idx = base + u * 256 + tid;
+                old[u] = idx < N * B ? out[(size_t)(idx / B) * N + col0 + idx % B] : Tout(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kLoadBatch; ++u) v[u] += (double)old[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int idx = base + u * 256 + tid;
+            if (idx < N * B) out[(size_t)(idx / B) * N + col0 + idx % B] = (Tout)v[u];
+        }
     }
 }
 

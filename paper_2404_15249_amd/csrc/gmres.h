@@ -1,20 +1,22 @@
 // Restarted GMRES (Alg. 5) on the boundary density, resident on the device.
 //
-// One step of the iteration follows one K_D apply (whose output is b.w) and is
-// five launches, so that the vector work is spread over many workgroups:
-//   dots1   per chunk: mode 0: phi <- xcur (the iterate the apply was given),
+// One step of the iteration follows one K_D apply and takes, besides it, three
+// launches, so the vector work is spread over many workgroups:
+//   dots1   fused into the apply's last launch (reduce_samples64), per 64
+//           samples: mode 0: phi <- xcur (the iterate the apply was given),
 //           z = ghat - w and partial |z|^2; mode 1: partial dots V_i . w, i <= j
-//   upd1    per chunk: h_i = sum of the partials; z = w - sum h_i V_i; partial
-//           dots V_i . z (classical Gram-Schmidt, second pass)
-//   upd2    per chunk: z -= sum h'_i V_i; partial |z|^2
-//   commit  one workgroup: the new Hessenberg column, the Givens rotations and
-//           the residual estimate (mode 1), or the true residual (mode 0);
-//           the state transition; at the end of a cycle the triangular solve
+//   upd1    per chunk of kGmChunk: h_i = sum of the partials; z = w - sum h_i
+//           V_i; partial dots V_i . z (classical Gram-Schmidt, second pass)
+//   upd2    per chunk: z -= sum h'_i V_i; partial |z|^2; the workgroup that
+//           finishes last (an atomic count, no waiting) then runs commit: the
+//           new Hessenberg column, the Givens rotations and the residual
+//           estimate (mode 1) or the true residual (mode 0), the state
+//           transition, and at the end of a cycle the triangular solve
 //   emit    per chunk: the next K_D input (new basis vector, or the updated
 //           iterate at the end of a cycle) and its spline second derivatives.
 // Partial sums are added in a fixed order, so results do not depend on timing.
-// Only commit writes the state, and it runs alone (one workgroup); every other
-// launch only reads it.
+// Only commit writes the state, and it runs after every other workgroup of its
+// launch has read it.
 #pragma once
 
 #include "device.h"
@@ -27,8 +29,33 @@ constexpr int kGmHalo = kSplineK + 1;    // reach of the spline filter on each s
 enum GmKind { kGmNewCycle = 0, kGmNextVector = 1, kGmCycleEnd = 2, kGmDone = 3 };
 
 __host__ __device__ inline int gm_chunks(int M) { return (M + kGmChunk - 1) / kGmChunk; }
-// doubles of partial sums a problem needs: two dot blocks of (m+1) x gc, one norm block of gc
-__host__ __device__ inline size_t gm_part_size(int m, int gc) { return (size_t)(2 * (m + 1) + 1) * gc; }
+__host__ __device__ inline int gm_chunks64(int M) { return (M + 63) / 64; }
+// doubles of partial sums a problem needs: first-pass dots (m+1) x gc64,
+// second-pass dots (m+1) x gc, norms of the update (gc) and of the residual (gc64)
+__host__ __device__ inline size_t gm_part_size(int m, int gc, int gc64) {
+    return (size_t)(m + 1) * (gc64 + gc) + gc + gc64;
+}
+
+struct GmPart {
+    double* d1;     // [i * gc64 + c64]
+    double* d2;     // [i * gc + c]
+    double* nrm;    // [c]
+    double* nrm0;   // [c64]
+};
+__device__ __forceinline__ GmPart gm_part(const GmresBufs& b) {
+    GmPart q;
+    q.d1 = b.part;
+    q.d2 = q.d1 + (size_t)(b.m + 1) * b.gc64;
+    q.nrm = q.d2 + (size_t)(b.m + 1) * b.gc;
+    q.nrm0 = q.nrm + b.gc;
+    return q;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
 
 __device__ inline double gm_block_sum(double v, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -40,92 +67,129 @@ __device__ inline double gm_block_sum(double v, double* red) {
     return red[0] + red[1] + red[2] + red[3];
 }
 
-// Partial dots of the chunk with V_0..V_j: x[q] is the vector at element
-// c0 + lane + 64 q.  Wave w takes i = w, w + 4, ...
-__device__ inline void gm_chunk_dots(const double* __restrict__ V, const double (&x)[4], int M, int c, int gc,
-                                     int j, double* __restrict__ out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int c0 = c * kGmChunk;
-    for (int i = wave; i <= j; i += 4) {
-        const double* Vi = V + (size_t)i * M + c0;
-        double s = 0.0;
+// Sums over the wavefront of G values per lane at once: log2(G) halving steps
+// (each lane keeps half of its values and adds its partner's other half), then
+// plain butterfly steps.  Returns the wavefront sum of value number
+// (lane >> (6 - log2 G)) & (G - 1); 64 / G lanes hold each sum.
+template <int G>
+__device__ __forceinline__ double wave_sum_many(double (&p)[G]) {
+    static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "G must be a power of two");
+    const int lane = threadIdx.x & 63;
+    int off = 32;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int t = lane + 64 * q;
-            if (c0 + t < M) s = fma(Vi[t], x[q], s);
+    for (int half = G / 2; half >= 1; half /= 2, off >>= 1) {
+        const bool hi = (lane & off) != 0;
+#pragma unroll
+        for (int u = 0; u < half; ++u) {
+            const double keep = hi ? p[u + half] : p[u];
+            const double send = hi ? p[u] : p[u + half];
+            p[u] = keep + __shfl_xor(send, off, 64);
         }
+    }
+    for (; off >= 1; off >>= 1) p[0] += __shfl_xor(p[0], off, 64);
+    return p[0];
+}
+
+// Loads V_i at element e (0 outside [0, M) and for i > j) for i < 4 * 16,
+// grouped by 16; groups beyond j are skipped.
+__device__ __forceinline__ void gm_load_basis(const double* __restrict__ V, int M, int e, int j, double (&v)[4][16]) {
+    const bool in = e < M;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-        if (lane == 0) out[(size_t)i * gc + c] = s;
+    for (int g = 0; g < 4; ++g) {
+        if (16 * g > j) break;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = 16 * g + u;
+            v[g][u] = (in && i <= j) ? V[(size_t)i * M + e] : 0.0;
+        }
     }
 }
 
-__device__ inline void gm_dots1(const GmresBufs& b, int M, int c) {
-    __shared__ double red[4];
+// Partial dots of chunk c with V_0..V_j from basis values held in registers
+// (v[g][u] = V_{16g+u} at this thread's element) times x:
+// out[i * gc + c] for i <= j.  red: 4 x 16 doubles of LDS.
+__device__ __forceinline__ void gm_chunk_dots(const double (&v)[4][16], double x, int j, int gc, int c,
+                                              double* __restrict__ red, double* __restrict__ out) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (16 * g > j) break;
+        double p[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) p[u] = v[g][u] * x;
+        const double s = wave_sum_many<16>(p);
+        if ((lane & 3) == 0) red[wave * 16 + (lane >> 2)] = s;
+        __syncthreads();
+        if (tid < 16 && 16 * g + tid <= j)
+            out[(size_t)(16 * g + tid) * gc + c] = red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid];
+        __syncthreads();
+    }
+}
+
+// First step of GMRES on samples c64 * 64 .. + 63, called by a workgroup of 16
+// wavefronts right after it computed w there (wv[lane] in LDS).
+__device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const double* wv) {
     const GmresState* st = b.st;
     const int mode = st->mode;
     if (mode == 2) return;
-    const int tid = threadIdx.x, lane = tid & 63, gc = b.gc, m = b.m;
-    const int c0 = c * kGmChunk, e = c0 + tid;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cp = c64 * 64 + lane;
+    const GmPart q = gm_part(b);
     if (mode == 0) {
+        if (wave != 0) return;
         double r = 0.0;
-        if (e < M) {
-            b.phi[e] = b.xcur[e];
-            r = b.ghat[e] - b.w[e];
-            b.z[e] = r;
+        if (cp < M) {
+            b.phi[cp] = b.xcur[cp];
+            r = b.ghat[cp] - wv[lane];
+            b.z[cp] = r;
         }
-        const double s = gm_block_sum(r * r, red);
-        if (tid == 0) b.part[(size_t)2 * (m + 1) * gc + c] = s;
+        const double s = wave_sum(r * r);
+        if (lane == 0) q.nrm0[c64] = s;
         return;
     }
-    double x[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int t = c0 + lane + 64 * q;
-        x[q] = t < M ? b.w[t] : 0.0;
+    const int j = st->j, gc64 = b.gc64;
+    const double x = cp < M ? wv[lane] : 0.0;
+    for (int i = wave; i <= j; i += 16) {
+        const double s = wave_sum(cp < M ? b.V[(size_t)i * M + cp] * x : 0.0);
+        if (lane == 0) q.d1[(size_t)i * gc64 + c64] = s;
     }
-    gm_chunk_dots(b.V, x, M, c, gc, st->j, b.part);
 }
 
-// pass 0: z = w - sum h_i V_i and the second-pass dots; pass 1: z -= sum h'_i V_i and |z|^2
+// pass 0: z = w - sum h_i V_i and the second-pass dots V_i . z; pass 1:
+// z -= sum h'_i V_i and |z|^2.  The basis values are loaded once per launch.
 __device__ inline void gm_update(const GmresBufs& b, int M, int c, int pass) {
     __shared__ double hs[kMaxRestart + 2];
-    __shared__ double zs[kGmChunk];
-    __shared__ double red[4];
+    __shared__ double red[64];
     const GmresState* st = b.st;
     if (st->mode != 1) return;
-    const int tid = threadIdx.x, lane = tid & 63, gc = b.gc, m = b.m, j = st->j;
-    const double* coef = b.part + (pass == 0 ? 0 : (size_t)(m + 1) * gc);
+    const int tid = threadIdx.x, gc = b.gc, j = st->j;
+    const GmPart q = gm_part(b);
+    const double* coef = pass == 0 ? q.d1 : q.d2;
+    const int nco = pass == 0 ? b.gc64 : gc;
     for (int i = tid; i <= j; i += kGmChunk) {
         double s = 0.0;
-        for (int cc = 0; cc < gc; ++cc) s += coef[(size_t)i * gc + cc];
+#pragma unroll 16
+        for (int cc = 0; cc < nco; ++cc) s += coef[(size_t)i * nco + cc];   // loads issued together
         hs[i] = s;
     }
+    const int e = c * kGmChunk + tid;
+    double v[4][16];
+    gm_load_basis(b.V, M, e, j, v);
+    double a = e < M ? (pass == 0 ? b.w[e] : b.z[e]) : 0.0;
     __syncthreads();
-    const int c0 = c * kGmChunk, e = c0 + tid;
-    double zv = 0.0;
-    if (e < M) {
-        double a = pass == 0 ? b.w[e] : b.z[e];
-        for (int i0 = 0; i0 <= j; i0 += 8) {
-            double v[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = i0 + u <= j ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+    for (int g = 0; g < 4; ++g) {
+        if (16 * g > j) break;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a -= (i0 + u <= j ? hs[i0 + u] : 0.0) * v[u];
-        }
-        zv = a;
-        b.z[e] = a;
+        for (int u = 0; u < 16; ++u)
+            if (16 * g + u <= j) a -= hs[16 * g + u] * v[g][u];
     }
+    if (e < M) b.z[e] = a;
     if (pass == 0) {
-        zs[tid] = zv;
-        __syncthreads();
-        double x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = zs[lane + 64 * q];
-        gm_chunk_dots(b.V, x, M, c, gc, j, b.part + (size_t)(m + 1) * gc);
+        gm_chunk_dots(v, a, j, gc, c, red, q.d2);
     } else {
-        const double s = gm_block_sum(zv * zv, red);
-        if (tid == 0) b.part[(size_t)2 * (m + 1) * gc + c] = s;
+        const double s = gm_block_sum(a * a, red);
+        if (tid == 0) q.nrm[c] = s;
     }
 }
 
@@ -133,18 +197,21 @@ __device__ inline void gm_update(const GmresBufs& b, int M, int c, int pass) {
 __device__ inline void gm_commit(const GmresBufs& b) {
     __shared__ double red[4];
     __shared__ double col[kMaxRestart + 2];
-    __shared__ double cs_s[kMaxRestart], sn_s[kMaxRestart];
+    __shared__ double cs_s[kMaxRestart], sn_s[kMaxRestart], rot[kMaxRestart];
     __shared__ double Hs[kMaxRestart * (kMaxRestart + 1)];
     __shared__ int s_end;
     GmresState* st = b.st;
     const int mode = st->mode;
     if (mode == 2) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = b.m, gc = b.gc, j = st->j, it = st->it, first = st->first, max_iter = st->max_iter;
+    const int m = b.m, gc = b.gc, gc64 = b.gc64, j = st->j, it = st->it, first = st->first;
+    const int max_iter = st->max_iter;
     const double r0_in = st->r0, tol = st->tol;
-    const double* norm = b.part + (size_t)2 * (m + 1) * gc;
+    const GmPart q = gm_part(b);
+    const double* norm = mode == 0 ? q.nrm0 : q.nrm;
+    const int nn = mode == 0 ? gc64 : gc;
     double v = 0.0;
-    for (int cc = tid; cc < gc; cc += kGmChunk) v += norm[cc];
+    for (int cc = tid; cc < nn; cc += kGmChunk) v += norm[cc];
     const double nrm = sqrt(gm_block_sum(v, red));
     if (mode == 0) {
         if (tid == 0) {
@@ -172,14 +239,12 @@ __device__ inline void gm_commit(const GmresBufs& b) {
         return;
     }
     // mode 1: column j of the Hessenberg matrix from the two Gram-Schmidt passes
-    const double* d1 = b.part;
-    const double* d2 = b.part + (size_t)(m + 1) * gc;
     for (int i = tid; i <= j; i += kGmChunk) {
         double s1 = 0.0, s2 = 0.0;
-        for (int cc = 0; cc < gc; ++cc) {
-            s1 += d1[(size_t)i * gc + cc];
-            s2 += d2[(size_t)i * gc + cc];
-        }
+#pragma unroll 16
+        for (int cc = 0; cc < gc64; ++cc) s1 += q.d1[(size_t)i * gc64 + cc];
+#pragma unroll 16
+        for (int cc = 0; cc < gc; ++cc) s2 += q.d2[(size_t)i * gc + cc];
         col[i] = s1 + s2;
     }
     if (tid < j) {
@@ -189,12 +254,15 @@ __device__ inline void gm_commit(const GmresBufs& b) {
     __syncthreads();
     if (tid == 0) {
         const double hn = nrm;
+        // previous rotations down the column; the rotated entries go to rot[]
+        // so the loads of col, cs and sn do not wait on the stores
         double a = col[0];
         for (int i = 0; i < j; ++i) {
             const double cn = col[i + 1], cc = cs_s[i], ss = sn_s[i];
-            col[i] = cc * a + ss * cn;
+            rot[i] = cc * a + ss * cn;
             a = -ss * a + cc * cn;
         }
+        for (int i = 0; i < j; ++i) col[i] = rot[i];
         const double den = hypot(a, hn);
         const double cs = den > 0.0 ? a / den : 1.0;
         const double sn = den > 0.0 ? hn / den : 0.0;
@@ -244,6 +312,26 @@ __device__ inline void gm_commit(const GmresBufs& b) {
     }
 }
 
+// upd2 on chunk c, then commit by the workgroup that finishes the problem's
+// last chunk (an atomic count of finished chunks; nobody waits).
+__device__ inline void gm_update2_commit(const GmresBufs& b, int M, int c) {
+    __shared__ int s_last;
+    const int mode = b.st->mode;
+    if (mode == 2) return;
+    if (mode == 1) gm_update(b, M, c, 1);
+    if (threadIdx.x == 0) {
+        __threadfence();                                   // this chunk's partials before the count
+        const unsigned done = atomicAdd(b.cnt, 1u) + 1;
+        s_last = done == (unsigned)b.gc;
+        if (s_last) {
+            __hip_atomic_store(b.cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence();                               // the other chunks' partials after it
+        }
+    }
+    __syncthreads();
+    if (s_last) gm_commit(b);
+}
+
 // The next K_D input for elements of chunk c, and its spline second derivatives
 // (the filter reads kGmHalo neighbours on each side, wrapping around Gamma).
 __device__ inline void gm_emit(const DevPlan& p, const GmresBufs& b, int M, int c) {
@@ -260,7 +348,14 @@ __device__ inline void gm_emit(const DevPlan& p, const GmresBufs& b, int M, int 
         double x;
         if (kind == kGmCycleEnd) {
             x = b.phi[e];
-            for (int i = 0; i < jn; ++i) x = fma(b.y[i], b.V[(size_t)i * M + e], x);
+            for (int i0 = 0; i0 < jn; i0 += 8) {
+                double vv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) vv[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (i0 + u < jn) x = fma(b.y[i0 + u], vv[u], x);
+            }
         } else {
             x = b.z[e] * scale;
         }

@@ -37,8 +37,10 @@ struct DevPlan {
     const int* col_ptr;       // N + 1 entries used (i = 0..N)
     const int* lane_ptr;      // 65: irregular nodes [lane_ptr[L], lane_ptr[L+1]) feed lane L of the
                               // sparse sine sums; the cuts fall on column starts
-    const int* il_ij;         // T x 64, slot t*64 + L: the t-th node of lane L packed as
-                              // (last-of-column << 31) | (i << 16) | j  (0: pad)
+    const int* il_ij;         // T x 64, slot t*64 + L: the t-th node (i, j) of lane L packed as
+                              // (last-of-column << 31) | (xpos << 16) | j  (0: pad), where
+                              // xpos = i + (i - 1) / (N / 64) is column i's place in the padded
+                              // per-wavefront mode solution of the sparse fast solve
     const int* il_pos;        // I: slot of irregular node r in the interleaved layout
     int T;                    // slots per lane, a multiple of kSlots
     const int4* cp_pack;      // M: (i0, j0, sxy, 0)
@@ -101,11 +103,13 @@ struct GmresBufs {
     double* s2cur;   // M: spline second derivatives of xcur
     double* w;       // M: output of the last K_D apply
     double* z;       // M: the vector being orthogonalised (or the residual)
-    double* part;    // gm_part_size(m, gc): per-chunk partial dots and norms
+    double* part;    // gm_part_size(m, gc, gc64): per-chunk partial dots and norms
     double* y;       // m + 1: solution of the cycle's triangular system
     GmresState* st;  // state machine; also holds tol and max_iter so launches are call independent
+    unsigned* cnt;   // chunks of the current update launch that have finished (0 between launches)
     int m;
     int gc;          // chunks of kGmChunk elements covering the M samples
+    int gc64;        // chunks of 64 samples (the first Gram-Schmidt pass)
 };
 
 // launchers (return hipError_t of the launch)
@@ -114,8 +118,10 @@ hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* co
 hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int G, int W,
                         const int* skip, hipStream_t s);
 hipError_t launch_spline(const DevPlan& p, const double* y, double* s2, const int* skip, hipStream_t s);
+// with gm non-null (a GMRES step) the output goes to gm->w, the launch is skipped
+// once GMRES is done, and it also makes the first Gram-Schmidt pass (gmres.h)
 hipError_t launch_reduce_interp(const DevPlan& p, JumpSrc js, const double* partial, int G, double* out,
-                                const int* skip, hipStream_t s);
+                                const int* skip, const GmresBufs* gm, hipStream_t s);
 hipError_t launch_interp_grid(const DevPlan& p, JumpSrc js, const double* R, double* out, hipStream_t s);
 hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double* R, hipStream_t s);
 // column sine transforms (dst.hip): FP64, and FP32 arithmetic reading an FP64

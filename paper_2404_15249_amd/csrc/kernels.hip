@@ -63,7 +63,7 @@ __global__ __launch_bounds__(W * 64) void k_modes(DevPlan p, const double* __res
     for (int k = tid; k < M; k += W * 64) L.acc[k] = 0.0;
     for (int base = blockIdx.x * W; base < p.n; base += gridDim.x * W)
         modes_round<C, W>(p, corr, base, L, [&](int cp, double s) { L.acc[cp] += s; });
-    for (int cp = tid; cp < M; cp += W * 64) partial[(size_t)cp * G + blockIdx.x] = L.acc[cp];
+    for (int cp = tid; cp < M; cp += W * 64) partial[(size_t)blockIdx.x * M + cp] = L.acc[cp];
 }
 
 // ---------------------------------------------------------------- spline of a density
@@ -77,13 +77,12 @@ __global__ __launch_bounds__(256) void k_spline(DevPlan p, const double* __restr
 
 // ---------------------------------------------------------------- interpolation (Alg. 3)
 
-// One wavefront per sample: the workgroup partials of the weighted sine sums,
-// added in a fixed order, plus the outside-node jump terms.
-__global__ __launch_bounds__(256) void k_reduce_interp(DevPlan p, JumpSrc js, const double* __restrict__ partial,
-                                                       int G, double* __restrict__ out, const int* __restrict__ skip) {
+// 64 samples per workgroup of 16 wavefronts (reduce_samples64).
+__global__ __launch_bounds__(1024) void k_reduce_interp(DevPlan p, JumpSrc js, const double* __restrict__ partial,
+                                                        int G, double* __restrict__ out, const int* __restrict__ skip) {
+    __shared__ double red[16 * 64];
     if (skip && *skip) return;
-    const int cp = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (cp < p.M) reduce_sample(p, js, partial, G, cp, out);
+    reduce_samples64(p, js, partial, G, blockIdx.x * 64, out, red);
 }
 
 // Interpolation from a full grid solution (dense path): R in the padded interior layout.
@@ -172,10 +171,16 @@ __global__ __launch_bounds__(256) void k_axpby(int n, double a, const double* __
 
 // ---------------------------------------------------------------- GMRES step (Alg. 5)
 
-__global__ __launch_bounds__(kGmChunk) void k_gm_dots1(GmresBufs b, int M) { gm_dots1(b, M, blockIdx.x); }
+// the apply's last launch inside GMRES: w at 64 samples, then the first pass
+__global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const double* __restrict__ partial, int G,
+                                                    GmresBufs b) {
+    __shared__ double red[16 * 64];
+    if (b.st->converged) return;
+    reduce_samples64(p, js, partial, G, blockIdx.x * 64, b.w, red);
+    gm_dots1_64(b, p.M, blockIdx.x, red);
+}
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 0); }
-__global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 1); }
-__global__ __launch_bounds__(kGmChunk) void k_gm_commit(GmresBufs b) { gm_commit(b); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_update2_commit(b, M, blockIdx.x); }
 __global__ __launch_bounds__(kGmChunk) void k_gm_emit(DevPlan p, GmresBufs b) { gm_emit(p, b, p.M, blockIdx.x); }
 
 
@@ -263,8 +268,9 @@ hipError_t launch_spline(const DevPlan& p, const double* y, double* s2, const in
 }
 
 hipError_t launch_reduce_interp(const DevPlan& p, JumpSrc js, const double* partial, int G, double* out,
-                                const int* skip, hipStream_t s) {
-    if (hipError_t e_ = klaunch(&k_reduce_interp, dim3((p.M + 3) / 4), dim3(256), 0, s, p, js, partial, G, out, skip)) return e_;
+                                const int* skip, const GmresBufs* gm, hipStream_t s) {
+    if (gm) return klaunch(&k_reduce_gm, dim3((p.M + 63) / 64), dim3(1024), 0, s, p, js, partial, G, *gm);
+    if (hipError_t e_ = klaunch(&k_reduce_interp, dim3((p.M + 63) / 64), dim3(1024), 0, s, p, js, partial, G, out, skip)) return e_;
     return hipGetLastError();
 }
 
@@ -303,10 +309,8 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
 
 hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s) {
     const dim3 g(b.gc), t(kGmChunk);
-    if (hipError_t e = klaunch(&k_gm_dots1, g, t, 0, s, b, p.M)) return e;
     if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, p.M)) return e;
     if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, p.M)) return e;
-    if (hipError_t e = klaunch(&k_gm_commit, dim3(1), t, 0, s, b)) return e;
     return klaunch(&k_gm_emit, g, t, 0, s, p, b);
 }
 
