@@ -189,8 +189,8 @@ kfbi_status kfbi_interface_solve_jumps(kfbi_prob* prob, const double* jq, const 
 
 /* Launch shapes of a problem's kernels. */
 typedef struct {
-    int modes_waves;      /* sparse fast solve: wavefronts (sine modes) per workgroup, 1/2/4/8 */
-    int modes_groups;     /* sparse fast solve: workgroups (each walks its share of the modes) */
+    int modes_per_group;  /* sparse fast solve: sine modes per workgroup, 1/2/4/8/16 */
+    int modes_groups;     /* sparse fast solve: workgroups, ceil((n-1) / modes_per_group) (output only) */
     int dst_cols;         /* column sine transforms: columns per workgroup, 4/8/16 */
     double apply_us;      /* autotune output: mean K_D apply time with this shape */
     double grid_solve_us; /* autotune output: mean dense grid solve time (transforms + row solves) */
@@ -198,11 +198,10 @@ typedef struct {
 
 /* Time the candidate shapes on this problem (each K_D apply and grid solve
  * candidate `reps` times, after one warm-up, with HIP events on the context
- * stream), keep the fastest and return it in *out.  Candidates: waves 1/2/4/8
- * whose local data share fits, workgroups n_cu/2, n_cu, 2 n_cu and one
- * workgroup per W modes (capped by the modes and by 2 n_cu); every valid
- * column tile.  Overwrites the problem's scratch vectors (not its results).
- * Synchronises.  reps <= 0: 10. */
+ * stream), keep the fastest and return it in *out.  Candidates: half, the same
+ * and twice the default modes per workgroup (where the local data share holds
+ * them); every valid column tile.  Overwrites the problem's scratch vectors
+ * (not its results).  Synchronises.  reps <= 0: 10. */
 kfbi_status kfbi_prob_autotune(kfbi_prob* prob, int reps, kfbi_tiles* out);
 /* The shapes in use (the times are those of the last autotune, else 0). */
 kfbi_status kfbi_prob_get_tiles(const kfbi_prob* prob, kfbi_tiles* out);

@@ -1,8 +1,8 @@
 """Autotuned launch shapes, cached across runs.
 
 ``kfbi_prob_autotune`` times the candidate shapes of one problem's kernels (the
-sparse fast solve's waves per workgroup and workgroup count, the column
-transforms' tile width) on the device and keeps the fastest.  Problems of the
+sparse fast solve's sine modes per workgroup, the column transforms' tile
+width) on the device and keeps the fastest.  Problems of the
 same grid, precision and size class run fastest with the same shapes, so the
 result is stored under a key of those and reused: a cache hit costs one
 ``kfbi_prob_set_tiles`` call instead of the timing runs.
@@ -58,7 +58,7 @@ class TileCache:
         e = self.entries.get(k)
         if e is not None:
             try:
-                prob.set_tiles(e["modes_waves"], e["modes_groups"], e["dst_cols"])
+                prob.set_tiles(e["modes_per_group"], e["dst_cols"])
                 self.hits += 1
                 return dict(e)
             except (KfbiError, KeyError, TypeError):

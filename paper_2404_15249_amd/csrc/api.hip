@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <queue>
 #include <cstring>
 #include <new>
 #include <string>
@@ -55,7 +56,7 @@ struct kfbi_prob {
     double kappa = 0, tol = 1e-10;
     int restart = 50, max_iter = 500;
     int N = 0, n = 0, M = 0, Q = 0, I = 0;
-    int W = 4, G = 1;
+    int Rm = 8, G = 1;           // sine modes per sparse-fast-solve workgroup; workgroups = ceil(n / Rm)
     DevPlan dp{};
     std::vector<void*> allocs;
     size_t bytes = 0;
@@ -220,7 +221,7 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
     if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, skip, s));
     if (ev) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(launch_modes(p->dp, p->corr_il, p->partial, p->G, p->W, skip, s));
+    HIP_TRY(launch_modes(p->dp, p->corr_il, p->partial, p->Rm, skip, s));
     if (ev) HIP_TRY(hipEventRecord(ev[2], s));
     HIP_TRY(launch_reduce_interp(p->dp, js, p->partial, p->G, out, skip, gm, s));
     if (ev) HIP_TRY(hipEventRecord(ev[3], s));
@@ -419,22 +420,26 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         delete p;
         return set_err(KFBI_ERR_UNSUPPORTED, "more than " + std::to_string(kMaxSamples) + " samples");
     }
-    // workgroup shape of the sparse fast solve: as many waves as the LDS allows
-    // as many waves per workgroup as the LDS allows while still giving every
-    // compute unit a workgroup
-    p->W = 1;
-    for (int W : {8, 4, 2, 1}) {
-        if (modes_lds_bytes(n, p->M, W) <= ctx->lds_max && ((n - 1 + W - 1) / W >= ctx->num_cu || W == 1)) {
-            p->W = W;
-            break;
+    // modes per workgroup of the sparse fast solve: the most the LDS holds that
+    // still leaves a workgroup for at least half of the compute units
+    {
+        int rmax = 0;
+        for (int r = kMaxModesPerGroup; r >= 1 && !rmax; r /= 2)
+            if (modes_lds_bytes(n, r) <= ctx->lds_max) rmax = r;
+        if (!rmax) {
+            delete p;
+            return set_err(KFBI_ERR_UNSUPPORTED, "problem too large for the local data share");
         }
+        p->Rm = 1;
+        for (int r = rmax; r >= 1; r /= 2)
+            if ((p->n + r - 1) / r >= ctx->num_cu / 2 || r == 1) {
+                p->Rm = r;
+                break;
+            }
+        p->G = (p->n + p->Rm - 1) / p->Rm;
+        // the autotuner may halve Rm once: room for that many partial rows
+        p->Gcap = (p->n + std::max(1, p->Rm / 2) - 1) / std::max(1, p->Rm / 2);
     }
-    if (modes_lds_bytes(n, p->M, p->W) > ctx->lds_max) {
-        delete p;
-        return set_err(KFBI_ERR_UNSUPPORTED, "problem too large for the local data share");
-    }
-    p->G = std::max(1, std::min((p->n + p->W - 1) / p->W, 2 * ctx->num_cu));
-    p->Gcap = std::max(p->G, std::min(p->n, 2 * ctx->num_cu));
     p->dstB = dst_default_tile(n, cpx_bytes(p->precision), ctx->lds_max);
     if (p->dstB == 0) {
         delete p;
@@ -468,33 +473,81 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     const int K = 30;
     dp.K = K;
     std::vector<int> colptr(P.col_ptr.begin(), P.col_ptr.end());
-    // balanced split of the irregular nodes over the 64 lanes of a wavefront,
-    // cut only at column starts so every column is summed by one lane
-    std::vector<int> laneptr(65, 0);
+    // node table of the sparse sine sums: kModeWaves sub-tables of 64 lanes
+    // (512 workers).  A column's nodes form one piece, or several pieces of at
+    // most `cap` nodes when the column is long (its extra pieces' sums are added
+    // to the first piece's in a fixed order); pieces go largest first to the
+    // least loaded worker, each worker's pieces in order, and sub-table w's rows
+    // are the longest worker list among its lanes
+    std::vector<int> sub_off(kModeWaves + 1, 0), il_ij, il_pos(std::max(p->I, 1), 0), split;
     {
-        int i = 0;
-        for (int L = 1; L < 64; ++L) {
-            const long want = (long)p->I * L / 64;
-            while (i <= n && colptr[i] < want) ++i;
-            laneptr[L] = std::max(laneptr[L - 1], i <= n ? colptr[i] : p->I);
+        constexpr int NW = kModeWaves * 64;
+        auto xpos_of = [&](int i) { return i + (i - 1) / (n / 64); };
+        int cap = std::max(1, (p->I + NW - 1) / NW);
+        for (;;) {
+            long extra = 0;
+            for (int i = 0; i <= n; ++i) extra += std::max(0, (colptr[i + 1] - colptr[i] + cap - 1) / cap - 1);
+            if (extra <= kMaxExtra) break;
+            cap *= 2;
         }
-        laneptr[64] = p->I;
+        struct Piece {
+            int first, count, dest;
+        };
+        std::vector<Piece> pieces;
+        int n_extra = 0;
+        for (int i = 0; i <= n; ++i) {
+            const int cnt = colptr[i + 1] - colptr[i];
+            if (cnt == 0) continue;
+            const int np = (cnt + cap - 1) / cap;
+            if (np > 1) {
+                split.push_back(xpos_of(i));
+                split.push_back(n_extra);
+                split.push_back(np - 1);
+            }
+            for (int k = 0; k < np; ++k) {
+                const int a = colptr[i] + k * cap, b = std::min(colptr[i + 1], a + cap);
+                pieces.push_back({a, b - a, k == 0 ? xpos_of(i) : (kExtraFlag | n_extra++)});
+            }
+        }
+        std::vector<int> order(pieces.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return pieces[a].count > pieces[b].count; });
+        using Load = std::pair<int, int>;               // (nodes so far, worker)
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (int w = 0; w < NW; ++w) heap.push({0, w});
+        std::vector<std::vector<int>> wpieces(NW);
+        std::vector<int> load(NW, 0);
+        for (int k : order) {
+            const Load top = heap.top();
+            heap.pop();
+            wpieces[top.second].push_back(k);
+            load[top.second] += pieces[k].count;
+            heap.push({load[top.second], top.second});
+        }
+        for (int w = 0; w < kModeWaves; ++w) {
+            int t = 0;
+            for (int L = 0; L < 64; ++L) t = std::max(t, load[w * 64 + L]);
+            sub_off[w + 1] = sub_off[w] + (t + kSlots - 1) / kSlots * kSlots;
+        }
+        const int T = std::max(sub_off[kModeWaves], kSlots);
+        dp.T = T;
+        il_ij.assign((size_t)T * 64, 0);
+        for (int w = 0; w < NW; ++w) {
+            const int sub = w / 64, L = w % 64;
+            int t = sub_off[sub];
+            for (int k : wpieces[w]) {
+                const Piece& pc = pieces[k];
+                for (int r = pc.first; r < pc.first + pc.count; ++r, ++t) {
+                    const size_t slot = (size_t)t * 64 + L;
+                    const bool last = r + 1 == pc.first + pc.count;
+                    il_ij[slot] = (last ? (int)0x80000000u : 0) | (pc.dest << 16) | P.irr_j[r];
+                    il_pos[r] = (int)slot;
+                }
+            }
+        }
+        dp.n_split = (int)split.size() / 3;
     }
-    // interleaved layout: the t-th node of lane L at slot t*64 + L
-    int T = 1;
-    for (int L = 0; L < 64; ++L) T = std::max(T, laneptr[L + 1] - laneptr[L]);
-    T = (T + kSlots - 1) / kSlots * kSlots;
-    dp.T = T;
-    std::vector<int> il_ij((size_t)T * 64, 0), il_pos(std::max(p->I, 1), 0);
-    for (int L = 0; L < 64; ++L)
-        for (int r = laneptr[L]; r < laneptr[L + 1]; ++r) {
-            const int slot = (r - laneptr[L]) * 64 + L;
-            const bool last = r + 1 == laneptr[L + 1] || P.irr_i[r + 1] != P.irr_i[r];
-            // the column's place in a wavefront's padded mode-solution layout
-            const int xpos = P.irr_i[r] + (P.irr_i[r] - 1) / (n / 64);
-            il_ij[slot] = (last ? (int)0x80000000u : 0) | (xpos << 16) | P.irr_j[r];
-            il_pos[r] = slot;
-        }
     std::vector<int4> cpk(p->M);
     for (int k = 0; k < p->M; ++k) cpk[k] = make_int4(P.cp_i0[k], P.cp_j0[k], sxy[k], 0);
     if ((st = upload(p, &dp.q_geo, P.q_geo)) || (st = upload(p, &dp.q_axis, P.q_axis)) ||
@@ -502,7 +555,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = upload(p, &dp.irr_i, P.irr_i)) || (st = upload(p, &dp.irr_j, P.irr_j)) ||
         (st = upload(p, &dp.irr_s, P.irr_s)) || (st = upload(p, &dp.arm_q, P.arm_q)) ||
         (st = upload(p, &dp.arm_d, P.arm_d)) || (st = upload(p, &dp.col_ptr, colptr)) ||
-        (st = upload(p, &dp.lane_ptr, laneptr)) || (st = upload(p, &dp.il_ij, il_ij)) ||
+        (st = upload(p, &dp.sub_off, sub_off)) || (st = upload(p, &dp.split, split)) || (st = upload(p, &dp.il_ij, il_ij)) ||
         (st = upload(p, &dp.il_pos, il_pos)) || (st = upload(p, &dp.cp_pack, cpk)) ||
         (st = upload(p, &dp.cp_i0, P.cp_i0)) || (st = upload(p, &dp.cp_j0, P.cp_j0)) ||
         (st = upload(p, &dp.cp_sxy, sxy)) || (st = upload(p, &dp.cp_w, P.cp_w)) ||
@@ -724,10 +777,10 @@ kfbi_status kfbi_apply_timing(kfbi_prob* p, double* a, double* b, double* c, int
 
 namespace {
 
-bool tiles_valid(const kfbi_prob* p, int W, int G, int B) {
-    if (W != 1 && W != 2 && W != 4 && W != 8) return false;
-    if (modes_lds_bytes(p->N, p->M, W) > p->ctx->lds_max) return false;
-    if (G < 1 || G > p->Gcap || G > (p->n + W - 1) / W) return false;
+bool tiles_valid(const kfbi_prob* p, int Rm, int B) {
+    if (Rm < 1 || Rm > kMaxModesPerGroup || (Rm & (Rm - 1))) return false;
+    if (modes_lds_bytes(p->N, Rm) > p->ctx->lds_max) return false;
+    if ((p->n + Rm - 1) / Rm > p->Gcap) return false;
     return dst_tile_ok(p->N, B, cpx_bytes(p->precision), p->ctx->lds_max);
 }
 
@@ -766,7 +819,7 @@ extern "C" {
 
 kfbi_status kfbi_prob_get_tiles(const kfbi_prob* p, kfbi_tiles* out) {
     if (!p || !out) return set_err(KFBI_ERR_ARG, "NULL argument");
-    out->modes_waves = p->W;
+    out->modes_per_group = p->Rm;
     out->modes_groups = p->G;
     out->dst_cols = p->dstB;
     out->apply_us = p->tuned_apply_us;
@@ -776,12 +829,12 @@ kfbi_status kfbi_prob_get_tiles(const kfbi_prob* p, kfbi_tiles* out) {
 
 kfbi_status kfbi_prob_set_tiles(kfbi_prob* p, const kfbi_tiles* t) {
     if (!p || !t) return set_err(KFBI_ERR_ARG, "NULL argument");
-    if (!tiles_valid(p, t->modes_waves, t->modes_groups, t->dst_cols))
+    if (!tiles_valid(p, t->modes_per_group, t->dst_cols))
         return set_err(KFBI_ERR_ARG, "tile shape not valid for this problem");
     HIP_TRY(hipSetDevice(p->ctx->device));
     HIP_TRY(hipStreamSynchronize(p->ctx->stream));      // a replayed graph may still use the old shape
-    p->W = t->modes_waves;
-    p->G = t->modes_groups;
+    p->Rm = t->modes_per_group;
+    p->G = (p->n + p->Rm - 1) / p->Rm;
     p->dstB = t->dst_cols;
     drop_graph(p);
     return KFBI_OK;
@@ -794,41 +847,36 @@ kfbi_status kfbi_prob_autotune(kfbi_prob* p, int reps, kfbi_tiles* out) {
     hipStream_t s = p->ctx->stream;
     HIP_TRY(hipStreamSynchronize(s));
     drop_graph(p);
-    const int ncu = p->ctx->num_cu;
     // a zero density in tmpM with its spline in s2a: the values do not change the work
     HIP_TRY(hipMemsetAsync(p->tmpM, 0, sizeof(double) * p->M, s));
     HIP_TRY(hipMemsetAsync(p->s2a, 0, sizeof(double) * p->M, s));
     double best = 1e300;
-    int bw = p->W, bg = p->G;
-    for (int W : {1, 2, 4, 8}) {
-        std::vector<int> gs = {ncu / 2, ncu, 2 * ncu, (p->n + W - 1) / W};
-        std::sort(gs.begin(), gs.end());
-        gs.erase(std::unique(gs.begin(), gs.end()), gs.end());
-        for (int G : gs) {
-            if (!tiles_valid(p, W, G, p->dstB)) continue;
-            p->W = W;
-            p->G = G;
-            double us = 0;
-            if (kfbi_status e = time_us(s, reps, &us, [&] { return sparse_apply(p, p->tmpM, p->s2a, p->s2b, nullptr, nullptr, s); })) {
-                p->W = bw;
-                p->G = bg;
-                return e;
-            }
-            if (us < best) {
-                best = us;
-                bw = W;
-                bg = G;
-            }
+    const int r0 = p->Rm;
+    int br = r0;
+    for (int Rm : {r0 / 2, r0, 2 * r0}) {
+        if (!tiles_valid(p, Rm, p->dstB)) continue;
+        p->Rm = Rm;
+        p->G = (p->n + Rm - 1) / Rm;
+        double us = 0;
+        if (kfbi_status e = time_us(s, reps, &us,
+                                    [&] { return sparse_apply(p, p->tmpM, p->s2a, p->s2b, nullptr, nullptr, s); })) {
+            p->Rm = r0;
+            p->G = (p->n + r0 - 1) / r0;
+            return e;
+        }
+        if (us < best) {
+            best = us;
+            br = Rm;
         }
     }
-    p->W = bw;
-    p->G = bg;
+    p->Rm = br;
+    p->G = (p->n + br - 1) / br;
     p->tuned_apply_us = best;
     double bestg = 1e300;
     int bb = p->dstB;
     const double* V = nullptr;
     for (int B : {4, 8, 16}) {
-        if (!tiles_valid(p, p->W, p->G, B)) continue;
+        if (!tiles_valid(p, p->Rm, B)) continue;
         p->dstB = B;
         double us = 0;
         if (kfbi_status e = time_us(s, reps, &us, [&] {
@@ -988,7 +1036,7 @@ BatchWork batch_work(const kfbi_batch* B) {
 
 kfbi_status batch_enqueue_steps(kfbi_batch* B, int nsteps, hipStream_t s) {
     for (int k = 0; k < nsteps; ++k)
-        HIP_TRY(launch_batch_step(B->d_slots, batch_work(B), kBatchNmax, B->mmax, B->ctx->num_cu, s));
+        HIP_TRY(launch_batch_step(B->d_slots, batch_work(B), B->ctx->num_cu, s));
     return KFBI_OK;
 }
 
@@ -1000,7 +1048,8 @@ void batch_ensure_graph(kfbi_batch* B) {
 }
 
 size_t batch_extra_bytes(int n, int m) {
-    const int Gs = (n - 1 + kBatchW - 1) / kBatchW;
+    const int r = batch_modes_per_group(n);
+    const int Gs = (n - 1 + r - 1) / r;
     return sizeof(double) * (size_t)m * Gs;
 }
 
@@ -1030,8 +1079,8 @@ kfbi_status kfbi_batch_create(kfbi_ctx* ctx, int max_slots, int m_max, size_t bu
     if (!ctx || !out || max_slots < 1 || max_slots > 1024 || m_max < 3 || m_max > kMaxSamples)
         return set_err(KFBI_ERR_ARG, "bad batch arguments");
     HIP_TRY(hipSetDevice(ctx->device));
-    if (modes_b_lds_bytes(kBatchNmax, m_max) > ctx->lds_max)
-        return set_err(KFBI_ERR_UNSUPPORTED, "m_max too large for the batched fast solve's LDS");
+    if (modes_b_lds_bytes() > ctx->lds_max)
+        return set_err(KFBI_ERR_UNSUPPORTED, "the batched fast solve does not fit this device's LDS");
     kfbi_batch* B = new (std::nothrow) kfbi_batch;
     if (!B) return set_err(KFBI_ERR_ARG, "host allocation failed");
     B->ctx = ctx;
@@ -1092,7 +1141,8 @@ kfbi_status kfbi_batch_admit(kfbi_batch* B, kfbi_prob* p, const double* f_grid, 
     HIP_TRY(hipSetDevice(B->ctx->device));
     hipStream_t s = B->ctx->stream;
     if (!p->partial_b) {
-        p->Gs = (p->n + kBatchW - 1) / kBatchW;
+        const int r = batch_modes_per_group(p->N);
+        p->Gs = (p->n + r - 1) / r;
         if (kfbi_status e = dev_alloc(p, &p->partial_b, (size_t)p->M * p->Gs)) return e;
     }
     // g^ = g - (Y f)^+ and a fresh GMRES state (phi_0 = 0)

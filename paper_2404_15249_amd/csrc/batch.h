@@ -7,8 +7,18 @@
 
 namespace kfbi {
 
-constexpr int kBatchW = 4;          // waves (sine modes) per workgroup in the batched fast solve
 constexpr int kBatchNmax = 2048;    // largest grid a batch serves
+// LDS of the batched fast solve holds this many doubles of mode solutions
+// (and, after them, kMaxModesPerGroup x kMaxExtra sums of extra pieces)
+constexpr int kBatchXs = 8 * (kBatchNmax + 64);
+
+// Modes per workgroup of a batched problem with grid N: the largest power of two
+// up to kMaxModesPerGroup whose padded solutions fit kBatchXs.
+__host__ __device__ constexpr int batch_modes_per_group(int N) {
+    int R = kMaxModesPerGroup;
+    while (R > 1 && R * (N + 64) > kBatchXs) R /= 2;
+    return R;
+}
 
 // One live problem of a batch, resident in device memory.
 struct SlotDev {
@@ -16,7 +26,7 @@ struct SlotDev {
     GmresBufs b;
     double* corr_il;   // interleaved corrections (T x 64)
     double* partial;   // Gs x M partial sums, one row per mode block
-    int Gs;            // mode blocks: ceil((n-1) / kBatchW)
+    int Gs;            // mode blocks: ceil((n-1) / batch_modes_per_group(N))
     int pad;
 };
 
@@ -26,7 +36,7 @@ struct SlotDev {
 struct BatchWork {
     const int* counts;
     const int2* corr_items;   // blocks of 256 irregular nodes
-    const int2* mode_items;   // mode blocks of kBatchW modes
+    const int2* mode_items;   // mode blocks of batch_modes_per_group(N) modes
     const int2* cp_items;     // blocks of 64 samples
     const int* live;          // live slot ids
     const int2* gm_items;     // (slot, chunk) of the GMRES vector launches
@@ -34,7 +44,7 @@ struct BatchWork {
 };
 constexpr int kBatchCounts = 5;
 
-size_t modes_b_lds_bytes(int Nmax, int Mmax);
-hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s);
+size_t modes_b_lds_bytes();
+hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int n_cu, hipStream_t s);
 
 }  // namespace kfbi

@@ -31,11 +31,19 @@ __global__ __launch_bounds__(256) void k_correct_b(const SlotDev* __restrict__ s
     }
 }
 
-template <int W>
-__global__ __launch_bounds__(W * 64) void k_modes_b(const SlotDev* __restrict__ slots, BatchWork w, int Nmax,
-                                                    int Mmax) {
+template <int C>
+__device__ __forceinline__ void modes_item(const DevPlan& p, const double* corr, int row, const ModesLds& L,
+                                           double* part) {
+    constexpr int R = batch_modes_per_group(64 * C);
+    modes_round<C, R>(p, corr, row * R, L, [&](int cp, double s) { part[(size_t)row * p.M + cp] = s; });
+}
+
+__global__ __launch_bounds__(kModeWaves * 64) void k_modes_b(const SlotDev* __restrict__ slots, BatchWork w) {
     extern __shared__ double smem[];
-    const ModesLds L = modes_lds<W>(smem, Nmax, Mmax);
+    ModesLds L;
+    L.sq = smem;
+    L.xs = smem + (kBatchNmax / 2 + 2);
+    L.ex = L.xs + kBatchXs;
     const int n_items = w.counts[1];
     int curN = -1;
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
@@ -45,20 +53,16 @@ __global__ __launch_bounds__(W * 64) void k_modes_b(const SlotDev* __restrict__ 
         const DevPlan& p = S.p;
         if (p.N != curN) {
             __syncthreads();
-            for (int k = threadIdx.x; k <= p.N / 2; k += W * 64) L.sq[k] = p.sinq[k];
+            for (int k = threadIdx.x; k <= p.N / 2; k += kModeWaves * 64) L.sq[k] = p.sinq[k];
             curN = p.N;
         }
-        double* part = S.partial;
-        const int Gs = S.Gs, row = item.y;
-        auto emit = [&](int cp, double s) { part[(size_t)row * p.M + cp] = s; };
-        const int base = row * W;
         switch (p.N) {
-            case 64: modes_round<1, W>(p, S.corr_il, base, L, emit); break;
-            case 128: modes_round<2, W>(p, S.corr_il, base, L, emit); break;
-            case 256: modes_round<4, W>(p, S.corr_il, base, L, emit); break;
-            case 512: modes_round<8, W>(p, S.corr_il, base, L, emit); break;
-            case 1024: modes_round<16, W>(p, S.corr_il, base, L, emit); break;
-            default: modes_round<32, W>(p, S.corr_il, base, L, emit); break;
+            case 64: modes_item<1>(p, S.corr_il, item.y, L, S.partial); break;
+            case 128: modes_item<2>(p, S.corr_il, item.y, L, S.partial); break;
+            case 256: modes_item<4>(p, S.corr_il, item.y, L, S.partial); break;
+            case 512: modes_item<8>(p, S.corr_il, item.y, L, S.partial); break;
+            case 1024: modes_item<16>(p, S.corr_il, item.y, L, S.partial); break;
+            default: modes_item<32>(p, S.corr_il, item.y, L, S.partial); break;
         }
     }
 }
@@ -95,20 +99,17 @@ __global__ __launch_bounds__(kGmChunk) void k_gm_vec_b(const SlotDev* __restrict
 
 }  // namespace
 
-size_t modes_b_lds_bytes(int Nmax, int Mmax) {
-    return sizeof(double) * ((size_t)(Nmax / 2 + 2) + (size_t)kBatchW * (Nmax + 64) + (size_t)Mmax) +
-           (sizeof(double) + sizeof(int)) * 2 * kChunk;
+size_t modes_b_lds_bytes() {
+    return sizeof(double) * ((size_t)(kBatchNmax / 2 + 2) + (size_t)kBatchXs + (size_t)kMaxModesPerGroup * kMaxExtra);
 }
 
-hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int Nmax, int Mmax, int n_cu, hipStream_t s) {
-    const size_t lds = modes_b_lds_bytes(Nmax, Mmax);
-    if (hipError_t e = hipFuncSetAttribute((const void*)k_modes_b<kBatchW>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds))
+hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int n_cu, hipStream_t s) {
+    const size_t lds = modes_b_lds_bytes();
+    if (hipError_t e = hipFuncSetAttribute((const void*)k_modes_b, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
         return e;
     const dim3 t(kGmChunk), gv(n_cu);
     if (hipError_t e = klaunch(&k_correct_b, dim3(n_cu * 2), dim3(256), 0, s, slots, w)) return e;
-    if (hipError_t e = klaunch(&k_modes_b<kBatchW>, dim3(n_cu), dim3(kBatchW * 64), lds, s, slots, w, Nmax, Mmax))
-        return e;
+    if (hipError_t e = klaunch(&k_modes_b, dim3(n_cu), dim3(kModeWaves * 64), lds, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_reduce_b, dim3(n_cu), dim3(1024), 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_gm_vec_b<1>, gv, t, 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_gm_vec_b<2>, gv, t, 0, s, slots, w)) return e;

@@ -144,6 +144,71 @@ __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, 
     if (lane == 63) e[C - 1] = 0.0;
 }
 
+// mode_solve on a wavefront's padded solution in LDS (node i at
+// i + (i - 1) / C, values scaled by h2 on the way in), for chunks too long to
+// keep in registers: the same steps, streamed through LDS.
+template <int C>
+__device__ __forceinline__ void mode_solve_lds(double* x, const ModeConst& mc, int lane, int N, double h2) {
+    double* e = x + lane * (C + 1) + 1;
+    const double r = mc.r;
+    double w = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < C; ++c) {
+        w = r * (w - e[c] * h2);
+        e[c] = w;
+    }
+    double val = w, mul = mc.rC;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_up(val, off, 64);
+        if (lane >= off) val += mul * t;
+        mul *= mul;
+    }
+    double carry = __shfl_up(val, 1, 64);
+    if (lane == 0) carry = 0.0;
+    double pw = r;
+#pragma unroll 8
+    for (int c = 0; c < C; ++c) {
+        e[c] += pw * carry;
+        pw *= r;
+    }
+    if (lane == 63) e[C - 1] = 0.0;
+    double y = 0.0;
+#pragma unroll 8
+    for (int c = C - 1; c >= 0; --c) {
+        y = e[c] + r * y;
+        e[c] = y;
+    }
+    val = y;
+    mul = mc.rC;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const double t = __shfl_down(val, off, 64);
+        if (lane + off < 64) val += mul * t;
+        mul *= mul;
+    }
+    carry = __shfl_down(val, 1, 64);
+    if (lane == 63) carry = 0.0;
+    pw = r;
+#pragma unroll 8
+    for (int c = C - 1; c >= 0; --c) {
+        e[c] += pw * carry;
+        pw *= r;
+    }
+    const double y1 = __shfl(e[0], 0, 64);
+    const int is = lane * C + 1;
+    double p1 = exp((double)is * mc.logr);
+    double p2 = exp((double)(2 * N - is) * mc.logr);
+    const double coef = y1 * mc.smc;
+#pragma unroll 8
+    for (int c = 0; c < C; ++c) {
+        e[c] += coef * (p1 - p2);
+        p1 *= r;
+        p2 *= mc.rinv;
+    }
+    if (lane == 63) e[C - 1] = 0.0;
+}
+
 // Jump terms of the stencil nodes outside Omega: the far-side value is moved to
 // the Omega side with the Taylor expansion of the jumps at the sample.
 __device__ inline double outside_terms(const DevPlan& p, const JumpSrc& js, int cp, const int (&ni)[6], const int (&nj)[6],
@@ -250,139 +315,139 @@ __device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, con
     __syncthreads();
 }
 
-// ---------------------------------------------------------------- sparse fast solve, one round of W modes
+// ---------------------------------------------------------------- sparse fast solve, R modes per workgroup
 //
-// LDS of the sparse fast solve: the quarter sine table, W padded per-wave mode
+// LDS of the sparse fast solve: the quarter sine table and R padded mode
 // solutions (node i at i + (i - 1) / C, so the lanes' chunk-strided accesses
-// fall in different banks), M accumulators and a double-buffered chunk of the
-// interleaved table.  The region sizes follow the largest N and M served.
+// fall in different banks).
 struct ModesLds {
-    double* sq;
-    double* xs;
-    double* acc;
-    double* bcv;
-    int* bij;
+    double* sq;   // N/2 + 2
+    double* xs;   // R x (N + 64)
+    double* ex;   // R x kMaxExtra: sums of the extra pieces of long columns
 };
 
-template <int W>
-__device__ __forceinline__ ModesLds modes_lds(double* smem, int Nmax, int Mmax) {
+template <int R>
+__device__ __forceinline__ ModesLds modes_lds(double* smem, int N) {
     ModesLds L;
-    L.sq = smem;                                        // Nmax/2 + 2
-    L.xs = L.sq + (Nmax / 2 + 2);                       // W (Nmax + 64)
-    L.acc = L.xs + W * (Nmax + 64);                     // Mmax
-    L.bcv = L.acc + Mmax;                               // 2 kChunk
-    L.bij = reinterpret_cast<int*>(L.bcv + 2 * kChunk); // 2 kChunk
+    L.sq = smem;
+    L.xs = smem + (N / 2 + 2);
+    L.ex = L.xs + (size_t)R * (N + 64);
     return L;
 }
 
-// Sine modes l = base + wave + 1 (<= n), one per wave: the sparse sine sums of
-// the corrected right-hand side along y (lane L owns whole columns; its
-// irregular nodes sit at slots t*64 + L of the interleaved table, staged
-// through LDS in double-buffered chunks so all waves share one read, with the
-// global loads issued kDepth chunks ahead), the
-// tridiagonal solve along x, and the weighted six-point gather at every
-// sample.  Calls emit(cp, s) for the samples cp = tid, tid + 64 W, ... with the
-// sum over the round's modes.  Must be called by the whole workgroup; L.sq must
-// hold the sine table of p.N.
-template <int C, int W, class Emit>
+// Sine modes l = base + 1 .. base + R (those <= n) by a workgroup of
+// kModeWaves wavefronts.
+//  1. Sparse sine sums of the corrected right-hand side along y: wavefront w
+//     walks sub-table w of the interleaved node table (each lane owns whole
+//     columns); per node the sines of all R modes come from two table lookups
+//     and the angle-addition recurrence sin((l+1)t) = sin(lt) cos t + cos(lt) sin t,
+//     and a column's R sums are stored when its last node is reached.
+//  2. The tridiagonal solve along x of each mode (one wavefront per mode).
+//  3. The weighted six-point gather at every sample: emit(cp, s) with s the sum
+//     over the R modes, for cp = tid, tid + 64 kModeWaves, ...
+// L.sq must hold the sine table of p.N; must be called by the whole workgroup.
+template <int C, int R, class Emit>
 __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __restrict__ corr, int base,
                                             const ModesLds& L, Emit emit) {
     constexpr int XS = 64 * (C + 1);
-    const int N = p.N, n = p.n, M = p.M, mask2 = 2 * N - 1;
+    constexpr int NT = kModeWaves * 64;
+    const int N = p.N, n = p.n, M = p.M, mask2 = 2 * N - 1, half = N / 2;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const double* sq = L.sq;
-    double* x = L.xs + wave * XS;
-    double* bcv = L.bcv;
-    int* bij = L.bij;
-    const int nch = p.T / kSlots;                       // T is a multiple of kSlots
-    const int l = base + wave + 1;
-    const bool active = l <= n;
-#pragma unroll
-    for (int c = 0; c < C; ++c) x[lane * (C + 1) + 1 + c] = 0.0;
-    if (lane == 0) x[0] = 0.0;
-    // Staging pipeline: chunk c of the table travels global -> registers (slot
-    // c % kDepth, issued kDepth iterations before it is needed) -> LDS buffer
-    // c & 1 (written one iteration before it is read), so the global latency
-    // overlaps the sums of the chunks in between.
-    constexpr int NT = W * 64;
-    constexpr int E = (kChunk + NT - 1) / NT;           // table entries per thread per chunk
-    int rij[kDepth][E];
-    double rcv[kDepth][E];
-    auto gload = [&](int slot, int ch) {
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int e = tid + q * NT;
-            if (ch < nch && e < kChunk) {
-                rij[slot][q] = p.il_ij[(size_t)ch * kChunk + e];
-                rcv[slot][q] = corr[(size_t)ch * kChunk + e];
-            }
-        }
-    };
-    auto lstore = [&](int slot, int buf) {
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int e = tid + q * NT;
-            if (e < kChunk) {
-                bij[buf * kChunk + e] = rij[slot][q];
-                bcv[buf * kChunk + e] = rcv[slot][q];
-            }
-        }
-    };
-#pragma unroll
-    for (int d = 0; d < kDepth; ++d) gload(d, d);
-    lstore(0, 0);
-    gload(0, kDepth);
+    const int l0 = base + 1;
+    const int nact = min(R, n - base);                  // modes of this round that exist
+    for (int k = tid; k < R * XS; k += NT) L.xs[k] = 0.0;
     __syncthreads();
-    double run = 0.0;
-    for (int ch0 = 0; ch0 < nch; ch0 += kDepth) {
+    {
+        const int t_beg = p.sub_off[wave], t_end = p.sub_off[wave + 1];   // multiples of kSlots
+        double acc[R];
 #pragma unroll
-        for (int d = 0; d < kDepth; ++d) {
-            const int ch = ch0 + d;
-            if (ch < nch) {
-                const int cur = ch & 1;
-                if (ch + 1 < nch) {
-                    lstore((d + 1) % kDepth, 1 - cur);
-                    gload((d + 1) % kDepth, ch + 1 + kDepth);
+        for (int r = 0; r < R; ++r) acc[r] = 0.0;
+        int pk[kSlots], pkn[kSlots];
+        double cv[kSlots], cvn[kSlots];
+        if (t_beg < t_end) {
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) {
+                pk[q] = p.il_ij[(size_t)(t_beg + q) * 64 + lane];
+                cv[q] = corr[(size_t)(t_beg + q) * 64 + lane];
+            }
+        }
+        for (int t0 = t_beg; t0 < t_end; t0 += kSlots) {
+            const bool more = t0 + kSlots < t_end;      // next group's loads overlap this group's sums
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < kSlots; ++q) {
+                    pkn[q] = p.il_ij[(size_t)(t0 + kSlots + q) * 64 + lane];
+                    cvn[q] = corr[(size_t)(t0 + kSlots + q) * 64 + lane];
                 }
-                if (active) {
-                    // all loads of the chunk first, then the sums: the LDS
-                    // latencies overlap instead of adding up slot by slot
-                    int pk[kSlots];
-                    double cv[kSlots], sv[kSlots];
+            }
 #pragma unroll
-                    for (int s = 0; s < kSlots; ++s) {
-                        pk[s] = bij[cur * kChunk + s * 64 + lane];
-                        cv[s] = bcv[cur * kChunk + s * 64 + lane];
-                    }
+            for (int q = 0; q < kSlots; ++q) {
+                const int j = pk[q] & 0xfff;
+                const int m0 = (int)(__umul24((unsigned)j, (unsigned)l0) & mask2);
+                double sn = sinpi_n(sq, m0, N);
+                double cs = sinpi_n(sq, (m0 + half) & mask2, N);
+                const double s1 = R > 1 ? sinpi_n(sq, j, N) : 0.0;
+                const double c1 = R > 1 ? sinpi_n(sq, (j + half) & mask2, N) : 0.0;
 #pragma unroll
-                    for (int s = 0; s < kSlots; ++s)
-                        sv[s] = sinpi_n(sq, (int)(__umul24((unsigned)(pk[s] & 0xfff), (unsigned)l) & mask2), N);
-#pragma unroll
-                    for (int s = 0; s < kSlots; ++s) {
-                        run += cv[s] * sv[s];
-                        if (pk[s] < 0) {                // last node of its column
-                            x[(pk[s] >> 16) & 0x7fff] = run;
-                            run = 0.0;
-                        }
+                for (int r = 0; r < R; ++r) {
+                    acc[r] = fma(cv[q], sn, acc[r]);
+                    if (r + 1 < R) {
+                        const double sn2 = sn * c1 + cs * s1;
+                        cs = cs * c1 - sn * s1;
+                        sn = sn2;
                     }
                 }
-                __syncthreads();
+                if (pk[q] < 0) {                        // last node of its piece
+                    const int dest = (pk[q] >> 16) & 0x7fff;
+                    double* to = dest < kExtraFlag ? L.xs + dest : L.ex + (dest - kExtraFlag);
+                    const int stride = dest < kExtraFlag ? XS : kMaxExtra;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        if (r < nact) to[r * stride] = acc[r];
+                        acc[r] = 0.0;
+                    }
+                }
+            }
+            if (more) {
+#pragma unroll
+                for (int q = 0; q < kSlots; ++q) {
+                    pk[q] = pkn[q];
+                    cv[q] = cvn[q];
+                }
             }
         }
     }
-    if (active) {
-        double e[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) e[c] = x[lane * (C + 1) + 1 + c] * p.h2;
-        mode_solve<C>(e, p.modes[l], lane, N);
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (lane < 63 || c < C - 1) x[lane * (C + 1) + 1 + c] = e[c];
+    __syncthreads();
+    // long columns: add their extra pieces in a fixed order
+    for (int k = tid; k < p.n_split * R; k += NT) {
+        const int c = k / R, r = k % R;
+        if (r < nact) {
+            const int pos = p.split[3 * c], e0 = p.split[3 * c + 1], ne = p.split[3 * c + 2];
+            double v = L.xs[r * XS + pos];
+            for (int e = 0; e < ne; ++e) v += L.ex[r * kMaxExtra + e0 + e];
+            L.xs[r * XS + pos] = v;
+        }
     }
     __syncthreads();
-    for (int cp = tid; cp < M; cp += W * 64) {
-        const int4 pk = p.cp_pack[cp];
-        const int i0 = pk.x, j0 = pk.y, sxy = pk.z;
+    for (int r = wave; r < nact; r += kModeWaves) {
+        double* x = L.xs + r * XS;
+        if constexpr (C > 32) {
+            mode_solve_lds<C>(x, p.modes[l0 + r], lane, N, p.h2);
+        } else {
+            double e[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) e[c] = x[lane * (C + 1) + 1 + c] * p.h2;
+            mode_solve<C>(e, p.modes[l0 + r], lane, N);
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (lane < 63 || c < C - 1) x[lane * (C + 1) + 1 + c] = e[c];
+        }
+    }
+    __syncthreads();
+    for (int cp = tid; cp < M; cp += NT) {
+        const int4 pk4 = p.cp_pack[cp];
+        const int i0 = pk4.x, j0 = pk4.y, sxy = pk4.z;
         const int sx = (sxy & 1) ? 1 : -1;
         const bool syp = (sxy & 2) != 0;
         const double2* w2 = reinterpret_cast<const double2*>(p.cp_w + 6 * (size_t)cp);
@@ -391,14 +456,13 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
         // places of the stencil columns in the padded layout (node 0 lies on
         // the box: zero); the sine arguments advance by j per mode
         const int pc = i0 + (i0 - 1) / C, pe = i0 + i0 / C + 1, pw = i0 > 1 ? i0 - 1 + (i0 - 2) / C : -1;
-        const int l0 = base + 1;
         int a0 = (int)(__umul24((unsigned)j0, (unsigned)l0) & mask2);
         int ap = (int)(__umul24((unsigned)(j0 + 1), (unsigned)l0) & mask2);
         int am = (int)(__umul24((unsigned)(j0 - 1), (unsigned)l0) & mask2);
         double s = 0.0;
-        // modes beyond n belong to idle wavefronts, whose solutions are zero
+        // modes beyond n were never written: their solutions are zero
 #pragma unroll
-        for (int q = 0; q < W; ++q) {
+        for (int q = 0; q < R; ++q) {
             const double* xq = L.xs + q * XS;
             const double s0 = sinpi_n(sq, a0, N);
             const double sp = sinpi_n(sq, ap, N);

@@ -35,12 +35,17 @@ struct DevPlan {
     const int* arm_q;         // 4 I
     const double* arm_d;      // 4 I
     const int* col_ptr;       // N + 1 entries used (i = 0..N)
-    const int* lane_ptr;      // 65: irregular nodes [lane_ptr[L], lane_ptr[L+1]) feed lane L of the
-                              // sparse sine sums; the cuts fall on column starts
-    const int* il_ij;         // T x 64, slot t*64 + L: the t-th node (i, j) of lane L packed as
-                              // (last-of-column << 31) | (xpos << 16) | j  (0: pad), where
-                              // xpos = i + (i - 1) / (N / 64) is column i's place in the padded
-                              // per-wavefront mode solution of the sparse fast solve
+    const int* sub_off;       // kModeWaves + 1: rows [sub_off[w], sub_off[w+1]) of the interleaved
+                              // table are sub-table w (multiples of kSlots)
+    const int* split;         // 3 n_split: (place, first extra piece, extra pieces) of each column
+                              // whose nodes are cut into several pieces (see il_ij)
+    int n_split;
+    const int* il_ij;         // T x 64, slot t*64 + L: node (i, j) of lane L of the sub-table owning row t, packed as
+                              // (last-of-piece << 31) | (dest << 16) | j  (0: pad).  A column's nodes
+                              // form one piece, or several when the column is long; dest of the
+                              // first piece is xpos = i + (i - 1) / (N / 64), column i's place in
+                              // the padded per-wavefront mode solution; dest of an extra piece is
+                              // kExtraFlag | its index in the extra-sums buffer
     const int* il_pos;        // I: slot of irregular node r in the interleaved layout
     int T;                    // slots per lane, a multiple of kSlots
     const int4* cp_pack;      // M: (i0, j0, sxy, 0)
@@ -57,9 +62,11 @@ struct DevPlan {
 };
 
 constexpr int kSplineK = 30;
-constexpr int kSlots = 4;          // table slots per LDS chunk of the sparse sine sums
-constexpr int kChunk = kSlots * 64;
-constexpr int kDepth = 4;          // table chunks in flight (global loads issued ahead of use)
+constexpr int kSlots = 4;          // table rows loaded together by the sparse sine sums
+constexpr int kModeWaves = 8;      // wavefronts of a sparse-fast-solve workgroup (= node sub-tables)
+constexpr int kMaxModesPerGroup = 8;
+constexpr int kMaxExtra = 128;      // extra pieces of long columns (per mode, in LDS)
+constexpr int kExtraFlag = 0x4000;  // dest field of an extra piece
 constexpr int kMaxRestart = 64;
 constexpr int kMaxSamples = 12288; // boundary samples per problem (the GMRES step keeps one M-vector in LDS)   // GMRES restart length cap (LDS-resident Hessenberg)
 
@@ -115,7 +122,9 @@ struct GmresBufs {
 // launchers (return hipError_t of the launch)
 hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* corr_il, double* dense,
                           const int* skip, hipStream_t s);
-hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int G, int W,
+// R modes per workgroup (a power of two <= kMaxModesPerGroup whose LDS fits);
+// ceil((N-1) / R) workgroups, each writing one row of M partial sums
+hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int R,
                         const int* skip, hipStream_t s);
 hipError_t launch_spline(const DevPlan& p, const double* y, double* s2, const int* skip, hipStream_t s);
 // with gm non-null (a GMRES step) the output goes to gm->w, the launch is skipped
@@ -150,6 +159,6 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
                         hipStream_t s);
 hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s);
 
-size_t modes_lds_bytes(int N, int M, int W);
+size_t modes_lds_bytes(int N, int R);
 
 }  // namespace kfbi

@@ -6,15 +6,16 @@
 //              (Alg. 2 line 5).  For the double-layer apply F = 0, so the
 //              right-hand side of the corrected system is nonzero only here.
 //   k_modes    the fast solver (Alg. 4) restricted to what the interpolation
-//              reads.  Along y the right-hand side is expanded in sines; for a
-//              sparse right-hand side each coefficient is a short sum over the
-//              irregular nodes of one grid column.  Along x each sine mode is a
-//              constant-coefficient tridiagonal system, solved by one wavefront
-//              as two first-order recurrences (chunked, with wave-wide carry
-//              scans) plus a rank-one boundary fix.  The inverse sine sum along
-//              y is evaluated only at the six stencil nodes of each boundary
-//              sample, already weighted by the interpolation weights, and summed
-//              per workgroup into a partial result.
+//              reads, R sine modes per workgroup.  Along y the right-hand side
+//              is expanded in sines; for a sparse right-hand side each
+//              coefficient is a short sum over the irregular nodes of one grid
+//              column.  Along x each sine mode is a constant-coefficient
+//              tridiagonal system, solved by one wavefront as two first-order
+//              recurrences (chunked, with wave-wide carry scans) plus a rank-one
+//              boundary fix.  The inverse sine sum along y is evaluated only at
+//              the six stencil nodes of each boundary sample, already weighted
+//              by the interpolation weights, and written as the workgroup's row
+//              of partial sums.
 //   k_reduce_interp  one wavefront per sample: the partials summed in a fixed
 //              order plus the jump terms of the stencil nodes outside Omega
 //              (Alg. 3).
@@ -51,19 +52,15 @@ __global__ __launch_bounds__(256) void k_correct(DevPlan p, JumpSrc js, double* 
 
 // ---------------------------------------------------------------- sparse fast solve + weighted gather
 
-template <int C, int W>
-__global__ __launch_bounds__(W * 64) void k_modes(DevPlan p, const double* __restrict__ corr,
-                                                  double* __restrict__ partial, int G, const int* __restrict__ skip) {
+template <int C, int R>
+__global__ __launch_bounds__(kModeWaves * 64) void k_modes(DevPlan p, const double* __restrict__ corr,
+                                                          double* __restrict__ partial, const int* __restrict__ skip) {
     if (skip && *skip) return;
     extern __shared__ double smem[];
-    const int N = p.N, M = p.M;
-    ModesLds L = modes_lds<W>(smem, N, M);
-    const int tid = threadIdx.x;
-    for (int k = tid; k <= N / 2; k += W * 64) L.sq[k] = p.sinq[k];
-    for (int k = tid; k < M; k += W * 64) L.acc[k] = 0.0;
-    for (int base = blockIdx.x * W; base < p.n; base += gridDim.x * W)
-        modes_round<C, W>(p, corr, base, L, [&](int cp, double s) { L.acc[cp] += s; });
-    for (int cp = tid; cp < M; cp += W * 64) partial[(size_t)blockIdx.x * M + cp] = L.acc[cp];
+    const ModesLds L = modes_lds<R>(smem, p.N);
+    for (int k = threadIdx.x; k <= p.N / 2; k += kModeWaves * 64) L.sq[k] = p.sinq[k];
+    double* row = partial + (size_t)blockIdx.x * p.M;
+    modes_round<C, R>(p, corr, blockIdx.x * R, L, [&](int cp, double v) { row[cp] = v; });
 }
 
 // ---------------------------------------------------------------- spline of a density
@@ -184,33 +181,30 @@ __global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_u
 __global__ __launch_bounds__(kGmChunk) void k_gm_emit(DevPlan p, GmresBufs b) { gm_emit(p, b, p.M, blockIdx.x); }
 
 
-template <int C>
-hipError_t modes_dispatch_w(const DevPlan& p, const double* corr, double* partial, int G, int W, const int* skip,
-                            hipStream_t s) {
-    const size_t lds = modes_lds_bytes(p.N, p.M, W);
-    switch (W) {
-        case 8:
-            if constexpr (C <= 32) {   // at N = 4096 eight mode solutions do not fit the local data share
-                if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-                if (hipError_t e_ = klaunch(&k_modes<C, 8>, dim3(G), dim3(512), lds, s, p, corr, partial, G, skip)) return e_;
-            } else {
-                return hipErrorInvalidValue;
-            }
-            break;
-        case 4:
-            if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            if (hipError_t e_ = klaunch(&k_modes<C, 4>, dim3(G), dim3(256), lds, s, p, corr, partial, G, skip)) return e_;
-            break;
-        case 2:
-            if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            if (hipError_t e_ = klaunch(&k_modes<C, 2>, dim3(G), dim3(128), lds, s, p, corr, partial, G, skip)) return e_;
-            break;
-        default:
-            if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
-            if (hipError_t e_ = klaunch(&k_modes<C, 1>, dim3(G), dim3(64), lds, s, p, corr, partial, G, skip)) return e_;
-            break;
+template <int C, int R>
+hipError_t modes_launch(const DevPlan& p, const double* corr, double* partial, const int* skip, hipStream_t s) {
+    constexpr size_t lds = sizeof(double) * ((size_t)(32 * C + 2) + (size_t)R * (64 * (C + 1) + kMaxExtra));
+    if constexpr (lds > 160 * 1024) {
+        return hipErrorInvalidValue;                  // never fits the local data share
+    } else {
+        if (hipError_t e = hipFuncSetAttribute((const void*)k_modes<C, R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds))
+            return e;
+        const int groups = (p.n + R - 1) / R;
+        return klaunch(&k_modes<C, R>, dim3(groups), dim3(kModeWaves * 64), lds, s, p, corr, partial, skip);
     }
-    return hipGetLastError();
+}
+
+template <int C>
+hipError_t modes_dispatch_r(const DevPlan& p, const double* corr, double* partial, int R, const int* skip,
+                            hipStream_t s) {
+    switch (R) {
+        case 1: return modes_launch<C, 1>(p, corr, partial, skip, s);
+        case 2: return modes_launch<C, 2>(p, corr, partial, skip, s);
+        case 4: return modes_launch<C, 4>(p, corr, partial, skip, s);
+        case 8: return modes_launch<C, 8>(p, corr, partial, skip, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int C, class T>
@@ -235,10 +229,8 @@ hipError_t rows_solve_any(const DevPlan& p, T* A, hipStream_t s) {
 
 }  // namespace
 
-size_t modes_lds_bytes(int N, int M, int W) {
-    // sine table, W padded mode solutions of 64 (C + 1) = N + 64 slots, M accumulators
-    return sizeof(double) * ((size_t)(N / 2 + 2) + (size_t)W * (N + 64) + (size_t)M) +
-           (sizeof(double) + sizeof(int)) * 2 * kChunk;
+size_t modes_lds_bytes(int N, int R) {
+    return sizeof(double) * ((size_t)(N / 2 + 2) + (size_t)R * (N + 64 + kMaxExtra));
 }
 
 hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* corr_il, double* dense,
@@ -248,16 +240,16 @@ hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* co
     return hipGetLastError();
 }
 
-hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int G, int W, const int* skip,
+hipError_t launch_modes(const DevPlan& p, const double* corr, double* partial, int R, const int* skip,
                         hipStream_t s) {
     switch (p.N) {
-        case 64: return modes_dispatch_w<1>(p, corr, partial, G, W, skip, s);
-        case 128: return modes_dispatch_w<2>(p, corr, partial, G, W, skip, s);
-        case 256: return modes_dispatch_w<4>(p, corr, partial, G, W, skip, s);
-        case 512: return modes_dispatch_w<8>(p, corr, partial, G, W, skip, s);
-        case 1024: return modes_dispatch_w<16>(p, corr, partial, G, W, skip, s);
-        case 2048: return modes_dispatch_w<32>(p, corr, partial, G, W, skip, s);
-        case 4096: return modes_dispatch_w<64>(p, corr, partial, G, W, skip, s);
+        case 64: return modes_dispatch_r<1>(p, corr, partial, R, skip, s);
+        case 128: return modes_dispatch_r<2>(p, corr, partial, R, skip, s);
+        case 256: return modes_dispatch_r<4>(p, corr, partial, R, skip, s);
+        case 512: return modes_dispatch_r<8>(p, corr, partial, R, skip, s);
+        case 1024: return modes_dispatch_r<16>(p, corr, partial, R, skip, s);
+        case 2048: return modes_dispatch_r<32>(p, corr, partial, R, skip, s);
+        case 4096: return modes_dispatch_r<64>(p, corr, partial, R, skip, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -49,7 +49,7 @@ _PRECISION = {"fp64": FP64, "fp32": FP32_REFINED}
 
 class Tiles(ct.Structure):
     """Launch shapes of a problem's kernels (``kfbi_tiles``)."""
-    _fields_ = [("modes_waves", ct.c_int), ("modes_groups", ct.c_int), ("dst_cols", ct.c_int),
+    _fields_ = [("modes_per_group", ct.c_int), ("modes_groups", ct.c_int), ("dst_cols", ct.c_int),
                 ("apply_us", ct.c_double), ("grid_solve_us", ct.c_double)]
 
     def as_dict(self):
@@ -294,8 +294,8 @@ class Problem:
         _check(_lib.kfbi_prob_get_tiles(self._h, ct.byref(t)))
         return t.as_dict()
 
-    def set_tiles(self, modes_waves: int, modes_groups: int, dst_cols: int):
-        t = Tiles(int(modes_waves), int(modes_groups), int(dst_cols), 0.0, 0.0)
+    def set_tiles(self, modes_per_group: int, dst_cols: int):
+        t = Tiles(int(modes_per_group), 0, int(dst_cols), 0.0, 0.0)
         _check(_lib.kfbi_prob_set_tiles(self._h, ct.byref(t)))
 
     # ---- timing of the three apply stages (HIP events on the context stream)

@@ -19,13 +19,13 @@ class FakeProb:
 
     def autotune(self, reps):
         self.tuned += 1
-        return {"modes_waves": 2, "modes_groups": 256, "dst_cols": 8, "apply_us": 12.5, "grid_solve_us": 40.0}
+        return {"modes_per_group": 8, "modes_groups": 256, "dst_cols": 8, "apply_us": 12.5, "grid_solve_us": 40.0}
 
-    def set_tiles(self, w, g, b):
+    def set_tiles(self, r, b):
         if not self.valid:
             from paper_2404_15249_amd.kfbi import KfbiError
             raise KfbiError(-1, "tile shape not valid for this problem")
-        self.set = (w, g, b)
+        self.set = (r, b)
 
 
 def test_miss_tunes_and_persists_then_hit_reuses(tmp_path):
@@ -33,12 +33,12 @@ def test_miss_tunes_and_persists_then_hit_reuses(tmp_path):
     c = TileCache(path, device_name="gfx950")
     p = FakeProb()
     t = c.apply(p)
-    assert p.tuned == 1 and c.misses == 1 and t["modes_waves"] == 2
+    assert p.tuned == 1 and c.misses == 1 and t["modes_per_group"] == 8
     assert json.load(open(path))                      # written to disk
     c2 = TileCache(path, device_name="gfx950")       # a later run
     q = FakeProb(M=250, I=1950)                       # same size class
     c2.apply(q)
-    assert q.tuned == 0 and q.set == (2, 256, 8) and c2.hits == 1
+    assert q.tuned == 0 and q.set == (8, 8) and c2.hits == 1
 
 
 def test_keys_separate_grid_precision_and_size_class(tmp_path):

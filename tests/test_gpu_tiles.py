@@ -1,6 +1,7 @@
-"""Launch shapes: every valid shape of the sparse fast solve and of the column
-transforms gives the oracle's K_D apply and grid solve (1e-12 relative: only
-the grouping of partial sums changes), and the autotuner returns one of them."""
+"""Launch shapes: every valid shape of the sparse fast solve (sine modes per
+workgroup) and of the column transforms gives the oracle's K_D apply and grid
+solve (1e-12 relative: only the grouping of partial sums changes), and the
+autotuner returns one of them."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,7 @@ def relerr(a, b):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
 
 
-@pytest.mark.parametrize("n", [64, 512])
+@pytest.mark.parametrize("n", [64, 512, 2048])
 def test_every_apply_shape_matches_oracle(K, ctx, n):
     p = synth.star_problem(n=n, kappa=1.0, m=max(64, n // 2))
     print(f"apply shapes {p.name}", flush=True)
@@ -51,16 +52,14 @@ def test_every_apply_shape_matches_oracle(K, ctx, n):
     ref = O.apply_KD(plan, phi, p.kappa)
     dst = prob.tiles()["dst_cols"]
     tried = 0
-    for w in (1, 2, 4, 8):
-        for g in (1, 7, 64, 256, 512):
-            try:
-                prob.set_tiles(w, g, dst)
-            except K.KfbiError:
-                continue
-            assert relerr(host(prob.apply(dev(phi))), ref) < 1e-12, (w, g)
-            tried += 1
-    assert tried >= 8
-
+    for r in (1, 2, 4, 8, 16):
+        try:
+            prob.set_tiles(r, dst)
+        except K.KfbiError:
+            continue
+        assert relerr(host(prob.apply(dev(phi))), ref) < 1e-12, r
+        tried += 1
+    assert tried >= 2
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_every_transform_tile_matches_oracle(K, ctx, precision):
@@ -75,7 +74,7 @@ def test_every_transform_tile_matches_oracle(K, ctx, precision):
     tol = 1e-12 if precision == "fp64" else 1e-10
     for b in (4, 8, 16):
         try:
-            prob.set_tiles(t["modes_waves"], t["modes_groups"], b)
+            prob.set_tiles(t["modes_per_group"], b)
         except K.KfbiError:
             continue
         assert relerr(host(prob.fast_solve(dev(rhs))), ref) < tol, b
@@ -85,10 +84,10 @@ def test_invalid_shapes_are_refused(K, ctx):
     p = synth.circle_problem(n=64, m=128)
     prob = K.Problem(ctx, p.xy, p.n, p.kappa)
     t = prob.tiles()
-    for bad in [(3, 8, 8), (1, 0, 8), (1, 10 ** 6, 8), (1, 8, 2), (1, 8, 32)]:
+    for bad in [(3, 8), (0, 8), (32, 8), (t["modes_per_group"], 2), (t["modes_per_group"], 32)]:
         with pytest.raises(K.KfbiError):
             prob.set_tiles(*bad)
-    assert prob.tiles()["modes_waves"] == t["modes_waves"]
+    assert prob.tiles()["modes_per_group"] == t["modes_per_group"]
 
 
 def test_autotune_picks_a_valid_shape_and_keeps_results(K, ctx):
@@ -99,5 +98,5 @@ def test_autotune_picks_a_valid_shape_and_keeps_results(K, ctx):
     t = prob.autotune(reps=3)
     print(f"autotune star512: {t}", flush=True)
     assert t["apply_us"] > 0 and t["grid_solve_us"] > 0
-    prob.set_tiles(t["modes_waves"], t["modes_groups"], t["dst_cols"])   # the choice is itself valid
+    prob.set_tiles(t["modes_per_group"], t["dst_cols"])   # the choice is itself valid
     assert relerr(host(prob.apply(phi)), before) < 1e-12

@@ -64,7 +64,7 @@ def test_struct_layouts_match_the_header(tmp_path):
         "  F(kfbi_desc, xy); F(kfbi_desc, tol); F(kfbi_desc, restart); F(kfbi_desc, max_iter);\n"
         "  F(kfbi_desc, precision); F(kfbi_desc, refine_steps);\n"
         '  printf("kfbi_tiles size %zu\\n", sizeof(kfbi_tiles));\n'
-        "  F(kfbi_tiles, modes_waves); F(kfbi_tiles, modes_groups); F(kfbi_tiles, dst_cols);\n"
+        "  F(kfbi_tiles, modes_per_group); F(kfbi_tiles, modes_groups); F(kfbi_tiles, dst_cols);\n"
         "  F(kfbi_tiles, apply_us); F(kfbi_tiles, grid_solve_us);\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
