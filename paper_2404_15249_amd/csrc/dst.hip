@@ -32,46 +32,71 @@ struct cpx {
 
 __device__ __forceinline__ int bitrev(int v, int bits) { return (int)(__brev((unsigned)v) >> (32 - bits)); }
 
+// two adjacent columns of one row travel as one vector load or store
+template <class T>
+struct pair_of;
+template <>
+struct pair_of<double> {
+    using type = double2;
+};
+template <>
+struct pair_of<float> {
+    using type = float2;
+};
+
+constexpr int kDstThreads = 1024;   // 16 wavefronts per workgroup: the LDS tile limits a CU to one
+constexpr int kLoadBatch = 8;       // vector loads in flight per thread
+
+// W_N^k = e^{-2 pi i k / N} for 0 <= k < N, from the quarter-period table
+__device__ __forceinline__ void twiddle(const double* sq, int k, int N, double& wr, double& wi) {
+    const int mask2 = 2 * N - 1;
+    wr = sinpi_n(sq, (2 * k + N / 2) & mask2, N);
+    wi = -sinpi_n(sq, (2 * k) & mask2, N);
+}
+
 template <class T, class Tin, class Tout, int B>
-__global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double* __restrict__ sinq,
-                                                  const Tin* __restrict__ in, Tout* __restrict__ out, double alpha,
-                                                  int accumulate) {
+__global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, const double* __restrict__ sinq,
+                                                          const Tin* in, Tout* out, double alpha, int accumulate) {
     extern __shared__ double smem_d[];
-    constexpr int P = B / 2;
+    constexpr int P = B / 2;                                 // column pairs
+    constexpr int LP = B == 4 ? 1 : B == 8 ? 2 : 3;          // log2 P
+    constexpr int NTH = kDstThreads;
+    using Vin = typename pair_of<Tin>::type;
+    using Vout = typename pair_of<Tout>::type;
     const int NS = N + 1;                                    // pair stride (one pad entry)
     double* sq = smem_d;                                     // N/2 + 2
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_d + (N / 2 + 2));   // P x NS
     const int tid = threadIdx.x;
-    const int col0 = blockIdx.x * B;
-    const int mask2 = 2 * N - 1;
-    for (int k = tid; k <= N / 2; k += 256) sq[k] = sinq[k];
-    // load: node j = r + 1 of column c at z[c/2][j] (.x even columns, .y odd);
-    // kLoadBatch loads per thread are issued before any is stored, so their
-    // latencies overlap
-    constexpr int kLoadBatch = 16;
-    for (int base = 0; base < N * B; base += 256 * kLoadBatch) {
-        Tin v[kLoadBatch];
+    // XCD-aware tile order: consecutive workgroups go round-robin over the 8
+    // XCDs, so give each XCD a contiguous range of tiles; neighbouring tiles
+    // share the cache lines of their row segments in that XCD's L2
+    const int G = gridDim.x;
+    const int tile = (G & 7) ? (int)blockIdx.x : ((int)blockIdx.x & 7) * (G >> 3) + ((int)blockIdx.x >> 3);
+    const int col0 = tile * B;
+    for (int k = tid; k <= N / 2; k += NTH) sq[k] = sinq[k];
+    // load: columns (2p, 2p+1) of row r -> z[p][r + 1]; the batch's loads are
+    // all issued before any is stored, so their latencies overlap
+    for (int base = 0; base < N * P; base += NTH * kLoadBatch) {
+        Vin v[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * 256 + tid;
-            const int r = idx / B, c = idx % B;
-            v[u] = (idx < N * B && r + 1 < N) ? in[(size_t)r * N + col0 + c] : Tin(0);
+            const int idx = base + u * NTH + tid;
+            const int r = idx >> LP, p = idx & (P - 1);
+            if (idx < N * P && r + 1 < N) v[u] = *reinterpret_cast<const Vin*>(in + (size_t)r * N + col0 + 2 * p);
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * 256 + tid;
-            const int r = idx / B, c = idx % B;
-            if (idx < N * B && r + 1 < N) {
-                cpx<T>& e = z[(c >> 1) * NS + r + 1];
-                if (c & 1) e.y = (T)v[u]; else e.x = (T)v[u];
-            }
+            const int idx = base + u * NTH + tid;
+            const int r = idx >> LP, p = idx & (P - 1);
+            if (idx < N * P && r + 1 < N) z[p * NS + r + 1] = cpx<T>{(T)v[u].x, (T)v[u].y};
         }
     }
     if (tid < P) z[tid * NS] = cpx<T>{T(0), T(0)};
     __syncthreads();
     // pre-process pairs (j, N - j)
-    for (int idx = tid; idx < P * (N / 2); idx += 256) {
-        const int p = idx / (N / 2), j = idx % (N / 2) + 1;         // 1 .. N/2
+    const int lh = log2N - 1;                                // log2 (N/2)
+    for (int idx = tid; idx < (P << lh); idx += NTH) {
+        const int p = idx >> lh, j = (idx & (N / 2 - 1)) + 1;        // 1 .. N/2
         cpx<T>* zp = z + p * NS;
         if (j == N / 2) {
             zp[j].x *= T(2);
@@ -84,9 +109,9 @@ __global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double
         }
     }
     __syncthreads();
-    // in-place radix-2 FFT: bit reversal, then log2 N butterfly passes
-    for (int idx = tid; idx < P * N; idx += 256) {
-        const int p = idx / N, j = idx % N;
+    // in-place FFT, decimation in time: bit reversal, then the passes
+    for (int idx = tid; idx < (P << log2N); idx += NTH) {
+        const int p = idx >> log2N, j = idx & (N - 1);
         const int rj = bitrev(j, log2N);
         if (j < rj) {
             cpx<T>* zp = z + p * NS;
@@ -96,15 +121,46 @@ __global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double
         }
     }
     __syncthreads();
-    for (int s = 1; s <= log2N; ++s) {
+    // passes s and s+1 together as one radix-4 step.  With h = 2^(s-1) and
+    // k = pos N / (4h), pass s uses W_N^{2k} = W^2 and pass s+1 uses W = W_N^k
+    // and W_N^{k + N/4} = -i W: one table lookup per four points.
+    int s = 1;
+    const int lq = log2N - 2;                                // log2 (N/4)
+    for (; s + 1 <= log2N; s += 2) {
+        const int h = 1 << (s - 1);
+        for (int idx = tid; idx < (P << lq); idx += NTH) {
+            const int p = idx >> lq, b = idx & (N / 4 - 1);
+            const int pos = b & (h - 1), grp = b >> (s - 1);
+            const int i0 = grp * 4 * h + pos;
+            cpx<T>* zp = z + p * NS;
+            const cpx<T> a = zp[i0], bb = zp[i0 + h], c = zp[i0 + 2 * h], d = zp[i0 + 3 * h];
+            double dr, di;
+            twiddle(sq, pos << (log2N - s - 1), N, dr, di);
+            const T w2r = (T)dr, w2i = (T)di;
+            const T w1r = (T)(dr * dr - di * di), w1i = (T)(2.0 * dr * di);
+            // pass s: (a, b) and (c, d) with W^2
+            const T tbr = w1r * bb.x - w1i * bb.y, tbi = w1r * bb.y + w1i * bb.x;
+            const T tdr = w1r * d.x - w1i * d.y, tdi = w1r * d.y + w1i * d.x;
+            const cpx<T> a1{a.x + tbr, a.y + tbi}, b1{a.x - tbr, a.y - tbi};
+            const cpx<T> c1{c.x + tdr, c.y + tdi}, d1{c.x - tdr, c.y - tdi};
+            // pass s + 1: (a, c) with W and (b, d) with -i W
+            const T tcr = w2r * c1.x - w2i * c1.y, tci = w2r * c1.y + w2i * c1.x;
+            const T ter = w2i * d1.x + w2r * d1.y, tei = w2i * d1.y - w2r * d1.x;
+            zp[i0] = cpx<T>{a1.x + tcr, a1.y + tci};
+            zp[i0 + 2 * h] = cpx<T>{a1.x - tcr, a1.y - tci};
+            zp[i0 + h] = cpx<T>{b1.x + ter, b1.y + tei};
+            zp[i0 + 3 * h] = cpx<T>{b1.x - ter, b1.y - tei};
+        }
+        __syncthreads();
+    }
+    if (s == log2N) {                                        // odd log2 N: one radix-2 pass left
         const int half = 1 << (s - 1);
-        for (int idx = tid; idx < P * (N / 2); idx += 256) {
-            const int p = idx / (N / 2), b = idx % (N / 2);
-            const int pos = b & (half - 1), grp = b >> (s - 1);
-            const int i1 = grp * 2 * half + pos, i2 = i1 + half;
-            const int k = pos << (log2N - s);                   // twiddle e^{-2 pi i k / N}
-            const T wr = (T)sinpi_n(sq, (2 * k + N / 2) & mask2, N);
-            const T wi = -(T)sinpi_n(sq, (2 * k) & mask2, N);
+        for (int idx = tid; idx < (P << lh); idx += NTH) {
+            const int p = idx >> lh, pos = idx & (N / 2 - 1);
+            const int i1 = pos, i2 = pos + half;
+            double dr, di;
+            twiddle(sq, pos, N, dr, di);
+            const T wr = (T)dr, wi = (T)di;
             cpx<T>* zp = z + p * NS;
             const cpx<T> a = zp[i1], c = zp[i2];
             const T tr = wr * c.x - wi * c.y, ti = wr * c.y + wi * c.x;
@@ -114,8 +170,8 @@ __global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double
         __syncthreads();
     }
     // separate the two columns: slot k <- (R_a, R_b), slot N-k <- (-I_a, -I_b) = X_2k
-    for (int idx = tid; idx < P * (N / 2); idx += 256) {
-        const int p = idx / (N / 2), k = idx % (N / 2);
+    for (int idx = tid; idx < (P << lh); idx += NTH) {
+        const int p = idx >> lh, k = idx & (N / 2 - 1);
         cpx<T>* zp = z + p * NS;
         const cpx<T> Zk = zp[k], Zn = zp[(N - k) & (N - 1)];
         const T ra = T(0.5) * (Zk.x + Zn.x), ia = T(0.5) * (Zk.y - Zn.y);
@@ -124,66 +180,85 @@ __global__ __launch_bounds__(256) void k_dst_cols(int N, int log2N, const double
         if (k > 0) zp[N - k] = cpx<T>{-ia, -ib};
     }
     __syncthreads();
-    // odd outputs: X_{2k+1} = R_0/2 + R_1 + ... + R_k, a scan per column
-    {
-        constexpr int TPC = 256 / B;                             // threads per column
-        const int c = tid / TPC, t = tid % TPC;
-        const int L = (N / 2) / TPC;                             // values per thread (>= 1)
-        cpx<T>* zp = z + (c >> 1) * NS;
-        const bool odd = c & 1;
-        // the running sums are carried in FP64 whatever the storage type
-        double run = 0.0;
-        for (int q = 0; q < L; ++q) {
-            const int k = t * L + q;
-            double v = odd ? zp[k].y : zp[k].x;
-            if (k == 0) v *= 0.5;
-            run += v;
+    // odd outputs: X_{2k+1} = R_0/2 + R_1 + ... + R_k, one wavefront per column.
+    // Lane t owns the L values t L .. t L + L - 1 and visits them rotated by
+    // t mod L, so that the lanes of a wavefront read different LDS banks; the
+    // values before the rotation point are summed separately, which keeps
+    // every running sum in index order.  Running sums are carried in FP64
+    // whatever the storage type.
+    if (tid < 64 * B) {
+        const int c = tid >> 6, t = tid & 63;
+        const int tpc = min(64, N / 2);                      // lanes with values
+        const int lL = (log2N - 1) - (tpc == 64 ? 6 : log2N - 1);
+        const int L = 1 << lL;
+        const int off = t & (L - 1);
+        T* col = reinterpret_cast<T*>(z + (c >> 1) * NS) + (c & 1);   // element k at col[2 k]
+        double lo = 0.0, hi = 0.0;                           // values before / from the rotation point
+        if (t < tpc) {
+            for (int q = 0; q < L; ++q) {
+                const int e = (q + off) & (L - 1), k = (t << lL) + e;
+                double v = (double)col[2 * k];
+                if (k == 0) v *= 0.5;
+                if (e >= off) hi += v; else lo += v;
+            }
         }
-        // exclusive prefix of the per-thread sums within the column's threads
-        double incl = run;
-        for (int off = 1; off < TPC; off <<= 1) {
-            const double o = __shfl_up(incl, off, TPC);
-            if (t >= off) incl += o;
+        double incl = lo + hi;
+        for (int o = 1; o < 64; o <<= 1) {
+            const double u = __shfl_up(incl, o, 64);
+            if (t >= o) incl += u;
         }
-        double acc = incl - run;
-        for (int q = 0; q < L; ++q) {
-            const int k = t * L + q;
-            double v = odd ? zp[k].y : zp[k].x;
-            if (k == 0) v *= 0.5;
-            acc += v;
-            if (odd) zp[k].y = (T)acc; else zp[k].x = (T)acc;
+        double excl = __shfl_up(incl, 1, 64);
+        if (t == 0) excl = 0.0;
+        if (t < tpc) {
+            double acc_hi = excl + lo, acc_lo = excl;
+            for (int q = 0; q < L; ++q) {
+                const int e = (q + off) & (L - 1), k = (t << lL) + e;
+                double v = (double)col[2 * k];
+                if (k == 0) v *= 0.5;
+                double w;
+                if (e >= off) w = (acc_hi += v); else w = (acc_lo += v);
+                col[2 * k] = (T)w;
+            }
         }
     }
     __syncthreads();
     // write: X_l to row l-1 (odd l from slot (l-1)/2, even l from slot N - l/2); row N-1 is the pad
-    for (int base = 0; base < N * B; base += 256 * kLoadBatch) {
-        double v[kLoadBatch];
+    for (int base = 0; base < N * P; base += NTH * kLoadBatch) {
+        double vx[kLoadBatch], vy[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * 256 + tid;
-            const int r = idx / B, c = idx % B;
+            const int idx = base + u * NTH + tid;
+            const int r = idx >> LP, p = idx & (P - 1);
             const int l = r + 1;
-            v[u] = 0.0;
-            if (idx < N * B && l < N) {
-                const cpx<T>* zp = z + (c >> 1) * NS;
-                const cpx<T> e = (l & 1) ? zp[(l - 1) >> 1] : zp[N - (l >> 1)];
-                v[u] = alpha * (double)((c & 1) ? e.y : e.x);
+            vx[u] = vy[u] = 0.0;
+            if (idx < N * P && l < N) {
+                const cpx<T> e = z[p * NS + ((l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
+                vx[u] = alpha * (double)e.x;
+                vy[u] = alpha * (double)e.y;
             }
         }
         if (accumulate) {
-            Tout old[kLoadBatch];
+            Vout old[kLoadBatch];
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
-                const int idx = base + u * 256 + tid;
-                old[u] = idx < N * B ? out[(size_t)(idx / B) * N + col0 + idx % B] : Tout(0);
+                const int idx = base + u * NTH + tid;
+                const int r = idx >> LP, p = idx & (P - 1);
+                if (idx < N * P) old[u] = *reinterpret_cast<const Vout*>(out + (size_t)r * N + col0 + 2 * p);
             }
 #pragma unroll
-            for (int u = 0; u < kLoadBatch; ++u) v[u] += (double)old[u];
+            for (int u = 0; u < kLoadBatch; ++u) {
+                vx[u] += (double)old[u].x;
+                vy[u] += (double)old[u].y;
+            }
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * 256 + tid;
-            if (idx < N * B) out[(size_t)(idx / B) * N + col0 + idx % B] = (Tout)v[u];
+            const int idx = base + u * NTH + tid;
+            const int r = idx >> LP, p = idx & (P - 1);
+            Vout o;
+            o.x = (Tout)vx[u];
+            o.y = (Tout)vy[u];
+            if (idx < N * P) *reinterpret_cast<Vout*>(out + (size_t)r * N + col0 + 2 * p) = o;
         }
     }
 }
@@ -194,7 +269,7 @@ hipError_t dst_launch(const DevPlan& p, const Tin* in, Tout* out, double alpha, 
     if (hipError_t e = hipFuncSetAttribute((const void*)k_dst_cols<T, Tin, Tout, B>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
         return e;
-    if (hipError_t e_ = klaunch(&k_dst_cols<T, Tin, Tout, B>, dim3(p.N / B), dim3(256), lds, s, p.N, p.log2N, p.sinq, in, out, alpha, acc ? 1 : 0)) return e_;
+    if (hipError_t e_ = klaunch(&k_dst_cols<T, Tin, Tout, B>, dim3(p.N / B), dim3(kDstThreads), lds, s, p.N, p.log2N, p.sinq, in, out, alpha, acc ? 1 : 0)) return e_;
     return hipGetLastError();
 }
 
