@@ -10,9 +10,12 @@ device-side Gram-Schmidt / Givens update.  The steps run back to back on the
 device with no convergence stop, so the timed work is fixed.
 
 The timed region replays the captured GMRES steps (the production path).  A
-second region of the same length launches the same steps one by one with HIP
-events recorded around every launch on the library's stream: the dominant
-kernel's average duration (roofline) and the per-stage times come from there.
+second region of the same length launches the same steps one by one, each
+apply kernel recording a start and an end HIP event from its own dispatch packet
+on the library's stream: the dominant kernel's average duration (roofline) and
+the per-stage times come from there.  The roofline's ``traffic`` is the HBM
+bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary, null when
+that summary was taken on other kernel sources.
 
 Also reported, outside the timed region:
   solve     one full Dirichlet solve of the workload (FP64), error vs exact;
@@ -28,9 +31,11 @@ workload (rank 0, one GPU only).  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
+import re
 import sys
 import time
 
@@ -40,6 +45,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X, dense FP64 vector
+
+# HBM traffic of k_modes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
+# what the same counters read for a plain copy (``--mode copy``); valid only for
+# the kernel sources, grid and launch shape it was taken with
+COUNTER_PROFILE = os.path.join(ROOT, "profiles", "k_modes_star2048_counters.md")
+KERNEL_SOURCES = ("device.h", "kernels.h", "kernels.hip", "api.hip", "plan.cpp")
 
 
 def modes_flops(n_grid: int, n_irr: int, m: int) -> float:
@@ -51,6 +62,50 @@ def modes_flops(n_grid: int, n_irr: int, m: int) -> float:
     weighted six-point gather.
     """
     return (n_grid - 1) * (2.0 * n_irr + 14.0 * n_grid + 16.0 * m)
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the sources that decide what k_modes reads and writes."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2404_15249_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counter_traffic(n_grid: int, modes_per_group: int):
+    """HBM bytes per k_modes launch from the committed counter summary, or None
+    when it is missing or was taken on other kernel sources, grid or shape."""
+    try:
+        with open(COUNTER_PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    try:
+        rec = json.loads(m.group(1))
+    except ValueError:
+        return None
+    if (rec.get("source_sha256") != kernel_source_hash() or rec.get("grid") != n_grid
+            or rec.get("modes_per_group") != modes_per_group):
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
+def copy_calibration() -> dict:
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = 32 << 20
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"mode": "copy", "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8, "copies": 5}
 
 
 def cpu_model() -> str:
@@ -191,8 +246,9 @@ def main():
     ap.add_argument("--mixed", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
-    ap.add_argument("--mode", choices=["apply", "serving"], default="apply",
-                    help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000")
+    ap.add_argument("--mode", choices=["apply", "serving", "copy"], default="apply",
+                    help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "
+                         "copy: a 256 MiB device copy to calibrate the HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the KFBI path here has no multi-GPU mode "
@@ -207,6 +263,9 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        print(json.dumps(copy_calibration()), flush=True)
+        return
     ctx = kfbi.Context(0)
     if args.mode == "serving":
         print(json.dumps(serving_line(ctx, args)), flush=True)
@@ -284,7 +343,7 @@ def main():
             "peak": FP64_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": counter_traffic(p.n, prob.tiles()["modes_per_group"]),
             "flops_per_launch": fl,
             "avg_us": tim["modes_us"],
         },

@@ -253,8 +253,9 @@ kfbi_status kfbi_batch_info(const kfbi_batch* batch, int* live, size_t* bytes_in
 const char* kfbi_status_str(kfbi_status s);
 const char* kfbi_last_error(void);
 /* Kernel timing of the K_D apply.  While timing is on, every apply (also the
- * ones inside kfbi_gmres and kfbi_solve) records HIP events around its three
- * launches on the context stream, without synchronising; kfbi_apply_timing
+ * ones inside kfbi_gmres and kfbi_solve) launches its three kernels directly
+ * on the context stream (no graph), each recording a start and an end HIP event
+ * from its own dispatch packet, without synchronising; kfbi_apply_timing
  * synchronises and returns the average duration in microseconds of the
  * correction (Alg. 2), the sparse fast solve (Alg. 4) and the interpolation
  * (Alg. 3) launches over the applies recorded since timing was switched on

@@ -24,6 +24,11 @@ GraphRec*& kfbi::graph_rec() {
     return rec;
 }
 
+LaunchEvents& kfbi::launch_events() {
+    thread_local LaunchEvents ev;
+    return ev;
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -80,7 +85,8 @@ struct kfbi_prob {
     double* s2b = nullptr;       // M: spline second derivatives (f on Gamma)
     GmresBufs gm{};
     GmresState st_host{};        // host copy of the GMRES state (stable address for async copies)
-    // timing: four events per recorded apply, read back by kfbi_apply_timing
+    // timing: a start and an end event for each of an apply's three launches,
+    // read back by kfbi_apply_timing
     static constexpr int kMaxTimed = 4096;
     bool timing = false;
     std::vector<hipEvent_t> ev;
@@ -211,20 +217,30 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
                          const GmresBufs* gm, hipStream_t s) {
     JumpSrc js{phi, phi_s2, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t* ev = nullptr;
-    if (p->timing && p->t_count < kfbi_prob::kMaxTimed) {
+    if (p->timing && p->t_count < kfbi_prob::kMaxTimed && !graph_rec()) {
         if (p->ev.empty()) {
-            p->ev.assign(4 * kfbi_prob::kMaxTimed, nullptr);
+            p->ev.assign(6 * kfbi_prob::kMaxTimed, nullptr);
             for (auto& e : p->ev) HIP_TRY(hipEventCreate(&e));
         }
-        ev = &p->ev[4 * p->t_count++];
+        ev = &p->ev[6 * p->t_count++];
     }
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    // each stage is one kernel launch; with timing on, the launch records its
+    // own start and end events
+    auto stage = [&](int q) {
+        if (ev) launch_events() = LaunchEvents{ev[2 * q], ev[2 * q + 1]};
+    };
+    stage(0);
     HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, skip, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    if (ev && launch_events().start) {            // no irregular nodes: nothing was launched
+        launch_events() = LaunchEvents{};
+        HIP_TRY(hipEventRecord(ev[0], s));
+        HIP_TRY(hipEventRecord(ev[1], s));
+    }
+    stage(1);
     HIP_TRY(launch_modes(p->dp, p->corr_il, p->partial, p->Rm, skip, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[2], s));
+    stage(2);
     HIP_TRY(launch_reduce_interp(p->dp, js, p->partial, p->G, out, skip, gm, s));
-    if (ev) HIP_TRY(hipEventRecord(ev[3], s));
+    launch_events() = LaunchEvents{};
     return KFBI_OK;
 }
 
@@ -759,7 +775,7 @@ kfbi_status kfbi_apply_timing(kfbi_prob* p, double* a, double* b, double* c, int
     for (int k = 0; k < p->t_count; ++k) {
         for (int q = 0; q < 3; ++q) {
             float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, p->ev[4 * k + q], p->ev[4 * k + q + 1]));
+            HIP_TRY(hipEventElapsedTime(&ms, p->ev[6 * k + 2 * q], p->ev[6 * k + 2 * q + 1]));
             acc[q] += 1e3 * ms;
         }
     }

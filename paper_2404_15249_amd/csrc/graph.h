@@ -6,6 +6,7 @@
 // stream) is unaffected, and nothing they enqueue can enter the graph.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <tuple>
@@ -21,6 +22,14 @@ struct GraphRec {
 };
 GraphRec*& graph_rec();
 
+// Events that the next direct launch from this host thread records from its
+// own dispatch packet: the kernel's start and end, without the gap between
+// a stream marker and the dispatch.  klaunch clears them after that launch.
+struct LaunchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+LaunchEvents& launch_events();
+
 template <class... KArgs, class... Args>
 hipError_t klaunch(void (*kern)(KArgs...), dim3 grid, dim3 block, size_t lds, hipStream_t s, Args&&... args) {
     static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
@@ -31,7 +40,16 @@ hipError_t klaunch(void (*kern)(KArgs...), dim3 grid, dim3 block, size_t lds, hi
         ((params[i++] = static_cast<void*>(&v)), ...);
     }, vals);
     GraphRec* r = graph_rec();
-    if (!r) return hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, params, lds, s);
+    if (!r) {
+        LaunchEvents& le = launch_events();
+        if (le.start || le.stop) {
+            const LaunchEvents use = le;
+            le = LaunchEvents{};
+            return hipExtLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, params, lds, s, use.start,
+                                      use.stop, 0);
+        }
+        return hipLaunchKernel(reinterpret_cast<const void*>(kern), grid, block, params, lds, s);
+    }
     hipKernelNodeParams kp{};
     kp.func = reinterpret_cast<void*>(kern);
     kp.gridDim = grid;
