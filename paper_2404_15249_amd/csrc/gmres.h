@@ -81,8 +81,13 @@ __device__ __forceinline__ double wave_sum_many(double (&p)[G]) {
         const bool hi = (lane & off) != 0;
 #pragma unroll
         for (int u = 0; u < half; ++u) {
-            const double keep = hi ? p[u + half] : p[u];
-            const double send = hi ? p[u] : p[u + half];
+            // the empty asm makes both operands register values: otherwise the
+            // compiler turns "hi ? p[a] : p[b]" into p[hi ? a : b], a run-time
+            // index into the array that it lowers to a chain of G selects
+            double lo_v = p[u], hi_v = p[u + half];
+            asm volatile("" : "+v"(lo_v), "+v"(hi_v));
+            const double keep = hi ? hi_v : lo_v;
+            const double send = hi ? lo_v : hi_v;
             p[u] = keep + __shfl_xor(send, off, 64);
         }
     }
@@ -91,12 +96,11 @@ __device__ __forceinline__ double wave_sum_many(double (&p)[G]) {
 }
 
 // Loads V_i at element e (0 outside [0, M) and for i > j) for i < 4 * 16,
-// grouped by 16; groups beyond j are skipped.
+// grouped by 16.
 __device__ __forceinline__ void gm_load_basis(const double* __restrict__ V, int M, int e, int j, double (&v)[4][16]) {
     const bool in = e < M;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        if (16 * g > j) break;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int i = 16 * g + u;
@@ -111,18 +115,22 @@ __device__ __forceinline__ void gm_load_basis(const double* __restrict__ V, int 
 __device__ __forceinline__ void gm_chunk_dots(const double (&v)[4][16], double x, int j, int gc, int c,
                                               double* __restrict__ red, double* __restrict__ out) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // every group index is a compile-time constant (a guarded, fully unrolled
+    // loop rather than an early exit), so v stays in registers without
+    // run-time indexing
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        if (16 * g > j) break;
-        double p[16];
+        if (16 * g <= j) {
+            double p[16];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) p[u] = v[g][u] * x;
-        const double s = wave_sum_many<16>(p);
-        if ((lane & 3) == 0) red[wave * 16 + (lane >> 2)] = s;
-        __syncthreads();
-        if (tid < 16 && 16 * g + tid <= j)
-            out[(size_t)(16 * g + tid) * gc + c] = red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid];
-        __syncthreads();
+            for (int u = 0; u < 16; ++u) p[u] = v[g][u] * x;
+            const double s = wave_sum_many<16>(p);
+            if ((lane & 3) == 0) red[wave * 16 + (lane >> 2)] = s;
+            __syncthreads();
+            if (tid < 16 && 16 * g + tid <= j)
+                out[(size_t)(16 * g + tid) * gc + c] = red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid];
+            __syncthreads();
+        }
     }
 }
 
@@ -157,7 +165,7 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
 
 // pass 0: z = w - sum h_i V_i and the second-pass dots V_i . z; pass 1:
 // z -= sum h'_i V_i and |z|^2.  The basis values are loaded once per launch.
-__device__ inline void gm_update(const GmresBufs& b, int M, int c, int pass) {
+__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int pass) {
     __shared__ double hs[kMaxRestart + 2];
     __shared__ double red[64];
     const GmresState* st = b.st;
@@ -179,10 +187,11 @@ __device__ inline void gm_update(const GmresBufs& b, int M, int c, int pass) {
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-        if (16 * g > j) break;
+        if (16 * g <= j) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (16 * g + u <= j) a -= hs[16 * g + u] * v[g][u];
+            for (int u = 0; u < 16; ++u)
+                if (16 * g + u <= j) a -= hs[16 * g + u] * v[g][u];
+        }
     }
     if (e < M) b.z[e] = a;
     if (pass == 0) {
