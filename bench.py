@@ -19,6 +19,8 @@ that summary was taken on other kernel sources.
 
 Also reported, outside the timed region:
   solve     one full Dirichlet solve of the workload (FP64), error vs exact;
+  convergence  full FP64 solves of the star workload at 512^2, 1024^2 and 2048^2:
+            L-infinity error against the exact solution and the observed order;
   mixed     the circle r = 0.8, M = N, kappa = 1 problem at the same grid:
             full solves with FP64 and with FP32-refined grid solves, their
             times and the L-infinity difference between the two;
@@ -45,6 +47,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6      # MI355X, dense FP64 vector
+HBM_PEAK_BYTES = 8.0e12             # MI355X HBM3E, bytes/s
 
 # HBM traffic of k_modes from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by
 # what the same counters read for a plain copy (``--mode copy``); valid only for
@@ -187,6 +190,33 @@ def mixed_precision(ctx, n: int) -> dict:
     return res
 
 
+def convergence(ctx, sizes=(512, 1024, 2048)) -> dict:
+    """Full FP64 solves of the star workload (kappa = 1, M = N/2,
+    u = sin(pi x) cos(pi y) + x^2) at several grids: L-infinity error against the
+    exact solution on the grid nodes in Omega and on Gamma, and the observed order."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    rows = []
+    for n in sizes:
+        p = synth.star_problem(n=n, kappa=1.0)
+        prob = kfbi.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-10)
+        u, ug, phi, it, rel, conv = prob.solve(dev(p.f_grid), dev(p.f_gamma), dev(p.g))
+        c = p.lo + np.arange(p.n + 1) * p.h
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        mask = prob.mask()
+        e_grid = float(np.max(np.abs(u.cpu().numpy() - p.exact.u(X, Y))[mask]))
+        e_gam = float(np.max(np.abs(ug.cpu().numpy() - p.exact.u(p.xy[:, 0], p.xy[:, 1]))))
+        rows.append({"n": n, "samples": prob.M, "gmres_iters": it, "converged": conv,
+                     "linf_err_grid": e_grid, "linf_err_gamma": e_gam})
+        prob.close()
+    for a, b in zip(rows, rows[1:]):
+        b["order_grid"] = float(np.log2(a["linf_err_grid"] / b["linf_err_grid"]))
+    return {"workload": "star r=0.6+0.15 sin 5t, kappa=1, M=N/2, u=sin(pi x)cos(pi y)+x^2, GMRES tol 1e-10",
+            "rows": rows}
+
+
 def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0):
     import synth
     from paper_2404_15249_amd.serving import GpuExecutor, Scheduler, summarize
@@ -244,6 +274,7 @@ def main():
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mixed", choices=["on", "off"], default="on")
+    ap.add_argument("--convergence", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
     ap.add_argument("--mode", choices=["apply", "serving", "copy"], default="apply",
@@ -347,6 +378,11 @@ def main():
             "flops_per_launch": fl,
             "avg_us": tim["modes_us"],
         },
+        # the method's own floor: one write and one read of a half-transformed
+        # FP64 grid per apply (16 bytes per unknown) at the 8 TB/s HBM peak
+        "method_ceiling": {"value": HBM_PEAK_BYTES / 16.0, "unit": "grid unknowns/s",
+                           "frac": value / (HBM_PEAK_BYTES / 16.0),
+                           "basis": "16 B per unknown (one FP64 write + read of the half-transformed grid) at 8 TB/s"},
         "stages_us": {"correct": tim["correct_us"], "modes": tim["modes_us"], "interp": tim["interp_us"],
                       "gmres_step_and_gaps": 1e6 * dt_ev / args.steps - tim["correct_us"] - tim["modes_us"]
                       - tim["interp_us"], "timed_applies": tim["count"], "all_applies": applies,
@@ -354,6 +390,8 @@ def main():
         "solve": {"ms": solve_ms, "gmres_iters": it, "relres": rel, "converged": conv,
                   "linf_err_vs_exact": float(err)},
     }
+    if args.convergence == "on":
+        out["convergence"] = convergence(ctx)
     if args.mixed == "on":
         out["mixed"] = mixed_precision(ctx, args.n)
     if args.serving_requests > 0:
