@@ -131,6 +131,24 @@ SIN_COS_X2 = Manufactured(
 )
 
 
+@dataclasses.dataclass(frozen=True)
+class Manufactured3:
+    """A closed-form solution ``u(x, y, z)`` with its Laplacian."""
+    name: str
+    u: callable
+    lap: callable
+
+    def f(self, x, y, z, kappa):
+        return self.lap(x, y, z) - kappa * self.u(x, y, z)
+
+
+EXP_XYZ = Manufactured3(
+    "exp(x+y+z)",
+    lambda x, y, z: np.exp(x + y + z),
+    lambda x, y, z: 3.0 * np.exp(x + y + z),
+)
+
+
 def random_manufactured(rng: np.random.Generator, xp=np) -> Manufactured:
     """``u = A sin(w1 x + a) cos(w2 y + b) + B (x^2 - y^2)`` with seeded parameters.
 
@@ -273,3 +291,67 @@ def serving_stream(n_requests: int, seed: int = 2404, qps: float = 100.0,
     ns = rng.choice(np.asarray(sizes), size=n_requests, p=np.asarray(weights))
     seeds = rng.integers(0, 2 ** 31 - 1, size=n_requests)
     return [(float(t), int(n), int(s)) for t, n, s in zip(arrivals, ns, seeds)]
+
+
+# --------------------------------------------------------------------------
+# 3D: the ellipsoid workload
+# --------------------------------------------------------------------------
+
+@dataclasses.dataclass
+class Problem3:
+    """A Dirichlet problem on the ellipsoid ``x^2/a^2 + y^2/b^2 + z^2/c^2 < 1``.
+
+    ``f_grid`` is sampled at every node of the ``(n+1)^3`` grid, indexed
+    ``[k, j, i]`` (k along z, j along y, i along x).  The boundary data live at
+    the control points, which the discretisation chooses (the grid-line /
+    surface intersections): ``boundary_data(points)`` samples them there.
+    """
+    name: str
+    axes: tuple
+    n: int
+    kappa: float
+    lo: float
+    hi: float
+    f_grid: np.ndarray
+    exact: Manufactured3
+
+    @property
+    def h(self):
+        return (self.hi - self.lo) / self.n
+
+    def node_coords(self):
+        return self.lo + np.arange(self.n + 1) * self.h
+
+    def boundary_data(self, pts):
+        """``(f_gamma, g)`` at the points ``pts`` (shape (M, 3))."""
+        x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+        return (np.asarray(self.exact.f(x, y, z, self.kappa), dtype=np.float64),
+                np.asarray(self.exact.u(x, y, z), dtype=np.float64))
+
+    def exact_grid(self):
+        c = self.node_coords()
+        Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+        return self.exact.u(X, Y, Z)
+
+
+def ellipsoid_problem(n=64, axes=(0.9, 0.7, 0.5), kappa=0.0, sol=EXP_XYZ, lo=BOX_LO, hi=BOX_HI) -> Problem3:
+    """Interior Dirichlet problem on the ellipsoid with semi-axes ``axes`` (``e^{x+y+z}`` by default)."""
+    h = (hi - lo) / n
+    c = lo + np.arange(n + 1) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    f_grid = np.ascontiguousarray(sol.f(X, Y, Z, kappa), dtype=np.float64)
+    return Problem3(f"ellipsoid {axes} n={n} kappa={kappa}", tuple(float(a) for a in axes), n, kappa, lo, hi,
+                    f_grid, sol)
+
+
+def smooth_density3(pts: np.ndarray, seed: int = 1234) -> np.ndarray:
+    """A smooth seeded density at the points ``pts``: a random combination of
+    low-order trigonometric functions of the position."""
+    rng = np.random.default_rng(seed)
+    x, y, z = pts[:, 0], pts[:, 1], pts[:, 2]
+    out = np.zeros(len(pts))
+    for k in range(1, 4):
+        a = rng.standard_normal(6) / (1.0 + k * k)
+        out += (a[0] * np.cos(k * x) + a[1] * np.sin(k * y) + a[2] * np.cos(k * z)
+                + a[3] * np.sin(k * (x + y)) + a[4] * np.cos(k * (y - z)) + a[5] * np.sin(k * (x - z)))
+    return out
