@@ -248,6 +248,71 @@ kfbi_status kfbi_batch_finish(kfbi_batch* batch, int slot, double* u_grid, doubl
 /* Live problems and the device bytes they hold. */
 kfbi_status kfbi_batch_info(const kfbi_batch* batch, int* live, size_t* bytes_in_use);
 
+/* ---------------------------------------------------------------- three dimensions */
+
+/* The same Dirichlet problem in the ellipsoid
+ *   Omega = { x^2/a^2 + y^2/b^2 + z^2/c^2 < 1 }
+ * inside the cube B = [lo, hi]^3, on the 7-point grid of n intervals per axis
+ * (Sec. 2 and Alg. 1-5 with the stencil, transforms and interpolation taken to
+ * three dimensions; the paper gives the method in two).  Node (i, j, k) sits at
+ * (lo + i h, lo + j h, lo + k h); a 3D grid array holds the (n+1)^3 node values,
+ * element (k (n+1) + j) (n+1) + i.  A node is in Omega iff the level function
+ * above is negative there.  The control points (the GMRES unknowns, where g and
+ * f on the surface are sampled and phi lives) are all crossings of grid edges
+ * with the surface, M of them, in the order kfbi3_prob_points reports.
+ * Surface derivatives of a density come from weighted least-squares
+ * tangent-plane quadratics over the control points within 2.5 h; jumps use the
+ * surface's shape operator; v+ at a control point is the quadratic through
+ * ten nodes around it (the 7-point cross plus three diagonals toward it).
+ * Conventions as above (device FP64 arrays, context stream, errors). */
+typedef struct kfbi_prob3 kfbi_prob3;
+
+typedef struct {
+    int n;              /* intervals per axis: 64, 128 or 256 */
+    double lo, hi;      /* the cube */
+    double kappa;       /* >= 0 */
+    double axes[3];     /* semi-axes a, b, c of the ellipsoid, centred at the origin;
+                           it must keep two cells away from the box */
+    double tol;         /* GMRES relative residual tolerance (<= 0: 1e-10) */
+    int restart;        /* GMRES restart length (<= 0: 50; at most 64) */
+    int max_iter;       /* GMRES iteration cap (<= 0: 500) */
+} kfbi_desc3;
+
+/* Builds the plan on the host (classification, crossings, fits, stencils) and
+ * uploads it.  KFBI_ERR_GEOMETRY: the ellipsoid reaches within two cells of the
+ * box, or n is not supported.  Synchronises. */
+kfbi_status kfbi3_prob_create(kfbi_ctx* ctx, const kfbi_desc3* desc, kfbi_prob3** out);
+kfbi_status kfbi3_prob_destroy(kfbi_prob3* prob);
+/* M control points, irregular nodes, device bytes held (host outputs, may be NULL). */
+kfbi_status kfbi3_prob_info(const kfbi_prob3* prob, int* M, int* n_irregular, size_t* device_bytes);
+/* pts: host M x 3 control point coordinates; axis: host M, the axis (0 x, 1 y,
+ * 2 z) of the grid edge each lies on.  Either may be NULL. */
+kfbi_status kfbi3_prob_points(const kfbi_prob3* prob, double* pts, int* axis);
+/* inside: host (n+1)^3 bytes, 1 for nodes in Omega. */
+kfbi_status kfbi3_prob_mask(const kfbi_prob3* prob, unsigned char* inside);
+/* node: host, one per irregular node: ((k-1) n + (j-1)) n + (i-1), in the
+ * order of increasing (k, j, i). */
+kfbi_status kfbi3_prob_irregular(const kfbi_prob3* prob, int* node);
+/* The Cartesian jumps at every control point for [v] = phi, [F] = f_gamma
+ * (NULL: 0) and [d_n v] = 0.  J: device 10 M, component-major: J[c M + m] for
+ * c = [v], [v_x], [v_y], [v_z], [v_xx], [v_yy], [v_zz], [v_xy], [v_xz], [v_yz]. */
+kfbi_status kfbi3_jumps(kfbi_prob3* prob, const double* phi, const double* f_gamma, double* J);
+/* K_D phi = (I/2 + W) phi at the control points.  phi, Kphi: device M. */
+kfbi_status kfbi3_apply(kfbi_prob3* prob, const double* phi, double* Kphi);
+/* One interface solve with [v] = phi (NULL: 0), F = f_grid masked to Omega
+ * (NULL: 0) and [F] = f_gamma (NULL: 0): the grid solution (vgrid, device
+ * (n+1)^3, may be NULL) and v+ at the control points (vz, device M, may be NULL). */
+kfbi_status kfbi3_interface_solve(kfbi_prob3* prob, const double* phi, const double* f_grid,
+                                  const double* f_gamma, double* vgrid, double* vz);
+/* The whole solve, as kfbi_solve: f_grid device (n+1)^3, f_gamma and g device M
+ * at the control points; u_grid (zero outside Omega) and u_gamma outputs; phi
+ * device M, initial guess in, density out.  Synchronises. */
+kfbi_status kfbi3_solve(kfbi_prob3* prob, const double* f_grid, const double* f_gamma, const double* g,
+                        double* u_grid, double* u_gamma, double* phi, int* iters, double* rel_res);
+/* Alg. 5 alone, as kfbi_gmres.  Synchronises. */
+kfbi_status kfbi3_gmres(kfbi_prob3* prob, const double* rhs, double* phi, double tol, int max_iter,
+                        int* iters, int* applies, double* rel_res);
+
 /* ---------------------------------------------------------------- diagnostics */
 
 const char* kfbi_status_str(kfbi_status s);

@@ -16,6 +16,7 @@
 #include "graph.h"
 #include "kernels.h"
 #include "plan.h"
+#include "api_common.h"
 
 using namespace kfbi;
 
@@ -29,31 +30,10 @@ LaunchEvents& kfbi::launch_events() {
     return ev;
 }
 
-namespace {
-
-thread_local std::string g_err;
-
-kfbi_status set_err(kfbi_status s, const std::string& msg) {
-    g_err = msg;
-    return s;
+std::string& kfbi::last_error() {
+    static thread_local std::string err;
+    return err;
 }
-
-#define HIP_TRY(expr)                                                                              \
-    do {                                                                                           \
-        hipError_t e_ = (expr);                                                                    \
-        if (e_ != hipSuccess)                                                                      \
-            return set_err(KFBI_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));    \
-    } while (0)
-
-}  // namespace
-
-struct kfbi_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    size_t lds_max = 65536;
-    int num_cu = 256;
-};
 
 struct kfbi_prob {
     kfbi_ctx* ctx = nullptr;
@@ -137,19 +117,9 @@ void free_prob(kfbi_prob* p) {
 // Per-mode constants of the x-direction tridiagonal systems (Alg. 4), FP64.
 std::vector<ModeConst> mode_constants(int N, double h, double kappa) {
     std::vector<ModeConst> mc(N);
-    const int C = N / 64;
     for (int l = 1; l < N; ++l) {
         const double s = std::sin(M_PI * l / (2.0 * N));
-        const double d = h * h * kappa + 4.0 * s * s;          // beta - 2 > 0
-        const double sq = std::sqrt(d * (4.0 + d));
-        const double r = 1.0 + 0.5 * d - 0.5 * sq;             // root of r^2 - beta r + 1 in (0, 1)
-        ModeConst& c = mc[l];
-        c.r = r;
-        c.rinv = 1.0 / r;
-        c.logr = std::log1p(0.5 * d - 0.5 * sq);
-        c.rC = std::pow(r, C);
-        const double r2N = std::exp(2.0 * N * c.logr);
-        c.smc = -r / (1.0 - r2N);
+        mc[l] = row_solve_constants(h * h * kappa + 4.0 * s * s, N);
     }
     return mc;
 }
@@ -157,10 +127,6 @@ std::vector<ModeConst> mode_constants(int N, double h, double kappa) {
 // bytes of one complex pair in the column transforms of a precision mode
 size_t cpx_bytes(int precision) { return precision == KFBI_FP64 ? 2 * sizeof(double) : 2 * sizeof(float); }
 
-kfbi_status check_ptr(const void* p, const char* name) {
-    if (!p) return set_err(KFBI_ERR_ARG, std::string(name) + " is NULL");
-    return KFBI_OK;
-}
 
 // Alg. 4 on the full grid: solve (L_h - kappa) V = R (R in the padded interior
 // layout, consumed).  FP64: in place, *V = R.  FP32 with refinement: an FP32
@@ -252,34 +218,9 @@ kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
     const int* skip = &b.st->converged;
     for (int k = 0; k < nsteps; ++k) {
         if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, &p->gm, s)) return e;
-        HIP_TRY(launch_gmres_step(p->dp, b, s));
+        HIP_TRY(launch_gmres_step(p->dp.taps, p->dp.M, b, s));
     }
     return KFBI_OK;
-}
-
-// Record what `enqueue(stream)` launches as the nodes of a new graph (see
-// graph.h: no stream capture) and instantiate it.  Returns false (and leaves
-// *out null) if recording or instantiation fails; the caller then launches
-// directly.  `enqueue` must issue kernel launches only.
-template <class F>
-bool build_graph(kfbi_ctx* ctx, hipGraphExec_t* out, F enqueue) {
-    *out = nullptr;
-    GraphRec rec;
-    if (hipGraphCreate(&rec.graph, 0) != hipSuccess) {
-        hipGetLastError();
-        return false;
-    }
-    graph_rec() = &rec;
-    const kfbi_status e = enqueue(ctx->stream);
-    graph_rec() = nullptr;
-    const bool ok = e == KFBI_OK && rec.last != nullptr &&
-                    hipGraphInstantiate(out, rec.graph, nullptr, nullptr, 0) == hipSuccess;
-    if (!ok) {
-        hipGetLastError();
-        *out = nullptr;
-    }
-    hipGraphDestroy(rec.graph);
-    return ok;
 }
 
 // Record kGraphSteps GMRES steps into a graph once per problem.  All launch
@@ -291,7 +232,7 @@ void ensure_graph(kfbi_prob* p) {
     const bool timing = p->timing;
     p->timing = false;
     p->graph_failed =
-        !build_graph(p->ctx, &p->gexec, [&](hipStream_t s) { return enqueue_steps(p, kfbi_prob::kGraphSteps, s); });
+        !record_graph(p->ctx->stream, &p->gexec, [&](hipStream_t s) { return enqueue_steps(p, kfbi_prob::kGraphSteps, s); });
     p->timing = timing;
 }
 
@@ -354,7 +295,7 @@ const char* kfbi_status_str(kfbi_status s) {
     }
 }
 
-const char* kfbi_last_error(void) { return g_err.c_str(); }
+const char* kfbi_last_error(void) { return last_error().c_str(); }
 
 kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
     if (!out) return set_err(KFBI_ERR_ARG, "out is NULL");
@@ -1058,7 +999,7 @@ kfbi_status batch_enqueue_steps(kfbi_batch* B, int nsteps, hipStream_t s) {
 
 void batch_ensure_graph(kfbi_batch* B) {
     if (B->gexec || B->graph_failed) return;
-    B->graph_failed = !build_graph(B->ctx, &B->gexec, [&](hipStream_t s) {
+    B->graph_failed = !record_graph(B->ctx->stream, &B->gexec, [&](hipStream_t s) {
         return batch_enqueue_steps(B, kfbi_batch::kGraphSteps, s);
     });
 }

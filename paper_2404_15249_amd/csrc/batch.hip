@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kGmChunk) void k_gm_vec_b(const SlotDev* __restrict
         const SlotDev& S = slots[item.x];
         if (Kind == 1) gm_update(S.b, S.p.M, item.y, 0);
         if (Kind == 2) gm_update2_commit(S.b, S.p.M, item.y);
-        if (Kind == 3) gm_emit(S.p, S.b, S.p.M, item.y);
+        if (Kind == 3) gm_emit(S.p.taps, S.b, S.p.M, item.y);
         __syncthreads();                                 // the item's LDS is reused by the next item
     }
 }

@@ -54,9 +54,15 @@ __device__ __forceinline__ void twiddle(const double* sq, int k, int N, double& 
     wi = -sinpi_n(sq, (2 * k) & mask2, N);
 }
 
+// Rows are ld elements apart; blockIdx.y selects a slice of `slice` elements
+// (several independent N-row arrays, as the planes of a 3D grid).
 template <class T, class Tin, class Tout, int B>
 __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, const double* __restrict__ sinq,
-                                                          const Tin* in, Tout* out, double alpha, int accumulate) {
+                                                          const Tin* in, Tout* out, double alpha, int accumulate,
+                                                          int ld, size_t slice, const int* __restrict__ skip) {
+    if (skip && *skip) return;
+    in += blockIdx.y * slice;
+    out += blockIdx.y * slice;
     extern __shared__ double smem_d[];
     constexpr int P = B / 2;                                 // column pairs
     constexpr int LP = B == 4 ? 1 : B == 8 ? 2 : 3;          // log2 P
@@ -82,7 +88,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * NTH + tid;
             const int r = idx >> LP, p = idx & (P - 1);
-            if (idx < N * P && r + 1 < N) v[u] = *reinterpret_cast<const Vin*>(in + (size_t)r * N + col0 + 2 * p);
+            if (idx < N * P && r + 1 < N) v[u] = *reinterpret_cast<const Vin*>(in + (size_t)r * ld + col0 + 2 * p);
         }
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             for (int u = 0; u < kLoadBatch; ++u) {
                 const int idx = base + u * NTH + tid;
                 const int r = idx >> LP, p = idx & (P - 1);
-                if (idx < N * P) old[u] = *reinterpret_cast<const Vout*>(out + (size_t)r * N + col0 + 2 * p);
+                if (idx < N * P) old[u] = *reinterpret_cast<const Vout*>(out + (size_t)r * ld + col0 + 2 * p);
             }
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
@@ -258,30 +264,44 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             Vout o;
             o.x = (Tout)vx[u];
             o.y = (Tout)vy[u];
-            if (idx < N * P) *reinterpret_cast<Vout*>(out + (size_t)r * N + col0 + 2 * p) = o;
+            if (idx < N * P) *reinterpret_cast<Vout*>(out + (size_t)r * ld + col0 + 2 * p) = o;
         }
     }
 }
 
+// The transform geometry of one launch: N-row arrays with rows ld elements
+// apart and ld columns, `slices` of them `slice` elements apart.
+struct Lines {
+    int N, log2N;
+    const double* sinq;
+    int ld, slices;
+    size_t slice;
+    const int* skip;
+};
+
 template <class T, class Tin, class Tout, int B>
-hipError_t dst_launch(const DevPlan& p, const Tin* in, Tout* out, double alpha, bool acc, hipStream_t s) {
-    const size_t lds = dst_lds_bytes(p.N, B, sizeof(cpx<T>));
+hipError_t dst_launch(const Lines& g, const Tin* in, Tout* out, double alpha, bool acc, hipStream_t s) {
+    const size_t lds = dst_lds_bytes(g.N, B, sizeof(cpx<T>));
     if (hipError_t e = hipFuncSetAttribute((const void*)k_dst_cols<T, Tin, Tout, B>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds))
         return e;
-    if (hipError_t e_ = klaunch(&k_dst_cols<T, Tin, Tout, B>, dim3(p.N / B), dim3(kDstThreads), lds, s, p.N, p.log2N, p.sinq, in, out, alpha, acc ? 1 : 0)) return e_;
+    if (hipError_t e_ = klaunch(&k_dst_cols<T, Tin, Tout, B>, dim3(g.ld / B, g.slices), dim3(kDstThreads), lds, s,
+                                g.N, g.log2N, g.sinq, in, out, alpha, acc ? 1 : 0, g.ld, g.slice, g.skip))
+        return e_;
     return hipGetLastError();
 }
 
 template <class T, class Tin, class Tout>
-hipError_t dst_dispatch(const DevPlan& p, const Tin* in, Tout* out, double alpha, bool acc, int B, hipStream_t s) {
-    if (!dst_tile_ok(p.N, B, sizeof(cpx<T>), ~(size_t)0)) return hipErrorInvalidValue;
+hipError_t dst_dispatch(const Lines& g, const Tin* in, Tout* out, double alpha, bool acc, int B, hipStream_t s) {
+    if (!dst_tile_ok(g.N, B, sizeof(cpx<T>), ~(size_t)0) || g.ld % B != 0) return hipErrorInvalidValue;
     switch (B) {
-        case 4: return dst_launch<T, Tin, Tout, 4>(p, in, out, alpha, acc, s);
-        case 8: return dst_launch<T, Tin, Tout, 8>(p, in, out, alpha, acc, s);
-        default: return dst_launch<T, Tin, Tout, 16>(p, in, out, alpha, acc, s);
+        case 4: return dst_launch<T, Tin, Tout, 4>(g, in, out, alpha, acc, s);
+        case 8: return dst_launch<T, Tin, Tout, 8>(g, in, out, alpha, acc, s);
+        default: return dst_launch<T, Tin, Tout, 16>(g, in, out, alpha, acc, s);
     }
 }
+
+Lines grid2(const DevPlan& p) { return Lines{p.N, p.log2N, p.sinq, p.N, 1, 0, nullptr}; }
 
 }  // namespace
 
@@ -304,16 +324,21 @@ int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max) {
 
 hipError_t launch_dst_cols(const DevPlan& p, const double* in, double* out, double alpha, bool acc, int B,
                            hipStream_t s) {
-    return dst_dispatch<double>(p, in, out, alpha, acc, B, s);
+    return dst_dispatch<double>(grid2(p), in, out, alpha, acc, B, s);
 }
 
 hipError_t launch_dst_cols_f32(const DevPlan& p, const double* in, float* out, double alpha, int B, hipStream_t s) {
-    return dst_dispatch<float>(p, in, out, alpha, false, B, s);
+    return dst_dispatch<float>(grid2(p), in, out, alpha, false, B, s);
 }
 
 hipError_t launch_dst_cols_f32_to64(const DevPlan& p, const float* in, double* out, double alpha, bool acc, int B,
                                     hipStream_t s) {
-    return dst_dispatch<float>(p, in, out, alpha, acc, B, s);
+    return dst_dispatch<float>(grid2(p), in, out, alpha, acc, B, s);
+}
+
+hipError_t launch_dst_lines(int N, int log2N, const double* sinq, double* a, double alpha, int B, int ld, int slices,
+                            size_t slice, const int* skip, hipStream_t s) {
+    return dst_dispatch<double>(Lines{N, log2N, sinq, ld, slices, slice, skip}, a, a, alpha, false, B, s);
 }
 
 }  // namespace kfbi

@@ -341,9 +341,11 @@ __device__ inline void gm_update2_commit(const GmresBufs& b, int M, int c) {
     if (s_last) gm_commit(b);
 }
 
-// The next K_D input for elements of chunk c, and its spline second derivatives
-// (the filter reads kGmHalo neighbours on each side, wrapping around Gamma).
-__device__ inline void gm_emit(const DevPlan& p, const GmresBufs& b, int M, int c) {
+// The next K_D input for elements of chunk c, and with taps (the spline filter
+// of a curve's density) its spline second derivatives (the filter reads
+// kGmHalo neighbours on each side, wrapping around Gamma); taps is null where
+// the density has no spline (the surface problem).
+__device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs& b, int M, int c) {
     __shared__ double win[kGmChunk + 2 * kGmHalo];
     const GmresState* st = b.st;
     const int kind = st->kind;
@@ -377,10 +379,11 @@ __device__ inline void gm_emit(const DevPlan& p, const GmresBufs& b, int M, int 
     if (kind == kGmNewCycle) b.V[e] = x;
     if (kind == kGmNextVector) b.V[(size_t)st->j * M + e] = x;
     b.xcur[e] = x;
+    if (!taps) return;
     constexpr int K = kSplineK;
     double s = 0.0;
 #pragma unroll
-    for (int q = -K - 1; q <= K + 1; ++q) s = fma(p.taps[q + K + 1], win[kGmHalo + tid + q], s);
+    for (int q = -K - 1; q <= K + 1; ++q) s = fma(taps[q + K + 1], win[kGmHalo + tid + q], s);
     b.s2cur[e] = s;
 }
 

@@ -145,6 +145,11 @@ hipError_t launch_dst_cols_f32_to64(const DevPlan& p, const float* in, double* o
 // LDS of a column-transform workgroup with B columns whose complex pairs take
 // cpx_bytes each; whether B is a valid tile for N within lds_max; the largest
 // valid tile (0 if none).
+// In-place FP64 transforms of `slices` N-row arrays (rows ld elements apart,
+// ld columns, arrays `slice` elements apart): the column transforms of the
+// planes of a 3D grid.  Skipped while *skip is nonzero (skip may be null).
+hipError_t launch_dst_lines(int N, int log2N, const double* sinq, double* a, double alpha, int B, int ld, int slices,
+                            size_t slice, const int* skip, hipStream_t s);
 size_t dst_lds_bytes(int N, int B, size_t cpx_bytes);
 bool dst_tile_ok(int N, int B, size_t cpx_bytes, size_t lds_max);
 int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max);
@@ -157,7 +162,8 @@ hipError_t launch_residual(const DevPlan& p, const double* V, double* R, double*
 hipError_t launch_grid_out(const DevPlan& p, const double* V, bool mask, double* u, hipStream_t s);
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z,
                         hipStream_t s);
-hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s);
+// taps: the spline filter of the density (null: no spline, the surface problem)
+hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s);
 
 size_t modes_lds_bytes(int N, int R);
 

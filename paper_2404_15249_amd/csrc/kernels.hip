@@ -178,7 +178,9 @@ __global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const
 }
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 0); }
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_update2_commit(b, M, blockIdx.x); }
-__global__ __launch_bounds__(kGmChunk) void k_gm_emit(DevPlan p, GmresBufs b) { gm_emit(p, b, p.M, blockIdx.x); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_emit(const double* taps, GmresBufs b, int M) {
+    gm_emit(taps, b, M, blockIdx.x);
+}
 
 
 template <int C, int R>
@@ -299,11 +301,11 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
     return hipGetLastError();
 }
 
-hipError_t launch_gmres_step(const DevPlan& p, GmresBufs b, hipStream_t s) {
+hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s) {
     const dim3 g(b.gc), t(kGmChunk);
-    if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, p.M)) return e;
-    if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, p.M)) return e;
-    return klaunch(&k_gm_emit, g, t, 0, s, p, b);
+    if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, M)) return e;
+    if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, M)) return e;
+    return klaunch(&k_gm_emit, g, t, 0, s, taps, b, M);
 }
 
 }  // namespace kfbi

@@ -42,6 +42,11 @@ class _Desc(ct.Structure):
                 ("restart", ct.c_int), ("max_iter", ct.c_int), ("precision", ct.c_int),
                 ("refine_steps", ct.c_int)]
 
+class _Desc3(ct.Structure):
+    _fields_ = [("n", ct.c_int), ("lo", ct.c_double), ("hi", ct.c_double), ("kappa", ct.c_double),
+                ("axes", ct.c_double * 3), ("tol", ct.c_double), ("restart", ct.c_int), ("max_iter", ct.c_int)]
+
+
 FP64 = 0            # KFBI_FP64
 FP32_REFINED = 1    # KFBI_FP32_REFINED
 _PRECISION = {"fp64": FP64, "fp32": FP32_REFINED}
@@ -86,6 +91,18 @@ _sigs = {
     "kfbi_prob_autotune": [_vp, ct.c_int, ct.POINTER(Tiles)],
     "kfbi_prob_get_tiles": [_vp, ct.POINTER(Tiles)],
     "kfbi_prob_set_tiles": [_vp, ct.POINTER(Tiles)],
+    "kfbi3_prob_create": [_vp, ct.POINTER(_Desc3), ct.POINTER(_vp)],
+    "kfbi3_prob_destroy": [_vp],
+    "kfbi3_prob_info": [_vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_size_t)],
+    "kfbi3_prob_points": [_vp, _vp, _vp],
+    "kfbi3_prob_mask": [_vp, _vp],
+    "kfbi3_prob_irregular": [_vp, _vp],
+    "kfbi3_jumps": [_vp, _vp, _vp, _vp],
+    "kfbi3_apply": [_vp, _vp, _vp],
+    "kfbi3_interface_solve": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi3_solve": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
+    "kfbi3_gmres": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                    ct.POINTER(ct.c_double)],
     "kfbi_set_timing": [_vp, ct.c_int],
     "kfbi_apply_timing": [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                           ct.POINTER(ct.c_int)],
@@ -306,6 +323,111 @@ class Problem:
         a, b, c, n = ct.c_double(), ct.c_double(), ct.c_double(), ct.c_int()
         _check(_lib.kfbi_apply_timing(self._h, ct.byref(a), ct.byref(b), ct.byref(c), ct.byref(n)))
         return {"correct_us": a.value, "modes_us": b.value, "interp_us": c.value, "count": n.value}
+
+
+class Problem3:
+    """The ellipsoid problem on an ``n^3``-interval grid (``kfbi3_*``).
+
+    The control points (the unknowns of the boundary equation) are the
+    grid-edge / surface crossings; ``points()`` gives them, so that ``g`` and
+    ``f`` on the surface can be sampled there.  3D grid arrays are indexed
+    ``[k, j, i]`` with shape ``(n+1, n+1, n+1)``.
+    """
+
+    def __init__(self, ctx: Context, n: int, axes=(0.9, 0.7, 0.5), kappa: float = 0.0, lo: float = -1.2,
+                 hi: float = 1.2, tol: float = 1e-10, restart: int = 50, max_iter: int = 500):
+        self.ctx = ctx
+        d = _Desc3(int(n), float(lo), float(hi), float(kappa), (ct.c_double * 3)(*[float(a) for a in axes]),
+                   float(tol), int(restart), int(max_iter))
+        h = _vp()
+        _check(_lib.kfbi3_prob_create(ctx._h, ct.byref(d), ct.byref(h)))
+        self._h = h
+        self.n, self.kappa, self.lo, self.hi, self.axes = int(n), float(kappa), lo, hi, tuple(axes)
+        m, ni, nb = ct.c_int(), ct.c_int(), ct.c_size_t()
+        _check(_lib.kfbi3_prob_info(h, ct.byref(m), ct.byref(ni), ct.byref(nb)))
+        self.M, self.I, self.device_bytes = m.value, ni.value, nb.value
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.kfbi3_prob_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def grid_numel(self):
+        return (self.n + 1) ** 3
+
+    def points(self):
+        """``(pts, axis)``: control point coordinates (M, 3) and the axis of each one's grid edge."""
+        pts = np.zeros((self.M, 3))
+        axis = np.zeros(self.M, dtype=np.int32)
+        _check(_lib.kfbi3_prob_points(self._h, _vp(pts.ctypes.data), _vp(axis.ctypes.data)))
+        return pts, axis
+
+    def mask(self) -> np.ndarray:
+        out = np.zeros((self.n + 1,) * 3, dtype=np.uint8)
+        _check(_lib.kfbi3_prob_mask(self._h, _vp(out.ctypes.data)))
+        return out.astype(bool)
+
+    def irregular(self) -> np.ndarray:
+        """Irregular nodes as ``(i, j, k)`` rows."""
+        node = np.zeros(self.I, dtype=np.int32)
+        _check(_lib.kfbi3_prob_irregular(self._h, _vp(node.ctypes.data)))
+        n = self.n
+        return np.stack([node % n + 1, (node // n) % n + 1, node // (n * n) + 1], axis=1)
+
+    def jumps(self, phi, f_gamma=None):
+        """Cartesian jumps, shape (10, M): [v], gradient, Hessian (xx, yy, zz, xy, xz, yz)."""
+        J = torch.empty((10, self.M), dtype=torch.float64, device=f"cuda:{self.ctx.device}")
+        with self.ctx:
+            _check(_lib.kfbi3_jumps(self._h, _dptr(phi, "phi", self.M), _dptr(f_gamma, "f_gamma", self.M),
+                                    _dptr(J, "J")))
+        return J
+
+    def apply(self, phi, out=None):
+        if out is None:
+            out = torch.empty_like(phi)
+        with self.ctx:
+            _check(_lib.kfbi3_apply(self._h, _dptr(phi, "phi", self.M), _dptr(out, "out", self.M)))
+        return out
+
+    def interface_solve(self, phi=None, f_grid=None, f_gamma=None):
+        dev = f"cuda:{self.ctx.device}"
+        vg = torch.empty((self.n + 1,) * 3, dtype=torch.float64, device=dev)
+        vz = torch.empty(self.M, dtype=torch.float64, device=dev)
+        with self.ctx:
+            _check(_lib.kfbi3_interface_solve(self._h, _dptr(phi, "phi", self.M),
+                                              _dptr(f_grid, "f_grid", self.grid_numel),
+                                              _dptr(f_gamma, "f_gamma", self.M), _dptr(vg, "vgrid"), _dptr(vz, "vz")))
+        return vg, vz
+
+    def solve(self, f_grid, f_gamma, g, phi0=None):
+        """Dirichlet solve; returns ``(u_grid, u_gamma, phi, iters, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        u = torch.empty((self.n + 1,) * 3, dtype=torch.float64, device=dev)
+        ug = torch.empty(self.M, dtype=torch.float64, device=dev)
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, rel = ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi3_solve(self._h, _dptr(f_grid, "f_grid", self.grid_numel),
+                                         _dptr(f_gamma, "f_gamma", self.M), _dptr(g, "g", self.M),
+                                         _dptr(u, "u_grid"), _dptr(ug, "u_gamma"), _dptr(phi, "phi"),
+                                         ct.byref(it), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return u, ug, phi, it.value, rel.value, st == OK
+
+    def gmres(self, rhs, phi0=None, tol=1e-10, max_iter=500):
+        """GMRES on ``K_D phi = rhs``; returns ``(phi, iters, applies, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, ap, rel = ct.c_int(), ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi3_gmres(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M), float(tol),
+                                         int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return phi, it.value, ap.value, rel.value, st == OK
 
 
 class Batch:

@@ -1,0 +1,148 @@
+"""GPU parity of the three-dimensional path (ellipsoid (0.9, 0.7, 0.5), 7-point
+grid) against the FP64 oracle: the plan (classification, control points,
+irregular nodes) exactly, the jumps, the K_D apply (relative 1e-12 of the
+largest value), and the whole Dirichlet solve (relative 1e-10), at 64^3 and
+128^3.  Every grid-edge crossing is a control point, so the points are closer
+than h and the boundary equation takes a few hundred GMRES steps (the oracle
+needs the same)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import kfbi_oracle3d as O3
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = synth.BOX_LO, synth.BOX_HI
+AXES = (0.9, 0.7, 0.5)
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def K():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_15249_amd import kfbi
+    return kfbi
+
+
+@pytest.fixture(scope="module")
+def ctx(K):
+    return K.Context(0)
+
+
+_plans = {}
+
+
+def oracle_plan(n):
+    if n not in _plans:
+        _plans[n] = O3.build_plan(n, LO, HI, AXES)
+    return _plans[n]
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda:0")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_plan_matches_oracle(K, ctx, n):
+    note(f"3D plan n={n}")
+    prob = K.Problem3(ctx, n, AXES)
+    op = oracle_plan(n)
+    pts, axis = prob.points()
+    assert prob.M == op.M
+    np.testing.assert_array_equal(axis, op.q_axis)
+    assert np.max(np.abs(pts - op.q_pos)) == 0.0
+    np.testing.assert_array_equal(prob.mask(), op.inside)
+    np.testing.assert_array_equal(prob.irregular(), np.array(op.irr))
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_jumps_match_oracle(K, ctx, n):
+    note(f"3D jumps n={n}")
+    prob = K.Problem3(ctx, n, AXES, kappa=1.5)
+    op = oracle_plan(n)
+    phi = synth.smooth_density3(op.q_pos, 1234)
+    fg = np.cos(op.q_pos[:, 0] + 2.0 * op.q_pos[:, 2])
+    ref = O3.jumps(op, phi, fg, 1.5)                        # (M, 10)
+    got = host(prob.jumps(dev(phi), dev(fg))).T
+    for c in range(10):
+        assert relerr(got[:, c], ref[:, c]) < 1e-11, c
+
+
+@pytest.mark.parametrize("n,kappa", [(64, 0.0), (64, 4.0), (128, 0.0)])
+def test_apply_matches_oracle(K, ctx, n, kappa):
+    note(f"3D apply n={n} kappa={kappa}")
+    prob = K.Problem3(ctx, n, AXES, kappa=kappa)
+    op = oracle_plan(n)
+    phi = synth.smooth_density3(op.q_pos, 77)
+    ref = O3.apply_KD(op, phi, kappa)
+    got = host(prob.apply(dev(phi)))
+    assert relerr(got, ref) < 1e-12
+
+
+def test_apply_of_a_constant_density_is_the_constant(K, ctx):
+    """K_D 1 = 1 at the control points for kappa = 0 (the double layer of a
+    constant density is that constant inside): a property of the discrete
+    operator up to its truncation error."""
+    prob = K.Problem3(ctx, 64, AXES)
+    import torch
+    one = torch.ones(prob.M, dtype=torch.float64, device="cuda:0")
+    got = host(prob.apply(one))
+    assert np.max(np.abs(got - 1.0)) < 1e-10
+
+
+@pytest.mark.parametrize("n", [64])
+def test_solve_matches_oracle_and_converges(K, ctx, n):
+    pr = synth.ellipsoid_problem(n=n)
+    note(f"3D solve {pr.name}")
+    op = oracle_plan(n)
+    fg, g = pr.boundary_data(op.q_pos)
+    # with every crossing a control point (spacing below h) the boundary
+    # equation needs a few hundred GMRES steps and the residual stagnates near
+    # 1.2e-12 (the oracle's too): both sides solve to 3e-12
+    ref = O3.solve_bvp(op, pr.kappa, pr.f_grid, fg, g, tol=3e-12, max_iter=1500)
+    rel_ref = float(ref.relres)
+    assert rel_ref < 3e-12, rel_ref
+    prob = K.Problem3(ctx, n, AXES, tol=3e-12, max_iter=1500)
+    u, ug, phi, it, rel, conv = prob.solve(dev(pr.f_grid), dev(fg), dev(g))
+    u, ug = host(u), host(ug)
+    note(f"  iters gpu {it} ({rel:.2e}) oracle {ref.iters} ({ref.relres:.2e}); "
+         f"relerr grid {relerr(u, ref.u_grid):.2e} gamma {relerr(ug, ref.u_gamma):.2e}")
+    assert conv
+    assert abs(it - ref.iters) <= max(2, ref.iters // 50)
+    assert relerr(u, ref.u_grid) < 1e-10
+    assert relerr(ug, ref.u_gamma) < 1e-10
+    e = np.max(np.abs(u - pr.exact_grid())[op.inside])
+    note(f"  Linf error vs exact {e:.3e}")
+    assert e < 2e-3
+
+
+def test_solve_converges_at_second_order_on_the_gpu(K, ctx):
+    errs = []
+    for n in (64, 128):
+        pr = synth.ellipsoid_problem(n=n)
+        prob = K.Problem3(ctx, n, AXES, tol=1e-10, max_iter=1500)
+        pts, _ = prob.points()
+        fg, g = pr.boundary_data(pts)
+        u, ug, phi, it, rel, conv = prob.solve(dev(pr.f_grid), dev(fg), dev(g))
+        assert conv
+        mask = prob.mask()
+        errs.append(float(np.max(np.abs(host(u) - pr.exact_grid())[mask])))
+        note(f"  n={n}: iters {it}, Linf error {errs[-1]:.3e}")
+    assert errs[1] < errs[0] / 3.0, errs

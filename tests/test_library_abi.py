@@ -17,13 +17,13 @@ def _lib_path():
 def declared_symbols():
     text = open(os.path.join(ROOT, "include", "kfbi.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(kfbi_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(kfbi3?_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_declares_the_hot_path():
     names = declared_symbols()
     for must in ("kfbi_ctx_create", "kfbi_prob_create", "kfbi_apply", "kfbi_solve", "kfbi_correct",
-                 "kfbi_fast_solve", "kfbi_interface_solve"):
+                 "kfbi_fast_solve", "kfbi_interface_solve", "kfbi3_prob_create", "kfbi3_apply", "kfbi3_solve"):
         assert must in names
 
 
@@ -47,7 +47,7 @@ def test_status_strings():
 
 
 def test_struct_layouts_match_the_header(tmp_path):
-    """The binding's ctypes structs have the C layout of kfbi_desc and kfbi_tiles."""
+    """The binding's ctypes structs have the C layout of kfbi_desc, kfbi_tiles and kfbi_desc3."""
     import shutil
     import subprocess
     cc = shutil.which("gcc") or shutil.which("cc")
@@ -66,13 +66,16 @@ def test_struct_layouts_match_the_header(tmp_path):
         '  printf("kfbi_tiles size %zu\\n", sizeof(kfbi_tiles));\n'
         "  F(kfbi_tiles, modes_per_group); F(kfbi_tiles, modes_groups); F(kfbi_tiles, dst_cols);\n"
         "  F(kfbi_tiles, apply_us); F(kfbi_tiles, grid_solve_us);\n"
+        '  printf("kfbi_desc3 size %zu\\n", sizeof(kfbi_desc3));\n'
+        "  F(kfbi_desc3, n); F(kfbi_desc3, lo); F(kfbi_desc3, hi); F(kfbi_desc3, kappa); F(kfbi_desc3, axes);\n"
+        "  F(kfbi_desc3, tol); F(kfbi_desc3, restart); F(kfbi_desc3, max_iter);\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     lines = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     _lib_path()
     from paper_2404_15249_amd import kfbi
-    structs = {"kfbi_desc": kfbi._Desc, "kfbi_tiles": kfbi.Tiles}
+    structs = {"kfbi_desc": kfbi._Desc, "kfbi_tiles": kfbi.Tiles, "kfbi_desc3": kfbi._Desc3}
     for line in filter(None, lines):
         name, field, value = line.split()
         st = structs[name]
