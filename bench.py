@@ -21,6 +21,8 @@ Also reported, outside the timed region:
   solve     one full Dirichlet solve of the workload (FP64), error vs exact;
   convergence  full FP64 solves of the star workload at 512^2, 1024^2 and 2048^2:
             L-infinity error against the exact solution and the observed order;
+  three_d   the ellipsoid Poisson problem at 64^3 and 128^3: GMRES steps per
+            second and a full solve with its error against the exact solution;
   mixed     the circle r = 0.8, M = N, kappa = 1 problem at the same grid:
             full solves with FP64 and with FP32-refined grid solves, their
             times and the L-infinity difference between the two;
@@ -217,6 +219,47 @@ def convergence(ctx, sizes=(512, 1024, 2048)) -> dict:
             "rows": rows}
 
 
+def three_d(ctx, sizes=(64, 128), steps: int = 200) -> dict:
+    """The ellipsoid (0.9, 0.7, 0.5) Poisson problem, u = e^(x+y+z): per size,
+    graphed GMRES steps with no convergence stop (grid unknowns per second per
+    step), and a full FP64 solve to 1e-10 with its error against the exact
+    solution."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    rows = []
+    for n in sizes:
+        pr = synth.ellipsoid_problem(n=n)
+        prob = kfbi.Problem3(ctx, n, pr.axes, kappa=pr.kappa, tol=1e-10, max_iter=1500)
+        pts, _ = prob.points()
+        fg, g = pr.boundary_data(pts)
+        rhs = dev(g)
+        prob.gmres(rhs, tol=0.0, max_iter=16)                  # warm-up (records the step graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.gmres(rhs, tol=0.0, max_iter=steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        f_grid, fgd, gd = dev(pr.f_grid), dev(fg), dev(g)
+        prob.solve(f_grid, fgd, gd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u, ug, phi, it, rel, conv = prob.solve(f_grid, fgd, gd)
+        torch.cuda.synchronize()
+        solve_ms = 1e3 * (time.perf_counter() - t1)
+        err = float(np.max(np.abs(u.cpu().numpy() - pr.exact_grid())[prob.mask()]))
+        unknowns = (n - 1) ** 3
+        rows.append({"n": n, "unknowns": unknowns, "control_points": prob.M, "irregular_nodes": prob.I,
+                     "us_per_step": 1e6 * dt / steps, "unknowns_per_s": unknowns * steps / dt,
+                     "solve_ms": solve_ms, "gmres_iters": it, "converged": conv, "linf_err_vs_exact": err})
+        prob.close()
+    for a, b in zip(rows, rows[1:]):
+        b["order"] = float(np.log2(a["linf_err_vs_exact"] / b["linf_err_vs_exact"]))
+    return {"workload": "ellipsoid (0.9,0.7,0.5) in [-1.2,1.2]^3, kappa=0, u=e^(x+y+z), 7-point grid, "
+                        "control points = grid-edge crossings; step = one GMRES iteration", "rows": rows}
+
+
 def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0):
     import synth
     from paper_2404_15249_amd.serving import GpuExecutor, Scheduler, summarize
@@ -275,11 +318,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--mixed", choices=["on", "off"], default="on")
     ap.add_argument("--convergence", choices=["on", "off"], default="on")
+    ap.add_argument("--three-d", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
-    ap.add_argument("--mode", choices=["apply", "serving", "copy"], default="apply",
+    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d"], default="apply",
                     help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "
-                         "copy: a 256 MiB device copy to calibrate the HBM byte counters")
+                         "copy: a 256 MiB device copy to calibrate the HBM byte counters; "
+                         "3d: only the ellipsoid section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the KFBI path here has no multi-GPU mode "
@@ -298,6 +343,9 @@ def main():
         print(json.dumps(copy_calibration()), flush=True)
         return
     ctx = kfbi.Context(0)
+    if args.mode == "3d":
+        print(json.dumps(three_d(ctx)), flush=True)
+        return
     if args.mode == "serving":
         print(json.dumps(serving_line(ctx, args)), flush=True)
         return
@@ -394,6 +442,8 @@ def main():
         out["convergence"] = convergence(ctx)
     if args.mixed == "on":
         out["mixed"] = mixed_precision(ctx, args.n)
+    if args.three_d == "on":
+        out["three_d"] = three_d(ctx)
     if args.serving_requests > 0:
         out["serving"] = serving(ctx, args.serving_requests, args.serving_seed)
     if args.cpu_baseline == "on":

@@ -1,6 +1,6 @@
 // Kernels of the three-dimensional problem (k3.h): the steps of Alg. 1 on the
 // 7-point grid around an ellipsoid.
-//   k_jumps3    one thread per control point: surface derivatives of the
+//   k_jumps3    eight lanes per control point: surface derivatives of the
 //               density from its fit neighbours (a fixed weighted sum), then
 //               the Cartesian jumps from the local frame and shape operator.
 //   k_fill3     the base right-hand side in the interior layout.
@@ -24,24 +24,40 @@ namespace kfbi {
 
 namespace {
 
+constexpr int kFitLanes = 8;   // lanes sharing one control point's neighbour sum
+
 __global__ __launch_bounds__(256) void k_jumps3(DevPlan3 p, const double* __restrict__ phi,
                                                 const double* __restrict__ fgam, double* __restrict__ J,
                                                 const int* __restrict__ skip) {
     if (skip && *skip) return;
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = gid / kFitLanes, sub = gid % kFitLanes;
     const int M = p.M;
-    if (m >= M) return;
-    const double ph = phi[m];
+    const bool valid = m < M;
+    const double ph = valid ? phi[m] : 0.0;
+    // the surface derivatives: each of the point's kFitLanes lanes takes every
+    // kFitLanes-th neighbour, then the lanes' sums are combined (fixed order)
     double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0, d4 = 0.0;
-    for (int e = p.fit_off[m], e1 = p.fit_off[m + 1]; e < e1; ++e) {
-        const double dv = phi[p.fit_idx[e]] - ph;
-        const double* w = p.fit_w + 5 * (size_t)e;
-        d0 = fma(w[0], dv, d0);
-        d1 = fma(w[1], dv, d1);
-        d2 = fma(w[2], dv, d2);
-        d3 = fma(w[3], dv, d3);
-        d4 = fma(w[4], dv, d4);
+    if (valid) {
+        for (int e = p.fit_off[m] + sub, e1 = p.fit_off[m + 1]; e < e1; e += kFitLanes) {
+            const double dv = phi[p.fit_idx[e]] - ph;
+            const double* w = p.fit_w + 5 * (size_t)e;
+            d0 = fma(w[0], dv, d0);
+            d1 = fma(w[1], dv, d1);
+            d2 = fma(w[2], dv, d2);
+            d3 = fma(w[3], dv, d3);
+            d4 = fma(w[4], dv, d4);
+        }
     }
+#pragma unroll
+    for (int off = kFitLanes / 2; off >= 1; off >>= 1) {
+        d0 += __shfl_xor(d0, off, 64);
+        d1 += __shfl_xor(d1, off, 64);
+        d2 += __shfl_xor(d2, off, 64);
+        d3 += __shfl_xor(d3, off, 64);
+        d4 += __shfl_xor(d4, off, 64);
+    }
+    if (!valid || sub != 0) return;
     const double* g = p.geo + 12 * (size_t)m;
     const double nx = g[0], ny = g[1], nz = g[2];
     const double ax = g[3], ay = g[4], az = g[5];     // t1
@@ -171,7 +187,10 @@ __global__ __launch_bounds__(256) void k_grid_out3(DevPlan3 p, const double* __r
 
 hipError_t launch_jumps3(const DevPlan3& p, const double* phi, const double* fgam, double* J, const int* skip,
                          hipStream_t s) {
-    if (hipError_t e = klaunch(&k_jumps3, dim3((p.M + 255) / 256), dim3(256), 0, s, p, phi, fgam, J, skip)) return e;
+    const size_t threads = (size_t)p.M * kFitLanes;
+    if (hipError_t e = klaunch(&k_jumps3, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, p, phi, fgam, J,
+                               skip))
+        return e;
     return hipGetLastError();
 }
 
