@@ -34,8 +34,8 @@
  *   kfbi_prob_create.  A problem or batch handle must not be used by two host
  *   threads at the same time; different handles on one context may be used
  *   from different threads (e.g. problems created by a preparation thread while
- *   another thread steps a batch): the library captures its graphs on a private
- *   stream, so such calls never enter a capture.
+ *   another thread steps a batch): the library builds its graphs node by node,
+ *   never by stream capture, so no call ever runs inside a capture.
  *
  * Errors: every call returns a kfbi_status; on error no output is written (for
  * enqueueing calls: nothing is enqueued) and kfbi_last_error() returns a
