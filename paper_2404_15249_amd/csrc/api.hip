@@ -179,8 +179,11 @@ kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, boo
     return KFBI_OK;
 }
 
+// K_D phi without the dense grid (correction, sparse fast solve, reduction and
+// interpolation).  With corr_ready the corrections are already in corr_il (made
+// by the previous GMRES step's emit launch) and the correction launch is skipped.
 kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, double* out, const int* skip,
-                         const GmresBufs* gm, hipStream_t s) {
+                         const GmresBufs* gm, hipStream_t s, bool corr_ready = false) {
     JumpSrc js{phi, phi_s2, nullptr, nullptr, nullptr, nullptr};
     hipEvent_t* ev = nullptr;
     if (p->timing && p->t_count < kfbi_prob::kMaxTimed && !graph_rec()) {
@@ -196,8 +199,8 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
         if (ev) launch_events() = LaunchEvents{ev[2 * q], ev[2 * q + 1]};
     };
     stage(0);
-    HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, skip, s));
-    if (ev && launch_events().start) {            // no irregular nodes: nothing was launched
+    if (!corr_ready) HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, skip, s));
+    if (ev && launch_events().start) {            // nothing was launched
         launch_events() = LaunchEvents{};
         HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(hipEventRecord(ev[1], s));
@@ -213,12 +216,21 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
 // Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps are
 // enqueued in batches; with tol > 0 the host polls the device state after each
 // batch, with tol <= 0 the work is fixed and the host waits once at the end.
+// One GMRES step is the apply and the orthogonalisation.  Outside timing mode
+// each step's emit launch also makes the next apply's corrections, so the
+// apply starts from them; run_gmres makes the first step's.  With timing on the
+// corrections get their own launch, timed as a stage of the apply.
 kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
     GmresBufs b = p->gm;
     const int* skip = &b.st->converged;
+    const bool fused = !p->timing;
     for (int k = 0; k < nsteps; ++k) {
-        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, &p->gm, s)) return e;
-        HIP_TRY(launch_gmres_step(p->dp.taps, p->dp.M, b, s));
+        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, &p->gm, s, fused)) return e;
+        if (fused) {
+            HIP_TRY(launch_gmres_step_corr(p->dp, b, p->corr_il, s));
+        } else {
+            HIP_TRY(launch_gmres_step(p->dp.taps, p->dp.M, b, s));
+        }
     }
     return KFBI_OK;
 }
@@ -253,6 +265,10 @@ kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_it
     st0.max_iter = max_iter;
     HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
+    if (!p->timing) {                                  // the first step's corrections
+        JumpSrc js{b.xcur, b.s2cur, nullptr, nullptr, nullptr, nullptr};
+        HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, nullptr, s));
+    }
     const int cycles = max_iter / std::max(1, p->restart) + 2;
     const int max_steps = max_iter + cycles;
     const int B = kfbi_prob::kGraphSteps;
@@ -507,6 +523,64 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     }
     std::vector<int4> cpk(p->M);
     for (int k = 0; k < p->M; ++k) cpk[k] = make_int4(P.cp_i0[k], P.cp_j0[k], sxy[k], 0);
+    // correction chunks: irregular nodes in the order of their first crossing
+    // along Gamma, cut where a chunk would exceed kCorrChunk nodes or its
+    // crossings' segments (with the spline filter's reach) a window of
+    // kCorrWindow knots
+    std::vector<int> cc_node(std::max(p->I, 1), 0);
+    std::vector<int4> cc_chunk;
+    {
+        const int M = p->M, I = p->I, reach = K + 1;
+        std::vector<int> key(I);
+        for (int r = 0; r < I; ++r) {
+            cc_node[r] = r;
+            key[r] = P.q_geo[P.arm_q[4 * r]].seg;
+        }
+        std::stable_sort(cc_node.begin(), cc_node.begin() + I, [&](int a, int b) { return key[a] < key[b]; });
+        auto offset = [M](int seg, int ref) {        // seg - ref on the circle, in (-M/2, M/2]
+            int o = ((seg - ref) % M + M) % M;
+            return o > M / 2 ? o - M : o;
+        };
+        int first = 0;
+        while (first < I) {
+            const int ref = key[cc_node[first]];
+            int lo = 0, hi = 0, end = first;
+            while (end < I && end - first < kCorrChunk) {
+                const int r = cc_node[end];
+                int nlo = lo, nhi = hi;
+                for (int a = 0; a < 4 && P.arm_q[4 * r + a] >= 0; ++a) {
+                    const int o = offset(P.q_geo[P.arm_q[4 * r + a]].seg, ref);
+                    nlo = std::min(nlo, o);
+                    nhi = std::max(nhi, o + 1);           // the segment's end knot
+                }
+                if (end > first && (nhi - nlo + 1) + 2 * reach > kCorrWindow) break;
+                lo = nlo;
+                hi = nhi;
+                ++end;
+            }
+            const int width = (hi - lo + 1) + 2 * reach;
+            if (width > kCorrWindow) return fail(set_err(KFBI_ERR_GEOMETRY, "an irregular node's crossings lie too far apart along the curve"));
+            const int k0 = ((ref + lo - reach) % M + M) % M;
+            cc_chunk.push_back(make_int4(first, end, k0, width));
+            first = end;
+        }
+        dp.n_cc = (int)cc_chunk.size();
+    }
+    if (cc_chunk.empty()) cc_chunk.push_back(make_int4(0, 0, 0, 0));
+    std::vector<int4> cc_arm(std::max(p->I, 1), make_int4(-1, -1, -1, -1));
+    std::vector<double4> cc_d(std::max(p->I, 1), make_double4(0, 0, 0, 0));
+    std::vector<double> cc_s(std::max(p->I, 1), 0.0);
+    std::vector<int> cc_pos(std::max(p->I, 1), 0);
+    for (int at = 0; at < p->I; ++at) {
+        const int r = cc_node[at];
+        cc_arm[at] = make_int4(P.arm_q[4 * r], P.arm_q[4 * r + 1], P.arm_q[4 * r + 2], P.arm_q[4 * r + 3]);
+        cc_d[at] = make_double4(P.arm_d[4 * r], P.arm_d[4 * r + 1], P.arm_d[4 * r + 2], P.arm_d[4 * r + 3]);
+        cc_s[at] = P.irr_s[r];
+        cc_pos[at] = il_pos[r];
+    }
+    if ((st = upload(p, &dp.cc_arm, cc_arm)) || (st = upload(p, &dp.cc_d, cc_d)) || (st = upload(p, &dp.cc_s, cc_s)) ||
+        (st = upload(p, &dp.cc_pos, cc_pos)) || (st = upload(p, &dp.cc_chunk, cc_chunk)))
+        return fail(st);
     if ((st = upload(p, &dp.q_geo, P.q_geo)) || (st = upload(p, &dp.q_axis, P.q_axis)) ||
         (st = upload(p, &dp.z_geo, P.z_geo)) || (st = upload(p, &dp.zx, P.px)) || (st = upload(p, &dp.zy, P.py)) ||
         (st = upload(p, &dp.irr_i, P.irr_i)) || (st = upload(p, &dp.irr_j, P.irr_j)) ||

@@ -345,6 +345,34 @@ __device__ inline void gm_update2_commit(const GmresBufs& b, int M, int c) {
 // of a curve's density) its spline second derivatives (the filter reads
 // kGmHalo neighbours on each side, wrapping around Gamma); taps is null where
 // the density has no spline (the surface problem).
+// Element e of the next K_D input the last commit left (kind != kGmDone): the
+// updated iterate at the end of a cycle, else the normalised vector.
+__device__ __forceinline__ double gm_next_x(const GmresBufs& b, int M, int kind, double scale, int jn, int e) {
+    if (kind == kGmCycleEnd) {
+        double x = b.phi[e];
+        for (int i0 = 0; i0 < jn; i0 += 8) {
+            double vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vv[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < jn) x = fma(b.y[i0 + u], vv[u], x);
+        }
+        return x;
+    }
+    return b.z[e] * scale;
+}
+
+// Spline second derivative at window place w (the filter reads kGmHalo places
+// on each side): the same periodic filter gm_emit applies.
+__device__ __forceinline__ double gm_spline_s2(const double* __restrict__ taps, const double* win, int w) {
+    constexpr int K = kSplineK;
+    double s = 0.0;
+#pragma unroll
+    for (int q = -K - 1; q <= K + 1; ++q) s = fma(taps[q + K + 1], win[w + q], s);
+    return s;
+}
+
 __device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs& b, int M, int c) {
     __shared__ double win[kGmChunk + 2 * kGmHalo];
     const GmresState* st = b.st;
@@ -356,21 +384,7 @@ __device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs&
     for (int k = tid; k < kGmChunk + 2 * kGmHalo; k += kGmChunk) {
         int e = (c0 - kGmHalo + k) % M;
         if (e < 0) e += M;
-        double x;
-        if (kind == kGmCycleEnd) {
-            x = b.phi[e];
-            for (int i0 = 0; i0 < jn; i0 += 8) {
-                double vv[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) vv[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (i0 + u < jn) x = fma(b.y[i0 + u], vv[u], x);
-            }
-        } else {
-            x = b.z[e] * scale;
-        }
-        win[k] = x;
+        win[k] = gm_next_x(b, M, kind, scale, jn, e);
     }
     __syncthreads();
     const int e = c0 + tid;
@@ -380,11 +394,90 @@ __device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs&
     if (kind == kGmNextVector) b.V[(size_t)st->j * M + e] = x;
     b.xcur[e] = x;
     if (!taps) return;
-    constexpr int K = kSplineK;
-    double s = 0.0;
+    b.s2cur[e] = gm_spline_s2(taps, win, kGmHalo + tid);
+}
+
+// The corrections (Alg. 2) of the next K_D apply for correction chunk cc, made
+// in the same launch as gm_emit: the chunk's window of the next input is
+// formed here from the same values gm_emit writes (gm_next_x), its spline
+// second derivatives by the same filter, and the corrections by the same
+// arithmetic as a separate correction launch after gm_emit.  One workgroup of
+// kGmChunk threads; corr_il in the sparse-sum layout.
+__device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b, int cc, double* __restrict__ corr_il) {
+    __shared__ double xw[kCorrWindow];
+    __shared__ double sw[kCorrWindow];
+    const int M = p.M, tid = threadIdx.x;
+    const int4 ch = p.cc_chunk[cc];                      // first, end, first knot, width
+    // the node's plan data first, so that its loads overlap the window's
+    const int at = ch.x + tid;
+    const bool act = at < ch.y;
+    int4 arm = make_int4(-1, -1, -1, -1);
+    double4 dd = make_double4(0.0, 0.0, 0.0, 0.0);
+    double sg = 0.0;
+    int slot = 0;
+    if (act) {
+        arm = p.cc_arm[at];
+        dd = p.cc_d[at];
+        sg = p.cc_s[at];
+        slot = p.cc_pos[at];
+    }
+    const int ks[4] = {arm.x, arm.y, arm.z, arm.w};
+    const double ds[4] = {dd.x, dd.y, dd.z, dd.w};
+    PointGeom gs[4];
+    int axs[4];
 #pragma unroll
-    for (int q = -K - 1; q <= K + 1; ++q) s = fma(taps[q + K + 1], win[kGmHalo + tid + q], s);
-    b.s2cur[e] = s;
+    for (int a = 0; a < 4; ++a) {
+        if (ks[a] >= 0) {
+            gs[a] = p.q_geo[ks[a]];
+            axs[a] = p.q_axis[ks[a]];
+        } else {
+            gs[a] = PointGeom{};
+            axs[a] = 0;
+        }
+    }
+    const GmresState* st = b.st;
+    const int kind = st->kind;
+    if (kind == kGmDone) return;
+    const double scale = st->scale;
+    const int jn = st->jn;
+    for (int w = tid; w < ch.w; w += kGmChunk) xw[w] = gm_next_x(b, M, kind, scale, jn, (ch.z + w) % M);
+    __syncthreads();
+    for (int w = kGmHalo + tid; w < ch.w - kGmHalo; w += kGmChunk) sw[w] = gm_spline_s2(p.taps, xw, w);
+    __syncthreads();
+    if (!act) return;
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        if (ks[a] < 0) continue;
+        const double d = ds[a];
+        const PointGeom& g = gs[a];
+        // the segment's first knot in the window; a window longer than M holds
+        // some knots twice, and the copy inside the filter's reach of the
+        // window's ends has no second derivative: take the other
+        int l = ((g.seg - ch.z) % M + M) % M;
+        if (l < kGmHalo) l += M;
+        // the spline on the segment, as spline_at computes it
+        const double s0 = sw[l], s1 = sw[l + 1];
+        const double y0 = xw[l], y1 = xw[l + 1], u = g.u, w = 1.0 - u;
+        const double sixth = 1.0 / 6.0;
+        const double P = w * y0 + u * y1 + (w * w * w - w) * s0 * sixth + (u * u * u - u) * s1 * sixth;
+        const double P1 = (y1 - y0) - (3.0 * w * w - 1.0) * s0 * sixth + (3.0 * u * u - 1.0) * s1 * sixth;
+        const double P2 = w * s0 + u * s1;
+        // the jumps, as jumps_at computes them with [F] = 0
+        const double Ps = P1 * g.a1;
+        const double Pss = P2 * g.a2 - P1 * g.a3;
+        const double vtt = Pss, vtn = -g.curv * Ps, vnn = 0.0 + p.kappa * P - vtt;
+        double gv, hh;
+        if (axs[a]) {
+            gv = Ps * g.ty;
+            hh = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
+        } else {
+            gv = Ps * g.tx;
+            hh = vtt * g.tx * g.tx + 2.0 * vtn * g.tx * g.nx + vnn * g.nx * g.nx;
+        }
+        acc -= sg * (P + d * gv + 0.5 * d * d * hh);
+    }
+    corr_il[slot] = acc * p.inv_h2;
 }
 
 }  // namespace kfbi

@@ -59,9 +59,23 @@ struct DevPlan {
     const ModeConst* modes;   // N (index l = 1..N-1 used)
     const double* taps;       // 2 K + 3 spline filter taps
     int K;                    // must equal kSplineK
+    // the irregular nodes in the order of their first crossing along Gamma, cut
+    // into chunks of at most kCorrChunk nodes whose crossings' spline segments
+    // span at most a window of kCorrWindow knots (with the filter's reach):
+    // chunk c = (first, end, first window knot, window length) of that order.
+    // Per place in the order: the node's arms (crossing index, -1 unused; the
+    // distance d), its side and its slot in the sparse-sum layout.
+    const int4* cc_arm;       // I
+    const double4* cc_d;      // I
+    const double* cc_s;       // I
+    const int* cc_pos;        // I
+    const int4* cc_chunk;     // n_cc
+    int n_cc;
 };
 
 constexpr int kSplineK = 30;
+constexpr int kCorrChunk = 256;    // irregular nodes per correction chunk (one workgroup)
+constexpr int kCorrWindow = 256;   // knots of a chunk's density window
 constexpr int kSlots = 4;          // table rows loaded together by the sparse sine sums
 constexpr int kModeWaves = 8;      // wavefronts of a sparse-fast-solve workgroup (= node sub-tables)
 constexpr int kMaxModesPerGroup = 8;
@@ -164,6 +178,9 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
                         hipStream_t s);
 // taps: the spline filter of the density (null: no spline, the surface problem)
 hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s);
+// the same step with the next apply's corrections made in the emit launch
+// (into corr_il, the sparse-sum layout)
+hipError_t launch_gmres_step_corr(const DevPlan& p, GmresBufs b, double* corr_il, hipStream_t s);
 
 size_t modes_lds_bytes(int N, int R);
 

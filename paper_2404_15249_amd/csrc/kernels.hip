@@ -181,6 +181,15 @@ __global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_u
 __global__ __launch_bounds__(kGmChunk) void k_gm_emit(const double* taps, GmresBufs b, int M) {
     gm_emit(taps, b, M, blockIdx.x);
 }
+// the emit launch with the next apply's corrections: workgroups 0 .. gc-1
+// emit, the rest make one correction chunk each
+__global__ __launch_bounds__(kGmChunk) void k_gm_emit_corr(DevPlan p, GmresBufs b, double* __restrict__ corr_il) {
+    if ((int)blockIdx.x < b.gc) {
+        gm_emit(p.taps, b, p.M, blockIdx.x);
+    } else {
+        gm_emit_corrections(p, b, (int)blockIdx.x - b.gc, corr_il);
+    }
+}
 
 
 template <int C, int R>
@@ -299,6 +308,13 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
     if (n <= 0) return hipSuccess;
     if (hipError_t e_ = klaunch(&k_axpby, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, b, y, z)) return e_;
     return hipGetLastError();
+}
+
+hipError_t launch_gmres_step_corr(const DevPlan& p, GmresBufs b, double* corr_il, hipStream_t s) {
+    const dim3 g(b.gc), t(kGmChunk);
+    if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, p.M)) return e;
+    if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, p.M)) return e;
+    return klaunch(&k_gm_emit_corr, dim3(b.gc + p.n_cc), t, 0, s, p, b, corr_il);
 }
 
 hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s) {

@@ -191,3 +191,22 @@ def test_solve_matches_oracle(K, ctx, name):
     assert relerr(host(u), ref.u_grid) < 1e-10
     assert relerr(host(ug), ref.u_gamma) < 1e-10
     assert abs(it - ref.iters) <= 2
+
+
+@pytest.mark.parametrize("name", ["circle64", "star512"])
+def test_gmres_with_corrections_in_the_emit_launch(K, ctx, name):
+    """Outside timing mode each GMRES step's emit launch also makes the next
+    apply's corrections from its own window of the next input; with timing on
+    they come from a separate correction launch.  Both runs, across a restart
+    (60 steps with restart 50), give the same iterate."""
+    p = CASES[name]()
+    note(f"fused corrections {name}")
+    prob = K.Problem(ctx, p.xy, p.n, p.kappa)
+    rhs = dev(p.g)
+    prob.set_timing(False)
+    a, it_a, *_ = prob.gmres(rhs, tol=0.0, max_iter=60)
+    prob.set_timing(True)
+    b, it_b, *_ = prob.gmres(rhs, tol=0.0, max_iter=60)
+    prob.set_timing(False)
+    assert it_a == it_b == 60
+    assert relerr(host(a), host(b)) < 1e-13
