@@ -31,9 +31,10 @@ enum GmKind { kGmNewCycle = 0, kGmNextVector = 1, kGmCycleEnd = 2, kGmDone = 3 }
 __host__ __device__ inline int gm_chunks(int M) { return (M + kGmChunk - 1) / kGmChunk; }
 __host__ __device__ inline int gm_chunks64(int M) { return (M + 63) / 64; }
 // doubles of partial sums a problem needs: first-pass dots (m+1) x gc64,
-// second-pass dots (m+1) x gc, norms of the update (gc) and of the residual (gc64)
+// second-pass dots (m+1) x gc, norms of the update (gc) and of the residual
+// (gc64), and the first-pass coefficients (m+1)
 __host__ __device__ inline size_t gm_part_size(int m, int gc, int gc64) {
-    return (size_t)(m + 1) * (gc64 + gc) + gc + gc64;
+    return (size_t)(m + 1) * (gc64 + gc + 1) + gc + gc64;
 }
 
 struct GmPart {
@@ -41,6 +42,7 @@ struct GmPart {
     double* d2;     // [i * gc + c]
     double* nrm;    // [c]
     double* nrm0;   // [c64]
+    double* h1;     // [i]: sum of d1 over the chunks (written by chunk 0 of the first update)
 };
 __device__ __forceinline__ GmPart gm_part(const GmresBufs& b) {
     GmPart q;
@@ -48,6 +50,7 @@ __device__ __forceinline__ GmPart gm_part(const GmresBufs& b) {
     q.d2 = q.d1 + (size_t)(b.m + 1) * b.gc64;
     q.nrm = q.d2 + (size_t)(b.m + 1) * b.gc;
     q.nrm0 = q.nrm + b.gc;
+    q.h1 = q.nrm0 + b.gc64;
     return q;
 }
 
@@ -165,11 +168,12 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
 
 // pass 0: z = w - sum h_i V_i and the second-pass dots V_i . z; pass 1:
 // z -= sum h'_i V_i and |z|^2.  The basis values are loaded once per launch.
-__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int pass) {
+// Returns the workgroup's copy of the pass's coefficients (LDS, i <= j).
+__device__ __forceinline__ const double* gm_update(const GmresBufs& b, int M, int c, int pass) {
     __shared__ double hs[kMaxRestart + 2];
     __shared__ double red[64];
     const GmresState* st = b.st;
-    if (st->mode != 1) return;
+    if (st->mode != 1) return hs;
     const int tid = threadIdx.x, gc = b.gc, j = st->j;
     const GmPart q = gm_part(b);
     const double* coef = pass == 0 ? q.d1 : q.d2;
@@ -179,6 +183,7 @@ __device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int 
 #pragma unroll 16
         for (int cc = 0; cc < nco; ++cc) s += coef[(size_t)i * nco + cc];   // loads issued together
         hs[i] = s;
+        if (pass == 0 && c == 0) q.h1[i] = s;
     }
     const int e = c * kGmChunk + tid;
     double v[4][16];
@@ -200,10 +205,12 @@ __device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int 
         const double s = gm_block_sum(a * a, red);
         if (tid == 0) q.nrm[c] = s;
     }
+    return hs;
 }
 
-// One workgroup of kGmChunk threads.
-__device__ inline void gm_commit(const GmresBufs& b) {
+// One workgroup of kGmChunk threads; h2: the second-pass coefficients this
+// workgroup's update left in LDS (mode 1).
+__device__ inline void gm_commit(const GmresBufs& b, const double* h2) {
     __shared__ double red[4];
     __shared__ double col[kMaxRestart + 2];
     __shared__ double cs_s[kMaxRestart], sn_s[kMaxRestart], rot[kMaxRestart];
@@ -219,8 +226,18 @@ __device__ inline void gm_commit(const GmresBufs& b) {
     const GmPart q = gm_part(b);
     const double* norm = mode == 0 ? q.nrm0 : q.nrm;
     const int nn = mode == 0 ? gc64 : gc;
+    // every load first: the norm partials, the Hessenberg column (first-pass
+    // coefficients plus this workgroup's second-pass ones), the rotations
     double v = 0.0;
     for (int cc = tid; cc < nn; cc += kGmChunk) v += norm[cc];
+    double colv = 0.0, csv = 0.0, snv = 0.0;
+    if (mode == 1) {
+        if (tid <= j) colv = q.h1[tid] + h2[tid];
+        if (tid < j) {
+            csv = b.cs[tid];
+            snv = b.sn[tid];
+        }
+    }
     const double nrm = sqrt(gm_block_sum(v, red));
     if (mode == 0) {
         if (tid == 0) {
@@ -248,28 +265,33 @@ __device__ inline void gm_commit(const GmresBufs& b) {
         return;
     }
     // mode 1: column j of the Hessenberg matrix from the two Gram-Schmidt passes
-    for (int i = tid; i <= j; i += kGmChunk) {
-        double s1 = 0.0, s2 = 0.0;
-#pragma unroll 16
-        for (int cc = 0; cc < gc64; ++cc) s1 += q.d1[(size_t)i * gc64 + cc];
-#pragma unroll 16
-        for (int cc = 0; cc < gc; ++cc) s2 += q.d2[(size_t)i * gc + cc];
-        col[i] = s1 + s2;
-    }
+    if (tid <= j) col[tid] = colv;
     if (tid < j) {
-        cs_s[tid] = b.cs[tid];
-        sn_s[tid] = b.sn[tid];
+        cs_s[tid] = csv;
+        sn_s[tid] = snv;
     }
     __syncthreads();
     if (tid == 0) {
         const double hn = nrm;
-        // previous rotations down the column; the rotated entries go to rot[]
-        // so the loads of col, cs and sn do not wait on the stores
+        // previous rotations down the column, eight at a time: their operands
+        // are read together; the rotated entries go to rot[]
         double a = col[0];
-        for (int i = 0; i < j; ++i) {
-            const double cn = col[i + 1], cc = cs_s[i], ss = sn_s[i];
-            rot[i] = cc * a + ss * cn;
-            a = -ss * a + cc * cn;
+        for (int i0 = 0; i0 < j; i0 += 8) {
+            double cn[8], c8[8], s8[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const bool in = i0 + u < j;
+                cn[u] = in ? col[i0 + u + 1] : 0.0;
+                c8[u] = in ? cs_s[i0 + u] : 1.0;
+                s8[u] = in ? sn_s[i0 + u] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (i0 + u < j) {
+                    rot[i0 + u] = c8[u] * a + s8[u] * cn[u];
+                    a = -s8[u] * a + c8[u] * cn[u];
+                }
+            }
         }
         for (int i = 0; i < j; ++i) col[i] = rot[i];
         const double den = hypot(a, hn);
@@ -327,7 +349,7 @@ __device__ inline void gm_update2_commit(const GmresBufs& b, int M, int c) {
     __shared__ int s_last;
     const int mode = b.st->mode;
     if (mode == 2) return;
-    if (mode == 1) gm_update(b, M, c, 1);
+    const double* h2 = gm_update(b, M, c, 1);
     if (threadIdx.x == 0) {
         __threadfence();                                   // this chunk's partials before the count
         const unsigned done = atomicAdd(b.cnt, 1u) + 1;
@@ -338,7 +360,7 @@ __device__ inline void gm_update2_commit(const GmresBufs& b, int M, int c) {
         }
     }
     __syncthreads();
-    if (s_last) gm_commit(b);
+    if (s_last) gm_commit(b, h2);
 }
 
 // The next K_D input for elements of chunk c, and with taps (the spline filter
