@@ -339,12 +339,13 @@ __device__ __forceinline__ ModesLds modes_lds(double* smem, int N) {
 // kModeWaves wavefronts.
 //  1. Sparse sine sums of the corrected right-hand side along y: wavefront w
 //     walks sub-table w of the interleaved node table (each lane owns whole
-//     columns); per node the sines of all R modes come from two table lookups
-//     and the angle-addition recurrence sin((l+1)t) = sin(lt) cos t + cos(lt) sin t,
+//     columns); per node the sines of all R modes come from three table
+//     lookups and the recurrence sin((l+1)t) = 2 cos t sin(lt) - sin((l-1)t),
 //     and a column's R sums are stored when its last node is reached.
 //  2. The tridiagonal solve along x of each mode (one wavefront per mode).
-//  3. The weighted six-point gather at every sample: emit(cp, s) with s the sum
-//     over the R modes, for cp = tid, tid + 64 kModeWaves, ...
+//  3. The weighted six-point gather at every sample (the row sines by the same
+//     recurrence): emit(cp, s) with s the sum over the R modes, for
+//     cp = tid, tid + 64 kModeWaves, ...
 // L.sq must hold the sine table of p.N; must be called by the whole workgroup.
 template <int C, int R, class Emit>
 __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __restrict__ corr, int base,
@@ -383,20 +384,21 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
             }
 #pragma unroll
             for (int q = 0; q < kSlots; ++q) {
+                // sin((l0 + r) t), t = pi j / N, for r = 0 .. R-1: two table
+                // values, then s_{r+1} = 2 cos t s_r - s_{r-1}
                 const int j = pk[q] & 0xfff;
                 const int m0 = (int)(__umul24((unsigned)j, (unsigned)l0) & mask2);
-                double sn = sinpi_n(sq, m0, N);
-                double cs = sinpi_n(sq, (m0 + half) & mask2, N);
-                const double s1 = R > 1 ? sinpi_n(sq, j, N) : 0.0;
-                const double c1 = R > 1 ? sinpi_n(sq, (j + half) & mask2, N) : 0.0;
+                double sp = sinpi_n(sq, m0, N);
+                double sc = R > 1 ? sinpi_n(sq, (m0 + j) & mask2, N) : 0.0;
+                const double c2 = R > 2 ? 2.0 * sinpi_n(sq, (j + half) & mask2, N) : 0.0;
+                acc[0] = fma(cv[q], sp, acc[0]);
+                if (R > 1) acc[1] = fma(cv[q], sc, acc[1]);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
+                for (int r = 2; r < R; ++r) {
+                    const double sn = fma(c2, sc, -sp);
                     acc[r] = fma(cv[q], sn, acc[r]);
-                    if (r + 1 < R) {
-                        const double sn2 = sn * c1 + cs * s1;
-                        cs = cs * c1 - sn * s1;
-                        sn = sn2;
-                    }
+                    sp = sc;
+                    sc = sn;
                 }
                 if (pk[q] < 0) {                        // last node of its piece
                     const int dest = (pk[q] >> 16) & 0x7fff;
@@ -456,25 +458,53 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
         // places of the stencil columns in the padded layout (node 0 lies on
         // the box: zero); the sine arguments advance by j per mode
         const int pc = i0 + (i0 - 1) / C, pe = i0 + i0 / C + 1, pw = i0 > 1 ? i0 - 1 + (i0 - 2) / C : -1;
-        int a0 = (int)(__umul24((unsigned)j0, (unsigned)l0) & mask2);
-        int ap = (int)(__umul24((unsigned)(j0 + 1), (unsigned)l0) & mask2);
-        int am = (int)(__umul24((unsigned)(j0 - 1), (unsigned)l0) & mask2);
+        // sines of the rows j0, j0 + 1, j0 - 1 for the modes l0 + q: two table
+        // values each, then the three-term recurrence in q
+        const int a0 = (int)(__umul24((unsigned)j0, (unsigned)l0) & mask2);
+        const int ap = (int)(__umul24((unsigned)(j0 + 1), (unsigned)l0) & mask2);
+        const int am = (int)(__umul24((unsigned)(j0 - 1), (unsigned)l0) & mask2);
+        double s0p = sinpi_n(sq, a0, N), spp = sinpi_n(sq, ap, N), smp = sinpi_n(sq, am, N);
+        double s0c = 0.0, spc = 0.0, smc = 0.0, c0 = 0.0, cpl = 0.0, cmi = 0.0;
+        if (R > 1) {
+            s0c = sinpi_n(sq, (a0 + j0) & mask2, N);
+            spc = sinpi_n(sq, (ap + j0 + 1) & mask2, N);
+            smc = sinpi_n(sq, (am + j0 - 1) & mask2, N);
+        }
+        if (R > 2) {
+            c0 = 2.0 * sinpi_n(sq, (j0 + half) & mask2, N);
+            cpl = 2.0 * sinpi_n(sq, (j0 + 1 + half) & mask2, N);
+            cmi = 2.0 * sinpi_n(sq, (j0 - 1 + half) & mask2, N);
+        }
         double s = 0.0;
         // modes beyond n were never written: their solutions are zero
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const double* xq = L.xs + q * XS;
-            const double s0 = sinpi_n(sq, a0, N);
-            const double sp = sinpi_n(sq, ap, N);
-            const double sm = sinpi_n(sq, am, N);
+            double s0, sp, sm;
+            if (q == 0) {
+                s0 = s0p;
+                sp = spp;
+                sm = smp;
+            } else if (q == 1) {
+                s0 = s0c;
+                sp = spc;
+                sm = smc;
+            } else {
+                s0 = fma(c0, s0c, -s0p);
+                sp = fma(cpl, spc, -spp);
+                sm = fma(cmi, smc, -smp);
+                s0p = s0c;
+                spp = spc;
+                smp = smc;
+                s0c = s0;
+                spc = sp;
+                smc = sm;
+            }
             const double xc = xq[pc];
             const double xe = xq[pe];
             const double xw = pw >= 0 ? xq[pw] : 0.0;
             const double xd = sx > 0 ? xe : xw;
             s += s0 * (w0 * xc + wE * xe + wW * xw) + sp * wN * xc + sm * wS * xc + (syp ? sp : sm) * wD * xd;
-            a0 = (a0 + j0) & mask2;
-            ap = (ap + j0 + 1) & mask2;
-            am = (am + j0 - 1) & mask2;
         }
         emit(cp, s);
     }
