@@ -83,13 +83,26 @@ __device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSr
 // Lane L of the wavefront owns i = L C + 1 .. L C + C (i = N is a zero pad);
 // each recurrence runs locally per lane and the lanes are joined by a scan of
 // the carries with multiplier r^C.
+// base^k for 0 <= k < 256 by repeated squaring (eight fixed steps)
+__device__ __forceinline__ double pow_u8(double base, int k) {
+    double res = 1.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        if ((k >> b) & 1) res *= base;
+        base *= base;
+    }
+    return res;
+}
+
 template <int C>
 __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, int lane, int N) {
-    const double r = mc.r;
+    const double r = mc.r, rinv = mc.rinv;
+    // forward recurrence w = r (w - e): one dependent fma per step
     double w = 0.0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        w = r * (w - e[c]);
+        const double re = r * e[c];
+        w = fma(r, w, -re);
         e[c] = w;
     }
     double val = w, mul = mc.rC;
@@ -101,17 +114,19 @@ __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, 
     }
     double carry = __shfl_up(val, 1, 64);
     if (lane == 0) carry = 0.0;
-    double pw = r;
+    // e[c] += r^(c+1) carry; the powers in four interleaved chains
+    const double r2 = r * r, r4 = r2 * r2;
+    double pw[4] = {r, r2, r2 * r, r4};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        e[c] += pw * carry;
-        pw *= r;
+        e[c] = fma(pw[c & 3], carry, e[c]);
+        pw[c & 3] *= r4;
     }
     if (lane == 63) e[C - 1] = 0.0;
     double y = 0.0;
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
-        y = e[c] + r * y;
+        y = fma(r, y, e[c]);
         e[c] = y;
     }
     val = y;
@@ -124,22 +139,32 @@ __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, 
     }
     carry = __shfl_down(val, 1, 64);
     if (lane == 63) carry = 0.0;
-    pw = r;
+    // e[c] += r^(C-c) carry
+    pw[0] = r;
+    pw[1] = r2;
+    pw[2] = r2 * r;
+    pw[3] = r4;
 #pragma unroll
     for (int c = C - 1; c >= 0; --c) {
-        e[c] += pw * carry;
-        pw *= r;
+        const int k = (C - 1 - c) & 3;
+        e[c] = fma(pw[k], carry, e[c]);
+        pw[k] *= r4;
     }
+    // rank-one fix: e[c] += y1 smc (r^i - r^(2N-i)) at i = lane C + 1 + c, with
+    // r^(lane C + 1) = r (r^C)^lane and r^(2N - lane C - 1) = (r^C)^(128 - lane) / r
+    // (2N = 128 C); the powers along c again in four chains
     const double y1 = __shfl(e[0], 0, 64);
-    const int is = lane * C + 1;
-    double p1 = exp((double)is * mc.logr);
-    double p2 = exp((double)(2 * N - is) * mc.logr);
     const double coef = y1 * mc.smc;
+    const double p1 = r * pow_u8(mc.rC, lane);
+    const double p2 = rinv * pow_u8(mc.rC, 128 - lane);
+    const double ri2 = rinv * rinv, ri4 = ri2 * ri2;
+    double pa[4] = {p1, p1 * r, p1 * r2, p1 * r2 * r};
+    double pb[4] = {p2, p2 * rinv, p2 * ri2, p2 * ri2 * rinv};
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        e[c] += coef * (p1 - p2);
-        p1 *= r;
-        p2 *= mc.rinv;
+        e[c] = fma(coef, pa[c & 3] - pb[c & 3], e[c]);
+        pa[c & 3] *= r4;
+        pb[c & 3] *= ri4;
     }
     if (lane == 63) e[C - 1] = 0.0;
 }
@@ -196,9 +221,8 @@ __device__ __forceinline__ void mode_solve_lds(double* x, const ModeConst& mc, i
         pw *= r;
     }
     const double y1 = __shfl(e[0], 0, 64);
-    const int is = lane * C + 1;
-    double p1 = exp((double)is * mc.logr);
-    double p2 = exp((double)(2 * N - is) * mc.logr);
+    double p1 = r * pow_u8(mc.rC, lane);                    // r^(lane C + 1)
+    double p2 = mc.rinv * pow_u8(mc.rC, 128 - lane);        // r^(2N - lane C - 1), 2N = 128 C
     const double coef = y1 * mc.smc;
 #pragma unroll 8
     for (int c = 0; c < C; ++c) {
