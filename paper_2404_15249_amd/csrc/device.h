@@ -83,6 +83,25 @@ __device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSr
 // Lane L of the wavefront owns i = L C + 1 .. L C + C (i = N is a zero pad);
 // each recurrence runs locally per lane and the lanes are joined by a scan of
 // the carries with multiplier r^C.
+// ---------------------------------------------------------------- wavefront scans with DPP
+//
+// A lane's FP64 value moved by a DPP control (row shifts stay inside rows of
+// 16 lanes, wave shifts cross them); lanes without a source get 0.
+constexpr int kDppRowShl1 = 0x101, kDppRowShr1 = 0x111, kDppWaveShl1 = 0x130, kDppWaveShr1 = 0x138;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
 // base^k for 0 <= k < 256 by repeated squaring (eight fixed steps)
 __device__ __forceinline__ double pow_u8(double base, int k) {
     double res = 1.0;
@@ -92,6 +111,37 @@ __device__ __forceinline__ double pow_u8(double base, int k) {
         base *= base;
     }
     return res;
+}
+
+// Weighted inclusive scans over the wavefront, v_L <- sum_k m^|L-k| v_k over
+// k <= L (up) or k >= L (down): inside each row of 16 lanes by four DPP row
+// shifts, then across the rows from the row ends read as scalars.
+__device__ __forceinline__ double wave_scan_up(double v, double m, int lane) {
+    const double m2 = m * m, m4 = m2 * m2, m8 = m4 * m4, m16 = m8 * m8;
+    v = fma(m, dpp_f64<kDppRowShr1>(v), v);
+    v = fma(m2, dpp_f64<kDppRowShr1 + 1>(v), v);
+    v = fma(m4, dpp_f64<kDppRowShr1 + 3>(v), v);
+    v = fma(m8, dpp_f64<kDppRowShr1 + 7>(v), v);
+    const double p0 = readlane_f64(v, 15);
+    const double p1 = fma(m16, p0, readlane_f64(v, 31));
+    const double p2 = fma(m16, p1, readlane_f64(v, 47));
+    const int row = lane >> 4;
+    const double before = row == 0 ? 0.0 : row == 1 ? p0 : row == 2 ? p1 : p2;
+    return fma(pow_u8(m, (lane & 15) + 1), before, v);
+}
+
+__device__ __forceinline__ double wave_scan_down(double v, double m, int lane) {
+    const double m2 = m * m, m4 = m2 * m2, m8 = m4 * m4, m16 = m8 * m8;
+    v = fma(m, dpp_f64<kDppRowShl1>(v), v);
+    v = fma(m2, dpp_f64<kDppRowShl1 + 1>(v), v);
+    v = fma(m4, dpp_f64<kDppRowShl1 + 3>(v), v);
+    v = fma(m8, dpp_f64<kDppRowShl1 + 7>(v), v);
+    const double q3 = readlane_f64(v, 48);
+    const double q2 = fma(m16, q3, readlane_f64(v, 32));
+    const double q1 = fma(m16, q2, readlane_f64(v, 16));
+    const int row = lane >> 4;
+    const double after = row == 3 ? 0.0 : row == 2 ? q3 : row == 1 ? q2 : q1;
+    return fma(pow_u8(m, 16 - (lane & 15)), after, v);
 }
 
 template <int C>
@@ -105,15 +155,8 @@ __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, 
         w = fma(r, w, -re);
         e[c] = w;
     }
-    double val = w, mul = mc.rC;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_up(val, off, 64);
-        if (lane >= off) val += mul * t;
-        mul *= mul;
-    }
-    double carry = __shfl_up(val, 1, 64);
-    if (lane == 0) carry = 0.0;
+    // the lanes' carries: the weighted prefix of the chunk ends, from lane L-1
+    double carry = dpp_f64<kDppWaveShr1>(wave_scan_up(w, mc.rC, lane));
     // e[c] += r^(c+1) carry; the powers in four interleaved chains
     const double r2 = r * r, r4 = r2 * r2;
     double pw[4] = {r, r2, r2 * r, r4};
@@ -129,16 +172,7 @@ __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, 
         y = fma(r, y, e[c]);
         e[c] = y;
     }
-    val = y;
-    mul = mc.rC;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_down(val, off, 64);
-        if (lane + off < 64) val += mul * t;
-        mul *= mul;
-    }
-    carry = __shfl_down(val, 1, 64);
-    if (lane == 63) carry = 0.0;
+    carry = dpp_f64<kDppWaveShl1>(wave_scan_down(y, mc.rC, lane));
     // e[c] += r^(C-c) carry
     pw[0] = r;
     pw[1] = r2;
@@ -153,7 +187,7 @@ __device__ __forceinline__ void mode_solve(double (&e)[C], const ModeConst& mc, 
     // rank-one fix: e[c] += y1 smc (r^i - r^(2N-i)) at i = lane C + 1 + c, with
     // r^(lane C + 1) = r (r^C)^lane and r^(2N - lane C - 1) = (r^C)^(128 - lane) / r
     // (2N = 128 C); the powers along c again in four chains
-    const double y1 = __shfl(e[0], 0, 64);
+    const double y1 = readlane_f64(e[0], 0);
     const double coef = y1 * mc.smc;
     const double p1 = r * pow_u8(mc.rC, lane);
     const double p2 = rinv * pow_u8(mc.rC, 128 - lane);
@@ -182,15 +216,7 @@ __device__ __forceinline__ void mode_solve_lds(double* x, const ModeConst& mc, i
         w = r * (w - e[c] * h2);
         e[c] = w;
     }
-    double val = w, mul = mc.rC;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_up(val, off, 64);
-        if (lane >= off) val += mul * t;
-        mul *= mul;
-    }
-    double carry = __shfl_up(val, 1, 64);
-    if (lane == 0) carry = 0.0;
+    double carry = dpp_f64<kDppWaveShr1>(wave_scan_up(w, mc.rC, lane));
     double pw = r;
 #pragma unroll 8
     for (int c = 0; c < C; ++c) {
@@ -204,23 +230,14 @@ __device__ __forceinline__ void mode_solve_lds(double* x, const ModeConst& mc, i
         y = e[c] + r * y;
         e[c] = y;
     }
-    val = y;
-    mul = mc.rC;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const double t = __shfl_down(val, off, 64);
-        if (lane + off < 64) val += mul * t;
-        mul *= mul;
-    }
-    carry = __shfl_down(val, 1, 64);
-    if (lane == 63) carry = 0.0;
+    carry = dpp_f64<kDppWaveShl1>(wave_scan_down(y, mc.rC, lane));
     pw = r;
 #pragma unroll 8
     for (int c = C - 1; c >= 0; --c) {
         e[c] += pw * carry;
         pw *= r;
     }
-    const double y1 = __shfl(e[0], 0, 64);
+    const double y1 = readlane_f64(e[0], 0);
     double p1 = r * pow_u8(mc.rC, lane);                    // r^(lane C + 1)
     double p2 = mc.rinv * pow_u8(mc.rC, 128 - lane);        // r^(2N - lane C - 1), 2N = 128 C
     const double coef = y1 * mc.smc;
@@ -370,10 +387,11 @@ __device__ __forceinline__ ModesLds modes_lds(double* smem, int N) {
 //  3. The weighted six-point gather at every sample (the row sines by the same
 //     recurrence): emit(cp, s) with s the sum over the R modes, for
 //     cp = tid, tid + 64 kModeWaves, ...
-// L.sq must hold the sine table of p.N; must be called by the whole workgroup.
+// L.sq must hold the sine table of p.N, or sinq (the table in device memory)
+// is given and loaded here; must be called by the whole workgroup.
 template <int C, int R, class Emit>
 __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __restrict__ corr, int base,
-                                            const ModesLds& L, Emit emit) {
+                                            const ModesLds& L, Emit emit, const double* __restrict__ sinq = nullptr) {
     constexpr int XS = 64 * (C + 1);
     constexpr int NT = kModeWaves * 64;
     const int N = p.N, n = p.n, M = p.M, mask2 = 2 * N - 1, half = N / 2;
@@ -381,22 +399,26 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
     const double* sq = L.sq;
     const int l0 = base + 1;
     const int nact = min(R, n - base);                  // modes of this round that exist
+    // the first rows of this wavefront's node table are requested before
+    // anything waits, so their latency overlaps the table load and the clear
+    const int t_beg = p.sub_off[wave], t_end = p.sub_off[wave + 1];   // multiples of kSlots
+    int pk[kSlots], pkn[kSlots];
+    double cv[kSlots], cvn[kSlots];
+    if (t_beg < t_end) {
+#pragma unroll
+        for (int q = 0; q < kSlots; ++q) {
+            pk[q] = p.il_ij[(size_t)(t_beg + q) * 64 + lane];
+            cv[q] = corr[(size_t)(t_beg + q) * 64 + lane];
+        }
+    }
+    if (sinq)
+        for (int k = tid; k <= N / 2; k += NT) L.sq[k] = sinq[k];
     for (int k = tid; k < R * XS; k += NT) L.xs[k] = 0.0;
     __syncthreads();
     {
-        const int t_beg = p.sub_off[wave], t_end = p.sub_off[wave + 1];   // multiples of kSlots
         double acc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] = 0.0;
-        int pk[kSlots], pkn[kSlots];
-        double cv[kSlots], cvn[kSlots];
-        if (t_beg < t_end) {
-#pragma unroll
-            for (int q = 0; q < kSlots; ++q) {
-                pk[q] = p.il_ij[(size_t)(t_beg + q) * 64 + lane];
-                cv[q] = corr[(size_t)(t_beg + q) * 64 + lane];
-            }
-        }
         for (int t0 = t_beg; t0 < t_end; t0 += kSlots) {
             const bool more = t0 + kSlots < t_end;      // next group's loads overlap this group's sums
             if (more) {
