@@ -411,6 +411,24 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
             cv[q] = corr[(size_t)(t_beg + q) * 64 + lane];
         }
     }
+    // also requested now: this wavefront's mode constants (phase 2) and the
+    // stencil data of the thread's first kPre samples (phase 3)
+    constexpr int kPre = 2;
+    ModeConst mcw{};
+    if (wave < nact) mcw = p.modes[l0 + wave];
+    int4 pre_pk[kPre];
+    double2 pre_w[kPre][3];
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int cp = tid + q * NT;
+        if (cp < M) {
+            pre_pk[q] = p.cp_pack[cp];
+            const double2* w2 = reinterpret_cast<const double2*>(p.cp_w + 6 * (size_t)cp);
+            pre_w[q][0] = w2[0];
+            pre_w[q][1] = w2[1];
+            pre_w[q][2] = w2[2];
+        }
+    }
     if (sinq)
         for (int k = tid; k <= N / 2; k += NT) L.sq[k] = sinq[k];
     for (int k = tid; k < R * XS; k += NT) L.xs[k] = 0.0;
@@ -478,28 +496,26 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
         }
     }
     __syncthreads();
-    for (int r = wave; r < nact; r += kModeWaves) {
-        double* x = L.xs + r * XS;
+    static_assert(R <= kModeWaves, "one mode per wavefront at most");
+    if (wave < nact) {
+        double* x = L.xs + wave * XS;
         if constexpr (C > 32) {
-            mode_solve_lds<C>(x, p.modes[l0 + r], lane, N, p.h2);
+            mode_solve_lds<C>(x, mcw, lane, N, p.h2);
         } else {
             double e[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) e[c] = x[lane * (C + 1) + 1 + c] * p.h2;
-            mode_solve<C>(e, p.modes[l0 + r], lane, N);
+            mode_solve<C>(e, mcw, lane, N);
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (lane < 63 || c < C - 1) x[lane * (C + 1) + 1 + c] = e[c];
         }
     }
     __syncthreads();
-    for (int cp = tid; cp < M; cp += NT) {
-        const int4 pk4 = p.cp_pack[cp];
+    auto gather = [&](int cp, const int4 pk4, const double2 wa, const double2 wb, const double2 wc) {
         const int i0 = pk4.x, j0 = pk4.y, sxy = pk4.z;
         const int sx = (sxy & 1) ? 1 : -1;
         const bool syp = (sxy & 2) != 0;
-        const double2* w2 = reinterpret_cast<const double2*>(p.cp_w + 6 * (size_t)cp);
-        const double2 wa = w2[0], wb = w2[1], wc = w2[2];
         const double w0 = wa.x, wE = wa.y, wW = wb.x, wN = wb.y, wS = wc.x, wD = wc.y;
         // places of the stencil columns in the padded layout (node 0 lies on
         // the box: zero); the sine arguments advance by j per mode
@@ -553,6 +569,15 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
             s += s0 * (w0 * xc + wE * xe + wW * xw) + sp * wN * xc + sm * wS * xc + (syp ? sp : sm) * wD * xd;
         }
         emit(cp, s);
+    };
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+        const int cp = tid + q * NT;
+        if (cp < M) gather(cp, pre_pk[q], pre_w[q][0], pre_w[q][1], pre_w[q][2]);
+    }
+    for (int cp = tid + kPre * NT; cp < M; cp += NT) {
+        const double2* w2 = reinterpret_cast<const double2*>(p.cp_w + 6 * (size_t)cp);
+        gather(cp, p.cp_pack[cp], w2[0], w2[1], w2[2]);
     }
     __syncthreads();
 }
