@@ -58,9 +58,8 @@ __global__ __launch_bounds__(kModeWaves * 64) void k_modes(DevPlan p, const doub
     if (skip && *skip) return;
     extern __shared__ double smem[];
     const ModesLds L = modes_lds<R>(smem, p.N);
-    for (int k = threadIdx.x; k <= p.N / 2; k += kModeWaves * 64) L.sq[k] = p.sinq[k];
     double* row = partial + (size_t)blockIdx.x * p.M;
-    modes_round<C, R>(p, corr, blockIdx.x * R, L, [&](int cp, double v) { row[cp] = v; });
+    modes_round<C, R>(p, corr, blockIdx.x * R, L, [&](int cp, double v) { row[cp] = v; }, p.sinq);
 }
 
 // ---------------------------------------------------------------- spline of a density
