@@ -334,12 +334,28 @@ __device__ inline double correction_at(const DevPlan& p, const JumpSrc& js, int 
 // red: 16 x 64 doubles of LDS.
 __device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial,
                                         int G, int cp0, double* __restrict__ out, double* red) {
+    __shared__ double outside[64];
+    constexpr int kOutsideWave = 15;                    // also makes the jump terms
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cp = cp0 + lane, M = p.M;
     double s = 0.0;
     if (cp < M) {
-#pragma unroll 16
-        for (int g = wave; g < G; g += 16) s += partial[(size_t)g * M + cp];
+        // the wavefront's first 16 partial rows are requested before anything
+        // waits; the jump terms' loads follow them, so both latencies overlap
+        double r[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int g = wave + 16 * k;
+            r[k] = g < G ? partial[(size_t)g * M + cp] : 0.0;
+        }
+        if (wave == kOutsideWave) {
+            int ni[6], nj[6];
+            stencil_nodes(p, cp, ni, nj);
+            outside[lane] = outside_terms(p, js, cp, ni, nj, p.cp_w + 6 * (size_t)cp);
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) s += r[k];
+        for (int g = wave + 256; g < G; g += 16) s += partial[(size_t)g * M + cp];
     }
     red[wave * 64 + lane] = s;
     __syncthreads();
@@ -347,9 +363,7 @@ __device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, con
         double t = 0.0;
 #pragma unroll
         for (int w = 0; w < 16; ++w) t += red[w * 64 + lane];
-        int ni[6], nj[6];
-        stencil_nodes(p, cp, ni, nj);
-        const double v = t * (2.0 / p.N) + outside_terms(p, js, cp, ni, nj, p.cp_w + 6 * (size_t)cp);
+        const double v = t * (2.0 / p.N) + outside[lane];
         out[cp] = v;
         red[lane] = v;                                  // left in LDS for the caller
     }
