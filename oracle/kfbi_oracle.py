@@ -19,6 +19,10 @@ for PDEs on irregular domain", arXiv 2404.15249):
   fast solve (Alg. 4, here a DST-I on both axes: the same discrete system),
   interpolation to the boundary (Alg. 3).
 * Alg. 5: restarted GMRES on ``K_D phi = g - (Y f)^+``.
+* The Neumann problem ``d_n u = g_n`` (Sec. 4 procedure, which extracts
+  ``d_n u`` instead of ``u+``): the same interface problem with the density as
+  the normal-derivative jump, ``K_N psi = d_n v+``, and GMRES on
+  ``K_N psi = g_n - d_n (Y f)^+``.
 * Sec. 5: the error norms and the relative-residual stopping rule.
 
 The paper defers the discrete details to the first KFBI paper, which is not
@@ -42,6 +46,9 @@ R-10 Correction from the second-order Taylor expansion of the jump along the
 R-11 The six-point interpolation stencil is the 5-point cross around the
      nearest node plus the diagonal node on the side of the boundary point.
 R-13 GMRES(50), modified Gram-Schmidt, Givens rotations, ``phi_0 = 0``.
+R-20 Neumann problem: ``[v] = 0``, ``[d_n v] = psi``; ``d_n v+`` is the gradient
+     of the six-point quadratic at the sample along the spline's outward
+     normal; ``kappa > 0``.
 """
 from __future__ import annotations
 
@@ -328,24 +335,27 @@ def cartesian_jumps(T, nrm, curv, Phi, Phi_s, Phi_ss, Psi, Psi_s, Fjump, kappa):
     return np.stack([np.broadcast_to(Phi, gx.shape), gx, gy, hxx, hxy, hyy], axis=-1)
 
 
-def jumps_at(plan: Plan, t, phi, f_gamma, kappa):
-    """Cartesian jumps at curve parameters ``t`` for density ``phi`` and ``[F] = f_gamma``.
+def jumps_at(plan: Plan, t, phi, f_gamma, kappa, psi=None):
+    """Cartesian jumps at curve parameters ``t`` for ``[v] = phi``, ``[d_n v] = psi``, ``[F] = f_gamma``.
 
-    ``phi`` and ``f_gamma`` are sampled at the knots; both are interpolated by the
-    periodic spline.  Arc-length derivatives: ``Phi_s = Phi'/sig``,
-    ``Phi_ss = Phi''/sig^2 - Phi' (X'.X'')/sig^4``.  ``Psi = 0`` (Dirichlet).
+    The densities and ``f_gamma`` are sampled at the knots and interpolated by
+    the periodic spline; ``None`` stands for zero.  Arc-length derivatives:
+    ``Y_s = Y'/sig``, ``Y_ss = Y''/sig^2 - Y' (X'.X'')/sig^4``.  The Dirichlet
+    operator has ``psi = 0``; the Neumann operator has ``phi = 0`` (R-20).
     """
     T, nrm, curv, sig, xdx = local_geometry(plan, t)
-    s2 = spline_second_derivs(phi)
-    P, P1, P2 = spline_eval(phi, s2, t)
-    Phi_s = P1 / sig
-    Phi_ss = P2 / sig ** 2 - P1 * xdx / sig ** 4
-    if f_gamma is None:
-        Fj = np.zeros_like(P)
-    else:
-        Fj = spline_eval(f_gamma, spline_second_derivs(f_gamma), t)[0]
-    zero = np.zeros_like(P)
-    return cartesian_jumps(T, nrm, curv, P, Phi_s, Phi_ss, zero, zero, Fj, kappa)
+    zero = np.zeros(np.shape(np.asarray(t, dtype=np.float64)))
+
+    def along(y):
+        if y is None:
+            return zero, zero, zero
+        Y, Y1, Y2 = spline_eval(y, spline_second_derivs(y), t)
+        return Y, Y1 / sig, Y2 / sig ** 2 - Y1 * xdx / sig ** 4
+
+    P, Phi_s, Phi_ss = along(phi)
+    Psi, Psi_s, _ = along(psi)
+    Fj = along(f_gamma)[0]
+    return cartesian_jumps(T, nrm, curv, P, Phi_s, Phi_ss, Psi, Psi_s, Fj, kappa)
 
 
 # ==========================================================================
@@ -412,17 +422,19 @@ def stencils(plan: Plan, z: np.ndarray):
     return np.stack(nodes, axis=1)            # (M, 6, 2)
 
 
-def interpolate(plan: Plan, vgrid: np.ndarray, z: np.ndarray, jz: np.ndarray) -> np.ndarray:
-    """One-sided limit ``v+`` at the boundary points ``z`` from the grid solution.
+def local_quadratics(plan: Plan, vgrid: np.ndarray, z: np.ndarray, jz: np.ndarray) -> np.ndarray:
+    """Coefficients of the six-point quadratic of the Omega-side solution at each point ``z``.
 
     Stencil values on the far side of Gamma are moved to the Omega side with
-    the Taylor expansion of the jumps at ``z``; the quadratic through the six
-    values (a 6x6 linear system per point) is evaluated at ``z``.
-    ``vgrid`` is the full ``(n+1, n+1)`` grid (zero on the box).
+    the Taylor expansion of the jumps at ``z``; the quadratic
+    ``c0 + c1 xi + c2 eta + c3 xi^2 + c4 xi eta + c5 eta^2`` in the scaled
+    offsets ``xi = (x - z_x)/h``, ``eta = (y - z_y)/h`` through the six values
+    is found from a 6x6 linear system per point (Alg. 3).  ``vgrid`` is the
+    full ``(n+1, n+1)`` grid (zero on the box).  Returns ``(len(z), 6)``.
     """
     st = stencils(plan, z)
     h = plan.h
-    out = np.empty(len(z))
+    out = np.empty((len(z), 6))
     for m in range(len(z)):
         A = np.empty((6, 6))
         rhs = np.empty(6)
@@ -437,20 +449,31 @@ def interpolate(plan: Plan, vgrid: np.ndarray, z: np.ndarray, jz: np.ndarray) ->
             xi, eta = (px - z[m, 0]) / h, (py - z[m, 1]) / h
             A[k] = [1.0, xi, eta, xi * xi, xi * eta, eta * eta]
             rhs[k] = val
-        coef = np.linalg.solve(A, rhs)
-        out[m] = coef[0]                       # the quadratic centred at z, evaluated at z
+        out[m] = np.linalg.solve(A, rhs)
     return out
+
+
+def interpolate(plan: Plan, vgrid: np.ndarray, z: np.ndarray, jz: np.ndarray) -> np.ndarray:
+    """One-sided limit ``v+`` at the boundary points ``z``: the local quadratic at ``z``."""
+    return local_quadratics(plan, vgrid, z, jz)[:, 0]
+
+
+def normal_derivative(plan: Plan, coef: np.ndarray, nrm: np.ndarray) -> np.ndarray:
+    """``d_n v+`` at the points of ``coef`` (from ``local_quadratics``): the gradient of
+    the local quadratic at its centre, ``(c1, c2)/h``, along the unit normals ``nrm``
+    (Alg. 3 extracts the value and its derivatives from the same system)."""
+    return (coef[:, 1] * nrm[:, 0] + coef[:, 2] * nrm[:, 1]) / plan.h
 
 
 # ==========================================================================
 # one interface solve (Alg. 1 steps 4-6) and the boundary operator
 # ==========================================================================
 
-def interface_solve_with_jumps(plan: Plan, jq, jz, ftilde, kappa):
-    """Correct, fast-solve and interpolate with given jumps at crossings and at the samples.
+def grid_solve_with_jumps(plan: Plan, jq, ftilde, kappa):
+    """Correct and fast-solve with given jumps at the crossings (Alg. 1 steps 4-5).
 
     ``ftilde`` is the ``(n+1, n+1)`` base right-hand side (``F``; zero on the
-    box).  Returns the full grid solution and ``v+`` at the samples.
+    box).  Returns the full grid solution.
     """
     n = plan.n
     rhs = np.array(ftilde[1:n, 1:n], dtype=np.float64, copy=True)
@@ -459,6 +482,15 @@ def interface_solve_with_jumps(plan: Plan, jq, jz, ftilde, kappa):
         rhs[j - 1, i - 1] += c
     v = np.zeros((n + 1, n + 1))
     v[1:n, 1:n] = dst_solve(rhs, plan.h, kappa)
+    return v
+
+
+def interface_solve_with_jumps(plan: Plan, jq, jz, ftilde, kappa):
+    """Correct, fast-solve and interpolate with given jumps at crossings and at the samples.
+
+    Returns the full grid solution and ``v+`` at the samples.
+    """
+    v = grid_solve_with_jumps(plan, jq, ftilde, kappa)
     return v, interpolate(plan, v, plan.xy, jz)
 
 
@@ -578,3 +610,72 @@ def error_norms(plan: Plan, u_grid, exact):
     X, Y = np.meshgrid(c, c, indexing="xy")
     e = (u_grid - exact(X, Y))[plan.inside]
     return float(np.max(np.abs(e))), float(np.sqrt(np.mean(e * e)))
+
+
+# ==========================================================================
+# the Neumann boundary value problem (Sec. 2 interface problem with a
+# normal-derivative jump; Sec. 4 procedure: extract d_n u for Neumann; R-20)
+# ==========================================================================
+
+def sample_normals(plan: Plan) -> np.ndarray:
+    """Unit outward normals of the spline curve at the samples."""
+    return local_geometry(plan, np.arange(plan.M, dtype=np.float64))[1]
+
+
+def interface_solve_neumann(plan: Plan, psi, ftilde, f_gamma, kappa):
+    """Solve the interface problem with ``[v] = 0``, ``[d_n v] = psi`` and ``F = ftilde``.
+
+    ``psi`` (samples, or ``None`` for zero) and ``f_gamma`` (``[F]`` at the
+    samples, or ``None``) are splined.  Returns the full grid solution and
+    ``v+`` and ``d_n v+`` at the samples.
+    """
+    t_z = np.arange(plan.M, dtype=np.float64)
+    jq = jumps_at(plan, plan.q_t, None, f_gamma, kappa, psi=psi)
+    jz = jumps_at(plan, t_z, None, f_gamma, kappa, psi=psi)
+    v = grid_solve_with_jumps(plan, jq, ftilde, kappa)
+    coef = local_quadratics(plan, v, plan.xy, jz)
+    return v, coef[:, 0], normal_derivative(plan, coef, sample_normals(plan))
+
+
+def apply_KN(plan: Plan, psi, kappa):
+    """``K_N psi = d_n v+`` at the samples for ``[v] = 0``, ``[d_n v] = psi``, ``F = 0``.
+
+    ``v`` is a single-layer potential of the box Green's function (up to the
+    sign convention of the density), so ``K_N psi = psi/2 - K' psi`` with
+    ``K'`` the adjoint double-layer operator: a second-kind operator.
+    """
+    zero = np.zeros((plan.n + 1, plan.n + 1))
+    return interface_solve_neumann(plan, np.asarray(psi, dtype=np.float64), zero, None, kappa)[2]
+
+
+@dataclasses.dataclass
+class NeumannSolution:
+    u_grid: np.ndarray        # (n+1, n+1), zero outside Omega
+    u_gamma: np.ndarray       # u+ at the samples (the Dirichlet trace, an output here)
+    dn_gamma: np.ndarray      # d_n u+ at the samples (reproduces g_N to the GMRES tolerance)
+    psi: np.ndarray
+    iters: int
+    relres: float
+    plan: Plan
+
+
+def solve_neumann(xy, n, lo, hi, kappa, f_grid, f_gamma, g_n, tol=1e-10, restart=50, max_iter=500):
+    """Solve ``Lap u - kappa u = f`` in Omega, ``d_n u = g_n`` on Gamma (``kappa > 0``).
+
+    ``u = v_psi + Y f`` with ``v_psi`` the interface solution for ``[v] = 0``,
+    ``[d_n v] = psi``; the boundary condition gives the second-kind equation
+    ``K_N psi = g_n - d_n (Y f)^+``, solved by GMRES; the final interface solve
+    with ``[d_n v] = psi`` and ``F = f~`` gives ``u`` on the grid.  For
+    ``kappa = 0`` the interior problem loses uniqueness (constants), so it is
+    rejected.
+    """
+    if not kappa > 0.0:
+        raise ValueError("the Neumann problem needs kappa > 0")
+    plan = build_plan(xy, n, lo, hi)
+    ft = zero_extension(plan, f_grid)
+    _, _, dyf = interface_solve_neumann(plan, None, ft, f_gamma, kappa)
+    ghat = np.asarray(g_n, dtype=np.float64) - dyf
+    psi, it, rel = gmres(lambda p: apply_KN(plan, p, kappa), ghat, tol, restart, max_iter)
+    v, ug, dn = interface_solve_neumann(plan, psi, ft, f_gamma, kappa)
+    u = np.where(plan.inside, v, 0.0)
+    return NeumannSolution(u, ug, dn, psi, it, rel, plan)

@@ -82,6 +82,22 @@ def star_points(m: int, r0: float = 0.6, a: float = 0.15, k: int = 5,
     return np.stack([r * np.cos(t), r * np.sin(t)], axis=1)
 
 
+def circle_normals(xy: np.ndarray) -> np.ndarray:
+    """Exact outward unit normals of a circle centred at the origin at points ``xy``."""
+    return xy / np.hypot(xy[:, 0], xy[:, 1])[:, None]
+
+
+def star_normals(xy: np.ndarray, r0: float = 0.6, a: float = 0.15, k: int = 5) -> np.ndarray:
+    """Exact outward unit normals of ``r(theta) = r0 + a sin(k theta)`` at its points ``xy``:
+    the tangent ``X'(theta)`` turned clockwise."""
+    t = np.arctan2(xy[:, 1], xy[:, 0])
+    r = r0 + a * np.sin(k * t)
+    dr = a * k * np.cos(k * t)
+    tx, ty = dr * np.cos(t) - r * np.sin(t), dr * np.sin(t) + r * np.cos(t)
+    sp = np.hypot(tx, ty)
+    return np.stack([ty / sp, -tx / sp], axis=1)
+
+
 def star_perimeter(r0: float, a: float, k: int, n: int = 8192) -> float:
     th = 2.0 * np.pi * np.arange(n) / n
     return float(np.mean(_star_speed(th, r0, a, k)) * 2.0 * np.pi)
@@ -102,10 +118,11 @@ def star_min_radius_of_curvature(r0: float, a: float, k: int, n: int = 20000) ->
 
 @dataclasses.dataclass(frozen=True)
 class Manufactured:
-    """A closed-form solution ``u`` with its Laplacian."""
+    """A closed-form solution ``u`` with its Laplacian and gradient."""
     name: str
     u: callable
     lap: callable
+    grad: callable = None       # (x, y) -> (u_x, u_y)
 
     def f(self, x, y, kappa):
         """Right-hand side of ``Lap u - kappa u = f``."""
@@ -116,6 +133,7 @@ EXP_SIN = Manufactured(
     "exp(x) sin(y)",
     lambda x, y: np.exp(x) * np.sin(y),
     lambda x, y: np.zeros_like(np.asarray(x, dtype=float) + np.asarray(y, dtype=float)),
+    lambda x, y: (np.exp(x) * np.sin(y), np.exp(x) * np.cos(y)),
 )
 
 PAPER_EX1 = Manufactured(
@@ -128,6 +146,8 @@ SIN_COS_X2 = Manufactured(
     "sin(pi x) cos(pi y) + x^2",
     lambda x, y: np.sin(np.pi * x) * np.cos(np.pi * y) + x * x,
     lambda x, y: -2.0 * np.pi ** 2 * np.sin(np.pi * x) * np.cos(np.pi * y) + 2.0,
+    lambda x, y: (np.pi * np.cos(np.pi * x) * np.cos(np.pi * y) + 2.0 * x,
+                  -np.pi * np.sin(np.pi * x) * np.sin(np.pi * y)),
 )
 
 
@@ -162,6 +182,8 @@ def random_manufactured(rng: np.random.Generator, xp=np) -> Manufactured:
         f"{A:.3f} sin({w1:.3f}x+{al:.3f}) cos({w2:.3f}y+{be:.3f}) + {B:.3f}(x^2-y^2)",
         lambda x, y: A * xp.sin(w1 * x + al) * xp.cos(w2 * y + be) + B * (x * x - y * y),
         lambda x, y: -(w1 * w1 + w2 * w2) * A * xp.sin(w1 * x + al) * xp.cos(w2 * y + be),
+        lambda x, y: (A * w1 * xp.cos(w1 * x + al) * xp.cos(w2 * y + be) + 2.0 * B * x,
+                      -A * w2 * xp.sin(w1 * x + al) * xp.sin(w2 * y + be) - 2.0 * B * y),
     )
 
 
@@ -235,6 +257,51 @@ def star_problem(n=512, m=None, kappa=1.0, sol=SIN_COS_X2, r0=0.6, a=0.15, k=5) 
         m = n // 2
     return make_problem(f"star {r0}+{a}sin({k}t) n={n} m={m} kappa={kappa}",
                         star_points(m, r0, a, k), n, kappa, sol)
+
+
+@dataclasses.dataclass
+class NeumannProblem:
+    """Everything a Neumann solve needs: as ``Problem`` with ``g_n = d_n u`` (exact
+    outward normals) in place of the Dirichlet data; ``g`` is the exact trace, for
+    checking the solution on Gamma."""
+    name: str
+    xy: np.ndarray
+    n: int
+    kappa: float
+    lo: float
+    hi: float
+    f_grid: np.ndarray
+    f_gamma: np.ndarray
+    g_n: np.ndarray
+    g: np.ndarray
+    exact: Manufactured
+
+    @property
+    def h(self):
+        return (self.hi - self.lo) / self.n
+
+
+def make_neumann_problem(name, xy, normals, n, kappa, sol: Manufactured, lo=BOX_LO, hi=BOX_HI) -> NeumannProblem:
+    p = make_problem(name, xy, n, kappa, sol, lo, hi)
+    gx, gy = sol.grad(xy[:, 0], xy[:, 1])
+    g_n = np.asarray(gx * normals[:, 0] + gy * normals[:, 1], dtype=np.float64)
+    return NeumannProblem(name, p.xy, n, kappa, lo, hi, p.f_grid, p.f_gamma, g_n, p.g, sol)
+
+
+def circle_neumann_problem(n=64, m=128, kappa=1.0, sol=EXP_SIN, r=0.8) -> NeumannProblem:
+    """Interior Neumann problem on the circle of radius ``r``."""
+    xy = circle_points(m, r)
+    return make_neumann_problem(f"neumann circle r={r} n={n} m={m} kappa={kappa}", xy, circle_normals(xy),
+                                n, kappa, sol)
+
+
+def star_neumann_problem(n=512, m=None, kappa=1.0, sol=SIN_COS_X2, r0=0.6, a=0.15, k=5) -> NeumannProblem:
+    """Modified Helmholtz Neumann problem on the star ``r0 + a sin(k theta)``, ``m = n/2`` by default."""
+    if m is None:
+        m = n // 2
+    xy = star_points(m, r0, a, k)
+    return make_neumann_problem(f"neumann star {r0}+{a}sin({k}t) n={n} m={m} kappa={kappa}", xy,
+                                star_normals(xy, r0, a, k), n, kappa, sol)
 
 
 @dataclasses.dataclass
