@@ -160,6 +160,47 @@ kfbi_status kfbi_solve(kfbi_prob* prob, const double* f_grid, const double* f_ga
 kfbi_status kfbi_gmres(kfbi_prob* prob, const double* rhs, double* phi, double tol, int max_iter,
                        int* iters, int* applies, double* rel_res);
 
+/* ---------------------------------------------------------------- the Neumann problem */
+/* The paper names the Neumann problem (its Sec. 4 procedure extracts d_n u in
+ * place of u+) without stating its form.  Here the density psi is the jump of
+ * the normal derivative: v_psi solves the interface problem of Sec. 2.2 with
+ * [v] = 0, [d_n v] = psi (n the outward normal of Omega), and u = v_psi + Y f.
+ * The jumps at a point of Gamma are then [v_n] = psi, [v_tautau] = c psi,
+ * [v_taun] = psi_s and [v_nn] = [F] - c psi (c the curvature); correction, fast
+ * solve and interpolation are those of the Dirichlet path, and d_n v+ is the
+ * gradient of the same six-point quadratic (Alg. 3) along the spline's outward
+ * normal at the sample.  All arrays are device memory, same layouts as above. */
+
+/* K_N psi = d_n v+ at the M samples for [v] = 0, [d_n v] = psi, F = 0 (sparse
+ * path, as kfbi_apply).  psi, out: device, M doubles. */
+kfbi_status kfbi_apply_neumann(kfbi_prob* prob, const double* psi, double* out);
+
+/* One full-grid interface solve with [v] = 0, [d_n v] = psi (NULL: 0),
+ * F = ftilde (used as given; NULL: 0) and [F] = f_gamma (NULL: 0).  Outputs,
+ * each may be NULL but not all: vgrid (grid), vz (v+ at the samples), dnz
+ * (d_n v+ at the samples). */
+kfbi_status kfbi_interface_solve_neumann(kfbi_prob* prob, const double* psi, const double* ftilde,
+                                         const double* f_gamma, double* vgrid, double* vz, double* dnz);
+
+/* Restarted GMRES on K_N psi = rhs, as kfbi_gmres. */
+kfbi_status kfbi_gmres_neumann(kfbi_prob* prob, const double* rhs, double* psi, double tol, int max_iter,
+                               int* iters, int* applies, double* rel_res);
+
+/* Full Neumann solve of Lap u - kappa u = f in Omega, d_n u = g_n on Gamma:
+ * g^ = g_n - d_n (Y f)^+, GMRES on K_N psi = g^ (tolerance and cap of the
+ * problem's descriptor), then u = v_psi + Y f.  Needs kappa > 0 (for kappa = 0
+ * the constants solve the homogeneous problem): KFBI_ERR_ARG otherwise.
+ *   f_grid, f_gamma: as kfbi_solve;  g_n: device M, Neumann data at the samples
+ *   u_grid  : grid out, u at nodes in Omega, 0 elsewhere
+ *   u_gamma : M out, the trace u+ at the samples
+ *   dn_gamma: M out, d_n u+ at the samples (g_n to the solver tolerance)
+ *   psi     : M in/out, initial guess in, density out
+ *   iters, rel_res: host out (may be NULL).
+ * Synchronises.  Returns KFBI_NOT_CONVERGED when max_iter was reached. */
+kfbi_status kfbi_solve_neumann(kfbi_prob* prob, const double* f_grid, const double* f_gamma,
+                               const double* g_n, double* u_grid, double* u_gamma, double* dn_gamma,
+                               double* psi, int* iters, double* rel_res);
+
 /* ---------------------------------------------------------------- steps (for tests and tools) */
 
 /* Alg. 2 alone: the correction of the right-hand side at every irregular node

@@ -42,7 +42,8 @@ struct kfbi_prob {
     int restart = 50, max_iter = 500;
     int N = 0, n = 0, M = 0, Q = 0, I = 0;
     int Rm = 8, G = 1;           // sine modes per sparse-fast-solve workgroup; workgroups = ceil(n / Rm)
-    DevPlan dp{};
+    DevPlan dp{};                // the double-layer operator's view (see plan_view)
+    const double* cp_wn = nullptr;   // 6 M: weights of d_n v+ at the samples (the Neumann operator)
     std::vector<void*> allocs;
     size_t bytes = 0;
     // work buffers
@@ -72,10 +73,11 @@ struct kfbi_prob {
     std::vector<hipEvent_t> ev;
     int t_count = 0;
     double tuned_apply_us = 0, tuned_grid_us = 0;
-    // a captured batch of GMRES steps (apply + Arnoldi update), replayed per batch
+    // a captured batch of GMRES steps (apply + Arnoldi update) per operator
+    // (kOpD, kOpN), replayed per batch
     static constexpr int kGraphSteps = 8;
-    hipGraphExec_t gexec = nullptr;
-    bool graph_failed = false;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool graph_failed[2] = {false, false};
 };
 
 namespace {
@@ -110,8 +112,10 @@ void free_prob(kfbi_prob* p) {
     for (auto& e : p->ev)
         if (e) hipEventDestroy(e);
     p->ev.clear();
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    p->gexec = nullptr;
+    for (auto& g : p->gexec) {
+        if (g) hipGraphExecDestroy(g);
+        g = nullptr;
+    }
 }
 
 // Per-mode constants of the x-direction tridiagonal systems (Alg. 4), FP64.
@@ -123,6 +127,21 @@ std::vector<ModeConst> mode_constants(int N, double h, double kappa) {
     }
     return mc;
 }
+
+// The two boundary operators: K_D (the density is [v], the samples get v+) and
+// K_N (the density is [d_n v], the samples get d_n v+).
+enum Op { kOpD = 0, kOpN = 1 };
+
+// The plan as one kernel sequence sees it: which jump the density is, and
+// whether the interpolation extracts v+ or d_n v+ (the six weights it uses).
+DevPlan plan_view(const kfbi_prob* p, bool normal_jump, bool normal_deriv) {
+    DevPlan d = p->dp;
+    d.normal_jump = normal_jump ? 1 : 0;
+    if (normal_deriv) d.cp_w = p->cp_wn;
+    return d;
+}
+
+DevPlan op_view(const kfbi_prob* p, int op) { return plan_view(p, op == kOpN, op == kOpN); }
 
 // bytes of one complex pair in the column transforms of a precision mode
 size_t cpx_bytes(int precision) { return precision == KFBI_FP64 ? 2 * sizeof(double) : 2 * sizeof(float); }
@@ -158,9 +177,11 @@ kfbi_status grid_solve(kfbi_prob* p, const double** V) {
 }
 
 // Dense interface solve: R <- f~ (+ corrections), the grid solve, then
-// interpolation at the samples and, optionally, the grid written to `vgrid`.
-kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, bool mask, double* vgrid,
-                                  bool mask_out, double* vz) {
+// interpolation at the samples (v+ into vz, d_n v+ into dnz; either may be
+// null) and, optionally, the grid written to `vgrid`.  normal_jump: the
+// density in js is [d_n v] (else [v]).
+kfbi_status dense_interface_solve(kfbi_prob* p, bool normal_jump, JumpSrc js, const double* f, bool mask,
+                                  double* vgrid, bool mask_out, double* vz, double* dnz = nullptr) {
     hipStream_t s = p->ctx->stream;
     if (js.phi) {
         HIP_TRY(launch_spline(p->dp, js.phi, p->s2a, nullptr, s));
@@ -170,21 +191,25 @@ kfbi_status dense_interface_solve(kfbi_prob* p, JumpSrc js, const double* f, boo
         HIP_TRY(launch_spline(p->dp, js.fgam, p->s2b, nullptr, s));
         js.fgam_s2 = p->s2b;
     }
-    HIP_TRY(launch_fill_rhs(p->dp, f, mask, p->R, s));
-    HIP_TRY(launch_correct(p->dp, js, nullptr, nullptr, p->R, nullptr, s));
+    const DevPlan dv = plan_view(p, normal_jump, false);
+    HIP_TRY(launch_fill_rhs(dv, f, mask, p->R, s));
+    HIP_TRY(launch_correct(dv, js, nullptr, nullptr, p->R, nullptr, s));
     const double* V = nullptr;
     if (kfbi_status e = grid_solve(p, &V)) return e;
-    if (vz) HIP_TRY(launch_interp_grid(p->dp, js, V, vz, s));
-    if (vgrid) HIP_TRY(launch_grid_out(p->dp, V, mask_out, vgrid, s));
+    if (vz) HIP_TRY(launch_interp_grid(dv, js, V, vz, s));
+    if (dnz) HIP_TRY(launch_interp_grid(plan_view(p, normal_jump, true), js, V, dnz, s));
+    if (vgrid) HIP_TRY(launch_grid_out(dv, V, mask_out, vgrid, s));
     return KFBI_OK;
 }
 
-// K_D phi without the dense grid (correction, sparse fast solve, reduction and
-// interpolation).  With corr_ready the corrections are already in corr_il (made
-// by the previous GMRES step's emit launch) and the correction launch is skipped.
-kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, double* out, const int* skip,
+// K_D phi or K_N phi (op) without the dense grid (correction, sparse fast
+// solve, reduction and interpolation).  With corr_ready the corrections are
+// already in corr_il (made by the previous GMRES step's emit launch) and the
+// correction launch is skipped.
+kfbi_status sparse_apply(kfbi_prob* p, int op, const double* phi, const double* phi_s2, double* out, const int* skip,
                          const GmresBufs* gm, hipStream_t s, bool corr_ready = false) {
     JumpSrc js{phi, phi_s2, nullptr, nullptr, nullptr, nullptr};
+    const DevPlan d = op_view(p, op);
     hipEvent_t* ev = nullptr;
     if (p->timing && p->t_count < kfbi_prob::kMaxTimed && !graph_rec()) {
         if (p->ev.empty()) {
@@ -199,16 +224,16 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
         if (ev) launch_events() = LaunchEvents{ev[2 * q], ev[2 * q + 1]};
     };
     stage(0);
-    if (!corr_ready) HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, skip, s));
+    if (!corr_ready) HIP_TRY(launch_correct(d, js, nullptr, p->corr_il, nullptr, skip, s));
     if (ev && launch_events().start) {            // nothing was launched
         launch_events() = LaunchEvents{};
         HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(hipEventRecord(ev[1], s));
     }
     stage(1);
-    HIP_TRY(launch_modes(p->dp, p->corr_il, p->partial, p->Rm, skip, s));
+    HIP_TRY(launch_modes(d, p->corr_il, p->partial, p->Rm, skip, s));
     stage(2);
-    HIP_TRY(launch_reduce_interp(p->dp, js, p->partial, p->G, out, skip, gm, s));
+    HIP_TRY(launch_reduce_interp(d, js, p->partial, p->G, out, skip, gm, s));
     launch_events() = LaunchEvents{};
     return KFBI_OK;
 }
@@ -220,14 +245,14 @@ kfbi_status sparse_apply(kfbi_prob* p, const double* phi, const double* phi_s2, 
 // each step's emit launch also makes the next apply's corrections, so the
 // apply starts from them; run_gmres makes the first step's.  With timing on the
 // corrections get their own launch, timed as a stage of the apply.
-kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
+kfbi_status enqueue_steps(kfbi_prob* p, int op, int nsteps, hipStream_t s) {
     GmresBufs b = p->gm;
     const int* skip = &b.st->converged;
     const bool fused = !p->timing;
     for (int k = 0; k < nsteps; ++k) {
-        if (kfbi_status e = sparse_apply(p, b.xcur, b.s2cur, b.w, skip, &p->gm, s, fused)) return e;
+        if (kfbi_status e = sparse_apply(p, op, b.xcur, b.s2cur, b.w, skip, &p->gm, s, fused)) return e;
         if (fused) {
-            HIP_TRY(launch_gmres_step_corr(p->dp, b, p->corr_il, s));
+            HIP_TRY(launch_gmres_step_corr(op_view(p, op), b, p->corr_il, s));
         } else {
             HIP_TRY(launch_gmres_step(p->dp.taps, p->dp.M, b, s));
         }
@@ -239,20 +264,21 @@ kfbi_status enqueue_steps(kfbi_prob* p, int nsteps, hipStream_t s) {
 // arguments are fixed device pointers and the steps read their parameters from
 // the device state, so one graph serves every call.  If capture is not possible
 // the steps are launched directly.
-void ensure_graph(kfbi_prob* p) {
-    if (p->gexec || p->graph_failed) return;
+void ensure_graph(kfbi_prob* p, int op) {
+    if (p->gexec[op] || p->graph_failed[op]) return;
     const bool timing = p->timing;
     p->timing = false;
-    p->graph_failed =
-        !record_graph(p->ctx->stream, &p->gexec, [&](hipStream_t s) { return enqueue_steps(p, kfbi_prob::kGraphSteps, s); });
+    p->graph_failed[op] = !record_graph(p->ctx->stream, &p->gexec[op], [&](hipStream_t s) {
+        return enqueue_steps(p, op, kfbi_prob::kGraphSteps, s);
+    });
     p->timing = timing;
 }
 
-// Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps go in
-// batches (a replayed graph unless per-launch timing is on); with tol > 0 the
-// host polls the device state after each batch, with tol <= 0 the work is fixed
-// and the host waits once at the end.
-kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_iter, GmresState* out) {
+// Restarted GMRES on K phi = ghat (K_D or K_N by op; ghat already in
+// p->gm.ghat).  Steps go in batches (a replayed graph unless per-launch timing
+// is on); with tol > 0 the host polls the device state after each batch, with
+// tol <= 0 the work is fixed and the host waits once at the end.
+kfbi_status run_gmres(kfbi_prob* p, int op, const double* phi_in, double tol, int max_iter, GmresState* out) {
     hipStream_t s = p->ctx->stream;
     const int M = p->M;
     GmresBufs b = p->gm;
@@ -267,19 +293,19 @@ kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_it
     HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
     if (!p->timing) {                                  // the first step's corrections
         JumpSrc js{b.xcur, b.s2cur, nullptr, nullptr, nullptr, nullptr};
-        HIP_TRY(launch_correct(p->dp, js, nullptr, p->corr_il, nullptr, nullptr, s));
+        HIP_TRY(launch_correct(op_view(p, op), js, nullptr, p->corr_il, nullptr, nullptr, s));
     }
     const int cycles = max_iter / std::max(1, p->restart) + 2;
     const int max_steps = max_iter + cycles;
     const int B = kfbi_prob::kGraphSteps;
     const bool use_graph = !p->timing;
-    if (use_graph) ensure_graph(p);
+    if (use_graph) ensure_graph(p, op);
     const int poll_every = tol > 0 ? 1 : (max_steps + B - 1) / B;   // in batches
     GmresState& st = p->st_host;
     for (int done = 0, nb = 0; done < max_steps; done += B) {
-        if (use_graph && p->gexec) {
-            HIP_TRY(hipGraphLaunch(p->gexec, s));
-        } else if (kfbi_status e = enqueue_steps(p, B, s)) {
+        if (use_graph && p->gexec[op]) {
+            HIP_TRY(hipGraphLaunch(p->gexec[op], s));
+        } else if (kfbi_status e = enqueue_steps(p, op, B, s)) {
             return e;
         }
         if (++nb % poll_every == 0 || done + B >= max_steps) {
@@ -290,6 +316,28 @@ kfbi_status run_gmres(kfbi_prob* p, const double* phi_in, double tol, int max_it
     }
     *out = st;
     return KFBI_OK;
+}
+
+// GMRES on K x = rhs for the operator op, from the initial guess in x.
+kfbi_status gmres_call(kfbi_prob* p, int op, const double* rhs, double* x, double tol, int max_iter, int* iters,
+                       int* applies, double* rel_res) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status e = check_ptr(rhs, "rhs")) return e;
+    if (kfbi_status e = check_ptr(x, "x")) return e;
+    if (max_iter <= 0) return set_err(KFBI_ERR_ARG, "max_iter must be positive");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(hipMemcpyAsync(p->gm.ghat, rhs, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    GmresState st{};
+    if (kfbi_status e = run_gmres(p, op, x, tol, max_iter, &st)) return e;
+    HIP_TRY(hipMemcpyAsync(x, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (iters) *iters = st.it;
+    // one residual apply per cycle start, one more for the final residual check
+    if (applies) *applies = st.it + st.cycles + (st.converged ? 1 : 0);
+    if (rel_res) *rel_res = st.relres;
+    if (st.converged == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
 }
 
 }  // namespace
@@ -589,7 +637,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = upload(p, &dp.sub_off, sub_off)) || (st = upload(p, &dp.split, split)) || (st = upload(p, &dp.il_ij, il_ij)) ||
         (st = upload(p, &dp.il_pos, il_pos)) || (st = upload(p, &dp.cp_pack, cpk)) ||
         (st = upload(p, &dp.cp_i0, P.cp_i0)) || (st = upload(p, &dp.cp_j0, P.cp_j0)) ||
-        (st = upload(p, &dp.cp_sxy, sxy)) || (st = upload(p, &dp.cp_w, P.cp_w)) ||
+        (st = upload(p, &dp.cp_sxy, sxy)) || (st = upload(p, &dp.cp_w, P.cp_w)) || (st = upload(p, &p->cp_wn, P.cp_wn)) ||
         (st = upload(p, &dp.cp_out, P.cp_out)) || (st = upload(p, &dp.inside, P.inside)) ||
         (st = upload(p, &dp.sinq, sinq)) || (st = upload(p, &dp.modes, mode_constants(n, P.h, p->kappa))) ||
         (st = upload(p, &dp.taps, spline_filter_taps(K))))
@@ -674,7 +722,7 @@ kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
     HIP_TRY(launch_spline(p->dp, phi, p->s2a, nullptr, p->ctx->stream));
-    return sparse_apply(p, phi, p->s2a, out, nullptr, nullptr, p->ctx->stream);
+    return sparse_apply(p, kOpD, phi, p->s2a, out, nullptr, nullptr, p->ctx->stream);
 }
 
 kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {
@@ -714,7 +762,7 @@ kfbi_status kfbi_interface_solve(kfbi_prob* p, const double* phi, const double* 
     if (!vgrid && !vz) return set_err(KFBI_ERR_ARG, "no output requested");
     HIP_TRY(hipSetDevice(p->ctx->device));
     JumpSrc js{phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
-    return dense_interface_solve(p, js, ftilde, false, vgrid, false, vz);
+    return dense_interface_solve(p, false, js, ftilde, false, vgrid, false, vz);
 }
 
 kfbi_status kfbi_interface_solve_jumps(kfbi_prob* p, const double* jq, const double* jz, const double* ftilde,
@@ -724,7 +772,7 @@ kfbi_status kfbi_interface_solve_jumps(kfbi_prob* p, const double* jq, const dou
     if (kfbi_status s = check_ptr(jz, "jz")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
     JumpSrc js{nullptr, nullptr, nullptr, nullptr, jq, jz};
-    return dense_interface_solve(p, js, ftilde, false, vgrid, false, vz);
+    return dense_interface_solve(p, false, js, ftilde, false, vgrid, false, vz);
 }
 
 kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma, const double* g, double* u_grid,
@@ -738,15 +786,15 @@ kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma
     const int M = p->M;
     // g^ = g - (Y f)^+ (Sec. 2.1)
     JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
+    if (kfbi_status e = dense_interface_solve(p, false, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
     GmresBufs b = p->gm;
     HIP_TRY(launch_axpby(M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
     // GMRES (Alg. 5): every step is one K_D apply plus one orthogonalisation
     GmresState st{};
-    if (kfbi_status e = run_gmres(p, phi, p->tol, p->max_iter, &st)) return e;
+    if (kfbi_status e = run_gmres(p, kOpD, phi, p->tol, p->max_iter, &st)) return e;
     // u = W phi + Y f
     JumpSrc jf{b.phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, jf, f_grid, true, u_grid, true, u_gamma)) return e;
+    if (kfbi_status e = dense_interface_solve(p, false, jf, f_grid, true, u_grid, true, u_gamma)) return e;
     HIP_TRY(hipMemcpyAsync(phi, b.phi, M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (iters) *iters = st.it;
@@ -757,20 +805,58 @@ kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma
 
 kfbi_status kfbi_gmres(kfbi_prob* p, const double* rhs, double* phi, double tol, int max_iter, int* iters,
                        int* applies, double* rel_res) {
+    return gmres_call(p, kOpD, rhs, phi, tol, max_iter, iters, applies, rel_res);
+}
+
+kfbi_status kfbi_apply_neumann(kfbi_prob* p, const double* psi, double* out) {
     if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
-    if (kfbi_status e = check_ptr(rhs, "rhs")) return e;
-    if (kfbi_status e = check_ptr(phi, "phi")) return e;
-    if (max_iter <= 0) return set_err(KFBI_ERR_ARG, "max_iter must be positive");
+    if (kfbi_status s = check_ptr(psi, "psi")) return s;
+    if (kfbi_status s = check_ptr(out, "out")) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    HIP_TRY(launch_spline(p->dp, psi, p->s2a, nullptr, p->ctx->stream));
+    return sparse_apply(p, kOpN, psi, p->s2a, out, nullptr, nullptr, p->ctx->stream);
+}
+
+kfbi_status kfbi_interface_solve_neumann(kfbi_prob* p, const double* psi, const double* ftilde, const double* f_gamma,
+                                         double* vgrid, double* vz, double* dnz) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (!vgrid && !vz && !dnz) return set_err(KFBI_ERR_ARG, "no output requested");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    JumpSrc js{psi, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    return dense_interface_solve(p, true, js, ftilde, false, vgrid, false, vz, dnz);
+}
+
+kfbi_status kfbi_gmres_neumann(kfbi_prob* p, const double* rhs, double* psi, double tol, int max_iter, int* iters,
+                               int* applies, double* rel_res) {
+    return gmres_call(p, kOpN, rhs, psi, tol, max_iter, iters, applies, rel_res);
+}
+
+kfbi_status kfbi_solve_neumann(kfbi_prob* p, const double* f_grid, const double* f_gamma, const double* g_n,
+                               double* u_grid, double* u_gamma, double* dn_gamma, double* psi, int* iters,
+                               double* rel_res) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    for (auto [ptr, name] : {std::pair<const void*, const char*>{f_grid, "f_grid"}, {f_gamma, "f_gamma"},
+                             {g_n, "g_n"}, {u_grid, "u_grid"}, {u_gamma, "u_gamma"}, {dn_gamma, "dn_gamma"},
+                             {psi, "psi"}})
+        if (kfbi_status s = check_ptr(ptr, name)) return s;
+    if (!(p->kappa > 0.0)) return set_err(KFBI_ERR_ARG, "the Neumann problem needs kappa > 0");
     HIP_TRY(hipSetDevice(p->ctx->device));
     hipStream_t s = p->ctx->stream;
-    HIP_TRY(hipMemcpyAsync(p->gm.ghat, rhs, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int M = p->M;
+    // g^ = g_n - d_n (Y f)^+
+    JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, true, jy, f_grid, true, nullptr, false, nullptr, p->tmpM)) return e;
+    GmresBufs b = p->gm;
+    HIP_TRY(launch_axpby(M, 1.0, g_n, -1.0, p->tmpM, b.ghat, s));
+    // GMRES on K_N psi = g^: every step is one K_N apply plus one orthogonalisation
     GmresState st{};
-    if (kfbi_status e = run_gmres(p, phi, tol, max_iter, &st)) return e;
-    HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (kfbi_status e = run_gmres(p, kOpN, psi, p->tol, p->max_iter, &st)) return e;
+    // u = v_psi + Y f, with its trace and normal derivative at the samples
+    JumpSrc jf{b.phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, true, jf, f_grid, true, u_grid, true, u_gamma, dn_gamma)) return e;
+    HIP_TRY(hipMemcpyAsync(psi, b.phi, M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (iters) *iters = st.it;
-    // one residual apply per cycle start, one more for the final residual check
-    if (applies) *applies = st.it + st.cycles + (st.converged ? 1 : 0);
     if (rel_res) *rel_res = st.relres;
     if (st.converged == 1) return KFBI_OK;
     return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
@@ -816,9 +902,11 @@ bool tiles_valid(const kfbi_prob* p, int Rm, int B) {
 }
 
 void drop_graph(kfbi_prob* p) {
-    if (p->gexec) hipGraphExecDestroy(p->gexec);
-    p->gexec = nullptr;
-    p->graph_failed = false;
+    for (int op = 0; op < 2; ++op) {
+        if (p->gexec[op]) hipGraphExecDestroy(p->gexec[op]);
+        p->gexec[op] = nullptr;
+        p->graph_failed[op] = false;
+    }
 }
 
 // mean time in microseconds of `reps` runs of `body` (after one warm-up run)
@@ -890,7 +978,7 @@ kfbi_status kfbi_prob_autotune(kfbi_prob* p, int reps, kfbi_tiles* out) {
         p->G = (p->n + Rm - 1) / Rm;
         double us = 0;
         if (kfbi_status e = time_us(s, reps, &us,
-                                    [&] { return sparse_apply(p, p->tmpM, p->s2a, p->s2b, nullptr, nullptr, s); })) {
+                                    [&] { return sparse_apply(p, kOpD, p->tmpM, p->s2a, p->s2b, nullptr, nullptr, s); })) {
             p->Rm = r0;
             p->G = (p->n + r0 - 1) / r0;
             return e;
@@ -1178,7 +1266,7 @@ kfbi_status kfbi_batch_admit(kfbi_batch* B, kfbi_prob* p, const double* f_grid, 
     }
     // g^ = g - (Y f)^+ and a fresh GMRES state (phi_0 = 0)
     JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
+    if (kfbi_status e = dense_interface_solve(p, false, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
     GmresBufs b = p->gm;
     HIP_TRY(launch_axpby(p->M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
     HIP_TRY(launch_axpby(p->M, 0.0, b.ghat, 0.0, nullptr, b.phi, s));
@@ -1247,7 +1335,7 @@ kfbi_status kfbi_batch_finish(kfbi_batch* B, int slot, double* u_grid, double* u
     kfbi_prob* p = B->slot[slot];
     hipStream_t s = B->ctx->stream;
     JumpSrc jf{p->gm.phi, nullptr, p->b_fgam, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, jf, p->b_fgrid, true, u_grid, true, u_gamma)) return e;
+    if (kfbi_status e = dense_interface_solve(p, false, jf, p->b_fgrid, true, u_grid, true, u_gamma)) return e;
     HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
     B->used -= B->slot_bytes[slot];
     B->slot[slot] = nullptr;

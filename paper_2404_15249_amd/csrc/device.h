@@ -52,18 +52,29 @@ struct J6 {
     double v, gx, gy, hxx, hxy, hyy;
 };
 
-// Cartesian jumps of the interface problem at one point of Gamma.
-// [v] = Phi and [d_n v] = 0 (Sec. 2.2); differentiating along arc length gives
-// [v_tau] = Phi_s, [v_tautau] = Phi_ss, [v_taun] = -c Phi_s; the equation gives
-// [v_nn] = [F] + kappa Phi - [v_tautau].
+// Cartesian jumps of the interface problem at one point of Gamma.  With n the
+// outward normal, c the curvature and the density D along arc length:
+//   [v] = D, [d_n v] = 0 (Sec. 2.2):  [v_tau] = D_s, [v_tautau] = D_ss, [v_taun] = -c D_s;
+//   [v] = 0, [d_n v] = D (Neumann):   [v_n] = D, [v_tautau] = c D, [v_taun] = D_s;
+// and the equation gives [v_nn] = [F] + kappa [v] - [v_tautau].
 __device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSrc& js) {
     double P = 0.0, P1 = 0.0, P2 = 0.0, F = 0.0, t1, t2;
     if (js.phi) spline_at(js.phi, js.phi_s2, p, g.seg, g.u, P, P1, P2);
     if (js.fgam) spline_at(js.fgam, js.fgam_s2, p, g.seg, g.u, F, t1, t2);
     const double Ps = P1 * g.a1;
+    J6 J;
+    if (p.normal_jump) {
+        const double vtt = g.curv * P, vtn = Ps, vnn = F - vtt;
+        J.v = 0.0;
+        J.gx = P * g.nx;
+        J.gy = P * g.ny;
+        J.hxx = vtt * g.tx * g.tx + 2.0 * vtn * g.tx * g.nx + vnn * g.nx * g.nx;
+        J.hxy = vtt * g.tx * g.ty + vtn * (g.tx * g.ny + g.nx * g.ty) + vnn * g.nx * g.ny;
+        J.hyy = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
+        return J;
+    }
     const double Pss = P2 * g.a2 - P1 * g.a3;
     const double vtt = Pss, vtn = -g.curv * Ps, vnn = F + p.kappa * P - vtt;
-    J6 J;
     J.v = P;
     J.gx = Ps * g.tx;
     J.gy = Ps * g.ty;

@@ -487,17 +487,30 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
         const double P2 = w * s0 + u * s1;
         // the jumps, as jumps_at computes them with [F] = 0
         const double Ps = P1 * g.a1;
-        const double Pss = P2 * g.a2 - P1 * g.a3;
-        const double vtt = Pss, vtn = -g.curv * Ps, vnn = 0.0 + p.kappa * P - vtt;
-        double gv, hh;
-        if (axs[a]) {
-            gv = Ps * g.ty;
-            hh = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
+        double jv, gv, hh;
+        if (p.normal_jump) {
+            const double vtt = g.curv * P, vtn = Ps, vnn = 0.0 - vtt;
+            jv = 0.0;
+            if (axs[a]) {
+                gv = P * g.ny;
+                hh = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
+            } else {
+                gv = P * g.nx;
+                hh = vtt * g.tx * g.tx + 2.0 * vtn * g.tx * g.nx + vnn * g.nx * g.nx;
+            }
         } else {
-            gv = Ps * g.tx;
-            hh = vtt * g.tx * g.tx + 2.0 * vtn * g.tx * g.nx + vnn * g.nx * g.nx;
+            const double Pss = P2 * g.a2 - P1 * g.a3;
+            const double vtt = Pss, vtn = -g.curv * Ps, vnn = 0.0 + p.kappa * P - vtt;
+            jv = P;
+            if (axs[a]) {
+                gv = Ps * g.ty;
+                hh = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
+            } else {
+                gv = Ps * g.tx;
+                hh = vtt * g.tx * g.tx + 2.0 * vtn * g.tx * g.nx + vnn * g.nx * g.nx;
+            }
         }
-        acc -= sg * (P + d * gv + 0.5 * d * d * hh);
+        acc -= sg * (jv + d * gv + 0.5 * d * d * hh);
     }
     corr_il[slot] = acc * p.inv_h2;
 }

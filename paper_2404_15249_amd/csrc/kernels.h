@@ -23,6 +23,7 @@ struct ModeConst {
 struct DevPlan {
     int n, N, M, Q, I;
     int log2N;
+    int normal_jump;          // 0: the density is [v] ([d_n v] = 0); 1: it is [d_n v] ([v] = 0)
     double lo, h, inv_h2, h2, kappa;
     const PointGeom* q_geo;   // Q
     const int* q_axis;        // Q
@@ -52,7 +53,8 @@ struct DevPlan {
     const int* cp_i0;         // M
     const int* cp_j0;         // M
     const int* cp_sxy;        // M: bit 0 sx>0, bit 1 sy>0
-    const double* cp_w;       // 6 M
+    const double* cp_w;       // 6 M: weights of the six stencil values in the extracted quantity (v+, or
+                              // d_n v+ for a plan that extracts the normal derivative)
     const unsigned char* cp_out;   // 6 M
     const unsigned char* inside;   // (n+1)^2
     const double* sinq;       // N/2 + 1: sin(pi k / N)

@@ -353,6 +353,24 @@ Plan build_plan(const double* xy, int m, int n, double lo, double hi) {
                              0.5 * Y + 0.5 * Y * Y - 0.5 * Pm * (sy + 1),
                              -0.5 * Y + 0.5 * Y * Y + 0.5 * Pm * (sy - 1),
                              Pm};
+        // weights of its derivatives along x and y (in units of h) at the sample:
+        // the quadratic is a + b X + c Y + d X^2 + e X Y + f Y^2 with
+        // b = (E - W)/2, c = (N - S)/2, d = (E + W)/2 - C, f = (N + S)/2 - C and
+        // e = sx sy (D + C - E (sx+1)/2 + W (sx-1)/2 - N (sy+1)/2 + S (sy-1)/2)
+        const double sg = sx * sy;
+        const double wx[6] = {-2.0 * X + sg * Y,
+                              0.5 + X - 0.5 * sg * Y * (sx + 1),
+                              -0.5 + X + 0.5 * sg * Y * (sx - 1),
+                              -0.5 * sg * Y * (sy + 1),
+                              0.5 * sg * Y * (sy - 1),
+                              sg * Y};
+        const double wy[6] = {-2.0 * Y + sg * X,
+                              -0.5 * sg * X * (sx + 1),
+                              0.5 * sg * X * (sx - 1),
+                              0.5 + Y - 0.5 * sg * X * (sy + 1),
+                              -0.5 + Y + 0.5 * sg * X * (sy - 1),
+                              sg * X};
+        const PointGeom g = geom_at(P, k, 0.0);
         const int ni[6] = {i0, i0 + 1, i0 - 1, i0, i0, i0 + sx};
         const int nj[6] = {j0, j0, j0, j0 + 1, j0 - 1, j0 + sy};
         P.cp_i0.push_back(i0);
@@ -361,9 +379,10 @@ Plan build_plan(const double* xy, int m, int n, double lo, double hi) {
         P.cp_sy.push_back(sy);
         for (int s = 0; s < 6; ++s) {
             P.cp_w.push_back(w[s]);
+            P.cp_wn.push_back((g.nx * wx[s] + g.ny * wy[s]) / h);
             P.cp_out.push_back(in(ni[s], nj[s]) ? 0 : 1);
         }
-        P.z_geo.push_back(geom_at(P, k, 0.0));
+        P.z_geo.push_back(g);
     }
     return P;
 }

@@ -52,6 +52,7 @@ struct Plan {
     std::vector<PointGeom> z_geo;
     std::vector<int> cp_i0, cp_j0, cp_sx, cp_sy;
     std::vector<double> cp_w;            // 6 per sample: weights of nodes C, E, W, N, S, D
+    std::vector<double> cp_wn;           // 6 per sample: the same quadratic's outward normal derivative
     std::vector<unsigned char> cp_out;   // 6 per sample: 1 if that stencil node is outside Omega
 };
 

@@ -80,6 +80,11 @@ _sigs = {
     "kfbi_fast_solve": [_vp, _vp, _vp],
     "kfbi_interface_solve": [_vp, _vp, _vp, _vp, _vp, _vp],
     "kfbi_interface_solve_jumps": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi_apply_neumann": [_vp, _vp, _vp],
+    "kfbi_interface_solve_neumann": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi_gmres_neumann": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                           ct.POINTER(ct.c_double)],
+    "kfbi_solve_neumann": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
     "kfbi_batch_create": [_vp, ct.c_int, ct.c_int, ct.c_size_t, ct.POINTER(_vp)],
     "kfbi_batch_destroy": [_vp],
     "kfbi_batch_estimate_bytes": [ct.c_int, ct.c_int, ct.c_int, ct.POINTER(ct.c_size_t)],
@@ -298,6 +303,56 @@ class Problem:
                                         int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
                         allow=(OK, NOT_CONVERGED))
         return phi, it.value, ap.value, rel.value, st == OK
+
+    # ---- the Neumann problem
+    def apply_neumann(self, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """``K_N psi = d_n v+`` at the samples (``kfbi_apply_neumann``)."""
+        if out is None:
+            out = torch.empty_like(psi)
+        with self.ctx:
+            _check(_lib.kfbi_apply_neumann(self._h, _dptr(psi, "psi", self.M), _dptr(out, "out", self.M)))
+        return out
+
+    def interface_solve_neumann(self, psi=None, ftilde=None, f_gamma=None):
+        """``[v] = 0``, ``[d_n v] = psi``, ``F = ftilde``: returns ``(v_grid, v+, d_n v+)``."""
+        dev = f"cuda:{self.ctx.device}"
+        vg = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+        vz = torch.empty(self.M, dtype=torch.float64, device=dev)
+        dn = torch.empty(self.M, dtype=torch.float64, device=dev)
+        with self.ctx:
+            _check(_lib.kfbi_interface_solve_neumann(self._h, _dptr(psi, "psi", self.M),
+                                                     _dptr(ftilde, "ftilde", self.grid_numel),
+                                                     _dptr(f_gamma, "f_gamma", self.M), _dptr(vg, "vgrid"),
+                                                     _dptr(vz, "vz"), _dptr(dn, "dnz")))
+        return vg, vz, dn
+
+    def gmres_neumann(self, rhs, psi0=None, tol=1e-10, max_iter=500):
+        """GMRES on ``K_N psi = rhs``; returns ``(psi, iters, applies, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        psi = torch.zeros(self.M, dtype=torch.float64, device=dev) if psi0 is None else psi0.clone()
+        it, ap, rel = ct.c_int(), ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi_gmres_neumann(self._h, _dptr(rhs, "rhs", self.M), _dptr(psi, "psi", self.M),
+                                                float(tol), int(max_iter), ct.byref(it), ct.byref(ap),
+                                                ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return psi, it.value, ap.value, rel.value, st == OK
+
+    def solve_neumann(self, f_grid, f_gamma, g_n, psi0=None):
+        """Neumann solve; returns ``(u_grid, u_gamma, dn_gamma, psi, iters, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        u = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+        ug = torch.empty(self.M, dtype=torch.float64, device=dev)
+        dn = torch.empty(self.M, dtype=torch.float64, device=dev)
+        psi = torch.zeros(self.M, dtype=torch.float64, device=dev) if psi0 is None else psi0.clone()
+        it, rel = ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi_solve_neumann(self._h, _dptr(f_grid, "f_grid", self.grid_numel),
+                                                _dptr(f_gamma, "f_gamma", self.M), _dptr(g_n, "g_n", self.M),
+                                                _dptr(u, "u_grid"), _dptr(ug, "u_gamma"), _dptr(dn, "dn_gamma"),
+                                                _dptr(psi, "psi"), ct.byref(it), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return u, ug, dn, psi, it.value, rel.value, st == OK
 
     # ---- launch shapes
     def autotune(self, reps: int = 10) -> dict:
