@@ -260,6 +260,55 @@ def three_d(ctx, sizes=(64, 128), steps: int = 200) -> dict:
                         "control points = grid-edge crossings; step = one GMRES iteration", "rows": rows}
 
 
+def neumann(ctx, n: int = 2048, steps: int = 400, sizes=(512, 1024, 2048)) -> dict:
+    """The Neumann problem d_n u = g_n on the star workload (kappa = 1, M = N/2,
+    u = sin(pi x) cos(pi y) + x^2): graphed GMRES steps on K_N (grid unknowns per
+    second per step, as the headline's K_D step), a full FP64 solve to 1e-10,
+    and the L-infinity error against the exact solution at several grids."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    p = synth.star_neumann_problem(n=n, kappa=1.0)
+    prob = kfbi.Problem(ctx, p.xy, p.n, p.kappa, restart=50)
+    rhs = dev(p.g_n)
+    prob.gmres_neumann(rhs, tol=0.0, max_iter=50)              # warm-up (records the step graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, iters, _, _, _ = prob.gmres_neumann(rhs, tol=0.0, max_iter=steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    assert iters == steps
+    prob.close()
+    unknowns = (n - 1) ** 2
+    res = {"workload": f"Neumann problem on the star r=0.6+0.15 sin 5t, kappa=1, M=N/2, "
+                       f"u=sin(pi x)cos(pi y)+x^2; step = one GMRES iteration on K_N at {n}x{n}",
+           "us_per_step": 1e6 * dt / steps, "unknowns_per_s": unknowns * steps / dt}
+    rows = []
+    for m in sizes:
+        q = synth.star_neumann_problem(n=m, kappa=1.0)
+        pr = kfbi.Problem(ctx, q.xy, q.n, q.kappa, tol=1e-10)
+        args = (dev(q.f_grid), dev(q.f_gamma), dev(q.g_n))
+        pr.solve_neumann(*args)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        u, ug, dn, psi, it, rel, conv = pr.solve_neumann(*args)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t1)
+        c = q.lo + np.arange(q.n + 1) * q.h
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        mask = pr.mask()
+        rows.append({"n": m, "samples": pr.M, "solve_ms": ms, "gmres_iters": it, "converged": conv,
+                     "linf_err_grid": float(np.max(np.abs(u.cpu().numpy() - q.exact.u(X, Y))[mask])),
+                     "linf_err_trace": float(np.max(np.abs(ug.cpu().numpy() - q.g))),
+                     "linf_dn_minus_g_n": float(np.max(np.abs(dn.cpu().numpy() - q.g_n)))})
+        pr.close()
+    for a, b in zip(rows, rows[1:]):
+        b["order_grid"] = float(np.log2(a["linf_err_grid"] / b["linf_err_grid"]))
+    res["rows"] = rows
+    return res
+
+
 def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0):
     import synth
     from paper_2404_15249_amd.serving import GpuExecutor, Scheduler, summarize
@@ -319,12 +368,13 @@ def main():
     ap.add_argument("--mixed", choices=["on", "off"], default="on")
     ap.add_argument("--convergence", choices=["on", "off"], default="on")
     ap.add_argument("--three-d", choices=["on", "off"], default="on")
+    ap.add_argument("--neumann", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
-    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d"], default="apply",
+    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann"], default="apply",
                     help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "
                          "copy: a 256 MiB device copy to calibrate the HBM byte counters; "
-                         "3d: only the ellipsoid section")
+                         "3d: only the ellipsoid section; neumann: only the Neumann section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the KFBI path here has no multi-GPU mode "
@@ -345,6 +395,9 @@ def main():
     ctx = kfbi.Context(0)
     if args.mode == "3d":
         print(json.dumps(three_d(ctx)), flush=True)
+        return
+    if args.mode == "neumann":
+        print(json.dumps(neumann(ctx, args.n)), flush=True)
         return
     if args.mode == "serving":
         print(json.dumps(serving_line(ctx, args)), flush=True)
@@ -444,6 +497,8 @@ def main():
         out["mixed"] = mixed_precision(ctx, args.n)
     if args.three_d == "on":
         out["three_d"] = three_d(ctx)
+    if args.neumann == "on":
+        out["neumann"] = neumann(ctx, args.n)
     if args.serving_requests > 0:
         out["serving"] = serving(ctx, args.serving_requests, args.serving_seed)
     if args.cpu_baseline == "on":
