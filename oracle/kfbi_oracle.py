@@ -669,13 +669,17 @@ def solve_neumann(xy, n, lo, hi, kappa, f_grid, f_gamma, g_n, tol=1e-10, restart
     ``kappa = 0`` the interior problem loses uniqueness (constants), so it is
     rejected.
     """
+    return solve_neumann_on(build_plan(xy, n, lo, hi), kappa, f_grid, f_gamma, g_n, tol, restart, max_iter)
+
+
+def solve_neumann_on(plan: Plan, kappa, f_grid, f_gamma, g_n, tol=1e-10, restart=50, max_iter=500, psi0=None):
+    """``solve_neumann`` on a built plan, from the initial density ``psi0`` (``None``: zero)."""
     if not kappa > 0.0:
         raise ValueError("the Neumann problem needs kappa > 0")
-    plan = build_plan(xy, n, lo, hi)
     ft = zero_extension(plan, f_grid)
     _, _, dyf = interface_solve_neumann(plan, None, ft, f_gamma, kappa)
     ghat = np.asarray(g_n, dtype=np.float64) - dyf
-    psi, it, rel = gmres(lambda p: apply_KN(plan, p, kappa), ghat, tol, restart, max_iter)
+    psi, it, rel = gmres(lambda p: apply_KN(plan, p, kappa), ghat, tol, restart, max_iter, x0=psi0)
     v, ug, dn = interface_solve_neumann(plan, psi, ft, f_gamma, kappa)
     u = np.where(plan.inside, v, 0.0)
     return NeumannSolution(u, ug, dn, psi, it, rel, plan)

@@ -304,6 +304,43 @@ def star_neumann_problem(n=512, m=None, kappa=1.0, sol=SIN_COS_X2, r0=0.6, a=0.1
                                 star_normals(xy, r0, a, k), n, kappa, sol)
 
 
+# --------------------------------------------------------------------------
+# Gray-Scott reaction-diffusion (Example 3): disk r = 1.8 in the box (-2, 2)^2
+# --------------------------------------------------------------------------
+
+GS_LO, GS_HI, GS_RADIUS = -2.0, 2.0, 1.8
+
+
+@dataclasses.dataclass(frozen=True)
+class GrayScottParams:
+    """``u_t = eps1 Lap u + (gamma (1-u) - u v^2) / eps0``,
+    ``v_t = eps2 Lap v + (u v^2 - (gamma + kill) v) / eps0`` (the paper's
+    removal rate, called kappa there, is ``kill`` here)."""
+    gamma: float = 0.024
+    kill: float = 0.06
+    eps0: float = 0.01
+    eps1: float = 0.008
+    eps2: float = 0.004
+
+
+def gray_scott_initial(x, y):
+    """Initial ``(u, v)``: ``v = sin^2(4 pi x) sin^2(4 pi y) / 4`` on ``[-1/4, 1/4]^2``, else 0;
+    ``u = 1 - 2 v``."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    box = (np.abs(x) <= 0.25) & (np.abs(y) <= 0.25)
+    v = np.where(box, 0.25 * np.sin(4 * np.pi * x) ** 2 * np.sin(4 * np.pi * y) ** 2, 0.0)
+    return 1.0 - 2.0 * v, v
+
+
+def gray_scott_samples(n: int) -> np.ndarray:
+    """Boundary samples of the disk for an ``n x n`` grid on the box: ``M = 64 ceil(P / (128 h))``,
+    about two grid spacings apart."""
+    h = (GS_HI - GS_LO) / n
+    m = 64 * int(math.ceil(2.0 * np.pi * GS_RADIUS / (128.0 * h)))
+    return circle_points(m, GS_RADIUS)
+
+
 @dataclasses.dataclass
 class RequestSpec:
     """Domain and data of one serving request, before any grid array exists."""
