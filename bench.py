@@ -309,6 +309,58 @@ def neumann(ctx, n: int = 2048, steps: int = 400, sizes=(512, 1024, 2048)) -> di
     return res
 
 
+# Table of Example 3 (Neumann row): the paper's GPU times in seconds on its own
+# machine, for context only
+PAPER_GS_GPU_S = {128: 0.40, 256: 1.04, 512: 3.29, 1024: 12.07}
+
+
+def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: float = 1.0) -> dict:
+    """Example 3: Gray-Scott on the disk r = 1.8 in (-2, 2)^2 with the paper's
+    parameters, Strang splitting, GMRES tol 1e-8, at the grid sizes and step
+    counts of the paper's table (final time T = 1).  The timed region is the time
+    stepping alone, with the state resident on the device."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    lo, hi = synth.GS_LO, synth.GS_HI
+    rows = []
+    for n, steps in configs:
+        xy = synth.gray_scott_samples(n)
+        dt = T / steps
+        mask = kfbi.Problem(ctx, xy, n, 1.0, lo=lo, hi=hi).mask()
+        c = lo + np.arange(n + 1) * (hi - lo) / n
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        u0, v0 = synth.gray_scott_initial(X, Y)
+        ug0, vg0 = synth.gray_scott_initial(xy[:, 0], xy[:, 1])
+        init = (dev(np.where(mask, u0, 0.0)), dev(np.where(mask, v0, 0.0)), dev(ug0), dev(vg0))
+        gs = kfbi.GrayScott(ctx, xy, n, dt, lo=lo, hi=hi, tol=1e-8)
+        gs.set_state(*init)
+        gs.step(1)                                   # warm-up (first launches, allocations)
+        gs.set_state(*init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gs.step(steps)
+        torch.cuda.synchronize()
+        run_s = time.perf_counter() - t0
+        u, v, ug, vg = [t.cpu().numpy() for t in gs.state()]
+        info = gs.info()
+        gs.close()
+        row = {"n": n, "steps": steps, "dt": dt, "samples": int(xy.shape[0]), "run_s": run_s,
+               "ms_per_step": 1e3 * run_s / steps, "gmres_iters": info["gmres_iters"],
+               "u_max": float(u[mask].max()), "u_min": float(u[mask].min()), "v_max": float(v[mask].max()),
+               "u_trace_max": float(ug.max())}
+        if n in PAPER_GS_GPU_S:
+            row["paper_gpu_s"] = PAPER_GS_GPU_S[n]
+            row["paper_gpu_s_over_this"] = PAPER_GS_GPU_S[n] / run_s
+        rows.append(row)
+    return {"workload": "Gray-Scott (Example 3): disk r=1.8 in (-2,2)^2, gamma=0.024, kill=0.06, eps0=0.01, "
+                        "eps1=0.008, eps2=0.004, T=1, Strang splitting (RK4 reaction half steps, Crank-Nicolson "
+                        "diffusion as two warm-started Neumann solves per step), GMRES tol 1e-8; "
+                        "paper_gpu_s is the paper's own machine (context)",
+            "rows": rows}
+
+
 def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0):
     import synth
     from paper_2404_15249_amd.serving import GpuExecutor, Scheduler, summarize
@@ -369,12 +421,14 @@ def main():
     ap.add_argument("--convergence", choices=["on", "off"], default="on")
     ap.add_argument("--three-d", choices=["on", "off"], default="on")
     ap.add_argument("--neumann", choices=["on", "off"], default="on")
+    ap.add_argument("--gray-scott", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
-    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann"], default="apply",
+    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann", "gray_scott"], default="apply",
                     help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "
                          "copy: a 256 MiB device copy to calibrate the HBM byte counters; "
-                         "3d: only the ellipsoid section; neumann: only the Neumann section")
+                         "3d: only the ellipsoid section; neumann: only the Neumann section; "
+                         "gray_scott: only the Gray-Scott section")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the KFBI path here has no multi-GPU mode "
@@ -398,6 +452,9 @@ def main():
         return
     if args.mode == "neumann":
         print(json.dumps(neumann(ctx, args.n)), flush=True)
+        return
+    if args.mode == "gray_scott":
+        print(json.dumps(gray_scott(ctx)), flush=True)
         return
     if args.mode == "serving":
         print(json.dumps(serving_line(ctx, args)), flush=True)
@@ -499,6 +556,8 @@ def main():
         out["three_d"] = three_d(ctx)
     if args.neumann == "on":
         out["neumann"] = neumann(ctx, args.n)
+    if args.gray_scott == "on":
+        out["gray_scott"] = gray_scott(ctx)
     if args.serving_requests > 0:
         out["serving"] = serving(ctx, args.serving_requests, args.serving_seed)
     if args.cpu_baseline == "on":

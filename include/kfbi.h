@@ -201,6 +201,48 @@ kfbi_status kfbi_solve_neumann(kfbi_prob* prob, const double* f_grid, const doub
                                const double* g_n, double* u_grid, double* u_gamma, double* dn_gamma,
                                double* psi, int* iters, double* rel_res);
 
+/* ---------------------------------------------------------------- Gray-Scott time stepping */
+/* Example 3 of the paper: u_t = eps1 Lap u + (gamma (1-u) - u v^2)/eps0,
+ * v_t = eps2 Lap v + (u v^2 - (gamma + kill) v)/eps0 in Omega, d_n u = d_n v = 0
+ * on Gamma, by second-order Strang splitting (the paper names the splitting; the
+ * rest is this library's reading): each step is R(dt/2) D(dt) R(dt/2), with R one
+ * classical Runge-Kutta step of the pointwise reaction at the grid nodes in
+ * Omega and at the boundary samples, and D Crank-Nicolson as w <- 2 z - w, z the
+ * solution of the Neumann problem Lap z - kappa z = -kappa w, d_n z = 0,
+ * kappa = 2/(eps dt) (kfbi_solve_neumann, GMRES warm-started from the previous
+ * step's density).  The state is a grid of (n+1)^2 values (zero outside Omega)
+ * and the trace at the M boundary samples, per species. */
+typedef struct kfbi_gs kfbi_gs;
+
+typedef struct {
+    double lo, hi;        /* box [lo, hi]^2 */
+    int n;                /* intervals per axis, as kfbi_desc */
+    int m;                /* boundary samples */
+    const double* xy;     /* host, m x 2, counter-clockwise (read during create only) */
+    double gamma, kill;   /* feed and removal rates (the paper's gamma and kappa) */
+    double eps0, eps1, eps2;
+    double dt;            /* time step */
+    double tol;           /* GMRES tolerance of each solve (the paper: 1e-8); <= 0: 1e-10 */
+    int restart, max_iter;   /* as kfbi_desc (<= 0: defaults) */
+} kfbi_gs_desc;
+
+/* Two Neumann problems on one geometry (kappa = 2/(eps1 dt) and 2/(eps2 dt))
+ * and the state buffers, all zero.  Geometry errors as kfbi_prob_create. */
+kfbi_status kfbi_gs_create(kfbi_ctx* ctx, const kfbi_gs_desc* desc, kfbi_gs** out);
+kfbi_status kfbi_gs_destroy(kfbi_gs* gs);
+/* host out (each may be NULL): samples M, steps taken, GMRES iterations of all solves */
+kfbi_status kfbi_gs_info(const kfbi_gs* gs, int* m, int* steps, long long* gmres_iters);
+/* Copy in the state (device: grids (n+1)^2, zero outside Omega; traces M) and
+ * reset the warm starts and counters. */
+kfbi_status kfbi_gs_set_state(kfbi_gs* gs, const double* u_grid, const double* v_grid,
+                              const double* u_gamma, const double* v_gamma);
+/* Copy out the state (device; each pointer may be NULL).  Synchronises. */
+kfbi_status kfbi_gs_get_state(kfbi_gs* gs, double* u_grid, double* v_grid, double* u_gamma, double* v_gamma);
+/* Advance nsteps steps (two Neumann solves each).  Synchronises; returns
+ * KFBI_NOT_CONVERGED if a solve hit its iteration cap (the step count then
+ * stops at the step that failed). */
+kfbi_status kfbi_gs_step(kfbi_gs* gs, int nsteps);
+
 /* ---------------------------------------------------------------- steps (for tests and tools) */
 
 /* Alg. 2 alone: the correction of the right-hand side at every irregular node

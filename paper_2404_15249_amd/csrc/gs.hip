@@ -1,0 +1,271 @@
+// Gray-Scott reaction-diffusion by Strang splitting (Example 3) on the
+// Neumann solve of this library.
+//
+// One step is R(dt/2) D(dt) R(dt/2):
+//  - R: the pointwise reaction ODE u' = (gamma (1-u) - u v^2)/eps0,
+//    v' = (u v^2 - (gamma + kill) v)/eps0, one classical Runge-Kutta step of
+//    dt/2, at the grid nodes in Omega and at the boundary samples (the state
+//    keeps its trace on Gamma: the diffusion solve needs it as the jump [F]);
+//  - D: Crank-Nicolson for w' = eps Lap w with d_n w = 0, as w <- 2 z - w with
+//    z the backward-Euler half step Lap z - kappa z = -kappa w, kappa = 2/(eps dt):
+//    one Neumann solve per species (kfbi_solve_neumann), warm-started from the
+//    species' previous density.
+// Grid nodes outside Omega hold zero.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "api_common.h"
+
+using namespace kfbi;
+
+namespace {
+
+struct GsRates {
+    double gamma, kill, inv_eps0;
+};
+
+__device__ __forceinline__ void gs_rates(double u, double v, const GsRates& P, double& du, double& dv) {
+    const double uvv = u * v * v;
+    du = (P.gamma * (1.0 - u) - uvv) * P.inv_eps0;
+    dv = (uvv - (P.gamma + P.kill) * v) * P.inv_eps0;
+}
+
+// One classical RK4 step of size dt.
+__device__ __forceinline__ void gs_rk4(double& u, double& v, double dt, const GsRates& P) {
+    double a1, b1, a2, b2, a3, b3, a4, b4;
+    gs_rates(u, v, P, a1, b1);
+    gs_rates(u + 0.5 * dt * a1, v + 0.5 * dt * b1, P, a2, b2);
+    gs_rates(u + 0.5 * dt * a2, v + 0.5 * dt * b2, P, a3, b3);
+    gs_rates(u + dt * a3, v + dt * b3, P, a4, b4);
+    const double c = dt / 6.0;
+    u = u + c * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
+    v = v + c * (b1 + 2.0 * b2 + 2.0 * b3 + b4);
+}
+
+// Element t of the state: grid node t (t < ng, kept only where mask is set) or
+// boundary sample t - ng.
+struct GsState {
+    double* u;      // ng, then the M samples (one buffer: grid followed by trace)
+    double* v;
+    const unsigned char* mask;   // ng
+    int ng, M;
+};
+
+// R(dt/2), then the right-hand sides of the two half-step solves:
+// fu = -kappa_u u, fv = -kappa_v v (same layout as the state).
+__global__ __launch_bounds__(256) void k_gs_pre(GsState S, double* __restrict__ fu, double* __restrict__ fv,
+                                                double dth, double ku, double kv, GsRates P) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S.ng + S.M) return;
+    double u = 0.0, v = 0.0;
+    if (t >= S.ng || S.mask[t]) {
+        u = S.u[t];
+        v = S.v[t];
+        gs_rk4(u, v, dth, P);
+    }
+    S.u[t] = u;
+    S.v[t] = v;
+    fu[t] = -ku * u;
+    fv[t] = -kv * v;
+}
+
+// w <- 2 z - w for both species (z from the solves: grid zero outside Omega,
+// then the trace), then R(dt/2).
+__global__ __launch_bounds__(256) void k_gs_post(GsState S, const double* __restrict__ zu,
+                                                 const double* __restrict__ zv, double dth, GsRates P) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S.ng + S.M) return;
+    double u = 0.0, v = 0.0;
+    if (t >= S.ng || S.mask[t]) {
+        u = 2.0 * zu[t] - S.u[t];
+        v = 2.0 * zv[t] - S.v[t];
+        gs_rk4(u, v, dth, P);
+    }
+    S.u[t] = u;
+    S.v[t] = v;
+}
+
+}  // namespace
+
+struct kfbi_gs {
+    kfbi_ctx* ctx = nullptr;
+    kfbi_prob* pu = nullptr;     // kappa_u = 2/(eps1 dt)
+    kfbi_prob* pv = nullptr;     // kappa_v = 2/(eps2 dt)
+    kfbi_gs_desc d{};
+    int n = 0, M = 0, ng = 0;
+    double ku = 0, kv = 0;
+    // device buffers; grid arrays are followed by the M trace values
+    double *u = nullptr, *v = nullptr, *fu = nullptr, *fv = nullptr, *zu = nullptr, *zv = nullptr;
+    double *psi_u = nullptr, *psi_v = nullptr, *gn = nullptr, *dn = nullptr;
+    unsigned char* mask = nullptr;
+    std::vector<void*> allocs;
+    long long iters = 0;         // GMRES iterations of all solves so far
+    int steps = 0;
+};
+
+namespace {
+
+void gs_free(kfbi_gs* g) {
+    for (void* a : g->allocs) hipFree(a);
+    g->allocs.clear();
+    if (g->pu) kfbi_prob_destroy(g->pu);
+    if (g->pv) kfbi_prob_destroy(g->pv);
+    g->pu = g->pv = nullptr;
+}
+
+template <class T>
+kfbi_status gs_alloc(kfbi_gs* g, T** out, size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(T)) != hipSuccess) {
+        hipGetLastError();
+        return set_err(KFBI_ERR_OOM, "device allocation failed (Gray-Scott state)");
+    }
+    g->allocs.push_back(p);
+    *out = static_cast<T*>(p);
+    return KFBI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+kfbi_status kfbi_gs_create(kfbi_ctx* ctx, const kfbi_gs_desc* d, kfbi_gs** out) {
+    if (!ctx || !d || !out) return set_err(KFBI_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    if (!(d->dt > 0.0) || !(d->eps0 > 0.0) || !(d->eps1 > 0.0) || !(d->eps2 > 0.0))
+        return set_err(KFBI_ERR_ARG, "dt, eps0, eps1 and eps2 must be positive");
+    HIP_TRY(hipSetDevice(ctx->device));
+    kfbi_gs* g = new kfbi_gs;
+    g->ctx = ctx;
+    g->d = *d;
+    g->d.xy = nullptr;                       // host memory of the caller: not kept
+    g->ku = 2.0 / (d->eps1 * d->dt);
+    g->kv = 2.0 / (d->eps2 * d->dt);
+    auto fail = [&](kfbi_status s) {
+        gs_free(g);
+        delete g;
+        return s;
+    };
+    kfbi_desc pd{};
+    pd.lo = d->lo;
+    pd.hi = d->hi;
+    pd.n = d->n;
+    pd.m = d->m;
+    pd.xy = d->xy;
+    pd.tol = d->tol;
+    pd.restart = d->restart;
+    pd.max_iter = d->max_iter;
+    pd.precision = KFBI_FP64;
+    pd.kappa = g->ku;
+    if (kfbi_status s = kfbi_prob_create(ctx, &pd, &g->pu)) return fail(s);
+    pd.kappa = g->kv;
+    if (kfbi_status s = kfbi_prob_create(ctx, &pd, &g->pv)) return fail(s);
+    kfbi_prob_info(g->pu, &g->M, nullptr, nullptr, nullptr);
+    g->n = d->n;
+    g->ng = (d->n + 1) * (d->n + 1);
+    const size_t all = (size_t)g->ng + g->M;
+    kfbi_status st = KFBI_OK;
+    if ((st = gs_alloc(g, &g->u, all)) || (st = gs_alloc(g, &g->v, all)) || (st = gs_alloc(g, &g->fu, all)) ||
+        (st = gs_alloc(g, &g->fv, all)) || (st = gs_alloc(g, &g->zu, all)) || (st = gs_alloc(g, &g->zv, all)) ||
+        (st = gs_alloc(g, &g->psi_u, g->M)) || (st = gs_alloc(g, &g->psi_v, g->M)) ||
+        (st = gs_alloc(g, &g->gn, g->M)) || (st = gs_alloc(g, &g->dn, g->M)) || (st = gs_alloc(g, &g->mask, g->ng)))
+        return fail(st);
+    std::vector<unsigned char> mask(g->ng);
+    kfbi_prob_mask(g->pu, mask.data());
+    hipStream_t s = ctx->stream;
+    if (hipMemcpyAsync(g->mask, mask.data(), g->ng, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemsetAsync(g->u, 0, all * sizeof(double), s) != hipSuccess ||
+        hipMemsetAsync(g->v, 0, all * sizeof(double), s) != hipSuccess ||
+        hipMemsetAsync(g->psi_u, 0, g->M * sizeof(double), s) != hipSuccess ||
+        hipMemsetAsync(g->psi_v, 0, g->M * sizeof(double), s) != hipSuccess ||
+        hipMemsetAsync(g->gn, 0, g->M * sizeof(double), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+        hipGetLastError();
+        return fail(set_err(KFBI_ERR_DEVICE, "Gray-Scott state initialisation failed"));
+    }
+    *out = g;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_gs_destroy(kfbi_gs* g) {
+    if (!g) return KFBI_OK;
+    hipSetDevice(g->ctx->device);
+    hipStreamSynchronize(g->ctx->stream);
+    gs_free(g);
+    delete g;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_gs_info(const kfbi_gs* g, int* m, int* steps, long long* gmres_iters) {
+    if (!g) return set_err(KFBI_ERR_ARG, "gs is NULL");
+    if (m) *m = g->M;
+    if (steps) *steps = g->steps;
+    if (gmres_iters) *gmres_iters = g->iters;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_gs_set_state(kfbi_gs* g, const double* u_grid, const double* v_grid, const double* u_gamma,
+                              const double* v_gamma) {
+    if (!g) return set_err(KFBI_ERR_ARG, "gs is NULL");
+    for (auto [p, name] : {std::pair<const void*, const char*>{u_grid, "u_grid"}, {v_grid, "v_grid"},
+                           {u_gamma, "u_gamma"}, {v_gamma, "v_gamma"}})
+        if (kfbi_status s = check_ptr(p, name)) return s;
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t s = g->ctx->stream;
+    const size_t gb = (size_t)g->ng * sizeof(double), mb = (size_t)g->M * sizeof(double);
+    HIP_TRY(hipMemcpyAsync(g->u, u_grid, gb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->v, v_grid, gb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->u + g->ng, u_gamma, mb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(g->v + g->ng, v_gamma, mb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(g->psi_u, 0, mb, s));
+    HIP_TRY(hipMemsetAsync(g->psi_v, 0, mb, s));
+    g->steps = 0;
+    g->iters = 0;
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_gs_get_state(kfbi_gs* g, double* u_grid, double* v_grid, double* u_gamma, double* v_gamma) {
+    if (!g) return set_err(KFBI_ERR_ARG, "gs is NULL");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t s = g->ctx->stream;
+    const size_t gb = (size_t)g->ng * sizeof(double), mb = (size_t)g->M * sizeof(double);
+    if (u_grid) HIP_TRY(hipMemcpyAsync(u_grid, g->u, gb, hipMemcpyDeviceToDevice, s));
+    if (v_grid) HIP_TRY(hipMemcpyAsync(v_grid, g->v, gb, hipMemcpyDeviceToDevice, s));
+    if (u_gamma) HIP_TRY(hipMemcpyAsync(u_gamma, g->u + g->ng, mb, hipMemcpyDeviceToDevice, s));
+    if (v_gamma) HIP_TRY(hipMemcpyAsync(v_gamma, g->v + g->ng, mb, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return KFBI_OK;
+}
+
+kfbi_status kfbi_gs_step(kfbi_gs* g, int nsteps) {
+    if (!g) return set_err(KFBI_ERR_ARG, "gs is NULL");
+    if (nsteps < 0) return set_err(KFBI_ERR_ARG, "nsteps must be >= 0");
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    hipStream_t s = g->ctx->stream;
+    const GsRates P{g->d.gamma, g->d.kill, 1.0 / g->d.eps0};
+    const GsState S{g->u, g->v, g->mask, g->ng, g->M};
+    const int total = g->ng + g->M;
+    const dim3 grid((total + 255) / 256), block(256);
+    const double dth = 0.5 * g->d.dt;
+    for (int k = 0; k < nsteps; ++k) {
+        HIP_TRY(klaunch(k_gs_pre, grid, block, 0, s, S, g->fu, g->fv, dth, g->ku, g->kv, P));
+        int it = 0;
+        for (int sp = 0; sp < 2; ++sp) {
+            kfbi_prob* p = sp ? g->pv : g->pu;
+            double* f = sp ? g->fv : g->fu;
+            double* z = sp ? g->zv : g->zu;
+            double* psi = sp ? g->psi_v : g->psi_u;
+            if (kfbi_status e = kfbi_solve_neumann(p, f, f + g->ng, g->gn, z, z + g->ng, g->dn, psi, &it, nullptr))
+                return e;
+            g->iters += it;
+        }
+        HIP_TRY(klaunch(k_gs_post, grid, block, 0, s, S, g->zu, g->zv, dth, P));
+        g->steps++;
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return KFBI_OK;
+}
+
+}  // extern "C"

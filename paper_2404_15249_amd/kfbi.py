@@ -47,6 +47,13 @@ class _Desc3(ct.Structure):
                 ("axes", ct.c_double * 3), ("tol", ct.c_double), ("restart", ct.c_int), ("max_iter", ct.c_int)]
 
 
+class _GsDesc(ct.Structure):
+    _fields_ = [("lo", ct.c_double), ("hi", ct.c_double), ("n", ct.c_int), ("m", ct.c_int), ("xy", ct.c_void_p),
+                ("gamma", ct.c_double), ("kill", ct.c_double), ("eps0", ct.c_double), ("eps1", ct.c_double),
+                ("eps2", ct.c_double), ("dt", ct.c_double), ("tol", ct.c_double), ("restart", ct.c_int),
+                ("max_iter", ct.c_int)]
+
+
 FP64 = 0            # KFBI_FP64
 FP32_REFINED = 1    # KFBI_FP32_REFINED
 _PRECISION = {"fp64": FP64, "fp32": FP32_REFINED}
@@ -108,6 +115,12 @@ _sigs = {
     "kfbi3_solve": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
     "kfbi3_gmres": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
                     ct.POINTER(ct.c_double)],
+    "kfbi_gs_create": [_vp, ct.POINTER(_GsDesc), ct.POINTER(_vp)],
+    "kfbi_gs_destroy": [_vp],
+    "kfbi_gs_info": [_vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), ct.POINTER(ct.c_longlong)],
+    "kfbi_gs_set_state": [_vp, _vp, _vp, _vp, _vp],
+    "kfbi_gs_get_state": [_vp, _vp, _vp, _vp, _vp],
+    "kfbi_gs_step": [_vp, ct.c_int],
     "kfbi_set_timing": [_vp, ct.c_int],
     "kfbi_apply_timing": [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                           ct.POINTER(ct.c_int)],
@@ -483,6 +496,61 @@ class Problem3:
                                          int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
                         allow=(OK, NOT_CONVERGED))
         return phi, it.value, ap.value, rel.value, st == OK
+
+
+class GrayScott:
+    """Gray-Scott time stepping on a curved domain with zero Neumann data
+    (``kfbi_gs_*``): the state lives on the device; ``step`` advances it by
+    Strang splitting, two Neumann solves per step."""
+
+    def __init__(self, ctx: Context, xy, n: int, dt: float, gamma=0.024, kill=0.06, eps0=0.01, eps1=0.008,
+                 eps2=0.004, lo: float = -2.0, hi: float = 2.0, tol: float = 1e-8, restart: int = 50,
+                 max_iter: int = 500):
+        self.ctx = ctx
+        xy = np.ascontiguousarray(xy, dtype=np.float64)
+        d = _GsDesc(lo, hi, int(n), xy.shape[0], _vp(xy.ctypes.data), gamma, kill, eps0, eps1, eps2, dt, tol,
+                    restart, max_iter)
+        h = _vp()
+        with ctx:
+            _check(_lib.kfbi_gs_create(ctx._h, ct.byref(d), ct.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.lo, self.hi = lo, hi
+        m = ct.c_int()
+        _check(_lib.kfbi_gs_info(self._h, ct.byref(m), None, None))
+        self.M = m.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.kfbi_gs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        m, st, it = ct.c_int(), ct.c_int(), ct.c_longlong()
+        _check(_lib.kfbi_gs_info(self._h, ct.byref(m), ct.byref(st), ct.byref(it)))
+        return {"samples": m.value, "steps": st.value, "gmres_iters": it.value}
+
+    def set_state(self, u_grid, v_grid, u_gamma, v_gamma):
+        g = (self.n + 1) ** 2
+        with self.ctx:
+            _check(_lib.kfbi_gs_set_state(self._h, _dptr(u_grid, "u_grid", g), _dptr(v_grid, "v_grid", g),
+                                          _dptr(u_gamma, "u_gamma", self.M), _dptr(v_gamma, "v_gamma", self.M)))
+
+    def state(self):
+        """``(u_grid, v_grid, u_gamma, v_gamma)`` as new device tensors."""
+        dev = f"cuda:{self.ctx.device}"
+        out = [torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev) for _ in range(2)]
+        out += [torch.empty(self.M, dtype=torch.float64, device=dev) for _ in range(2)]
+        with self.ctx:
+            _check(_lib.kfbi_gs_get_state(self._h, *[_dptr(t, "state") for t in out]))
+        return tuple(out)
+
+    def step(self, nsteps: int = 1):
+        with self.ctx:
+            _check(_lib.kfbi_gs_step(self._h, int(nsteps)))
 
 
 class Batch:

@@ -47,7 +47,7 @@ def test_status_strings():
 
 
 def test_struct_layouts_match_the_header(tmp_path):
-    """The binding's ctypes structs have the C layout of kfbi_desc, kfbi_tiles and kfbi_desc3."""
+    """The binding's ctypes structs have the C layout of kfbi_desc, kfbi_tiles, kfbi_desc3 and kfbi_gs_desc."""
     import shutil
     import subprocess
     cc = shutil.which("gcc") or shutil.which("cc")
@@ -69,13 +69,19 @@ def test_struct_layouts_match_the_header(tmp_path):
         '  printf("kfbi_desc3 size %zu\\n", sizeof(kfbi_desc3));\n'
         "  F(kfbi_desc3, n); F(kfbi_desc3, lo); F(kfbi_desc3, hi); F(kfbi_desc3, kappa); F(kfbi_desc3, axes);\n"
         "  F(kfbi_desc3, tol); F(kfbi_desc3, restart); F(kfbi_desc3, max_iter);\n"
+        '  printf("kfbi_gs_desc size %zu\\n", sizeof(kfbi_gs_desc));\n'
+        "  F(kfbi_gs_desc, lo); F(kfbi_gs_desc, hi); F(kfbi_gs_desc, n); F(kfbi_gs_desc, m); F(kfbi_gs_desc, xy);\n"
+        "  F(kfbi_gs_desc, gamma); F(kfbi_gs_desc, kill); F(kfbi_gs_desc, eps0); F(kfbi_gs_desc, eps1);\n"
+        "  F(kfbi_gs_desc, eps2); F(kfbi_gs_desc, dt); F(kfbi_gs_desc, tol); F(kfbi_gs_desc, restart);\n"
+        "  F(kfbi_gs_desc, max_iter);\n"
         "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     lines = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     _lib_path()
     from paper_2404_15249_amd import kfbi
-    structs = {"kfbi_desc": kfbi._Desc, "kfbi_tiles": kfbi.Tiles, "kfbi_desc3": kfbi._Desc3}
+    structs = {"kfbi_desc": kfbi._Desc, "kfbi_tiles": kfbi.Tiles, "kfbi_desc3": kfbi._Desc3,
+               "kfbi_gs_desc": kfbi._GsDesc}
     for line in filter(None, lines):
         name, field, value = line.split()
         st = structs[name]
