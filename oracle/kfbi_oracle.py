@@ -18,7 +18,8 @@ for PDEs on irregular domain", arXiv 2404.15249):
 * Alg. 1: jumps, correction of the 5-point system at irregular nodes (Alg. 2),
   fast solve (Alg. 4, here a DST-I on both axes: the same discrete system),
   interpolation to the boundary (Alg. 3).
-* Alg. 5: restarted GMRES on ``K_D phi = g - (Y f)^+``.
+* Alg. 5: restarted GMRES on ``K_D phi = g - (Y f)^+``; the Richardson
+  iteration of Sec. 2.1 and BiCGSTAB, the alternatives Table 2 compares.
 * The Neumann problem ``d_n u = g_n`` (Sec. 4 procedure, which extracts
   ``d_n u`` instead of ``u+``): the same interface problem with the density as
   the normal-derivative jump, ``K_N psi = d_n v+``, and GMRES on
@@ -574,6 +575,76 @@ def gmres(apply, b, tol=1e-10, restart=50, max_iter=500, x0=None):
 
 
 # ==========================================================================
+# the other outer iterations of Table 2: Richardson (Sec. 2.1) and BiCGSTAB
+# ==========================================================================
+
+def richardson(apply, b, gamma=1.0, tol=1e-10, max_iter=500, x0=None):
+    """The Richardson iteration of Sec. 2.1: ``x <- x + gamma (b - A x)``.
+
+    Stops when ``||b - A x|| / ||b - A x0|| < tol`` (the residual of the current
+    iterate, which the next update needs anyway).  Returns ``(x, iters, relres)``;
+    ``iters`` counts the updates made (each costs one apply).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply(x)
+    r0 = np.linalg.norm(r)
+    if r0 == 0.0:
+        return x, 0, 0.0
+    it = 0
+    rel = 1.0
+    while it < max_iter:
+        x = x + gamma * r
+        it += 1
+        r = b - apply(x)
+        rel = np.linalg.norm(r) / r0
+        if rel < tol:
+            break
+    return x, it, rel
+
+
+def bicgstab(apply, b, tol=1e-10, max_iter=500, x0=None):
+    """Unpreconditioned BiCGSTAB (van der Vorst, 1992), shadow residual ``r^ = r_0``.
+
+    Per iteration: ``v = A p``, ``alpha = rho / (r^ . v)``, ``s = r - alpha v``;
+    ``t = A s``, ``omega = (t . s) / (t . t)``, ``x += alpha p + omega s``,
+    ``r = s - omega t``, ``rho' = r^ . r``, ``p = r + (rho'/rho)(alpha/omega)(p - omega v)``.
+    Stops when the updated residual satisfies ``||r|| / ||r_0|| < tol``, or when
+    ``||s|| / ||r_0|| < tol`` half way (then ``x += alpha p`` only).  Returns
+    ``(x, iters, relres)`` with ``relres`` the true relative residual at exit and
+    ``iters`` the iterations begun (two applies each, one if it stopped half way).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    r = b - apply(x)
+    r0 = np.linalg.norm(r)
+    if r0 == 0.0:
+        return x, 0, 0.0
+    rhat = r.copy()
+    rho = float(rhat @ r)
+    p = r.copy()
+    it = 0
+    while it < max_iter:
+        it += 1
+        v = apply(p)
+        alpha = rho / float(rhat @ v)
+        s = r - alpha * v
+        if np.linalg.norm(s) / r0 < tol:
+            x = x + alpha * p
+            break
+        t = apply(s)
+        omega = float(t @ s) / float(t @ t)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        if np.linalg.norm(r) / r0 < tol:
+            break
+        rho_new = float(rhat @ r)
+        p = r + (rho_new / rho) * (alpha / omega) * (p - omega * v)
+        rho = rho_new
+    return x, it, np.linalg.norm(b - apply(x)) / r0
+
+
+# ==========================================================================
 # the Dirichlet boundary value problem (Sec. 2.1)
 # ==========================================================================
 
@@ -587,18 +658,29 @@ class Solution:
     plan: Plan
 
 
-def solve_bvp(xy, n, lo, hi, kappa, f_grid, f_gamma, g, tol=1e-10, restart=50, max_iter=500):
+def solve_bvp(xy, n, lo, hi, kappa, f_grid, f_gamma, g, tol=1e-10, restart=50, max_iter=500,
+              method="gmres", relax=1.0):
     """Solve ``Lap u - kappa u = f`` in Omega, ``u = g`` on Gamma by the KFBI method.
 
-    ``g^ = g - (Y f)^+``; GMRES solves ``K_D phi = g^``; the final interface solve
-    with ``[v] = phi`` and ``F = f~`` gives ``u = W phi + Y f`` on the grid.
+    ``g^ = g - (Y f)^+``; GMRES (or ``method`` = ``"bicgstab"``, or
+    ``"richardson"`` with ``gamma = relax``: Table 2's alternatives) solves
+    ``K_D phi = g^``; the final interface solve with ``[v] = phi`` and ``F = f~``
+    gives ``u = W phi + Y f`` on the grid.
     """
     plan = build_plan(xy, n, lo, hi)
     ft = zero_extension(plan, f_grid)
     zeros_m = np.zeros(plan.M)
     _, yf = interface_solve(plan, zeros_m, ft, f_gamma, kappa)
     ghat = np.asarray(g, dtype=np.float64) - yf
-    phi, it, rel = gmres(lambda p: apply_KD(plan, p, kappa), ghat, tol, restart, max_iter)
+    A = lambda p: apply_KD(plan, p, kappa)
+    if method == "gmres":
+        phi, it, rel = gmres(A, ghat, tol, restart, max_iter)
+    elif method == "bicgstab":
+        phi, it, rel = bicgstab(A, ghat, tol, max_iter)
+    elif method == "richardson":
+        phi, it, rel = richardson(A, ghat, relax, tol, max_iter)
+    else:
+        raise ValueError(f"unknown method {method!r}")
     v, ug = interface_solve(plan, phi, ft, f_gamma, kappa)
     u = np.where(plan.inside, v, 0.0)
     return Solution(u, ug, phi, it, rel, plan)
