@@ -160,6 +160,37 @@ kfbi_status kfbi_solve(kfbi_prob* prob, const double* f_grid, const double* f_ga
 kfbi_status kfbi_gmres(kfbi_prob* prob, const double* rhs, double* phi, double tol, int max_iter,
                        int* iters, int* applies, double* rel_res);
 
+/* ---------------------------------------------------------------- other outer iterations (Table 2) */
+/* The paper compares GMRES with the Richardson iteration of Sec. 2.1 and with
+ * BiCGSTAB on the same boundary equation (Table 2).  Both run device resident
+ * on the K_D apply of kfbi_apply, with GMRES's stopping rule: the relative
+ * residual |rhs - K_D x| / |rhs - K_D x0| below tol, or max_iter reached.
+ * rhs: device M; phi: device M, initial guess in, iterate out.  Host outputs
+ * may be NULL.  Synchronise; KFBI_NOT_CONVERGED at the cap. */
+
+/* x <- x + gamma (rhs - K_D x) (Sec. 2.1; the paper shows convergence for
+ * gamma in (0, 1]).  iters: updates made (one K_D apply each, plus the initial
+ * residual); rel_res: the relative residual of the final iterate. */
+kfbi_status kfbi_richardson(kfbi_prob* prob, const double* rhs, double* phi, double gamma, double tol,
+                            int max_iter, int* iters, double* rel_res);
+
+/* Unpreconditioned BiCGSTAB (van der Vorst), shadow residual r0.  iters:
+ * iterations begun; applies: all K_D applications; rel_res: the true relative
+ * residual of the final iterate. */
+kfbi_status kfbi_bicgstab(kfbi_prob* prob, const double* rhs, double* phi, double tol, int max_iter,
+                          int* iters, int* applies, double* rel_res);
+
+#define KFBI_GMRES 0
+#define KFBI_BICGSTAB 1
+#define KFBI_RICHARDSON 2
+
+/* kfbi_solve with the outer iteration chosen: KFBI_GMRES (exactly kfbi_solve),
+ * KFBI_BICGSTAB or KFBI_RICHARDSON (relax = gamma), with the problem's
+ * tolerance and cap.  iters as the chosen method reports them. */
+kfbi_status kfbi_solve_method(kfbi_prob* prob, int method, double relax, const double* f_grid,
+                              const double* f_gamma, const double* g, double* u_grid, double* u_gamma,
+                              double* phi, int* iters, double* rel_res);
+
 /* ---------------------------------------------------------------- the Neumann problem */
 /* The paper names the Neumann problem (its Sec. 4 procedure extracts d_n u in
  * place of u+) without stating its form.  Here the density psi is the jump of

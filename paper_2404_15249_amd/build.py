@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libkfbi.so")
-SOURCES = ["plan.cpp", "plan3.cpp", "kernels.hip", "batch.hip", "dst.hip", "k3.hip", "api.hip", "api3.hip", "gs.hip"]
+SOURCES = ["plan.cpp", "plan3.cpp", "kernels.hip", "batch.hip", "dst.hip", "k3.hip", "api.hip", "api3.hip", "gs.hip", "krylov.hip"]
 ARCH = "gfx950"
 
 

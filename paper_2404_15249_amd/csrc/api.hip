@@ -78,6 +78,11 @@ struct kfbi_prob {
     static constexpr int kGraphSteps = 8;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     bool graph_failed[2] = {false, false};
+    // Richardson and BiCGSTAB (Table 2's alternatives): vectors, state, and a
+    // graph of a batch of iterations for each
+    IterBufs ib{};
+    hipGraphExec_t iexec[2] = {nullptr, nullptr};
+    bool iexec_failed[2] = {false, false};
 };
 
 namespace {
@@ -113,6 +118,10 @@ void free_prob(kfbi_prob* p) {
         if (e) hipEventDestroy(e);
     p->ev.clear();
     for (auto& g : p->gexec) {
+        if (g) hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+    for (auto& g : p->iexec) {
         if (g) hipGraphExecDestroy(g);
         g = nullptr;
     }
@@ -338,6 +347,97 @@ kfbi_status gmres_call(kfbi_prob* p, int op, const double* rhs, double* x, doubl
     if (rel_res) *rel_res = st.relres;
     if (st.converged == 1) return KFBI_OK;
     return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
+}
+
+// ---------------------------------------------------------------- Richardson and BiCGSTAB
+
+enum IterMethod { kRich = 0, kBicg = 1 };
+constexpr int kIterBatch[2] = {8, 4};   // iterations per replayed batch (8 applies each)
+
+// One K_D apply of `in` into ib.w (spline, correction, sparse solve, reduction),
+// skipped once the run is done.
+kfbi_status iter_apply(kfbi_prob* p, const double* in, const int* skip, hipStream_t s) {
+    HIP_TRY(launch_spline(p->dp, in, p->ib.s2, skip, s));
+    return sparse_apply(p, kOpD, in, p->ib.s2, p->ib.w, skip, nullptr, s);
+}
+
+kfbi_status enqueue_iters(kfbi_prob* p, int method, int n, hipStream_t s) {
+    const IterBufs& B = p->ib;
+    const int* skip = &B.st->done;
+    for (int k = 0; k < n; ++k) {
+        if (method == kRich) {
+            if (kfbi_status e = iter_apply(p, B.x, skip, s)) return e;
+            HIP_TRY(launch_iter_step(kIterRich, B, s));
+        } else {
+            if (kfbi_status e = iter_apply(p, B.q, skip, s)) return e;
+            HIP_TRY(launch_iter_step(kIterBicgHalf, B, s));
+            if (kfbi_status e = iter_apply(p, B.q, skip, s)) return e;
+            HIP_TRY(launch_iter_step(kIterBicgFull, B, s));
+        }
+    }
+    return KFBI_OK;
+}
+
+// Richardson (x <- x + gamma (b - K_D x)) or BiCGSTAB on K_D x = rhs from the
+// initial guess in x; same stopping rule as GMRES (relative to the initial
+// residual).  Batches of iterations are replayed from a graph; the host polls
+// the device state between batches.
+kfbi_status run_iters(kfbi_prob* p, int method, const double* rhs, double* x, double gamma, double tol, int max_iter,
+                      IterState* out) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status e = check_ptr(rhs, "rhs")) return e;
+    if (kfbi_status e = check_ptr(x, "x")) return e;
+    if (max_iter <= 0) return set_err(KFBI_ERR_ARG, "max_iter must be positive");
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    const IterBufs& B = p->ib;
+    const int M = p->M;
+    const bool timing = p->timing;
+    p->timing = false;                      // the per-stage events belong to GMRES steps
+    struct Restore {
+        kfbi_prob* p;
+        bool t;
+        ~Restore() { p->timing = t; }
+    } restore{p, timing};
+    HIP_TRY(hipMemcpyAsync(B.b, rhs, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(B.x, x, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    static thread_local IterState st0;
+    st0 = IterState{};
+    st0.max_iter = max_iter;
+    st0.tol = tol;
+    st0.gamma = gamma;
+    HIP_TRY(hipMemcpyAsync(B.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
+    if (method == kBicg) {                  // r0 = b - K x0, r^ = p = r0
+        if (kfbi_status e = iter_apply(p, B.x, &B.st->done, s)) return e;
+        HIP_TRY(launch_iter_step(kIterBicgInit, B, s));
+    }
+    if (!p->iexec[method] && !p->iexec_failed[method])
+        p->iexec_failed[method] = !record_graph(s, &p->iexec[method], [&](hipStream_t gs) {
+            return enqueue_iters(p, method, kIterBatch[method], gs);
+        });
+    const int nb = kIterBatch[method];
+    const int batches = (max_iter + 1) / nb + 2;
+    IterState st{};
+    for (int b = 0; b < batches; ++b) {
+        if (p->iexec[method]) {
+            HIP_TRY(hipGraphLaunch(p->iexec[method], s));
+        } else if (kfbi_status e = enqueue_iters(p, method, nb, s)) {
+            return e;
+        }
+        HIP_TRY(hipMemcpyAsync(&st0, B.st, sizeof st0, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        st = st0;
+        if (st.done) break;
+    }
+    if (method == kBicg) {                  // the true residual of the final iterate
+        if (kfbi_status e = iter_apply(p, B.x, nullptr, s)) return e;
+        HIP_TRY(launch_iter_step(kIterTrueRes, B, s));
+        HIP_TRY(hipMemcpyAsync(&st0, B.st, sizeof st0, hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipMemcpyAsync(x, B.x, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = st0;
+    return KFBI_OK;
 }
 
 }  // namespace
@@ -655,6 +755,14 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = dev_alloc(p, &p->gm.y, m + 1)) || (st = dev_alloc(p, &p->gm.st, 1)) ||
         (st = dev_alloc(p, &p->gm.cnt, 1)))
         return fail(st);
+    {
+        IterBufs& ib = p->ib;
+        double** vecs[] = {&ib.b, &ib.x, &ib.r, &ib.rhat, &ib.p, &ib.v, &ib.s, &ib.q, &ib.w, &ib.s2};
+        for (double** v : vecs)
+            if ((st = dev_alloc(p, v, M))) return fail(st);
+        if ((st = dev_alloc(p, &ib.st, 1))) return fail(st);
+        ib.M = M;
+    }
     HIP_TRY(hipMemset(p->gm.cnt, 0, sizeof(unsigned)));
     if (p->precision == KFBI_FP32_REFINED && (st = dev_alloc(p, &p->X32, (size_t)n * n))) return fail(st);
     if (p->refine >= 2 && (st = dev_alloc(p, &p->D, (size_t)n * n))) return fail(st);
@@ -806,6 +914,58 @@ kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma
 kfbi_status kfbi_gmres(kfbi_prob* p, const double* rhs, double* phi, double tol, int max_iter, int* iters,
                        int* applies, double* rel_res) {
     return gmres_call(p, kOpD, rhs, phi, tol, max_iter, iters, applies, rel_res);
+}
+
+kfbi_status kfbi_richardson(kfbi_prob* p, const double* rhs, double* phi, double gamma, double tol, int max_iter,
+                           int* iters, double* rel_res) {
+    if (!(gamma > 0.0)) return set_err(KFBI_ERR_ARG, "gamma must be positive");
+    IterState st{};
+    if (kfbi_status e = run_iters(p, kRich, rhs, phi, gamma, tol, max_iter, &st)) return e;
+    if (iters) *iters = st.it;
+    if (rel_res) *rel_res = st.relres;
+    if (st.done == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "Richardson reached the iteration cap");
+}
+
+kfbi_status kfbi_bicgstab(kfbi_prob* p, const double* rhs, double* phi, double tol, int max_iter, int* iters,
+                          int* applies, double* rel_res) {
+    IterState st{};
+    if (kfbi_status e = run_iters(p, kBicg, rhs, phi, 0.0, tol, max_iter, &st)) return e;
+    if (iters) *iters = st.it;
+    // the initial residual, two per iteration (one in a half-way stop), the final true residual
+    if (applies) *applies = 2 + 2 * st.it - st.half;
+    if (rel_res) *rel_res = st.relres;
+    if (st.done == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "BiCGSTAB reached the iteration cap");
+}
+
+kfbi_status kfbi_solve_method(kfbi_prob* p, int method, double relax, const double* f_grid, const double* f_gamma,
+                              const double* g, double* u_grid, double* u_gamma, double* phi, int* iters,
+                              double* rel_res) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (method == KFBI_GMRES) return kfbi_solve(p, f_grid, f_gamma, g, u_grid, u_gamma, phi, iters, rel_res);
+    if (method != KFBI_BICGSTAB && method != KFBI_RICHARDSON) return set_err(KFBI_ERR_ARG, "unknown method");
+    if (method == KFBI_RICHARDSON && !(relax > 0.0)) return set_err(KFBI_ERR_ARG, "relax must be positive");
+    for (auto [ptr, name] : {std::pair<const void*, const char*>{f_grid, "f_grid"}, {f_gamma, "f_gamma"}, {g, "g"},
+                             {u_grid, "u_grid"}, {u_gamma, "u_gamma"}, {phi, "phi"}})
+        if (kfbi_status s = check_ptr(ptr, name)) return s;
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    hipStream_t s = p->ctx->stream;
+    const int M = p->M;
+    JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, false, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
+    HIP_TRY(launch_axpby(M, 1.0, g, -1.0, p->tmpM, p->tmpM, s));
+    IterState st{};
+    if (kfbi_status e = run_iters(p, method == KFBI_BICGSTAB ? kBicg : kRich, p->tmpM, phi, relax, p->tol,
+                                  p->max_iter, &st))
+        return e;
+    JumpSrc jf{phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, false, jf, f_grid, true, u_grid, true, u_gamma)) return e;
+    HIP_TRY(hipStreamSynchronize(s));
+    if (iters) *iters = st.it;
+    if (rel_res) *rel_res = st.relres;
+    if (st.done == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "the iteration reached its cap");
 }
 
 kfbi_status kfbi_apply_neumann(kfbi_prob* p, const double* psi, double* out) {

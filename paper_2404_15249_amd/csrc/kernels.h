@@ -135,6 +135,32 @@ struct GmresBufs {
     int gc64;        // chunks of 64 samples (the first Gram-Schmidt pass)
 };
 
+// State of a Richardson or BiCGSTAB run (krylov.hip), in device memory.
+struct IterState {
+    int it;          // Richardson: updates made; BiCGSTAB: iterations begun
+    int done;        // 0 running, 1 converged, -1 iteration cap (launches skip while nonzero)
+    int max_iter;
+    int started;     // 1 once r0 is known
+    int half;        // BiCGSTAB: 1 if it stopped half way through an iteration (one apply short)
+    int pad;
+    double tol, r0, relres;
+    double rho, alpha, omega;
+    double gamma;    // Richardson relaxation
+};
+
+// Vectors of a Richardson or BiCGSTAB run (M doubles each).  The apply reads q
+// (BiCGSTAB) or x (Richardson) and writes w.
+struct IterBufs {
+    double *b, *x, *r, *rhat, *p, *v, *s, *q, *w, *s2;
+    IterState* st;
+    int M;
+};
+
+constexpr int kIterRich = 0, kIterBicgInit = 1, kIterBicgHalf = 2, kIterBicgFull = 3, kIterTrueRes = 4;
+
+// One single-workgroup step of the iterations (krylov.hip): which = kIter*.
+hipError_t launch_iter_step(int which, const IterBufs& B, hipStream_t s);
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_correct(const DevPlan& p, JumpSrc js, double* corr, double* corr_il, double* dense,
                           const int* skip, hipStream_t s);

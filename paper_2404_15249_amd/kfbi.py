@@ -87,6 +87,12 @@ _sigs = {
     "kfbi_fast_solve": [_vp, _vp, _vp],
     "kfbi_interface_solve": [_vp, _vp, _vp, _vp, _vp, _vp],
     "kfbi_interface_solve_jumps": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "kfbi_richardson": [_vp, _vp, _vp, ct.c_double, ct.c_double, ct.c_int, ct.POINTER(ct.c_int),
+                        ct.POINTER(ct.c_double)],
+    "kfbi_bicgstab": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
+                      ct.POINTER(ct.c_double)],
+    "kfbi_solve_method": [_vp, ct.c_int, ct.c_double, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int),
+                          ct.POINTER(ct.c_double)],
     "kfbi_apply_neumann": [_vp, _vp, _vp],
     "kfbi_interface_solve_neumann": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "kfbi_gmres_neumann": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
@@ -316,6 +322,48 @@ class Problem:
                                         int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
                         allow=(OK, NOT_CONVERGED))
         return phi, it.value, ap.value, rel.value, st == OK
+
+    # ---- Table 2's other outer iterations
+    def richardson(self, rhs, phi0=None, gamma=1.0, tol=1e-10, max_iter=500):
+        """``x <- x + gamma (rhs - K_D x)``; returns ``(phi, iters, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, rel = ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi_richardson(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M),
+                                             float(gamma), float(tol), int(max_iter), ct.byref(it), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return phi, it.value, rel.value, st == OK
+
+    def bicgstab(self, rhs, phi0=None, tol=1e-10, max_iter=500):
+        """BiCGSTAB on ``K_D phi = rhs``; returns ``(phi, iters, applies, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, ap, rel = ct.c_int(), ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi_bicgstab(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M),
+                                           float(tol), int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return phi, it.value, ap.value, rel.value, st == OK
+
+    METHODS = {"gmres": 0, "bicgstab": 1, "richardson": 2}
+
+    def solve_method(self, method, f_grid, f_gamma, g, phi0=None, relax=1.0):
+        """Dirichlet solve with ``method`` in ``gmres``/``bicgstab``/``richardson``;
+        returns ``(u_grid, u_gamma, phi, iters, relres, converged)``."""
+        dev = f"cuda:{self.ctx.device}"
+        u = torch.empty((self.n + 1, self.n + 1), dtype=torch.float64, device=dev)
+        ug = torch.empty(self.M, dtype=torch.float64, device=dev)
+        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        it, rel = ct.c_int(), ct.c_double()
+        with self.ctx:
+            st = _check(_lib.kfbi_solve_method(self._h, self.METHODS[method], float(relax),
+                                               _dptr(f_grid, "f_grid", self.grid_numel),
+                                               _dptr(f_gamma, "f_gamma", self.M), _dptr(g, "g", self.M),
+                                               _dptr(u, "u_grid"), _dptr(ug, "u_gamma"), _dptr(phi, "phi"),
+                                               ct.byref(it), ct.byref(rel)),
+                        allow=(OK, NOT_CONVERGED))
+        return u, ug, phi, it.value, rel.value, st == OK
 
     # ---- the Neumann problem
     def apply_neumann(self, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:

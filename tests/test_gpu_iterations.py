@@ -1,0 +1,132 @@
+"""GPU parity of Table 2's other outer iterations, Richardson (Sec. 2.1) and
+BiCGSTAB, on the library's K_D apply against the oracle's: the iterate after a
+fixed number of iterations, runs to tolerance with their iteration counts, and
+full Dirichlet solves of the paper's Example 1 with each method."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import kfbi_oracle as O
+
+pytestmark = pytest.mark.gpu
+
+LO, HI = synth.BOX_LO, synth.BOX_HI
+
+
+@pytest.fixture(scope="module")
+def K():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_15249_amd import kfbi
+    return kfbi
+
+
+@pytest.fixture(scope="module")
+def ctx(K):
+    return K.Context(0)
+
+
+def dev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda:0")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def relerr(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+CASES = {
+    "circle64": lambda: synth.circle_problem(n=64, m=128),
+    "star512": lambda: synth.star_problem(n=512, kappa=1.0),
+    "star2048": lambda: synth.star_problem(n=2048, kappa=1.0),
+}
+_plans = {}
+
+
+def setup(K, ctx, name):
+    p = CASES[name]()
+    if name not in _plans:
+        _plans[name] = O.build_plan(p.xy, p.n, LO, HI)
+    plan = _plans[name]
+    prob = K.Problem(ctx, p.xy, p.n, p.kappa)
+    return p, plan, prob, (lambda v: O.apply_KD(plan, v, p.kappa))
+
+
+@pytest.mark.parametrize("name", ["circle64", "star512"])
+@pytest.mark.parametrize("k", [1, 3])
+def test_bicgstab_iterate_after_k_iterations(K, ctx, name, k):
+    p, plan, prob, A = setup(K, ctx, name)
+    note(f"BiCGSTAB {k} iterations {name}")
+    b = synth.smooth_density(plan.M, 41)
+    x, it, ap, rel, conv = prob.bicgstab(dev(b), tol=0.0, max_iter=k)
+    ref, rit, rrel = O.bicgstab(A, b, tol=0.0, max_iter=k)
+    assert it == rit == k and not conv and ap == 2 + 2 * k
+    assert relerr(host(x), ref) < 1e-11
+    assert abs(rel - rrel) < 1e-9 * max(rrel, 1e-3)
+
+
+@pytest.mark.parametrize("name", ["circle64", "star512"])
+@pytest.mark.parametrize("gamma,k", [(1.0, 4), (0.7, 6)])
+def test_richardson_iterate_after_k_updates(K, ctx, name, gamma, k):
+    p, plan, prob, A = setup(K, ctx, name)
+    note(f"Richardson gamma={gamma} {k} updates {name}")
+    b = synth.smooth_density(plan.M, 42)
+    x, it, rel, conv = prob.richardson(dev(b), gamma=gamma, tol=0.0, max_iter=k)
+    ref, rit, rrel = O.richardson(A, b, gamma, tol=0.0, max_iter=k)
+    assert it == rit == k and not conv
+    assert relerr(host(x), ref) < 1e-11
+    assert abs(rel - rrel) < 1e-9 * rrel
+
+
+@pytest.mark.parametrize("name", ["circle64", "star512", "star2048"])
+def test_iterations_to_tolerance_match_the_oracle(K, ctx, name):
+    p, plan, prob, A = setup(K, ctx, name)
+    b = p.g
+    x, it, ap, rel, conv = prob.bicgstab(dev(b), tol=1e-12)
+    ref, rit, rrel = O.bicgstab(A, b, tol=1e-12)
+    note(f"BiCGSTAB {name}: gpu {it} its / {ap} applies ({rel:.2e}), oracle {rit} ({rrel:.2e})")
+    assert conv and it == rit and rel < 1e-11
+    assert relerr(host(x), ref) < 1e-10
+    x, it, rel, conv = prob.richardson(dev(b), gamma=1.0, tol=1e-12, max_iter=400)
+    ref, rit, rrel = O.richardson(A, b, 1.0, tol=1e-12, max_iter=400)
+    note(f"Richardson {name}: gpu {it} ({rel:.2e}), oracle {rit} ({rrel:.2e})")
+    assert conv and abs(it - rit) <= 1 and rel < 1e-12
+    assert relerr(host(x), ref) < 1e-10
+
+
+@pytest.mark.parametrize("method", ["gmres", "bicgstab", "richardson"])
+def test_solve_with_each_method_matches_the_oracle(K, ctx, method):
+    """Example 1: Laplace on the circle r = 1 in (-1.2, 1.2)^2, u = e^x cos y + e^y sin x."""
+    n = 512
+    p = synth.make_problem("circle r=1", synth.circle_points(n // 2, 1.0), n, 0.0, synth.PAPER_EX1)
+    note(f"Example 1 solve with {method}")
+    prob = K.Problem(ctx, p.xy, p.n, 0.0, tol=1e-12)
+    u, ug, phi, it, rel, conv = prob.solve_method(method, dev(p.f_grid), dev(p.f_gamma), dev(p.g))
+    ref = O.solve_bvp(p.xy, p.n, LO, HI, 0.0, p.f_grid, p.f_gamma, p.g, tol=1e-12, method=method)
+    note(f"  iters gpu {it} oracle {ref.iters}")
+    assert conv and abs(it - ref.iters) <= 1
+    assert relerr(host(u), ref.u_grid) < 1e-10
+    assert relerr(host(ug), ref.u_gamma) < 1e-10
+
+
+def test_bad_arguments_are_refused(K, ctx):
+    p, plan, prob, A = setup(K, ctx, "circle64")
+    b = dev(p.g)
+    with pytest.raises(K.KfbiError):
+        prob.richardson(b, gamma=0.0)
+    with pytest.raises(K.KfbiError):
+        prob.bicgstab(b, max_iter=0)
