@@ -309,6 +309,49 @@ def neumann(ctx, n: int = 2048, steps: int = 400, sizes=(512, 1024, 2048)) -> di
     return res
 
 
+# Table 2: the paper's GPU times in seconds of the Example 1 solve with each
+# outer iteration, on its own machine (context only)
+PAPER_ITER_GPU_S = {"richardson": {512: 0.19, 1024: 0.27, 2048: 0.66, 4096: 1.65},
+                    "gmres": {512: 0.13, 1024: 0.16, 2048: 0.18, 4096: 0.25},
+                    "bicgstab": {512: 0.45, 1024: 0.45, 2048: 0.63, 4096: 1.01}}
+
+
+def iterations(ctx, sizes=(512, 1024, 2048, 4096)) -> dict:
+    """Table 2: the Dirichlet problem of Example 1 (Laplace on the circle r = 1 in
+    (-1.2, 1.2)^2, u = e^x cos y + e^y sin x, M = n samples) solved with GMRES,
+    BiCGSTAB and Richardson (gamma = 1) to the paper's tolerance 1e-8: the time
+    of one full solve (volume potential, iteration, final solve) and the
+    iteration counts."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    rows = []
+    for n in sizes:
+        p = synth.make_problem(f"circle r=1 n={n}", synth.circle_points(n, 1.0), n, 0.0, synth.PAPER_EX1)
+        prob = kfbi.Problem(ctx, p.xy, p.n, 0.0, tol=1e-8)
+        args = (dev(p.f_grid), dev(p.f_gamma), dev(p.g))
+        c = p.lo + np.arange(n + 1) * p.h
+        X, Y = np.meshgrid(c, c, indexing="xy")
+        exact = p.exact.u(X, Y)
+        mask = prob.mask()
+        for method in ("gmres", "bicgstab", "richardson"):
+            prob.solve_method(method, *args)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, ug, phi, it, rel, conv = prob.solve_method(method, *args)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0)
+            rows.append({"n": n, "method": method, "solve_ms": ms, "iters": it, "relres": rel, "converged": conv,
+                         "linf_err": float(np.max(np.abs(u.cpu().numpy() - exact)[mask])),
+                         "paper_gpu_s": PAPER_ITER_GPU_S[method][n]})
+        prob.close()
+    return {"workload": "Example 1: Laplace on the circle r=1 in (-1.2,1.2)^2, u=e^x cos y+e^y sin x, M=n, "
+                        "tol 1e-8; iters: GMRES and Richardson count K_D applies, BiCGSTAB its iterations "
+                        "(two applies each); paper_gpu_s is the paper's own machine (context)",
+            "rows": rows}
+
+
 # Table of Example 3 (Neumann row): the paper's GPU times in seconds on its own
 # machine, for context only
 PAPER_GS_GPU_S = {128: 0.40, 256: 1.04, 512: 3.29, 1024: 12.07}
@@ -422,13 +465,15 @@ def main():
     ap.add_argument("--three-d", choices=["on", "off"], default="on")
     ap.add_argument("--neumann", choices=["on", "off"], default="on")
     ap.add_argument("--gray-scott", choices=["on", "off"], default="on")
+    ap.add_argument("--iterations", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
-    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann", "gray_scott"], default="apply",
+    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann", "gray_scott", "iterations"],
+                    default="apply",
                     help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "
                          "copy: a 256 MiB device copy to calibrate the HBM byte counters; "
                          "3d: only the ellipsoid section; neumann: only the Neumann section; "
-                         "gray_scott: only the Gray-Scott section")
+                         "gray_scott: only the Gray-Scott section; iterations: only Table 2's comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the KFBI path here has no multi-GPU mode "
@@ -455,6 +500,9 @@ def main():
         return
     if args.mode == "gray_scott":
         print(json.dumps(gray_scott(ctx)), flush=True)
+        return
+    if args.mode == "iterations":
+        print(json.dumps(iterations(ctx)), flush=True)
         return
     if args.mode == "serving":
         print(json.dumps(serving_line(ctx, args)), flush=True)
@@ -558,6 +606,8 @@ def main():
         out["neumann"] = neumann(ctx, args.n)
     if args.gray_scott == "on":
         out["gray_scott"] = gray_scott(ctx)
+    if args.iterations == "on":
+        out["iterations"] = iterations(ctx)
     if args.serving_requests > 0:
         out["serving"] = serving(ctx, args.serving_requests, args.serving_seed)
     if args.cpu_baseline == "on":
