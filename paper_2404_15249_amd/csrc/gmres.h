@@ -137,9 +137,30 @@ __device__ __forceinline__ void gm_chunk_dots(const double (&v)[4][16], double x
     }
 }
 
+// The basis values the first pass needs from this wavefront (V_i at its lane's
+// sample for i = wave, wave + 16, ...; kMaxRestart <= 64), requested before the
+// apply's reduction so that their latency overlaps it.
+struct GmPre {
+    double v[4];
+};
+__device__ __forceinline__ GmPre gm_dots1_prefetch(const GmresBufs& b, int M, int c64) {
+    static_assert(kMaxRestart <= 64, "four basis values per lane");
+    GmPre pre;
+    const GmresState* st = b.st;
+    const int mode = st->mode, j = st->j;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, cp = c64 * 64 + lane;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = wave + 16 * k;
+        pre.v[k] = (mode == 1 && i <= j && cp < M) ? b.V[(size_t)i * M + cp] : 0.0;
+    }
+    return pre;
+}
+
 // First step of GMRES on samples c64 * 64 .. + 63, called by a workgroup of 16
-// wavefronts right after it computed w there (wv[lane] in LDS).
-__device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const double* wv) {
+// wavefronts right after it computed w there (wv[lane] in LDS); pre: the basis
+// values from gm_dots1_prefetch (null: loaded here).
+__device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const double* wv, const GmPre* pre = nullptr) {
     const GmresState* st = b.st;
     const int mode = st->mode;
     if (mode == 2) return;
@@ -160,6 +181,17 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
     }
     const int j = st->j, gc64 = b.gc64;
     const double x = cp < M ? wv[lane] : 0.0;
+    if (pre) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int i = wave + 16 * k;
+            if (i <= j) {
+                const double s = wave_sum(cp < M ? pre->v[k] * x : 0.0);
+                if (lane == 0) q.d1[(size_t)i * gc64 + c64] = s;
+            }
+        }
+        return;
+    }
     for (int i = wave; i <= j; i += 16) {
         const double s = wave_sum(cp < M ? b.V[(size_t)i * M + cp] * x : 0.0);
         if (lane == 0) q.d1[(size_t)i * gc64 + c64] = s;
@@ -178,6 +210,12 @@ __device__ __forceinline__ const double* gm_update(const GmresBufs& b, int M, in
     const GmPart q = gm_part(b);
     const double* coef = pass == 0 ? q.d1 : q.d2;
     const int nco = pass == 0 ? b.gc64 : gc;
+    // the basis and vector loads first, then the coefficient partials: all in
+    // flight together, one memory round trip
+    const int e = c * kGmChunk + tid;
+    double v[4][16];
+    gm_load_basis(b.V, M, e, j, v);
+    double a = e < M ? (pass == 0 ? b.w[e] : b.z[e]) : 0.0;
     for (int i = tid; i <= j; i += kGmChunk) {
         double s = 0.0;
 #pragma unroll 16
@@ -185,10 +223,6 @@ __device__ __forceinline__ const double* gm_update(const GmresBufs& b, int M, in
         hs[i] = s;
         if (pass == 0 && c == 0) q.h1[i] = s;
     }
-    const int e = c * kGmChunk + tid;
-    double v[4][16];
-    gm_load_basis(b.V, M, e, j, v);
-    double a = e < M ? (pass == 0 ? b.w[e] : b.z[e]) : 0.0;
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -396,17 +430,30 @@ __device__ __forceinline__ double gm_spline_s2(const double* __restrict__ taps, 
 }
 
 __device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs& b, int M, int c) {
-    __shared__ double win[kGmChunk + 2 * kGmHalo];
+    constexpr int W = kGmChunk + 2 * kGmHalo;
+    __shared__ double win[W];
+    const int tid = threadIdx.x, c0 = c * kGmChunk;
+    // z at this thread's window places is requested before the state is read:
+    // it is the next input (scaled) unless the cycle has just ended
+    int ek[2];
+    double zk[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int k = tid + r * kGmChunk;
+        int e = (c0 - kGmHalo + k) % M;
+        if (e < 0) e += M;
+        ek[r] = e;
+        zk[r] = k < W ? b.z[e] : 0.0;
+    }
     const GmresState* st = b.st;
     const int kind = st->kind;
     if (kind == kGmDone) return;
-    const int tid = threadIdx.x, c0 = c * kGmChunk;
     const double scale = st->scale;
     const int jn = st->jn;
-    for (int k = tid; k < kGmChunk + 2 * kGmHalo; k += kGmChunk) {
-        int e = (c0 - kGmHalo + k) % M;
-        if (e < 0) e += M;
-        win[k] = gm_next_x(b, M, kind, scale, jn, e);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int k = tid + r * kGmChunk;
+        if (k < W) win[k] = kind == kGmCycleEnd ? gm_next_x(b, M, kind, scale, jn, ek[r]) : zk[r] * scale;
     }
     __syncthreads();
     const int e = c0 + tid;
@@ -430,7 +477,12 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
     __shared__ double sw[kCorrWindow];
     const int M = p.M, tid = threadIdx.x;
     const int4 ch = p.cc_chunk[cc];                      // first, end, first knot, width
-    // the node's plan data first, so that its loads overlap the window's
+    // z at the thread's window place is requested before anything else: it is
+    // the next input (scaled) unless the cycle has just ended
+    static_assert(kCorrWindow <= kGmChunk, "one window place per thread");
+    const int ew = (ch.z + tid) % M;
+    const double zw = tid < ch.w ? b.z[ew] : 0.0;
+    // the node's plan data next, so that its loads overlap the window's
     const int at = ch.x + tid;
     const bool act = at < ch.y;
     int4 arm = make_int4(-1, -1, -1, -1);
@@ -462,7 +514,7 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
     if (kind == kGmDone) return;
     const double scale = st->scale;
     const int jn = st->jn;
-    for (int w = tid; w < ch.w; w += kGmChunk) xw[w] = gm_next_x(b, M, kind, scale, jn, (ch.z + w) % M);
+    if (tid < ch.w) xw[tid] = kind == kGmCycleEnd ? gm_next_x(b, M, kind, scale, jn, ew) : zw * scale;
     __syncthreads();
     for (int w = kGmHalo + tid; w < ch.w - kGmHalo; w += kGmChunk) sw[w] = gm_spline_s2(p.taps, xw, w);
     __syncthreads();

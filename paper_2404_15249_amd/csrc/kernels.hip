@@ -172,8 +172,9 @@ __global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const
                                                     GmresBufs b) {
     __shared__ double red[16 * 64];
     if (b.st->converged) return;
+    const GmPre pre = gm_dots1_prefetch(b, p.M, blockIdx.x);
     reduce_samples64(p, js, partial, G, blockIdx.x * 64, b.w, red);
-    gm_dots1_64(b, p.M, blockIdx.x, red);
+    gm_dots1_64(b, p.M, blockIdx.x, red, &pre);
 }
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 0); }
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_update2_commit(b, M, blockIdx.x); }
