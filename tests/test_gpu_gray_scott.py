@@ -135,6 +135,20 @@ def test_gray_scott_state_is_mirror_symmetric_at_1024(K, ctx):
     assert v.min() > -1e-12 and v.max() < 1.0
 
 
+def test_gray_scott_zero_steps_keep_the_state(K, ctx):
+    n = 128
+    xy = synth.gray_scott_samples(n)
+    gs = K.GrayScott(ctx, xy, n, 0.125, lo=LO, hi=HI)
+    init = gpu_initial(K, ctx, xy, n, synth.gray_scott_initial)
+    gs.set_state(*init)
+    gs.step(0)
+    out = gs.state()
+    assert gs.info()["steps"] == 0
+    for a, b in zip(out, init):
+        assert np.array_equal(host(a), host(b))
+    gs.close()
+
+
 def test_gray_scott_rejects_bad_parameters(K, ctx):
     xy = synth.gray_scott_samples(128)
     for kw in ({"dt": 0.0}, {"dt": 0.1, "eps1": 0.0}, {"dt": 0.1, "eps0": -1.0}):

@@ -123,6 +123,17 @@ def test_solve_with_each_method_matches_the_oracle(K, ctx, method):
     assert relerr(host(ug), ref.u_gamma) < 1e-10
 
 
+def test_richardson_outside_the_contraction_range_reports_no_convergence(K, ctx):
+    """gamma = 3 makes I - gamma K_D expanding: the run ends at the cap, reports
+    KFBI_NOT_CONVERGED, and its iterate is still the oracle's."""
+    p, plan, prob, A = setup(K, ctx, "circle64")
+    b = p.g
+    x, it, rel, conv = prob.richardson(dev(b), gamma=3.0, tol=1e-10, max_iter=12)
+    ref, rit, rrel = O.richardson(A, b, 3.0, tol=1e-10, max_iter=12)
+    assert not conv and it == rit == 12 and rel > 1.0
+    assert relerr(host(x), ref) < 1e-10
+
+
 def test_bad_arguments_are_refused(K, ctx):
     p, plan, prob, A = setup(K, ctx, "circle64")
     b = dev(p.g)

@@ -90,6 +90,16 @@ def test_apply_neumann_matches_oracle(K, ctx, name):
         assert relerr(got, ref) < dn_tol(p.n), seed
 
 
+def test_apply_neumann_at_the_largest_grid(K, ctx):
+    """4096^2 (the largest grid the library takes), 2048 samples."""
+    p = synth.star_neumann_problem(n=4096, kappa=1.0)
+    note("K_N apply parity star4096")
+    prob = K.Problem(ctx, p.xy, p.n, p.kappa)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    psi = synth.smooth_density(plan.M, 8)
+    assert relerr(host(prob.apply_neumann(dev(psi))), O.apply_KN(plan, psi, p.kappa)) < dn_tol(p.n)
+
+
 def test_apply_neumann_laplace(K, ctx):
     """The operator itself is defined for kappa = 0 as well."""
     p = CASES["circle64"]()
