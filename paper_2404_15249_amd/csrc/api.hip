@@ -283,11 +283,18 @@ void ensure_graph(kfbi_prob* p, int op) {
     p->timing = timing;
 }
 
-// Restarted GMRES on K phi = ghat (K_D or K_N by op; ghat already in
-// p->gm.ghat).  Steps go in batches (a replayed graph unless per-launch timing
-// is on); with tol > 0 the host polls the device state after each batch, with
-// tol <= 0 the work is fixed and the host waits once at the end.
-kfbi_status run_gmres(kfbi_prob* p, int op, const double* phi_in, double tol, int max_iter, GmresState* out) {
+// One restarted-GMRES run in flight on a problem's stream (run_gmres and
+// run_gmres_pair drive it).
+struct GmresRun {
+    kfbi_prob* p = nullptr;
+    int op = kOpD;
+    int max_steps = 0, steps = 0, batches = 0, poll_every = 1;
+    bool use_graph = false, finished = false;
+};
+
+// Set up GMRES on K phi = ghat (K_D or K_N by op; ghat already in p->gm.ghat)
+// from phi_in: the state, the input's spline, the first step's corrections.
+kfbi_status gmres_start(kfbi_prob* p, int op, const double* phi_in, double tol, int max_iter, GmresRun* r) {
     hipStream_t s = p->ctx->stream;
     const int M = p->M;
     GmresBufs b = p->gm;
@@ -305,25 +312,81 @@ kfbi_status run_gmres(kfbi_prob* p, int op, const double* phi_in, double tol, in
         HIP_TRY(launch_correct(op_view(p, op), js, nullptr, p->corr_il, nullptr, nullptr, s));
     }
     const int cycles = max_iter / std::max(1, p->restart) + 2;
-    const int max_steps = max_iter + cycles;
-    const int B = kfbi_prob::kGraphSteps;
-    const bool use_graph = !p->timing;
-    if (use_graph) ensure_graph(p, op);
-    const int poll_every = tol > 0 ? 1 : (max_steps + B - 1) / B;   // in batches
-    GmresState& st = p->st_host;
-    for (int done = 0, nb = 0; done < max_steps; done += B) {
-        if (use_graph && p->gexec[op]) {
-            HIP_TRY(hipGraphLaunch(p->gexec[op], s));
-        } else if (kfbi_status e = enqueue_steps(p, op, B, s)) {
-            return e;
-        }
-        if (++nb % poll_every == 0 || done + B >= max_steps) {
-            HIP_TRY(hipMemcpyAsync(&st, b.st, sizeof st, hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (st.converged) break;
+    *r = GmresRun{};
+    r->p = p;
+    r->op = op;
+    r->max_steps = max_iter + cycles;
+    r->use_graph = !p->timing;
+    if (r->use_graph) ensure_graph(p, op);
+    r->poll_every = tol > 0 ? 1 : (r->max_steps + kfbi_prob::kGraphSteps - 1) / kfbi_prob::kGraphSteps;
+    return KFBI_OK;
+}
+
+// Enqueue the next batch of kGraphSteps steps (a replayed graph unless
+// per-launch timing is on); returns through *poll whether the state should be
+// read after it.
+kfbi_status gmres_batch(GmresRun& r, bool* poll) {
+    kfbi_prob* p = r.p;
+    hipStream_t s = p->ctx->stream;
+    if (r.use_graph && p->gexec[r.op]) {
+        HIP_TRY(hipGraphLaunch(p->gexec[r.op], s));
+    } else if (kfbi_status e = enqueue_steps(p, r.op, kfbi_prob::kGraphSteps, s)) {
+        return e;
+    }
+    r.steps += kfbi_prob::kGraphSteps;
+    *poll = ++r.batches % r.poll_every == 0 || r.steps >= r.max_steps;
+    return KFBI_OK;
+}
+
+// Request the state into p->st_host (completes with the stream).
+kfbi_status gmres_request_state(GmresRun& r) {
+    HIP_TRY(hipMemcpyAsync(&r.p->st_host, r.p->gm.st, sizeof(GmresState), hipMemcpyDeviceToHost, r.p->ctx->stream));
+    return KFBI_OK;
+}
+
+// Restarted GMRES on K phi = ghat (K_D or K_N by op; ghat already in
+// p->gm.ghat).  Steps go in batches (a replayed graph unless per-launch timing
+// is on); with tol > 0 the host polls the device state after each batch, with
+// tol <= 0 the work is fixed and the host waits once at the end.
+kfbi_status run_gmres(kfbi_prob* p, int op, const double* phi_in, double tol, int max_iter, GmresState* out) {
+    GmresRun r;
+    if (kfbi_status e = gmres_start(p, op, phi_in, tol, max_iter, &r)) return e;
+    while (r.steps < r.max_steps) {
+        bool poll = false;
+        if (kfbi_status e = gmres_batch(r, &poll)) return e;
+        if (poll) {
+            if (kfbi_status e = gmres_request_state(r)) return e;
+            HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+            if (p->st_host.converged) break;
         }
     }
-    *out = st;
+    *out = p->st_host;
+    return KFBI_OK;
+}
+
+// GMRES on two problems at once, each on its own stream: every round enqueues a
+// batch on each problem that is still running, then reads both states, so the
+// two runs overlap on the device.
+kfbi_status run_gmres_pair(kfbi_prob* pa, int opa, const double* xa, kfbi_prob* pb, int opb, const double* xb,
+                           GmresState* outa, GmresState* outb) {
+    GmresRun r[2];
+    if (kfbi_status e = gmres_start(pa, opa, xa, pa->tol, pa->max_iter, &r[0])) return e;
+    if (kfbi_status e = gmres_start(pb, opb, xb, pb->tol, pb->max_iter, &r[1])) return e;
+    while (!(r[0].finished && r[1].finished)) {
+        for (auto& q : r) {
+            if (q.finished) continue;
+            bool poll = false;
+            if (kfbi_status e = gmres_batch(q, &poll)) return e;
+            if (kfbi_status e = gmres_request_state(q)) return e;
+        }
+        for (auto& q : r) {
+            if (q.finished) continue;
+            HIP_TRY(hipStreamSynchronize(q.p->ctx->stream));
+            if (q.p->st_host.converged || q.steps >= q.max_steps) q.finished = true;
+        }
+    }
+    *outa = pa->st_host;
+    *outb = pb->st_host;
     return KFBI_OK;
 }
 
@@ -440,7 +503,57 @@ kfbi_status run_iters(kfbi_prob* p, int method, const double* rhs, double* x, do
     return KFBI_OK;
 }
 
+// ---------------------------------------------------------------- the Neumann solve in parts
+
+kfbi_status neumann_check(kfbi_prob* p, const NeumannIO& io) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    for (auto [ptr, name] : {std::pair<const void*, const char*>{io.f_grid, "f_grid"}, {io.f_gamma, "f_gamma"},
+                             {io.g_n, "g_n"}, {io.u_grid, "u_grid"}, {io.u_gamma, "u_gamma"},
+                             {io.dn_gamma, "dn_gamma"}, {io.psi, "psi"}})
+        if (kfbi_status s = check_ptr(ptr, name)) return s;
+    if (!(p->kappa > 0.0)) return set_err(KFBI_ERR_ARG, "the Neumann problem needs kappa > 0");
+    return KFBI_OK;
+}
+
+// g^ = g_n - d_n (Y f)^+ into the GMRES right-hand side.
+kfbi_status neumann_prepare(kfbi_prob* p, const NeumannIO& io) {
+    JumpSrc jy{nullptr, nullptr, io.f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, true, jy, io.f_grid, true, nullptr, false, nullptr, p->tmpM)) return e;
+    HIP_TRY(launch_axpby(p->M, 1.0, io.g_n, -1.0, p->tmpM, p->gm.ghat, p->ctx->stream));
+    return KFBI_OK;
+}
+
+// u = v_psi + Y f with its trace and normal derivative, and psi out.
+kfbi_status neumann_finish(kfbi_prob* p, const NeumannIO& io) {
+    JumpSrc jf{p->gm.phi, nullptr, io.f_gamma, nullptr, nullptr, nullptr};
+    if (kfbi_status e = dense_interface_solve(p, true, jf, io.f_grid, true, io.u_grid, true, io.u_gamma, io.dn_gamma))
+        return e;
+    HIP_TRY(hipMemcpyAsync(io.psi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, p->ctx->stream));
+    return KFBI_OK;
+}
+
 }  // namespace
+
+namespace kfbi {
+
+kfbi_status solve_neumann_pair(kfbi_prob* pa, const NeumannIO& ia, kfbi_prob* pb, const NeumannIO& ib, int* iters_a,
+                               int* iters_b) {
+    if (kfbi_status e = neumann_check(pa, ia)) return e;
+    if (kfbi_status e = neumann_check(pb, ib)) return e;
+    HIP_TRY(hipSetDevice(pa->ctx->device));
+    if (kfbi_status e = neumann_prepare(pa, ia)) return e;
+    if (kfbi_status e = neumann_prepare(pb, ib)) return e;
+    GmresState sa{}, sb{};
+    if (kfbi_status e = run_gmres_pair(pa, kOpN, ia.psi, pb, kOpN, ib.psi, &sa, &sb)) return e;
+    if (kfbi_status e = neumann_finish(pa, ia)) return e;
+    if (kfbi_status e = neumann_finish(pb, ib)) return e;
+    if (iters_a) *iters_a = sa.it;
+    if (iters_b) *iters_b = sb.it;
+    if (sa.converged == 1 && sb.converged == 1) return KFBI_OK;
+    return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
+}
+
+}  // namespace kfbi
 
 extern "C" {
 
@@ -994,28 +1107,15 @@ kfbi_status kfbi_gmres_neumann(kfbi_prob* p, const double* rhs, double* psi, dou
 kfbi_status kfbi_solve_neumann(kfbi_prob* p, const double* f_grid, const double* f_gamma, const double* g_n,
                                double* u_grid, double* u_gamma, double* dn_gamma, double* psi, int* iters,
                                double* rel_res) {
-    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
-    for (auto [ptr, name] : {std::pair<const void*, const char*>{f_grid, "f_grid"}, {f_gamma, "f_gamma"},
-                             {g_n, "g_n"}, {u_grid, "u_grid"}, {u_gamma, "u_gamma"}, {dn_gamma, "dn_gamma"},
-                             {psi, "psi"}})
-        if (kfbi_status s = check_ptr(ptr, name)) return s;
-    if (!(p->kappa > 0.0)) return set_err(KFBI_ERR_ARG, "the Neumann problem needs kappa > 0");
+    const NeumannIO io{f_grid, f_gamma, g_n, u_grid, u_gamma, dn_gamma, psi};
+    if (kfbi_status e = neumann_check(p, io)) return e;
     HIP_TRY(hipSetDevice(p->ctx->device));
-    hipStream_t s = p->ctx->stream;
-    const int M = p->M;
-    // g^ = g_n - d_n (Y f)^+
-    JumpSrc jy{nullptr, nullptr, f_gamma, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, true, jy, f_grid, true, nullptr, false, nullptr, p->tmpM)) return e;
-    GmresBufs b = p->gm;
-    HIP_TRY(launch_axpby(M, 1.0, g_n, -1.0, p->tmpM, b.ghat, s));
+    if (kfbi_status e = neumann_prepare(p, io)) return e;
     // GMRES on K_N psi = g^: every step is one K_N apply plus one orthogonalisation
     GmresState st{};
     if (kfbi_status e = run_gmres(p, kOpN, psi, p->tol, p->max_iter, &st)) return e;
-    // u = v_psi + Y f, with its trace and normal derivative at the samples
-    JumpSrc jf{b.phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, true, jf, f_grid, true, u_grid, true, u_gamma, dn_gamma)) return e;
-    HIP_TRY(hipMemcpyAsync(psi, b.phi, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (kfbi_status e = neumann_finish(p, io)) return e;
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
     if (iters) *iters = st.it;
     if (rel_res) *rel_res = st.relres;
     if (st.converged == 1) return KFBI_OK;

@@ -79,6 +79,23 @@ bool record_graph(hipStream_t stream, hipGraphExec_t* out, F enqueue) {
             return ::kfbi::set_err(KFBI_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+namespace kfbi {
+
+// Arguments of one Neumann solve (device pointers, as kfbi_solve_neumann).
+struct NeumannIO {
+    const double *f_grid, *f_gamma, *g_n;
+    double *u_grid, *u_gamma, *dn_gamma, *psi;
+};
+
+// Two Neumann solves whose problems enqueue on different streams, overlapped:
+// the volume potentials, then GMRES batches on both with the host reading both
+// states after each round, then the final solves.  Leaves the final solves
+// enqueued (no wait at the end).  KFBI_NOT_CONVERGED if either hit its cap.
+kfbi_status solve_neumann_pair(kfbi_prob* pa, const NeumannIO& ia, kfbi_prob* pb, const NeumannIO& ib, int* iters_a,
+                               int* iters_b);
+
+}  // namespace kfbi
+
 struct kfbi_ctx {
     int device = 0;
     hipStream_t stream = nullptr;

@@ -8,8 +8,9 @@
 //    keeps its trace on Gamma: the diffusion solve needs it as the jump [F]);
 //  - D: Crank-Nicolson for w' = eps Lap w with d_n w = 0, as w <- 2 z - w with
 //    z the backward-Euler half step Lap z - kappa z = -kappa w, kappa = 2/(eps dt):
-//    one Neumann solve per species (kfbi_solve_neumann), warm-started from the
-//    species' previous density.
+//    one Neumann solve per species, warm-started from the species' previous
+//    density.  The two species' solves are independent: each problem has its
+//    own stream and the solves overlap (solve_neumann_pair).
 // Grid nodes outside Omega hold zero.
 #include <hip/hip_runtime.h>
 
@@ -91,7 +92,9 @@ __global__ __launch_bounds__(256) void k_gs_post(GsState S, const double* __rest
 }  // namespace
 
 struct kfbi_gs {
-    kfbi_ctx* ctx = nullptr;
+    kfbi_ctx* ctx = nullptr;     // the caller's context: stream A (state, pointwise kernels, u)
+    kfbi_ctx* ctx2 = nullptr;    // the second stream (v's solve)
+    hipEvent_t ev_pre = nullptr, ev_solved = nullptr;
     kfbi_prob* pu = nullptr;     // kappa_u = 2/(eps1 dt)
     kfbi_prob* pv = nullptr;     // kappa_v = 2/(eps2 dt)
     kfbi_gs_desc d{};
@@ -109,11 +112,19 @@ struct kfbi_gs {
 namespace {
 
 void gs_free(kfbi_gs* g) {
-    for (void* a : g->allocs) hipFree(a);
-    g->allocs.clear();
+    // both streams drained (destroying a problem waits for its stream) before
+    // the state buffers go
     if (g->pu) kfbi_prob_destroy(g->pu);
     if (g->pv) kfbi_prob_destroy(g->pv);
     g->pu = g->pv = nullptr;
+    if (g->ctx2) hipStreamSynchronize(g->ctx2->stream);
+    for (void* a : g->allocs) hipFree(a);
+    g->allocs.clear();
+    if (g->ev_pre) hipEventDestroy(g->ev_pre);
+    if (g->ev_solved) hipEventDestroy(g->ev_solved);
+    g->ev_pre = g->ev_solved = nullptr;
+    if (g->ctx2) kfbi_ctx_destroy(g->ctx2);
+    g->ctx2 = nullptr;
 }
 
 template <class T>
@@ -161,8 +172,14 @@ kfbi_status kfbi_gs_create(kfbi_ctx* ctx, const kfbi_gs_desc* d, kfbi_gs** out) 
     pd.precision = KFBI_FP64;
     pd.kappa = g->ku;
     if (kfbi_status s = kfbi_prob_create(ctx, &pd, &g->pu)) return fail(s);
+    if (kfbi_status s = kfbi_ctx_create(ctx->device, nullptr, &g->ctx2)) return fail(s);
     pd.kappa = g->kv;
-    if (kfbi_status s = kfbi_prob_create(ctx, &pd, &g->pv)) return fail(s);
+    if (kfbi_status s = kfbi_prob_create(g->ctx2, &pd, &g->pv)) return fail(s);
+    if (hipEventCreateWithFlags(&g->ev_pre, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&g->ev_solved, hipEventDisableTiming) != hipSuccess) {
+        hipGetLastError();
+        return fail(set_err(KFBI_ERR_DEVICE, "event creation failed"));
+    }
     kfbi_prob_info(g->pu, &g->M, nullptr, nullptr, nullptr);
     g->n = d->n;
     g->ng = (d->n + 1) * (d->n + 1);
@@ -171,7 +188,8 @@ kfbi_status kfbi_gs_create(kfbi_ctx* ctx, const kfbi_gs_desc* d, kfbi_gs** out) 
     if ((st = gs_alloc(g, &g->u, all)) || (st = gs_alloc(g, &g->v, all)) || (st = gs_alloc(g, &g->fu, all)) ||
         (st = gs_alloc(g, &g->fv, all)) || (st = gs_alloc(g, &g->zu, all)) || (st = gs_alloc(g, &g->zv, all)) ||
         (st = gs_alloc(g, &g->psi_u, g->M)) || (st = gs_alloc(g, &g->psi_v, g->M)) ||
-        (st = gs_alloc(g, &g->gn, g->M)) || (st = gs_alloc(g, &g->dn, g->M)) || (st = gs_alloc(g, &g->mask, g->ng)))
+        (st = gs_alloc(g, &g->gn, g->M)) || (st = gs_alloc(g, &g->dn, 2 * (size_t)g->M)) ||
+        (st = gs_alloc(g, &g->mask, g->ng)))
         return fail(st);
     std::vector<unsigned char> mask(g->ng);
     kfbi_prob_mask(g->pu, mask.data());
@@ -249,18 +267,18 @@ kfbi_status kfbi_gs_step(kfbi_gs* g, int nsteps) {
     const int total = g->ng + g->M;
     const dim3 grid((total + 255) / 256), block(256);
     const double dth = 0.5 * g->d.dt;
+    hipStream_t s2 = g->ctx2->stream;
+    const NeumannIO iu{g->fu, g->fu + g->ng, g->gn, g->zu, g->zu + g->ng, g->dn, g->psi_u};
+    const NeumannIO iv{g->fv, g->fv + g->ng, g->gn, g->zv, g->zv + g->ng, g->dn + g->M, g->psi_v};
     for (int k = 0; k < nsteps; ++k) {
         HIP_TRY(klaunch(k_gs_pre, grid, block, 0, s, S, g->fu, g->fv, dth, g->ku, g->kv, P));
-        int it = 0;
-        for (int sp = 0; sp < 2; ++sp) {
-            kfbi_prob* p = sp ? g->pv : g->pu;
-            double* f = sp ? g->fv : g->fu;
-            double* z = sp ? g->zv : g->zu;
-            double* psi = sp ? g->psi_v : g->psi_u;
-            if (kfbi_status e = kfbi_solve_neumann(p, f, f + g->ng, g->gn, z, z + g->ng, g->dn, psi, &it, nullptr))
-                return e;
-            g->iters += it;
-        }
+        HIP_TRY(hipEventRecord(g->ev_pre, s));             // v's solve reads what k_gs_pre wrote
+        HIP_TRY(hipStreamWaitEvent(s2, g->ev_pre, 0));
+        int itu = 0, itv = 0;
+        if (kfbi_status e = solve_neumann_pair(g->pu, iu, g->pv, iv, &itu, &itv)) return e;
+        g->iters += itu + itv;
+        HIP_TRY(hipEventRecord(g->ev_solved, s2));         // k_gs_post reads v's solution
+        HIP_TRY(hipStreamWaitEvent(s, g->ev_solved, 0));
         HIP_TRY(klaunch(k_gs_post, grid, block, 0, s, S, g->zu, g->zv, dth, P));
         g->steps++;
     }
