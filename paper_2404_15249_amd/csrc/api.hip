@@ -674,7 +674,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         // the autotuner may halve Rm once: room for that many partial rows
         p->Gcap = (p->n + std::max(1, p->Rm / 2) - 1) / std::max(1, p->Rm / 2);
     }
-    p->dstB = dst_default_tile(n, cpx_bytes(p->precision), ctx->lds_max);
+    p->dstB = dst_default_tile(n, cpx_bytes(p->precision), ctx->lds_max, n, ctx->num_cu);
     if (p->dstB == 0) {
         delete p;
         return set_err(KFBI_ERR_UNSUPPORTED, "grid too large for the column transforms' local data share");

@@ -221,7 +221,7 @@ kfbi_status kfbi3_prob_create(kfbi_ctx* ctx, const kfbi_desc3* d, kfbi_prob3** o
     b.gc64 = gm_chunks64(M);
     if (hipMemset(b.cnt, 0, sizeof(unsigned)) != hipSuccess || hipMemset(p->zeroM, 0, M * sizeof(double)) != hipSuccess)
         return fail(set_err(KFBI_ERR_DEVICE, "hipMemset failed"));
-    p->dstB = dst_default_tile(N, 2 * sizeof(double), ctx->lds_max);
+    p->dstB = dst_default_tile(N, 2 * sizeof(double), ctx->lds_max, (long)N * N, ctx->num_cu);
     if (p->dstB == 0) return fail(set_err(KFBI_ERR_UNSUPPORTED, "no column-transform tile fits this grid"));
     *out = p;
     return KFBI_OK;

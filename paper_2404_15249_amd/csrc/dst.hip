@@ -316,8 +316,13 @@ bool dst_tile_ok(int N, int B, size_t cpx_bytes, size_t lds_max) {
     return dst_lds_bytes(N, B, cpx_bytes) <= lds_max;
 }
 
-int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max) {
+int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max, long lines, int min_groups) {
+    // the widest valid tile that still gives min_groups workgroups (wider
+    // tiles read longer row segments, more workgroups fill the chip); else the
+    // narrowest valid one
     for (int B : {16, 8, 4})
+        if (dst_tile_ok(N, B, cpx_bytes, lds_max) && lines / B >= min_groups) return B;
+    for (int B : {4, 8, 16})
         if (dst_tile_ok(N, B, cpx_bytes, lds_max)) return B;
     return 0;
 }

@@ -184,17 +184,18 @@ hipError_t launch_dst_cols(const DevPlan& p, const double* in, double* out, doub
 hipError_t launch_dst_cols_f32(const DevPlan& p, const double* in, float* out, double alpha, int B, hipStream_t s);
 hipError_t launch_dst_cols_f32_to64(const DevPlan& p, const float* in, double* out, double alpha, bool acc, int B,
                                     hipStream_t s);
-// LDS of a column-transform workgroup with B columns whose complex pairs take
-// cpx_bytes each; whether B is a valid tile for N within lds_max; the largest
-// valid tile (0 if none).
 // In-place FP64 transforms of `slices` N-row arrays (rows ld elements apart,
 // ld columns, arrays `slice` elements apart): the column transforms of the
 // planes of a 3D grid.  Skipped while *skip is nonzero (skip may be null).
 hipError_t launch_dst_lines(int N, int log2N, const double* sinq, double* a, double alpha, int B, int ld, int slices,
                             size_t slice, const int* skip, hipStream_t s);
+// LDS of a column-transform workgroup with B columns whose complex pairs take
+// cpx_bytes each; whether B is a valid tile for N within lds_max.
 size_t dst_lds_bytes(int N, int B, size_t cpx_bytes);
 bool dst_tile_ok(int N, int B, size_t cpx_bytes, size_t lds_max);
-int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max);
+// The default tile: the widest valid one that splits `lines` columns into at
+// least min_groups workgroups, else the narrowest valid one (0 if none).
+int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max, long lines, int min_groups);
 // tridiagonal solves along x of every sine mode (FP64 arithmetic; FP64 or FP32 storage)
 hipError_t launch_rows_solve(const DevPlan& p, double* A, hipStream_t s);
 hipError_t launch_rows_solve_f32(const DevPlan& p, float* A, hipStream_t s);
