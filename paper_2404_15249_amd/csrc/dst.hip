@@ -32,6 +32,15 @@ struct cpx {
 
 __device__ __forceinline__ int bitrev(int v, int bits) { return (int)(__brev((unsigned)v) >> (32 - bits)); }
 
+// LDS slot of element i of a column pair's array: the low three bits of i
+// XORed with a hash of the rest (a permutation inside each group of eight).
+// The early FFT passes (strides 4 and 16) and the bit reversal (strides N/64
+// and up) would otherwise put the lanes of a wavefront on the same banks.
+__device__ __forceinline__ int zs(int i) {
+    const int b = i >> 3;
+    return i ^ (((b * 3) ^ ((b >> 3) * 5) ^ (b >> 6)) & 7);
+}
+
 // two adjacent columns of one row travel as one vector load or store
 template <class T>
 struct pair_of;
@@ -94,10 +103,10 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         for (int u = 0; u < kLoadBatch; ++u) {
             const int idx = base + u * NTH + tid;
             const int r = idx >> LP, p = idx & (P - 1);
-            if (idx < N * P && r + 1 < N) z[p * NS + r + 1] = cpx<T>{(T)v[u].x, (T)v[u].y};
+            if (idx < N * P && r + 1 < N) z[p * NS + zs(r + 1)] = cpx<T>{(T)v[u].x, (T)v[u].y};
         }
     }
-    if (tid < P) z[tid * NS] = cpx<T>{T(0), T(0)};
+    if (tid < P) z[tid * NS + zs(0)] = cpx<T>{T(0), T(0)};
     __syncthreads();
     // pre-process pairs (j, N - j)
     const int lh = log2N - 1;                                // log2 (N/2)
@@ -105,13 +114,13 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         const int p = idx >> lh, j = (idx & (N / 2 - 1)) + 1;        // 1 .. N/2
         cpx<T>* zp = z + p * NS;
         if (j == N / 2) {
-            zp[j].x *= T(2);
-            zp[j].y *= T(2);
+            zp[zs(j)].x *= T(2);
+            zp[zs(j)].y *= T(2);
         } else {
-            const cpx<T> a = zp[j], b = zp[N - j];
+            const cpx<T> a = zp[zs(j)], b = zp[zs(N - j)];
             const T s = (T)sq[j];
-            zp[j] = cpx<T>{s * (a.x + b.x) + T(0.5) * (a.x - b.x), s * (a.y + b.y) + T(0.5) * (a.y - b.y)};
-            zp[N - j] = cpx<T>{s * (b.x + a.x) + T(0.5) * (b.x - a.x), s * (b.y + a.y) + T(0.5) * (b.y - a.y)};
+            zp[zs(j)] = cpx<T>{s * (a.x + b.x) + T(0.5) * (a.x - b.x), s * (a.y + b.y) + T(0.5) * (a.y - b.y)};
+            zp[zs(N - j)] = cpx<T>{s * (b.x + a.x) + T(0.5) * (b.x - a.x), s * (b.y + a.y) + T(0.5) * (b.y - a.y)};
         }
     }
     __syncthreads();
@@ -121,9 +130,9 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         const int rj = bitrev(j, log2N);
         if (j < rj) {
             cpx<T>* zp = z + p * NS;
-            const cpx<T> t = zp[j];
-            zp[j] = zp[rj];
-            zp[rj] = t;
+            const cpx<T> t = zp[zs(j)];
+            zp[zs(j)] = zp[zs(rj)];
+            zp[zs(rj)] = t;
         }
     }
     __syncthreads();
@@ -139,7 +148,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int pos = b & (h - 1), grp = b >> (s - 1);
             const int i0 = grp * 4 * h + pos;
             cpx<T>* zp = z + p * NS;
-            const cpx<T> a = zp[i0], bb = zp[i0 + h], c = zp[i0 + 2 * h], d = zp[i0 + 3 * h];
+            const cpx<T> a = zp[zs(i0)], bb = zp[zs(i0 + h)], c = zp[zs(i0 + 2 * h)], d = zp[zs(i0 + 3 * h)];
             double dr, di;
             twiddle(sq, pos << (log2N - s - 1), N, dr, di);
             const T w2r = (T)dr, w2i = (T)di;
@@ -152,10 +161,10 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             // pass s + 1: (a, c) with W and (b, d) with -i W
             const T tcr = w2r * c1.x - w2i * c1.y, tci = w2r * c1.y + w2i * c1.x;
             const T ter = w2i * d1.x + w2r * d1.y, tei = w2i * d1.y - w2r * d1.x;
-            zp[i0] = cpx<T>{a1.x + tcr, a1.y + tci};
-            zp[i0 + 2 * h] = cpx<T>{a1.x - tcr, a1.y - tci};
-            zp[i0 + h] = cpx<T>{b1.x + ter, b1.y + tei};
-            zp[i0 + 3 * h] = cpx<T>{b1.x - ter, b1.y - tei};
+            zp[zs(i0)] = cpx<T>{a1.x + tcr, a1.y + tci};
+            zp[zs(i0 + 2 * h)] = cpx<T>{a1.x - tcr, a1.y - tci};
+            zp[zs(i0 + h)] = cpx<T>{b1.x + ter, b1.y + tei};
+            zp[zs(i0 + 3 * h)] = cpx<T>{b1.x - ter, b1.y - tei};
         }
         __syncthreads();
     }
@@ -168,10 +177,10 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             twiddle(sq, pos, N, dr, di);
             const T wr = (T)dr, wi = (T)di;
             cpx<T>* zp = z + p * NS;
-            const cpx<T> a = zp[i1], c = zp[i2];
+            const cpx<T> a = zp[zs(i1)], c = zp[zs(i2)];
             const T tr = wr * c.x - wi * c.y, ti = wr * c.y + wi * c.x;
-            zp[i1] = cpx<T>{a.x + tr, a.y + ti};
-            zp[i2] = cpx<T>{a.x - tr, a.y - ti};
+            zp[zs(i1)] = cpx<T>{a.x + tr, a.y + ti};
+            zp[zs(i2)] = cpx<T>{a.x - tr, a.y - ti};
         }
         __syncthreads();
     }
@@ -179,11 +188,11 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     for (int idx = tid; idx < (P << lh); idx += NTH) {
         const int p = idx >> lh, k = idx & (N / 2 - 1);
         cpx<T>* zp = z + p * NS;
-        const cpx<T> Zk = zp[k], Zn = zp[(N - k) & (N - 1)];
+        const cpx<T> Zk = zp[zs(k)], Zn = zp[zs((N - k) & (N - 1))];
         const T ra = T(0.5) * (Zk.x + Zn.x), ia = T(0.5) * (Zk.y - Zn.y);
         const T rb = T(0.5) * (Zk.y + Zn.y), ib = -T(0.5) * (Zk.x - Zn.x);
-        zp[k] = cpx<T>{ra, rb};
-        if (k > 0) zp[N - k] = cpx<T>{-ia, -ib};
+        zp[zs(k)] = cpx<T>{ra, rb};
+        if (k > 0) zp[zs(N - k)] = cpx<T>{-ia, -ib};
     }
     __syncthreads();
     // odd outputs: X_{2k+1} = R_0/2 + R_1 + ... + R_k, one wavefront per column.
@@ -203,7 +212,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         if (t < tpc) {
             for (int q = 0; q < L; ++q) {
                 const int e = (q + off) & (L - 1), k = (t << lL) + e;
-                double v = (double)col[2 * k];
+                double v = (double)col[2 * zs(k)];
                 if (k == 0) v *= 0.5;
                 if (e >= off) hi += v; else lo += v;
             }
@@ -219,11 +228,11 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             double acc_hi = excl + lo, acc_lo = excl;
             for (int q = 0; q < L; ++q) {
                 const int e = (q + off) & (L - 1), k = (t << lL) + e;
-                double v = (double)col[2 * k];
+                double v = (double)col[2 * zs(k)];
                 if (k == 0) v *= 0.5;
                 double w;
                 if (e >= off) w = (acc_hi += v); else w = (acc_lo += v);
-                col[2 * k] = (T)w;
+                col[2 * zs(k)] = (T)w;
             }
         }
     }
@@ -238,7 +247,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int l = r + 1;
             vx[u] = vy[u] = 0.0;
             if (idx < N * P && l < N) {
-                const cpx<T> e = z[p * NS + ((l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
+                const cpx<T> e = z[p * NS + zs((l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
                 vx[u] = alpha * (double)e.x;
                 vy[u] = alpha * (double)e.y;
             }
