@@ -59,7 +59,7 @@ typedef int kfbi_status;
 #define KFBI_ERR_DEVICE (-4)       /* HIP runtime error */
 #define KFBI_ERR_BUDGET (-5)       /* request can never fit the batch's memory budget */
 #define KFBI_ERR_NONFINITE (-6)    /* NaN or Inf met in the data */
-#define KFBI_ERR_UNSUPPORTED (-7)  /* configuration outside what this build handles */
+#define KFBI_ERR_UNSUPPORTED (-7)  /* configuration outside what the library handles */
 
 typedef struct kfbi_ctx kfbi_ctx;
 typedef struct kfbi_prob kfbi_prob;
