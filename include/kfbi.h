@@ -276,6 +276,13 @@ kfbi_status kfbi_gs_step(kfbi_gs* gs, int nsteps);
 
 /* ---------------------------------------------------------------- steps (for tests and tools) */
 
+/* Gram-Schmidt of the GMRES steps (kfbi_gmres, kfbi_solve and their Neumann
+ * and batched forms): one classical pass, and a second one over the new
+ * vector only when its norm after the first pass is below eta times its norm
+ * before (the cancellation that would cost orthogonality).  eta in [0, 1]:
+ * 0 never, 1 always; default 1e-3.  Takes effect at the next GMRES run. */
+kfbi_status kfbi_prob_set_reorth(kfbi_prob* prob, double eta);
+
 /* Alg. 2 alone: the correction of the right-hand side at every irregular node
  * for [v] = phi and [F] = f_gamma (f_gamma may be NULL: [F] = 0).  corr: device,
  * I doubles in the order of kfbi_prob_irregular. */

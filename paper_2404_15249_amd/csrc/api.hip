@@ -40,6 +40,7 @@ struct kfbi_prob {
     Plan plan;
     double kappa = 0, tol = 1e-10;
     int restart = 50, max_iter = 500;
+    double reorth = kGmReorthDefault;   // second Gram-Schmidt pass when |z| < reorth |w|
     int N = 0, n = 0, M = 0, Q = 0, I = 0;
     int Rm = 8, G = 1;           // sine modes per sparse-fast-solve workgroup; workgroups = ceil(n / Rm)
     DevPlan dp{};                // the double-layer operator's view (see plan_view)
@@ -305,6 +306,7 @@ kfbi_status gmres_start(kfbi_prob* p, int op, const double* phi_in, double tol, 
     st0.first = 1;
     st0.tol = tol;
     st0.max_iter = max_iter;
+    st0.reorth = p->reorth;
     HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
     if (!p->timing) {                                  // the first step's corrections
@@ -1122,6 +1124,13 @@ kfbi_status kfbi_solve_neumann(kfbi_prob* p, const double* f_grid, const double*
     return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
 }
 
+kfbi_status kfbi_prob_set_reorth(kfbi_prob* p, double eta) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (!(eta >= 0.0 && eta <= 1.0)) return set_err(KFBI_ERR_ARG, "eta must lie in [0, 1]");
+    p->reorth = eta;
+    return KFBI_OK;
+}
+
 kfbi_status kfbi_set_timing(kfbi_prob* p, int on) {
     if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
     p->timing = on != 0;
@@ -1536,6 +1545,7 @@ kfbi_status kfbi_batch_admit(kfbi_batch* B, kfbi_prob* p, const double* f_grid, 
     p->st_host.first = 1;
     p->st_host.tol = p->tol;
     p->st_host.max_iter = p->max_iter;
+    p->st_host.reorth = p->reorth;
     HIP_TRY(hipMemcpyAsync(b.st, &p->st_host, sizeof p->st_host, hipMemcpyHostToDevice, s));
     SlotDev& S = B->h_slots[free_slot];
     S.p = p->dp;

@@ -111,6 +111,7 @@ kfbi_status run_gmres3(kfbi_prob3* p, const double* phi_in, double tol, int max_
     st0.first = 1;
     st0.tol = tol;
     st0.max_iter = max_iter;
+    st0.reorth = kGmReorthDefault;
     HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
     if (!p->gexec && !p->graph_failed)
         p->graph_failed = !record_graph(s, &p->gexec,

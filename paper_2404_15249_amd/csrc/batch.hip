@@ -82,15 +82,14 @@ __global__ __launch_bounds__(1024) void k_reduce_b(const SlotDev* __restrict__ s
 }
 
 // GMRES (gmres.h): the update and emit launches walk (slot, chunk) items; the
-// first pass rides on k_reduce_b and the commit on the second update.
+// first pass's dots ride on k_reduce_b and the commit on the update.
 template <int Kind>
 __global__ __launch_bounds__(kGmChunk) void k_gm_vec_b(const SlotDev* __restrict__ slots, BatchWork w) {
     const int n_items = w.counts[4];
     for (int it = blockIdx.x; it < n_items; it += gridDim.x) {
         const int2 item = w.gm_items[it];
         const SlotDev& S = slots[item.x];
-        if (Kind == 1) gm_update(S.b, S.p.M, item.y, 0);
-        if (Kind == 2) gm_update2_commit(S.b, S.p.M, item.y);
+        if (Kind == 1) gm_update1_commit(S.b, S.p.M, item.y);
         if (Kind == 3) gm_emit(S.p.taps, S.b, S.p.M, item.y);
         __syncthreads();                                 // the item's LDS is reused by the next item
     }
@@ -112,7 +111,6 @@ hipError_t launch_batch_step(const SlotDev* slots, BatchWork w, int n_cu, hipStr
     if (hipError_t e = klaunch(&k_modes_b, dim3(n_cu), dim3(kModeWaves * 64), lds, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_reduce_b, dim3(n_cu), dim3(1024), 0, s, slots, w)) return e;
     if (hipError_t e = klaunch(&k_gm_vec_b<1>, gv, t, 0, s, slots, w)) return e;
-    if (hipError_t e = klaunch(&k_gm_vec_b<2>, gv, t, 0, s, slots, w)) return e;
     return klaunch(&k_gm_vec_b<3>, gv, t, 0, s, slots, w);
 }
 

@@ -1,15 +1,18 @@
 // Restarted GMRES (Alg. 5) on the boundary density, resident on the device.
 //
-// One step of the iteration follows one K_D apply and takes, besides it, three
+// One step of the iteration follows one K_D apply and takes, besides it, two
 // launches, so the vector work is spread over many workgroups:
 //   dots1   fused into the apply's last launch (reduce_samples64), per 64
 //           samples: mode 0: phi <- xcur (the iterate the apply was given),
 //           z = ghat - w and partial |z|^2; mode 1: partial dots V_i . w, i <= j
 //   upd1    per chunk of kGmChunk: h_i = sum of the partials; z = w - sum h_i
-//           V_i; partial dots V_i . z (classical Gram-Schmidt, second pass)
-//   upd2    per chunk: z -= sum h'_i V_i; partial |z|^2; the workgroup that
-//           finishes last (an atomic count, no waiting) then runs commit: the
-//           new Hessenberg column, the Givens rotations and the residual
+//           V_i; partial |z|^2 and |w|^2.  The workgroup that finishes last (an
+//           atomic count, no waiting) commits.  Classical Gram-Schmidt keeps
+//           the new vector orthogonal to the basis to about eps |w| / |z|; only
+//           when |z| < reorth |w| (1e-3 by default) does that workgroup first
+//           make a second pass over the whole vector itself.  For these
+//           second-kind operators the cancellation stays far above that bound.
+//   commit  the new Hessenberg column, the Givens rotations and the residual
 //           estimate (mode 1) or the true residual (mode 0), the state
 //           transition, and at the end of a cycle the triangular solve
 //   emit    per chunk: the next K_D input (new basis vector, or the updated
@@ -30,27 +33,27 @@ enum GmKind { kGmNewCycle = 0, kGmNextVector = 1, kGmCycleEnd = 2, kGmDone = 3 }
 
 __host__ __device__ inline int gm_chunks(int M) { return (M + kGmChunk - 1) / kGmChunk; }
 __host__ __device__ inline int gm_chunks64(int M) { return (M + 63) / 64; }
-// doubles of partial sums a problem needs: first-pass dots (m+1) x gc64,
-// second-pass dots (m+1) x gc, norms of the update (gc) and of the residual
-// (gc64), and the first-pass coefficients (m+1)
+// doubles of partial sums a problem needs: first-pass dots (m+1) x gc64, norms
+// of the update (gc), of the residual (gc64) and of the apply's output (gc),
+// and the first-pass coefficients (m+1)
 __host__ __device__ inline size_t gm_part_size(int m, int gc, int gc64) {
-    return (size_t)(m + 1) * (gc64 + gc + 1) + gc + gc64;
+    return (size_t)(m + 1) * (gc64 + 1) + 2 * gc + gc64;
 }
 
 struct GmPart {
     double* d1;     // [i * gc64 + c64]
-    double* d2;     // [i * gc + c]
     double* nrm;    // [c]
     double* nrm0;   // [c64]
     double* h1;     // [i]: sum of d1 over the chunks (written by chunk 0 of the first update)
+    double* nrmw;   // [c]: |w|^2 of the chunk (first update)
 };
 __device__ __forceinline__ GmPart gm_part(const GmresBufs& b) {
     GmPart q;
     q.d1 = b.part;
-    q.d2 = q.d1 + (size_t)(b.m + 1) * b.gc64;
-    q.nrm = q.d2 + (size_t)(b.m + 1) * b.gc;
+    q.nrm = q.d1 + (size_t)(b.m + 1) * b.gc64;
     q.nrm0 = q.nrm + b.gc;
     q.h1 = q.nrm0 + b.gc64;
+    q.nrmw = q.h1 + (b.m + 1);
     return q;
 }
 
@@ -108,31 +111,6 @@ __device__ __forceinline__ void gm_load_basis(const double* __restrict__ V, int 
         for (int u = 0; u < 16; ++u) {
             const int i = 16 * g + u;
             v[g][u] = (in && i <= j) ? V[(size_t)i * M + e] : 0.0;
-        }
-    }
-}
-
-// Partial dots of chunk c with V_0..V_j from basis values held in registers
-// (v[g][u] = V_{16g+u} at this thread's element) times x:
-// out[i * gc + c] for i <= j.  red: 4 x 16 doubles of LDS.
-__device__ __forceinline__ void gm_chunk_dots(const double (&v)[4][16], double x, int j, int gc, int c,
-                                              double* __restrict__ red, double* __restrict__ out) {
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // every group index is a compile-time constant (a guarded, fully unrolled
-    // loop rather than an early exit), so v stays in registers without
-    // run-time indexing
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        if (16 * g <= j) {
-            double p[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) p[u] = v[g][u] * x;
-            const double s = wave_sum_many<16>(p);
-            if ((lane & 3) == 0) red[wave * 16 + (lane >> 2)] = s;
-            __syncthreads();
-            if (tid < 16 && 16 * g + tid <= j)
-                out[(size_t)(16 * g + tid) * gc + c] = red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid];
-            __syncthreads();
         }
     }
 }
@@ -198,30 +176,28 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
     }
 }
 
-// pass 0: z = w - sum h_i V_i and the second-pass dots V_i . z; pass 1:
-// z -= sum h'_i V_i and |z|^2.  The basis values are loaded once per launch.
-// Returns the workgroup's copy of the pass's coefficients (LDS, i <= j).
-__device__ __forceinline__ const double* gm_update(const GmresBufs& b, int M, int c, int pass) {
+// The first Gram-Schmidt pass on chunk c: h_i = sum of the first-pass
+// partials, z = w - sum h_i V_i, and the chunk's |z|^2 and |w|^2.  The basis
+// values are loaded once per launch.
+__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c) {
     __shared__ double hs[kMaxRestart + 2];
     __shared__ double red[64];
     const GmresState* st = b.st;
-    if (st->mode != 1) return hs;
-    const int tid = threadIdx.x, gc = b.gc, j = st->j;
+    const int tid = threadIdx.x, j = st->j, nco = b.gc64;
     const GmPart q = gm_part(b);
-    const double* coef = pass == 0 ? q.d1 : q.d2;
-    const int nco = pass == 0 ? b.gc64 : gc;
     // the basis and vector loads first, then the coefficient partials: all in
     // flight together, one memory round trip
     const int e = c * kGmChunk + tid;
     double v[4][16];
     gm_load_basis(b.V, M, e, j, v);
-    double a = e < M ? (pass == 0 ? b.w[e] : b.z[e]) : 0.0;
+    double a = e < M ? b.w[e] : 0.0;
+    const double a_in = a;
     for (int i = tid; i <= j; i += kGmChunk) {
         double s = 0.0;
 #pragma unroll 16
-        for (int cc = 0; cc < nco; ++cc) s += coef[(size_t)i * nco + cc];   // loads issued together
+        for (int cc = 0; cc < nco; ++cc) s += q.d1[(size_t)i * nco + cc];   // loads issued together
         hs[i] = s;
-        if (pass == 0 && c == 0) q.h1[i] = s;
+        if (c == 0) q.h1[i] = s;
     }
     __syncthreads();
 #pragma unroll
@@ -233,13 +209,12 @@ __device__ __forceinline__ const double* gm_update(const GmresBufs& b, int M, in
         }
     }
     if (e < M) b.z[e] = a;
-    if (pass == 0) {
-        gm_chunk_dots(v, a, j, gc, c, red, q.d2);
-    } else {
-        const double s = gm_block_sum(a * a, red);
-        if (tid == 0) q.nrm[c] = s;
+    const double sz = gm_block_sum(a * a, red);
+    const double sw = gm_block_sum(a_in * a_in, red);
+    if (tid == 0) {
+        q.nrm[c] = sz;
+        q.nrmw[c] = sw;
     }
-    return hs;
 }
 
 // One workgroup of kGmChunk threads; h2: the second-pass coefficients this
@@ -377,24 +352,88 @@ __device__ inline void gm_commit(const GmresBufs& b, const double* h2) {
     }
 }
 
-// upd2 on chunk c, then commit by the workgroup that finishes the problem's
-// last chunk (an atomic count of finished chunks; nobody waits).
-__device__ inline void gm_update2_commit(const GmresBufs& b, int M, int c) {
-    __shared__ int s_last;
-    const int mode = b.st->mode;
-    if (mode == 2) return;
-    const double* h2 = gm_update(b, M, c, 1);
+// Whether this workgroup finished the problem's last chunk of the launch (an
+// atomic count of finished chunks; nobody waits); the last one resets the
+// count for the next launch.  Called by the whole workgroup after its writes.
+__device__ inline bool gm_last_chunk(const GmresBufs& b, int* s_last) {
     if (threadIdx.x == 0) {
         __threadfence();                                   // this chunk's partials before the count
         const unsigned done = atomicAdd(b.cnt, 1u) + 1;
-        s_last = done == (unsigned)b.gc;
-        if (s_last) {
+        *s_last = done == (unsigned)b.gc;
+        if (*s_last) {
             __hip_atomic_store(b.cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __threadfence();                               // the other chunks' partials after it
         }
     }
     __syncthreads();
-    if (s_last) gm_commit(b, h2);
+    return *s_last != 0;
+}
+
+// The second Gram-Schmidt pass over the whole vector by the one workgroup that
+// commits (only when the first pass cancelled below the threshold): h2 = V^T z
+// in groups of sixteen basis vectors, z -= V h2, and |z|^2 left as the only
+// nonzero norm partial.  h2 goes to h2s (LDS).
+__device__ inline void gm_second_pass(const GmresBufs& b, int M, int j, double* h2s, double* red) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        if (16 * g <= j) {
+            double p[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) p[u] = 0.0;
+            for (int e = tid; e < M; e += kGmChunk) {
+                const double ze = b.z[e];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (16 * g + u <= j) p[u] = fma(b.V[(size_t)(16 * g + u) * M + e], ze, p[u]);
+            }
+            const double s = wave_sum_many<16>(p);
+            if ((lane & 3) == 0) red[wave * 16 + (lane >> 2)] = s;
+            __syncthreads();
+            if (tid < 16) h2s[16 * g + tid] = 16 * g + tid <= j ? red[tid] + red[16 + tid] + red[32 + tid] + red[48 + tid] : 0.0;
+            __syncthreads();
+        }
+    }
+    double zz = 0.0;
+    for (int e = tid; e < M; e += kGmChunk) {
+        double a = b.z[e];
+        for (int i = 0; i <= j; ++i) a -= h2s[i] * b.V[(size_t)i * M + e];
+        b.z[e] = a;
+        zz = fma(a, a, zz);
+    }
+    const double tot = gm_block_sum(zz, red);
+    const GmPart q = gm_part(b);
+    for (int cc = tid; cc < b.gc; cc += kGmChunk) q.nrm[cc] = cc == 0 ? tot : 0.0;
+    __syncthreads();
+}
+
+// upd1 on chunk c; the workgroup that finishes the problem's last chunk then
+// commits: a residual step (mode 0) from the residual's norm partials, an
+// Arnoldi step (mode 1) from the first pass, after a second pass of its own
+// when |z| < reorth |w|.
+__device__ inline void gm_update1_commit(const GmresBufs& b, int M, int c) {
+    __shared__ int s_last;
+    __shared__ int s_second;
+    __shared__ double h2s[kMaxRestart + 2];
+    __shared__ double red[64];
+    const int mode = b.st->mode;
+    if (mode == 2) return;
+    if (mode == 1) gm_update(b, M, c);
+    if (!gm_last_chunk(b, &s_last)) return;
+    for (int i = threadIdx.x; i < kMaxRestart + 2; i += kGmChunk) h2s[i] = 0.0;
+    if (mode == 1 && threadIdx.x == 0) {
+        const GmPart q = gm_part(b);
+        double zz = 0.0, ww = 0.0;
+        for (int cc = 0; cc < b.gc; ++cc) {                // fixed order
+            zz += q.nrm[cc];
+            ww += q.nrmw[cc];
+        }
+        const double eta = b.st->reorth;
+        s_second = zz < eta * eta * ww;
+    }
+    __syncthreads();
+    if (mode == 1 && s_second) gm_second_pass(b, M, b.st->j, h2s, red);
+    gm_commit(b, h2s);
 }
 
 // The next K_D input for elements of chunk c, and with taps (the spline filter

@@ -112,6 +112,7 @@ struct GmresState {
     int jn;          // columns of the cycle just finished (kGmCycleEnd)
     int pad;
     double scale;    // 1/beta (new cycle) or 1/h_{j+1,j} (next vector)
+    double reorth;   // second Gram-Schmidt pass when |z| < reorth |w| (0: never, 1: always)
 };
 
 struct GmresBufs {
@@ -207,6 +208,8 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
                         hipStream_t s);
 // taps: the spline filter of the density (null: no spline, the surface problem)
 hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s);
+// default of GmresState::reorth (see gmres.h)
+constexpr double kGmReorthDefault = 1e-3;
 // the same step with the next apply's corrections made in the emit launch
 // (into corr_il, the sparse-sum layout)
 hipError_t launch_gmres_step_corr(const DevPlan& p, GmresBufs b, double* corr_il, hipStream_t s);

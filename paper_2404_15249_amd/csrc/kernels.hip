@@ -176,8 +176,7 @@ __global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const
     reduce_samples64(p, js, partial, G, blockIdx.x * 64, b.w, red);
     gm_dots1_64(b, p.M, blockIdx.x, red, &pre);
 }
-__global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update(b, M, blockIdx.x, 0); }
-__global__ __launch_bounds__(kGmChunk) void k_gm_upd2(GmresBufs b, int M) { gm_update2_commit(b, M, blockIdx.x); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update1_commit(b, M, blockIdx.x); }
 __global__ __launch_bounds__(kGmChunk) void k_gm_emit(const double* taps, GmresBufs b, int M) {
     gm_emit(taps, b, M, blockIdx.x);
 }
@@ -313,14 +312,12 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
 hipError_t launch_gmres_step_corr(const DevPlan& p, GmresBufs b, double* corr_il, hipStream_t s) {
     const dim3 g(b.gc), t(kGmChunk);
     if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, p.M)) return e;
-    if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, p.M)) return e;
     return klaunch(&k_gm_emit_corr, dim3(b.gc + p.n_cc), t, 0, s, p, b, corr_il);
 }
 
 hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s) {
     const dim3 g(b.gc), t(kGmChunk);
     if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, M)) return e;
-    if (hipError_t e = klaunch(&k_gm_upd2, g, t, 0, s, b, M)) return e;
     return klaunch(&k_gm_emit, g, t, 0, s, taps, b, M);
 }
 

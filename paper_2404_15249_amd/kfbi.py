@@ -127,6 +127,7 @@ _sigs = {
     "kfbi_gs_set_state": [_vp, _vp, _vp, _vp, _vp],
     "kfbi_gs_get_state": [_vp, _vp, _vp, _vp, _vp],
     "kfbi_gs_step": [_vp, ct.c_int],
+    "kfbi_prob_set_reorth": [_vp, ct.c_double],
     "kfbi_set_timing": [_vp, ct.c_int],
     "kfbi_apply_timing": [_vp, ct.POINTER(ct.c_double), ct.POINTER(ct.c_double), ct.POINTER(ct.c_double),
                           ct.POINTER(ct.c_int)],
@@ -322,6 +323,10 @@ class Problem:
                                         int(max_iter), ct.byref(it), ct.byref(ap), ct.byref(rel)),
                         allow=(OK, NOT_CONVERGED))
         return phi, it.value, ap.value, rel.value, st == OK
+
+    def set_reorth(self, eta: float):
+        """Threshold of the second Gram-Schmidt pass (``kfbi_prob_set_reorth``)."""
+        _check(_lib.kfbi_prob_set_reorth(self._h, float(eta)))
 
     # ---- Table 2's other outer iterations
     def richardson(self, rhs, phi0=None, gamma=1.0, tol=1e-10, max_iter=500):

@@ -210,3 +210,21 @@ def test_gmres_with_corrections_in_the_emit_launch(K, ctx, name):
     prob.set_timing(False)
     assert it_a == it_b == 60
     assert relerr(host(a), host(b)) < 1e-13
+
+
+@pytest.mark.parametrize("eta", [0.0, 1.0])
+def test_solve_with_and_without_the_second_gram_schmidt_pass(K, ctx, eta):
+    """The second Gram-Schmidt pass, made on every step (eta = 1, by the
+    committing workgroup) or never (eta = 0), gives the oracle's solution and
+    iteration count, as the default threshold does."""
+    p = CASES["star512"]()
+    note(f"solve with reorth eta={eta}")
+    prob = K.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-12)
+    prob.set_reorth(eta)
+    u, ug, phi, it, rel, conv = prob.solve(dev(p.f_grid), dev(p.f_gamma), dev(p.g))
+    ref = O.solve_bvp(p.xy, p.n, LO, HI, p.kappa, p.f_grid, p.f_gamma, p.g, tol=1e-12)
+    assert conv and rel < 1e-12 and abs(it - ref.iters) <= 1
+    assert relerr(host(u), ref.u_grid) < 1e-10
+    assert relerr(host(phi), ref.phi) < 1e-10
+    with pytest.raises(K.KfbiError):
+        prob.set_reorth(1.5)
