@@ -260,7 +260,7 @@ def three_d(ctx, sizes=(64, 128), steps: int = 200) -> dict:
                         "control points = grid-edge crossings; step = one GMRES iteration", "rows": rows}
 
 
-def neumann(ctx, n: int = 2048, steps: int = 400, sizes=(512, 1024, 2048)) -> dict:
+def neumann(ctx, n: int = 2048, steps: int = 400, sizes=(512, 1024, 2048), cpu: bool = True) -> dict:
     """The Neumann problem d_n u = g_n on the star workload (kappa = 1, M = N/2,
     u = sin(pi x) cos(pi y) + x^2): graphed GMRES steps on K_N (grid unknowns per
     second per step, as the headline's K_D step), a full FP64 solve to 1e-10,
@@ -284,6 +284,17 @@ def neumann(ctx, n: int = 2048, steps: int = 400, sizes=(512, 1024, 2048)) -> di
     res = {"workload": f"Neumann problem on the star r=0.6+0.15 sin 5t, kappa=1, M=N/2, "
                        f"u=sin(pi x)cos(pi y)+x^2; step = one GMRES iteration on K_N at {n}x{n}",
            "us_per_step": 1e6 * dt / steps, "unknowns_per_s": unknowns * steps / dt}
+    if cpu:
+        # the oracle's K_N apply on the same problem, beside it (one host core)
+        from oracle import kfbi_oracle as O
+        plan = O.build_plan(p.xy, p.n, p.lo, p.hi)
+        psi = synth.smooth_density(plan.M, 5)
+        O.apply_KN(plan, psi, p.kappa)
+        t0 = time.perf_counter()
+        for _ in range(3):
+            O.apply_KN(plan, psi, p.kappa)
+        res["cpu_oracle"] = {"us_per_apply": 1e6 * (time.perf_counter() - t0) / 3, "cores": 1, "kind": "oracle",
+                             "sample": f"3 oracle K_N applies at {n}x{n}"}
     rows = []
     for m in sizes:
         q = synth.star_neumann_problem(n=m, kappa=1.0)
@@ -316,7 +327,7 @@ PAPER_ITER_GPU_S = {"richardson": {512: 0.19, 1024: 0.27, 2048: 0.66, 4096: 1.65
                     "bicgstab": {512: 0.45, 1024: 0.45, 2048: 0.63, 4096: 1.01}}
 
 
-def iterations(ctx, sizes=(512, 1024, 2048, 4096)) -> dict:
+def iterations(ctx, sizes=(512, 1024, 2048, 4096), cpu: bool = True) -> dict:
     """Table 2: the Dirichlet problem of Example 1 (Laplace on the circle r = 1 in
     (-1.2, 1.2)^2, u = e^x cos y + e^y sin x, M = n samples) solved with GMRES,
     BiCGSTAB and Richardson (gamma = 1) to the paper's tolerance 1e-8: the time
@@ -346,7 +357,19 @@ def iterations(ctx, sizes=(512, 1024, 2048, 4096)) -> dict:
                          "linf_err": float(np.max(np.abs(u.cpu().numpy() - exact)[mask])),
                          "paper_gpu_s": PAPER_ITER_GPU_S[method][n]})
         prob.close()
-    return {"workload": "Example 1: Laplace on the circle r=1 in (-1.2,1.2)^2, u=e^x cos y+e^y sin x, M=n, "
+    out = {}
+    if cpu:
+        # the oracle's solves of the smallest size with each method, beside them (one host core)
+        from oracle import kfbi_oracle as O
+        n = sizes[0]
+        p = synth.make_problem(f"circle r=1 n={n}", synth.circle_points(n, 1.0), n, 0.0, synth.PAPER_EX1)
+        ms = {}
+        for method in ("gmres", "bicgstab", "richardson"):
+            t0 = time.perf_counter()
+            O.solve_bvp(p.xy, p.n, p.lo, p.hi, 0.0, p.f_grid, p.f_gamma, p.g, tol=1e-8, method=method)
+            ms[method] = 1e3 * (time.perf_counter() - t0)
+        out["cpu_oracle"] = {"solve_ms": ms, "cores": 1, "kind": "oracle", "sample": f"one oracle solve per method at {n}x{n}"}
+    return {**out, "workload": "Example 1: Laplace on the circle r=1 in (-1.2,1.2)^2, u=e^x cos y+e^y sin x, M=n, "
                         "tol 1e-8; iters: GMRES and Richardson count K_D applies, BiCGSTAB its iterations "
                         "(two applies each); paper_gpu_s is the paper's own machine (context)",
             "rows": rows}
@@ -357,7 +380,7 @@ def iterations(ctx, sizes=(512, 1024, 2048, 4096)) -> dict:
 PAPER_GS_GPU_S = {128: 0.40, 256: 1.04, 512: 3.29, 1024: 12.07}
 
 
-def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: float = 1.0) -> dict:
+def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: float = 1.0, cpu: bool = True) -> dict:
     """Example 3: Gray-Scott on the disk r = 1.8 in (-2, 2)^2 with the paper's
     parameters, Strang splitting, GMRES tol 1e-8, at the grid sizes and step
     counts of the paper's table (final time T = 1).  The timed region is the time
@@ -397,7 +420,20 @@ def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: flo
             row["paper_gpu_s"] = PAPER_GS_GPU_S[n]
             row["paper_gpu_s_over_this"] = PAPER_GS_GPU_S[n] / run_s
         rows.append(row)
-    return {"workload": "Gray-Scott (Example 3): disk r=1.8 in (-2,2)^2, gamma=0.024, kill=0.06, eps0=0.01, "
+    out = {}
+    if cpu:
+        # the oracle's Strang steps on the smallest configuration, beside it (one host core)
+        from oracle import gray_scott as G
+        from oracle import kfbi_oracle as O
+        n, steps = configs[0]
+        xy = synth.gray_scott_samples(n)
+        plan = O.build_plan(xy, n, lo, hi)
+        st = G.initial_state(plan, synth.gray_scott_initial)
+        t0 = time.perf_counter()
+        G.run(plan, st, T / steps, steps, synth.GrayScottParams(), tol=1e-8)
+        out["cpu_oracle"] = {"ms_per_step": 1e3 * (time.perf_counter() - t0) / steps, "cores": 1, "kind": "oracle",
+                             "sample": f"{steps} oracle steps at {n}x{n} (T = {T})"}
+    return {**out, "workload": "Gray-Scott (Example 3): disk r=1.8 in (-2,2)^2, gamma=0.024, kill=0.06, eps0=0.01, "
                         "eps1=0.008, eps2=0.004, T=1, Strang splitting (RK4 reaction half steps, Crank-Nicolson "
                         "diffusion as two warm-started Neumann solves per step), GMRES tol 1e-8; "
                         "paper_gpu_s is the paper's own machine (context)",
@@ -495,14 +531,15 @@ def main():
     if args.mode == "3d":
         print(json.dumps(three_d(ctx)), flush=True)
         return
+    cpu = args.cpu_baseline == "on"
     if args.mode == "neumann":
-        print(json.dumps(neumann(ctx, args.n)), flush=True)
+        print(json.dumps(neumann(ctx, args.n, cpu=cpu)), flush=True)
         return
     if args.mode == "gray_scott":
-        print(json.dumps(gray_scott(ctx)), flush=True)
+        print(json.dumps(gray_scott(ctx, cpu=cpu)), flush=True)
         return
     if args.mode == "iterations":
-        print(json.dumps(iterations(ctx)), flush=True)
+        print(json.dumps(iterations(ctx, cpu=cpu)), flush=True)
         return
     if args.mode == "serving":
         print(json.dumps(serving_line(ctx, args)), flush=True)
@@ -602,12 +639,13 @@ def main():
         out["mixed"] = mixed_precision(ctx, args.n)
     if args.three_d == "on":
         out["three_d"] = three_d(ctx)
+    cpu = args.cpu_baseline == "on"
     if args.neumann == "on":
-        out["neumann"] = neumann(ctx, args.n)
+        out["neumann"] = neumann(ctx, args.n, cpu=cpu)
     if args.gray_scott == "on":
-        out["gray_scott"] = gray_scott(ctx)
+        out["gray_scott"] = gray_scott(ctx, cpu=cpu)
     if args.iterations == "on":
-        out["iterations"] = iterations(ctx)
+        out["iterations"] = iterations(ctx, cpu=cpu)
     if args.serving_requests > 0:
         out["serving"] = serving(ctx, args.serving_requests, args.serving_seed)
     if args.cpu_baseline == "on":
