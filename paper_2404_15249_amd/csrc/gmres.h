@@ -34,17 +34,15 @@ enum GmKind { kGmNewCycle = 0, kGmNextVector = 1, kGmCycleEnd = 2, kGmDone = 3 }
 __host__ __device__ inline int gm_chunks(int M) { return (M + kGmChunk - 1) / kGmChunk; }
 __host__ __device__ inline int gm_chunks64(int M) { return (M + 63) / 64; }
 // doubles of partial sums a problem needs: first-pass dots (m+1) x gc64, norms
-// of the update (gc), of the residual (gc64) and of the apply's output (gc),
-// and the first-pass coefficients (m+1)
+// of the update (gc), of the residual (gc64) and of the apply's output (gc)
 __host__ __device__ inline size_t gm_part_size(int m, int gc, int gc64) {
-    return (size_t)(m + 1) * (gc64 + 1) + 2 * gc + gc64;
+    return (size_t)(m + 1) * gc64 + 2 * gc + gc64;
 }
 
 struct GmPart {
     double* d1;     // [i * gc64 + c64]
     double* nrm;    // [c]
     double* nrm0;   // [c64]
-    double* h1;     // [i]: sum of d1 over the chunks (written by chunk 0 of the first update)
     double* nrmw;   // [c]: |w|^2 of the chunk (first update)
 };
 __device__ __forceinline__ GmPart gm_part(const GmresBufs& b) {
@@ -52,10 +50,38 @@ __device__ __forceinline__ GmPart gm_part(const GmresBufs& b) {
     q.d1 = b.part;
     q.nrm = q.d1 + (size_t)(b.m + 1) * b.gc64;
     q.nrm0 = q.nrm + b.gc;
-    q.h1 = q.nrm0 + b.gc64;
-    q.nrmw = q.h1 + (b.m + 1);
+    q.nrmw = q.nrm0 + b.gc64;
     return q;
 }
+
+// The state an update launch works from, read once at its start: only the
+// commit writes the state, after every workgroup of the launch has read it.
+struct GmSnap {
+    int mode, j, it, first, max_iter;
+    double r0, tol, reorth;
+};
+__device__ __forceinline__ GmSnap gm_snap(const GmresState* st) {
+    GmSnap s;
+    s.mode = st->mode;
+    s.j = st->j;
+    s.it = st->it;
+    s.first = st->first;
+    s.max_iter = st->max_iter;
+    s.r0 = st->r0;
+    s.tol = st->tol;
+    s.reorth = st->reorth;
+    return s;
+}
+
+// What the commit of an Arnoldi step reads besides the norms: the first-pass
+// coefficients, the previous rotations and g_j.  Every workgroup of the update
+// loads them beside its basis values (none changes before the commit), so the
+// one that commits has them at hand.
+struct GmCommitIn {
+    double h1[kMaxRestart + 2];
+    double cs[kMaxRestart], sn[kMaxRestart];
+    double gj;
+};
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -177,35 +203,43 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
 }
 
 // The first Gram-Schmidt pass on chunk c: h_i = sum of the first-pass
-// partials, z = w - sum h_i V_i, and the chunk's |z|^2 and |w|^2.  The basis
-// values are loaded once per launch.
-__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c) {
-    __shared__ double hs[kMaxRestart + 2];
-    __shared__ double red[64];
-    const GmresState* st = b.st;
-    const int tid = threadIdx.x, j = st->j, nco = b.gc64;
+// partials (into ci.h1, with the commit's other operands), z = w - sum h_i
+// V_i, and the chunk's |z|^2 and |w|^2.  The basis values are loaded once per
+// launch.
+__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int j, GmCommitIn& ci, double* red) {
+    const int tid = threadIdx.x, nco = b.gc64;
     const GmPart q = gm_part(b);
-    // the basis and vector loads first, then the coefficient partials: all in
-    // flight together, one memory round trip
+    // the basis and vector loads first, then the coefficient partials and the
+    // commit's operands: all in flight together, one memory round trip
     const int e = c * kGmChunk + tid;
     double v[4][16];
     gm_load_basis(b.V, M, e, j, v);
     double a = e < M ? b.w[e] : 0.0;
     const double a_in = a;
+    double csv = 0.0, snv = 0.0, gj = 0.0;
+    if (tid < j) {
+        csv = b.cs[tid];
+        snv = b.sn[tid];
+    }
+    if (tid == 0) gj = b.g[j];
     for (int i = tid; i <= j; i += kGmChunk) {
         double s = 0.0;
 #pragma unroll 16
         for (int cc = 0; cc < nco; ++cc) s += q.d1[(size_t)i * nco + cc];   // loads issued together
-        hs[i] = s;
-        if (c == 0) q.h1[i] = s;
+        ci.h1[i] = s;
     }
+    if (tid < j) {
+        ci.cs[tid] = csv;
+        ci.sn[tid] = snv;
+    }
+    if (tid == 0) ci.gj = gj;
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if (16 * g <= j) {
 #pragma unroll
             for (int u = 0; u < 16; ++u)
-                if (16 * g + u <= j) a -= hs[16 * g + u] * v[g][u];
+                if (16 * g + u <= j) a -= ci.h1[16 * g + u] * v[g][u];
         }
     }
     if (e < M) b.z[e] = a;
@@ -217,71 +251,55 @@ __device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c) {
     }
 }
 
-// One workgroup of kGmChunk threads; h2: the second-pass coefficients this
-// workgroup's update left in LDS (mode 1).
-__device__ inline void gm_commit(const GmresBufs& b, const double* h2) {
-    __shared__ double red[4];
+// Commit of a residual step (mode 0), by one workgroup of kGmChunk threads:
+// beta = |ghat - K phi| from the partials the apply's reduction left, then the
+// end of the solve or a new cycle.
+__device__ inline void gm_commit_residual(const GmresBufs& b, const GmSnap& s, double* red) {
+    const int tid = threadIdx.x, m = b.m;
+    const GmPart q = gm_part(b);
+    double v = 0.0;
+    for (int cc = tid; cc < b.gc64; cc += kGmChunk) v += q.nrm0[cc];
+    const double beta = sqrt(gm_block_sum(v, red));
+    if (tid != 0) return;
+    GmresState* st = b.st;
+    const double r0 = s.first ? beta : s.r0;
+    const double rel = r0 > 0.0 ? beta / r0 : 0.0;
+    const bool done = r0 == 0.0 || beta == 0.0 || rel < s.tol || s.it >= s.max_iter;
+    st->r0 = r0;
+    st->first = 0;
+    st->relres = rel;
+    if (done) {
+        st->converged = (r0 == 0.0 || beta == 0.0 || rel < s.tol) ? 1 : -1;
+        st->mode = 2;
+        st->kind = kGmDone;
+    } else {
+        b.g[0] = beta;
+        for (int k = 1; k <= m; ++k) b.g[k] = 0.0;
+        st->j = 0;
+        st->mode = 1;
+        st->cycles += 1;
+        st->kind = kGmNewCycle;
+        st->scale = 1.0 / beta;
+    }
+}
+
+// Commit of an Arnoldi step (mode 1), by one workgroup of kGmChunk threads:
+// column j of the Hessenberg matrix (h1 + h2 from the two Gram-Schmidt
+// passes, h_{j+1,j} = hn), the previous rotations down it and a new one, the
+// residual estimate, the state transition, and at the end of a cycle the
+// triangular solve.
+__device__ inline void gm_commit_arnoldi(const GmresBufs& b, const GmSnap& s, const GmCommitIn& ci,
+                                         const double* h2, double hn) {
     __shared__ double col[kMaxRestart + 2];
-    __shared__ double cs_s[kMaxRestart], sn_s[kMaxRestart], rot[kMaxRestart];
+    __shared__ double rot[kMaxRestart];
     __shared__ double Hs[kMaxRestart * (kMaxRestart + 1)];
     __shared__ int s_end;
     GmresState* st = b.st;
-    const int mode = st->mode;
-    if (mode == 2) return;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int m = b.m, gc = b.gc, gc64 = b.gc64, j = st->j, it = st->it, first = st->first;
-    const int max_iter = st->max_iter;
-    const double r0_in = st->r0, tol = st->tol;
-    const GmPart q = gm_part(b);
-    const double* norm = mode == 0 ? q.nrm0 : q.nrm;
-    const int nn = mode == 0 ? gc64 : gc;
-    // every load first: the norm partials, the Hessenberg column (first-pass
-    // coefficients plus this workgroup's second-pass ones), the rotations
-    double v = 0.0;
-    for (int cc = tid; cc < nn; cc += kGmChunk) v += norm[cc];
-    double colv = 0.0, csv = 0.0, snv = 0.0;
-    if (mode == 1) {
-        if (tid <= j) colv = q.h1[tid] + h2[tid];
-        if (tid < j) {
-            csv = b.cs[tid];
-            snv = b.sn[tid];
-        }
-    }
-    const double nrm = sqrt(gm_block_sum(v, red));
-    if (mode == 0) {
-        if (tid == 0) {
-            const double beta = nrm;
-            const double r0 = first ? beta : r0_in;
-            const double rel = r0 > 0.0 ? beta / r0 : 0.0;
-            const bool done = r0 == 0.0 || beta == 0.0 || rel < tol || it >= max_iter;
-            st->r0 = r0;
-            st->first = 0;
-            st->relres = rel;
-            if (done) {
-                st->converged = (r0 == 0.0 || beta == 0.0 || rel < tol) ? 1 : -1;
-                st->mode = 2;
-                st->kind = kGmDone;
-            } else {
-                b.g[0] = beta;
-                for (int k = 1; k <= m; ++k) b.g[k] = 0.0;
-                st->j = 0;
-                st->mode = 1;
-                st->cycles += 1;
-                st->kind = kGmNewCycle;
-                st->scale = 1.0 / beta;
-            }
-        }
-        return;
-    }
-    // mode 1: column j of the Hessenberg matrix from the two Gram-Schmidt passes
-    if (tid <= j) col[tid] = colv;
-    if (tid < j) {
-        cs_s[tid] = csv;
-        sn_s[tid] = snv;
-    }
+    const int m = b.m, j = s.j;
+    if (tid <= j) col[tid] = ci.h1[tid] + h2[tid];
     __syncthreads();
     if (tid == 0) {
-        const double hn = nrm;
         // previous rotations down the column, eight at a time: their operands
         // are read together; the rotated entries go to rot[]
         double a = col[0];
@@ -291,8 +309,8 @@ __device__ inline void gm_commit(const GmresBufs& b, const double* h2) {
             for (int u = 0; u < 8; ++u) {
                 const bool in = i0 + u < j;
                 cn[u] = in ? col[i0 + u + 1] : 0.0;
-                c8[u] = in ? cs_s[i0 + u] : 1.0;
-                s8[u] = in ? sn_s[i0 + u] : 0.0;
+                c8[u] = in ? ci.cs[i0 + u] : 1.0;
+                s8[u] = in ? ci.sn[i0 + u] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -310,14 +328,14 @@ __device__ inline void gm_commit(const GmresBufs& b, const double* h2) {
         col[j + 1] = 0.0;
         b.cs[j] = cs;
         b.sn[j] = sn;
-        const double gj = b.g[j];
+        const double gj = ci.gj;
         b.g[j + 1] = -sn * gj;
         b.g[j] = cs * gj;
-        const int jn = j + 1, itn = it + 1;
-        const double est = fabs(sn * gj) / r0_in;
+        const int jn = j + 1, itn = s.it + 1;
+        const double est = fabs(sn * gj) / s.r0;
         st->relres = est;
         st->it = itn;
-        const bool end = est < tol || jn == m || itn >= max_iter || hn == 0.0;
+        const bool end = est < s.tol || jn == m || itn >= s.max_iter || hn == 0.0;
         s_end = end ? 1 : 0;
         st->jn = jn;
         if (end) {
@@ -356,6 +374,11 @@ __device__ inline void gm_commit(const GmresBufs& b, const double* h2) {
 // atomic count of finished chunks; nobody waits); the last one resets the
 // count for the next launch.  Called by the whole workgroup after its writes.
 __device__ inline bool gm_last_chunk(const GmresBufs& b, int* s_last) {
+    // every wavefront's stores (z, which a second pass of the committing
+    // workgroup reads) complete before thread 0's fence publishes them: the
+    // workgroup barrier alone does not wait for them
+    __builtin_amdgcn_s_waitcnt(0x0F70);                    // vmcnt(0) (expcnt, lgkmcnt not waited)
+    __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();                                   // this chunk's partials before the count
         const unsigned done = atomicAdd(b.cnt, 1u) + 1;
@@ -371,9 +394,9 @@ __device__ inline bool gm_last_chunk(const GmresBufs& b, int* s_last) {
 
 // The second Gram-Schmidt pass over the whole vector by the one workgroup that
 // commits (only when the first pass cancelled below the threshold): h2 = V^T z
-// in groups of sixteen basis vectors, z -= V h2, and |z|^2 left as the only
-// nonzero norm partial.  h2 goes to h2s (LDS).
-__device__ inline void gm_second_pass(const GmresBufs& b, int M, int j, double* h2s, double* red) {
+// in groups of sixteen basis vectors, z -= V h2; returns the new |z|^2.  h2
+// goes to h2s (LDS).
+__device__ inline double gm_second_pass(const GmresBufs& b, int M, int j, double* h2s, double* red) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -401,10 +424,7 @@ __device__ inline void gm_second_pass(const GmresBufs& b, int M, int j, double* 
         b.z[e] = a;
         zz = fma(a, a, zz);
     }
-    const double tot = gm_block_sum(zz, red);
-    const GmPart q = gm_part(b);
-    for (int cc = tid; cc < b.gc; cc += kGmChunk) q.nrm[cc] = cc == 0 ? tot : 0.0;
-    __syncthreads();
+    return gm_block_sum(zz, red);
 }
 
 // upd1 on chunk c; the workgroup that finishes the problem's last chunk then
@@ -414,26 +434,33 @@ __device__ inline void gm_second_pass(const GmresBufs& b, int M, int j, double* 
 __device__ inline void gm_update1_commit(const GmresBufs& b, int M, int c) {
     __shared__ int s_last;
     __shared__ int s_second;
+    __shared__ double s_zz;
     __shared__ double h2s[kMaxRestart + 2];
     __shared__ double red[64];
-    const int mode = b.st->mode;
-    if (mode == 2) return;
-    if (mode == 1) gm_update(b, M, c);
+    __shared__ GmCommitIn ci;
+    const GmSnap s = gm_snap(b.st);
+    if (s.mode == 2) return;
+    if (s.mode == 1) gm_update(b, M, c, s.j, ci, red);
     if (!gm_last_chunk(b, &s_last)) return;
+    if (s.mode == 0) {
+        gm_commit_residual(b, s, red);
+        return;
+    }
     for (int i = threadIdx.x; i < kMaxRestart + 2; i += kGmChunk) h2s[i] = 0.0;
-    if (mode == 1 && threadIdx.x == 0) {
+    if (threadIdx.x == 0) {
         const GmPart q = gm_part(b);
         double zz = 0.0, ww = 0.0;
+#pragma unroll 8
         for (int cc = 0; cc < b.gc; ++cc) {                // fixed order
             zz += q.nrm[cc];
             ww += q.nrmw[cc];
         }
-        const double eta = b.st->reorth;
-        s_second = zz < eta * eta * ww;
+        s_second = zz < s.reorth * s.reorth * ww;
+        s_zz = zz;
     }
     __syncthreads();
-    if (mode == 1 && s_second) gm_second_pass(b, M, b.st->j, h2s, red);
-    gm_commit(b, h2s);
+    const double zz = s_second ? gm_second_pass(b, M, s.j, h2s, red) : s_zz;
+    gm_commit_arnoldi(b, s, ci, h2s, sqrt(zz));
 }
 
 // The next K_D input for elements of chunk c, and with taps (the spline filter
