@@ -57,10 +57,9 @@ struct J6 {
 //   [v] = D, [d_n v] = 0 (Sec. 2.2):  [v_tau] = D_s, [v_tautau] = D_ss, [v_taun] = -c D_s;
 //   [v] = 0, [d_n v] = D (Neumann):   [v_n] = D, [v_tautau] = c D, [v_taun] = D_s;
 // and the equation gives [v_nn] = [F] + kappa [v] - [v_tautau].
-__device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSrc& js) {
-    double P = 0.0, P1 = 0.0, P2 = 0.0, F = 0.0, t1, t2;
-    if (js.phi) spline_at(js.phi, js.phi_s2, p, g.seg, g.u, P, P1, P2);
-    if (js.fgam) spline_at(js.fgam, js.fgam_s2, p, g.seg, g.u, F, t1, t2);
+// P, P1, P2: the density's spline value and parameter derivatives at the
+// point; F: the jump of f there.
+__device__ inline J6 jumps_from(const DevPlan& p, const PointGeom& g, double P, double P1, double P2, double F) {
     const double Ps = P1 * g.a1;
     J6 J;
     if (p.normal_jump) {
@@ -82,6 +81,14 @@ __device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSr
     J.hxy = vtt * g.tx * g.ty + vtn * (g.tx * g.ny + g.nx * g.ty) + vnn * g.nx * g.ny;
     J.hyy = vtt * g.ty * g.ty + 2.0 * vtn * g.ty * g.ny + vnn * g.ny * g.ny;
     return J;
+}
+
+// The same at the point of segment g.seg, offset g.u, from the densities' splines.
+__device__ inline J6 jumps_at(const DevPlan& p, const PointGeom& g, const JumpSrc& js) {
+    double P = 0.0, P1 = 0.0, P2 = 0.0, F = 0.0, t1, t2;
+    if (js.phi) spline_at(js.phi, js.phi_s2, p, g.seg, g.u, P, P1, P2);
+    if (js.fgam) spline_at(js.fgam, js.fgam_s2, p, g.seg, g.u, F, t1, t2);
+    return jumps_from(p, g, P, P1, P2, F);
 }
 
 // ---------------------------------------------------------------- tridiagonal mode solve (Alg. 4)
@@ -262,24 +269,39 @@ __device__ __forceinline__ void mode_solve_lds(double* x, const ModeConst& mc, i
 }
 
 // Jump terms of the stencil nodes outside Omega: the far-side value is moved to
-// the Omega side with the Taylor expansion of the jumps at the sample.
+// the Omega side with the Taylor expansion of the jumps at the sample.  Every
+// load is issued before any is used: sample cp is the knot that starts spline
+// segment cp (u = 0, as the plan builds it), so the density's values there do
+// not wait for the sample's geometry.
 __device__ inline double outside_terms(const DevPlan& p, const JumpSrc& js, int cp, const int (&ni)[6], const int (&nj)[6],
                                 const double* __restrict__ w) {
     const unsigned char* o6 = p.cp_out + 6 * (size_t)cp;
-    if (!(o6[0] | o6[1] | o6[2] | o6[3] | o6[4] | o6[5])) return 0.0;
+    unsigned char o[6];
+    double wk[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        o[k] = o6[k];
+        wk[k] = w[k];
+    }
+    const PointGeom g = p.z_geo[cp];
+    const double zx = p.zx[cp], zy = p.zy[cp];
     J6 J;
     if (js.jz) {
         const double* q = js.jz + 6 * (size_t)cp;
         J = {q[0], q[1], q[2], q[3], q[4], q[5]};
     } else {
-        J = jumps_at(p, p.z_geo[cp], js);
+        double P = 0.0, P1 = 0.0, P2 = 0.0, F = 0.0, t1, t2;
+        if (js.phi) spline_at(js.phi, js.phi_s2, p, cp, 0.0, P, P1, P2);
+        if (js.fgam) spline_at(js.fgam, js.fgam_s2, p, cp, 0.0, F, t1, t2);
+        J = jumps_from(p, g, P, P1, P2, F);
     }
-    const double zx = p.zx[cp], zy = p.zy[cp];
+    if (!(o[0] | o[1] | o[2] | o[3] | o[4] | o[5])) return 0.0;
     double s = 0.0;
+#pragma unroll
     for (int k = 0; k < 6; ++k) {
-        if (!o6[k]) continue;
+        if (!o[k]) continue;
         const double dx = p.lo + ni[k] * p.h - zx, dy = p.lo + nj[k] * p.h - zy;
-        s += w[k] * (J.v + dx * J.gx + dy * J.gy + 0.5 * (dx * dx * J.hxx + 2.0 * dx * dy * J.hxy + dy * dy * J.hyy));
+        s += wk[k] * (J.v + dx * J.gx + dy * J.gy + 0.5 * (dx * dx * J.hxx + 2.0 * dx * dy * J.hxy + dy * dy * J.hyy));
     }
     return s;
 }
