@@ -202,49 +202,62 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
     }
 }
 
-// The first Gram-Schmidt pass on chunk c: h_i = sum of the first-pass
-// partials (into ci.h1, with the commit's other operands), z = w - sum h_i
-// V_i, and the chunk's |z|^2 and |w|^2.  The basis values are loaded once per
-// launch.
-__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int j, GmCommitIn& ci, double* red) {
-    const int tid = threadIdx.x, nco = b.gc64;
-    const GmPart q = gm_part(b);
-    // the basis and vector loads first, then the coefficient partials and the
-    // commit's operands: all in flight together, one memory round trip
-    const int e = c * kGmChunk + tid;
+// What one update workgroup loads, requested before the state is known: the
+// basis values at its element for every row that can be in use (i < m; rows
+// past the current column are loaded and not used), w, and per thread i < m
+// row i's first-pass dot partials summed, the rotation (c_i, s_i) and g_i.
+struct GmUpdIn {
     double v[4][16];
-    gm_load_basis(b.V, M, e, j, v);
-    double a = e < M ? b.w[e] : 0.0;
-    const double a_in = a;
-    double csv = 0.0, snv = 0.0, gj = 0.0;
-    if (tid < j) {
-        csv = b.cs[tid];
-        snv = b.sn[tid];
-    }
-    if (tid == 0) gj = b.g[j];
-    for (int i = tid; i <= j; i += kGmChunk) {
-        double s = 0.0;
+    double w;
+    double h, cs, sn, g;
+};
+__device__ __forceinline__ GmUpdIn gm_update_loads(const GmresBufs& b, int M, int c) {
+    const int tid = threadIdx.x, m = b.m, nco = b.gc64;
+    const GmPart q = gm_part(b);
+    const int e = c * kGmChunk + tid;
+    GmUpdIn u;
+    gm_load_basis(b.V, M, e, m - 1, u.v);
+    u.w = e < M ? b.w[e] : 0.0;
+    u.h = u.cs = u.sn = u.g = 0.0;
+    if (tid < m) {
+        u.cs = b.cs[tid];
+        u.sn = b.sn[tid];
+        u.g = b.g[tid];
+        double sum = 0.0;
 #pragma unroll 16
-        for (int cc = 0; cc < nco; ++cc) s += q.d1[(size_t)i * nco + cc];   // loads issued together
-        ci.h1[i] = s;
+        for (int cc = 0; cc < nco; ++cc) sum += q.d1[(size_t)tid * nco + cc];   // loads issued together
+        u.h = sum;
     }
+    return u;
+}
+
+// The first Gram-Schmidt pass on chunk c from the loads above: h_i (into
+// ci.h1, with the commit's other operands), z = w - sum h_i V_i, and the
+// chunk's |z|^2 and |w|^2.
+__device__ __forceinline__ void gm_update(const GmresBufs& b, int M, int c, int j, const GmUpdIn& u, GmCommitIn& ci,
+                                          double* red) {
+    const int tid = threadIdx.x;
+    const GmPart q = gm_part(b);
+    const int e = c * kGmChunk + tid;
+    if (tid <= j) ci.h1[tid] = u.h;
     if (tid < j) {
-        ci.cs[tid] = csv;
-        ci.sn[tid] = snv;
+        ci.cs[tid] = u.cs;
+        ci.sn[tid] = u.sn;
     }
-    if (tid == 0) ci.gj = gj;
+    if (tid == j) ci.gj = u.g;
     __syncthreads();
+    double a = u.w;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         if (16 * g <= j) {
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                if (16 * g + u <= j) a -= ci.h1[16 * g + u] * v[g][u];
+            for (int k = 0; k < 16; ++k)
+                if (16 * g + k <= j) a -= ci.h1[16 * g + k] * u.v[g][k];
         }
     }
     if (e < M) b.z[e] = a;
     const double sz = gm_block_sum(a * a, red);
-    const double sw = gm_block_sum(a_in * a_in, red);
+    const double sw = gm_block_sum(u.w * u.w, red);
     if (tid == 0) {
         q.nrm[c] = sz;
         q.nrmw[c] = sw;
@@ -438,9 +451,10 @@ __device__ inline void gm_update1_commit(const GmresBufs& b, int M, int c) {
     __shared__ double h2s[kMaxRestart + 2];
     __shared__ double red[64];
     __shared__ GmCommitIn ci;
+    const GmUpdIn u = gm_update_loads(b, M, c);
     const GmSnap s = gm_snap(b.st);
     if (s.mode == 2) return;
-    if (s.mode == 1) gm_update(b, M, c, s.j, ci, red);
+    if (s.mode == 1) gm_update(b, M, c, s.j, u, ci, red);
     if (!gm_last_chunk(b, &s_last)) return;
     if (s.mode == 0) {
         gm_commit_residual(b, s, red);
