@@ -857,6 +857,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         (st = upload(p, &dp.sinq, sinq)) || (st = upload(p, &dp.modes, mode_constants(n, P.h, p->kappa))) ||
         (st = upload(p, &dp.taps, spline_filter_taps(K))))
         return fail(st);
+    for (int w = 0; w <= kModeWaves; ++w) dp.sub_offv[w] = sub_off[w];
     const int M = p->M, m = p->restart;
     if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->corr_il, (size_t)dp.T * 64)) || (st = dev_alloc(p, &p->partial, (size_t)p->Gcap * M)) ||
         (st = dev_alloc(p, &p->R, (size_t)n * n)) || (st = dev_alloc(p, &p->A, (size_t)n * n)) ||

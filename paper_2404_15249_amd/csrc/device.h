@@ -7,6 +7,21 @@
 
 namespace kfbi {
 
+// A flag or state word another launch wrote, read through the vector memory
+// path: such loads are waited for only where the value is used, where a scalar
+// load here is waited for at once, before the loads issued after it.
+__device__ __forceinline__ int load_flag(const int* f) {
+    // a global (not flat) load: a flat load also counts as a scalar-memory
+    // access, so the next wait for the kernel's arguments would wait for it too
+    using global_int = __attribute__((address_space(1))) int;
+    return __hip_atomic_load((global_int*)f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// A flag that is never set, read in place of a null one (a load from one of two
+// addresses, with no branch that would wait for it).
+static __device__ const int kFlagZero = 0;
+__device__ __forceinline__ int load_flag_or_zero(const int* f) { return load_flag(f ? f : &kFlagZero); }
+
+
 // sin(pi m / N), 0 <= m < 2N, from the quarter-period table sq[0..N/2].
 __device__ __forceinline__ double sinpi_n(const double* __restrict__ sq, int m, int N) {
     const double sgn = (m & N) ? -1.0 : 1.0;
@@ -364,13 +379,16 @@ __device__ inline double correction_at(const DevPlan& p, const JumpSrc& js, int 
 // workgroup g's sums for all M samples) are split over the wavefronts, added in
 // a fixed order, and wavefront 0 adds the jump terms of the stencil nodes
 // outside Omega and writes out[cp] (also to red[lane], for the caller).
-// red: 16 x 64 doubles of LDS.
-__device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial,
-                                        int G, int cp0, double* __restrict__ out, double* red) {
+// red: 16 x 64 doubles of LDS.  Returns false, having written nothing, while
+// *skip is nonzero (skip may be null); the flag's latency overlaps the loads.
+__device__ inline bool reduce_samples64(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial,
+                                        int G, int cp0, double* __restrict__ out, double* red,
+                                        const int* __restrict__ skip = nullptr) {
     __shared__ double outside[64];
     constexpr int kOutsideWave = 15;                    // also makes the jump terms
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cp = cp0 + lane, M = p.M;
+    const int skipped = load_flag_or_zero(skip);
     double s = 0.0;
     if (cp < M) {
         // the wavefront's first 16 partial rows are requested before anything
@@ -390,6 +408,7 @@ __device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, con
         for (int k = 0; k < 16; ++k) s += r[k];
         for (int g = wave + 256; g < G; g += 16) s += partial[(size_t)g * M + cp];
     }
+    if (skipped) return false;                          // the same for the whole workgroup
     red[wave * 64 + lane] = s;
     __syncthreads();
     if (wave == 0 && cp < M) {
@@ -401,6 +420,7 @@ __device__ inline void reduce_samples64(const DevPlan& p, const JumpSrc& js, con
         red[lane] = v;                                  // left in LDS for the caller
     }
     __syncthreads();
+    return true;
 }
 
 // ---------------------------------------------------------------- sparse fast solve, R modes per workgroup
@@ -435,10 +455,13 @@ __device__ __forceinline__ ModesLds modes_lds(double* smem, int N) {
 //     recurrence): emit(cp, s) with s the sum over the R modes, for
 //     cp = tid, tid + 64 kModeWaves, ...
 // L.sq must hold the sine table of p.N, or sinq (the table in device memory)
-// is given and loaded here; must be called by the whole workgroup.
+// is given and loaded here; must be called by the whole workgroup.  The round
+// does nothing while *skip is nonzero (skip may be null); the flag is checked
+// after the first requests and the clear, so its latency overlaps theirs.
 template <int C, int R, class Emit>
 __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __restrict__ corr, int base,
-                                            const ModesLds& L, Emit emit, const double* __restrict__ sinq = nullptr) {
+                                            const ModesLds& L, Emit emit, const double* __restrict__ sinq = nullptr,
+                                            const int* __restrict__ skip = nullptr) {
     constexpr int XS = 64 * (C + 1);
     constexpr int NT = kModeWaves * 64;
     const int N = p.N, n = p.n, M = p.M, mask2 = 2 * N - 1, half = N / 2;
@@ -446,9 +469,18 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
     const double* sq = L.sq;
     const int l0 = base + 1;
     const int nact = min(R, n - base);                  // modes of this round that exist
+    const int skipped = load_flag_or_zero(skip);
     // the first rows of this wavefront's node table are requested before
-    // anything waits, so their latency overlaps the table load and the clear
-    const int t_beg = p.sub_off[wave], t_end = p.sub_off[wave + 1];   // multiples of kSlots
+    // anything waits, so their latency overlaps the table load and the clear;
+    // the sub-table's bounds come with the plan's fields, not from memory
+    const int wu = __builtin_amdgcn_readfirstlane(wave);
+    int t_beg = p.sub_offv[0], t_end = p.sub_offv[1];  // multiples of kSlots
+#pragma unroll
+    for (int w = 1; w < kModeWaves; ++w)               // constant indices: loaded with the other fields
+        if (wu == w) {
+            t_beg = p.sub_offv[w];
+            t_end = p.sub_offv[w + 1];
+        }
     int pk[kSlots], pkn[kSlots];
     double cv[kSlots], cvn[kSlots];
     if (t_beg < t_end) {
@@ -479,6 +511,7 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
     if (sinq)
         for (int k = tid; k <= N / 2; k += NT) L.sq[k] = sinq[k];
     for (int k = tid; k < R * XS; k += NT) L.xs[k] = 0.0;
+    if (skipped) return;                                // the same for the whole workgroup
     __syncthreads();
     {
         double acc[R];

@@ -143,30 +143,38 @@ __device__ __forceinline__ void gm_load_basis(const double* __restrict__ V, int 
 
 // The basis values the first pass needs from this wavefront (V_i at its lane's
 // sample for i = wave, wave + 16, ...; kMaxRestart <= 64), requested before the
-// apply's reduction so that their latency overlaps it.
+// apply's reduction so that their latency overlaps it.  Every row that can be
+// in use (i < m) is requested without waiting for the state; rows past the
+// current column are not used.
+// Wavefront 0 also requests what a residual step reads: the iterate the apply
+// was given and ghat at its lane's sample.
 struct GmPre {
     double v[4];
+    double xc, gh;
 };
 __device__ __forceinline__ GmPre gm_dots1_prefetch(const GmresBufs& b, int M, int c64) {
     static_assert(kMaxRestart <= 64, "four basis values per lane");
     GmPre pre;
-    const GmresState* st = b.st;
-    const int mode = st->mode, j = st->j;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, cp = c64 * 64 + lane;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int i = wave + 16 * k;
-        pre.v[k] = (mode == 1 && i <= j && cp < M) ? b.V[(size_t)i * M + cp] : 0.0;
+        pre.v[k] = (i < b.m && cp < M) ? b.V[(size_t)i * M + cp] : 0.0;
+    }
+    pre.xc = pre.gh = 0.0;
+    if (wave == 0 && cp < M) {
+        pre.xc = b.xcur[cp];
+        pre.gh = b.ghat[cp];
     }
     return pre;
 }
 
 // First step of GMRES on samples c64 * 64 .. + 63, called by a workgroup of 16
-// wavefronts right after it computed w there (wv[lane] in LDS); pre: the basis
-// values from gm_dots1_prefetch (null: loaded here).
-__device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const double* wv, const GmPre* pre = nullptr) {
-    const GmresState* st = b.st;
-    const int mode = st->mode;
+// wavefronts right after it computed w there (wv[lane] in LDS); pre: the
+// values from gm_dots1_prefetch (null: loaded here); mode, j: the state's, as
+// read by the caller at its start.
+__device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const double* wv, const GmPre* pre, int mode,
+                                   int j) {
     if (mode == 2) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cp = c64 * 64 + lane;
@@ -175,15 +183,16 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
         if (wave != 0) return;
         double r = 0.0;
         if (cp < M) {
-            b.phi[cp] = b.xcur[cp];
-            r = b.ghat[cp] - wv[lane];
+            const double xc = pre ? pre->xc : b.xcur[cp], gh = pre ? pre->gh : b.ghat[cp];
+            b.phi[cp] = xc;
+            r = gh - wv[lane];
             b.z[cp] = r;
         }
         const double s = wave_sum(r * r);
         if (lane == 0) q.nrm0[c64] = s;
         return;
     }
-    const int j = st->j, gc64 = b.gc64;
+    const int gc64 = b.gc64;
     const double x = cp < M ? wv[lane] : 0.0;
     if (pre) {
 #pragma unroll
@@ -200,6 +209,9 @@ __device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const dou
         const double s = wave_sum(cp < M ? b.V[(size_t)i * M + cp] * x : 0.0);
         if (lane == 0) q.d1[(size_t)i * gc64 + c64] = s;
     }
+}
+__device__ inline void gm_dots1_64(const GmresBufs& b, int M, int c64, const double* wv) {
+    gm_dots1_64(b, M, c64, wv, nullptr, b.st->mode, b.st->j);
 }
 
 // What one update workgroup loads, requested before the state is known: the

@@ -19,6 +19,8 @@ struct ModeConst {
     double pad[3];
 };
 
+constexpr int kModeWaves = 8;      // wavefronts of a sparse-fast-solve workgroup (= node sub-tables)
+
 // Everything a kernel needs to read one problem's plan on the device.
 struct DevPlan {
     int n, N, M, Q, I;
@@ -38,6 +40,8 @@ struct DevPlan {
     const int* col_ptr;       // N + 1 entries used (i = 0..N)
     const int* sub_off;       // kModeWaves + 1: rows [sub_off[w], sub_off[w+1]) of the interleaved
                               // table are sub-table w (multiples of kSlots)
+    int sub_offv[kModeWaves + 1];   // the same offsets by value, so that a kernel given the plan by
+                                    // value reads them with its arguments
     const int* split;         // 3 n_split: (place, first extra piece, extra pieces) of each column
                               // whose nodes are cut into several pieces (see il_ij)
     int n_split;
@@ -79,7 +83,6 @@ constexpr int kSplineK = 30;
 constexpr int kCorrChunk = 256;    // irregular nodes per correction chunk (one workgroup)
 constexpr int kCorrWindow = 256;   // knots of a chunk's density window
 constexpr int kSlots = 4;          // table rows loaded together by the sparse sine sums
-constexpr int kModeWaves = 8;      // wavefronts of a sparse-fast-solve workgroup (= node sub-tables)
 constexpr int kMaxModesPerGroup = 8;
 constexpr int kMaxExtra = 128;      // extra pieces of long columns (per mode, in LDS)
 constexpr int kExtraFlag = 0x4000;  // dest field of an extra piece

@@ -55,11 +55,10 @@ __global__ __launch_bounds__(256) void k_correct(DevPlan p, JumpSrc js, double* 
 template <int C, int R>
 __global__ __launch_bounds__(kModeWaves * 64) void k_modes(DevPlan p, const double* __restrict__ corr,
                                                           double* __restrict__ partial, const int* __restrict__ skip) {
-    if (skip && *skip) return;
     extern __shared__ double smem[];
     const ModesLds L = modes_lds<R>(smem, p.N);
     double* row = partial + (size_t)blockIdx.x * p.M;
-    modes_round<C, R>(p, corr, blockIdx.x * R, L, [&](int cp, double v) { row[cp] = v; }, p.sinq);
+    modes_round<C, R>(p, corr, blockIdx.x * R, L, [&](int cp, double v) { row[cp] = v; }, p.sinq, skip);
 }
 
 // ---------------------------------------------------------------- spline of a density
@@ -77,8 +76,7 @@ __global__ __launch_bounds__(256) void k_spline(DevPlan p, const double* __restr
 __global__ __launch_bounds__(1024) void k_reduce_interp(DevPlan p, JumpSrc js, const double* __restrict__ partial,
                                                         int G, double* __restrict__ out, const int* __restrict__ skip) {
     __shared__ double red[16 * 64];
-    if (skip && *skip) return;
-    reduce_samples64(p, js, partial, G, blockIdx.x * 64, out, red);
+    reduce_samples64(p, js, partial, G, blockIdx.x * 64, out, red, skip);
 }
 
 // Interpolation from a full grid solution (dense path): R in the padded interior layout.
@@ -171,10 +169,10 @@ __global__ __launch_bounds__(256) void k_axpby(int n, double a, const double* __
 __global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const double* __restrict__ partial, int G,
                                                     GmresBufs b) {
     __shared__ double red[16 * 64];
-    if (b.st->converged) return;
     const GmPre pre = gm_dots1_prefetch(b, p.M, blockIdx.x);
-    reduce_samples64(p, js, partial, G, blockIdx.x * 64, b.w, red);
-    gm_dots1_64(b, p.M, blockIdx.x, red, &pre);
+    const int mode = load_flag(&b.st->mode), j = load_flag(&b.st->j);   // their latency overlaps the loads around
+    if (!reduce_samples64(p, js, partial, G, blockIdx.x * 64, b.w, red, &b.st->converged)) return;
+    gm_dots1_64(b, p.M, blockIdx.x, red, &pre, mode, j);
 }
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update1_commit(b, M, blockIdx.x); }
 __global__ __launch_bounds__(kGmChunk) void k_gm_emit(const double* taps, GmresBufs b, int M) {
