@@ -830,16 +830,23 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         dp.n_cc = (int)cc_chunk.size();
     }
     if (cc_chunk.empty()) cc_chunk.push_back(make_int4(0, 0, 0, 0));
-    std::vector<int4> cc_arm(std::max(p->I, 1), make_int4(-1, -1, -1, -1));
-    std::vector<double4> cc_d(std::max(p->I, 1), make_double4(0, 0, 0, 0));
-    std::vector<double> cc_s(std::max(p->I, 1), 0.0);
-    std::vector<int> cc_pos(std::max(p->I, 1), 0);
-    for (int at = 0; at < p->I; ++at) {
-        const int r = cc_node[at];
-        cc_arm[at] = make_int4(P.arm_q[4 * r], P.arm_q[4 * r + 1], P.arm_q[4 * r + 2], P.arm_q[4 * r + 3]);
-        cc_d[at] = make_double4(P.arm_d[4 * r], P.arm_d[4 * r + 1], P.arm_d[4 * r + 2], P.arm_d[4 * r + 3]);
-        cc_s[at] = P.irr_s[r];
-        cc_pos[at] = il_pos[r];
+    // the nodes' data by chunk, kCorrChunk places per chunk (pads have no arms),
+    // so that a workgroup finds its chunk's data without reading the chunk first
+    const size_t n_places = cc_chunk.size() * (size_t)kCorrChunk;
+    std::vector<int4> cc_arm(n_places, make_int4(-1, -1, -1, -1));
+    std::vector<double4> cc_d(n_places, make_double4(0, 0, 0, 0));
+    std::vector<double> cc_s(n_places, 0.0);
+    std::vector<int> cc_pos(n_places, 0);
+    for (int c = 0; c < dp.n_cc; ++c) {
+        const int4 ch = cc_chunk[c];
+        for (int at = ch.x; at < ch.y; ++at) {
+            const int r = cc_node[at];
+            const size_t q = (size_t)c * kCorrChunk + (at - ch.x);
+            cc_arm[q] = make_int4(P.arm_q[4 * r], P.arm_q[4 * r + 1], P.arm_q[4 * r + 2], P.arm_q[4 * r + 3]);
+            cc_d[q] = make_double4(P.arm_d[4 * r], P.arm_d[4 * r + 1], P.arm_d[4 * r + 2], P.arm_d[4 * r + 3]);
+            cc_s[q] = P.irr_s[r];
+            cc_pos[q] = il_pos[r];
+        }
     }
     if ((st = upload(p, &dp.cc_arm, cc_arm)) || (st = upload(p, &dp.cc_d, cc_d)) || (st = upload(p, &dp.cc_s, cc_s)) ||
         (st = upload(p, &dp.cc_pos, cc_pos)) || (st = upload(p, &dp.cc_chunk, cc_chunk)))

@@ -568,25 +568,26 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
     __shared__ double xw[kCorrWindow];
     __shared__ double sw[kCorrWindow];
     const int M = p.M, tid = threadIdx.x;
-    const int4 ch = p.cc_chunk[cc];                      // first, end, first knot, width
-    // z at the thread's window place is requested before anything else: it is
-    // the next input (scaled) unless the cycle has just ended
-    static_assert(kCorrWindow <= kGmChunk, "one window place per thread");
-    const int ew = (ch.z + tid) % M;
-    const double zw = tid < ch.w ? b.z[ew] : 0.0;
-    // the node's plan data next, so that its loads overlap the window's
-    const int at = ch.x + tid;
-    const bool act = at < ch.y;
+    static_assert(kCorrWindow <= kGmChunk && kCorrChunk <= kGmChunk, "one window place and one node place per thread");
+    // the node's plan data (place tid of the chunk's kCorrChunk) is requested
+    // with the chunk itself: neither waits for the other
     int4 arm = make_int4(-1, -1, -1, -1);
     double4 dd = make_double4(0.0, 0.0, 0.0, 0.0);
     double sg = 0.0;
     int slot = 0;
-    if (act) {
+    if (tid < kCorrChunk) {
+        const size_t at = (size_t)cc * kCorrChunk + tid;
         arm = p.cc_arm[at];
         dd = p.cc_d[at];
         sg = p.cc_s[at];
         slot = p.cc_pos[at];
     }
+    const int4 ch = p.cc_chunk[cc];                      // first, end, first knot, width
+    const bool act = tid < ch.y - ch.x;
+    // z at the thread's window place: the next input (scaled) unless the cycle
+    // has just ended
+    const int ew = (ch.z + tid) % M;
+    const double zw = tid < ch.w ? b.z[ew] : 0.0;
     const int ks[4] = {arm.x, arm.y, arm.z, arm.w};
     const double ds[4] = {dd.x, dd.y, dd.z, dd.w};
     PointGeom gs[4];

@@ -69,12 +69,13 @@ struct DevPlan {
     // into chunks of at most kCorrChunk nodes whose crossings' spline segments
     // span at most a window of kCorrWindow knots (with the filter's reach):
     // chunk c = (first, end, first window knot, window length) of that order.
-    // Per place in the order: the node's arms (crossing index, -1 unused; the
-    // distance d), its side and its slot in the sparse-sum layout.
-    const int4* cc_arm;       // I
-    const double4* cc_d;      // I
-    const double* cc_s;       // I
-    const int* cc_pos;        // I
+    // Per node, at place c kCorrChunk + (its place in the order - first): its
+    // arms (crossing index, -1 unused; the distance d), its side and its slot in
+    // the sparse-sum layout; the places past a chunk's end are pads with no arms.
+    const int4* cc_arm;       // n_cc kCorrChunk
+    const double4* cc_d;      // n_cc kCorrChunk
+    const double* cc_s;       // n_cc kCorrChunk
+    const int* cc_pos;        // n_cc kCorrChunk
     const int4* cc_chunk;     // n_cc
     int n_cc;
 };
