@@ -380,7 +380,7 @@ def iterations(ctx, sizes=(512, 1024, 2048, 4096), cpu: bool = True) -> dict:
 PAPER_GS_GPU_S = {128: 0.40, 256: 1.04, 512: 3.29, 1024: 12.07}
 
 
-def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: float = 1.0, cpu: bool = True) -> dict:
+def gray_scott(ctx, grid_steps=((128, 8), (256, 16), (512, 32), (1024, 64)), T: float = 1.0, cpu: bool = True) -> dict:
     """Example 3: Gray-Scott on the disk r = 1.8 in (-2, 2)^2 with the paper's
     parameters, Strang splitting, GMRES tol 1e-8, at the grid sizes and step
     counts of the paper's table (final time T = 1).  The timed region is the time
@@ -391,7 +391,7 @@ def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: flo
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
     lo, hi = synth.GS_LO, synth.GS_HI
     rows = []
-    for n, steps in configs:
+    for n, steps in grid_steps:
         xy = synth.gray_scott_samples(n)
         dt = T / steps
         mask = kfbi.Problem(ctx, xy, n, 1.0, lo=lo, hi=hi).mask()
@@ -425,7 +425,7 @@ def gray_scott(ctx, configs=((128, 8), (256, 16), (512, 32), (1024, 64)), T: flo
         # the oracle's Strang steps on the smallest configuration, beside it (one host core)
         from oracle import gray_scott as G
         from oracle import kfbi_oracle as O
-        n, steps = configs[0]
+        n, steps = grid_steps[0]
         xy = synth.gray_scott_samples(n)
         plan = O.build_plan(xy, n, lo, hi)
         st = G.initial_state(plan, synth.gray_scott_initial)
