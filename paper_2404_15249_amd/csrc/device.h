@@ -16,6 +16,14 @@ __device__ __forceinline__ int load_flag(const int* f) {
     using global_int = __attribute__((address_space(1))) int;
     return __hip_atomic_load((global_int*)f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// load_flag for a value used only late in the kernel: the address is offset by
+// a zero the compiler cannot see through, so the value stays per lane and is
+// not moved to a scalar register (which waits for it) right after the load.
+__device__ __forceinline__ int load_flag_late(const int* f) {
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    return load_flag(f + zero);
+}
 // A flag that is never set, read in place of a null one (a load from one of two
 // addresses, with no branch that would wait for it).
 static __device__ const int kFlagZero = 0;
@@ -376,37 +384,41 @@ __device__ inline double correction_at(const DevPlan& p, const JumpSrc& js, int 
 
 // Samples cp0 .. cp0 + 63 (one per lane) by a workgroup of 16 wavefronts: the
 // workgroup partials of the weighted sine sums (row g of `partial` holds
-// workgroup g's sums for all M samples) are split over the wavefronts, added in
-// a fixed order, and wavefront 0 adds the jump terms of the stencil nodes
-// outside Omega and writes out[cp] (also to red[lane], for the caller).
+// workgroup g's sums for all M samples) are split over wavefronts 0..14, added
+// in a fixed order; wavefront 15 makes the jump terms of the stencil nodes
+// outside Omega, and wavefront 0 adds them and writes out[cp] (also to
+// red[lane], for the caller).
 // red: 16 x 64 doubles of LDS.  Returns false, having written nothing, while
 // *skip is nonzero (skip may be null); the flag's latency overlaps the loads.
 __device__ inline bool reduce_samples64(const DevPlan& p, const JumpSrc& js, const double* __restrict__ partial,
                                         int G, int cp0, double* __restrict__ out, double* red,
                                         const int* __restrict__ skip = nullptr) {
     __shared__ double outside[64];
-    constexpr int kOutsideWave = 15;                    // also makes the jump terms
+    constexpr int kOutsideWave = 15;                    // makes the jump terms only
+    constexpr int kRowWaves = 15, kRows = 18;           // rows wave + 15 k, k < 18, requested at once
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int cp = cp0 + lane, M = p.M;
     const int skipped = load_flag_or_zero(skip);
     double s = 0.0;
     if (cp < M) {
-        // the wavefront's first 16 partial rows are requested before anything
-        // waits; the jump terms' loads follow them, so both latencies overlap
-        double r[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int g = wave + 16 * k;
-            r[k] = g < G ? partial[(size_t)g * M + cp] : 0.0;
-        }
         if (wave == kOutsideWave) {
             int ni[6], nj[6];
             stencil_nodes(p, cp, ni, nj);
             outside[lane] = outside_terms(p, js, cp, ni, nj, p.cp_w + 6 * (size_t)cp);
-        }
+        } else {
+            // every row is loaded from a row that exists (then selected), so no
+            // load waits under its own condition before the next is requested
+            double r[kRows];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) s += r[k];
-        for (int g = wave + 256; g < G; g += 16) s += partial[(size_t)g * M + cp];
+            for (int k = 0; k < kRows; ++k) {
+                const int g = wave + kRowWaves * k;
+                const double v = partial[(size_t)(g < G ? g : G - 1) * M + cp];
+                r[k] = g < G ? v : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kRows; ++k) s += r[k];
+            for (int g = wave + kRowWaves * kRows; g < G; g += kRowWaves) s += partial[(size_t)g * M + cp];
+        }
     }
     if (skipped) return false;                          // the same for the whole workgroup
     red[wave * 64 + lane] = s;

@@ -170,7 +170,7 @@ __global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const
                                                     GmresBufs b) {
     __shared__ double red[16 * 64];
     const GmPre pre = gm_dots1_prefetch(b, p.M, blockIdx.x);
-    const int mode = load_flag(&b.st->mode), j = load_flag(&b.st->j);   // their latency overlaps the loads around
+    const int mode = load_flag_late(&b.st->mode), j = load_flag_late(&b.st->j);   // waited for where used
     if (!reduce_samples64(p, js, partial, G, blockIdx.x * 64, b.w, red, &b.st->converged)) return;
     gm_dots1_64(b, p.M, blockIdx.x, red, &pre, mode, j);
 }
