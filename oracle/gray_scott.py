@@ -26,6 +26,15 @@ splitting.  The paper names the splitting and nothing else; the readings here
   ``Lap z - kappa z = -kappa w``, ``d_n z = 0``, ``kappa = 2 / (eps dt)``
   (Sec. 2 interface problem with the normal-derivative jump as the density);
   GMRES starts from the previous step's density of the same species;
+* the half step is solved for the deviation from a constant: with ``c`` the
+  mean of the trace of ``w`` at the samples, ``z = c + z'`` and ``z'`` solves
+  ``Lap z' - kappa z' = -kappa (w - c)``, ``d_n z' = 0``.  A constant solves
+  the Neumann problem exactly, so this is the same ``z``; but the volume
+  potential's zero extension (the Sec. 2.2 table) now jumps across Gamma by
+  ``kappa (w - c)`` instead of ``kappa w``.  At Example 3's ``kappa h^2`` of
+  about 2 the exterior boundary layer of that jump is narrower than a cell,
+  and solving for ``z`` itself moved the uniform state ``u = 1`` near Gamma to
+  1.24 within eight steps at 128^2;
 * grid nodes outside Omega hold zero.
 """
 from __future__ import annotations
@@ -56,13 +65,16 @@ def reaction_step(u, v, dt, P):
 def diffusion_step(plan, w_grid, w_gamma, eps, dt, psi0=None, tol=1e-10):
     """Crank-Nicolson step of ``w_t = eps Lap w`` with ``d_n w = 0``.
 
-    Returns the new grid (zero outside Omega), the new trace at the samples, the
-    Neumann density of the half-step solve and its GMRES iterations.
+    The half step is solved as ``c + z'`` with ``c`` the trace's mean (module
+    docstring).  Returns the new grid (zero outside Omega), the new trace at the
+    samples, the Neumann density of the ``z'`` solve and its GMRES iterations.
     """
     kappa = 2.0 / (eps * dt)
-    sol = O.solve_neumann_on(plan, kappa, -kappa * w_grid, -kappa * w_gamma, np.zeros(plan.M), tol=tol, psi0=psi0)
-    new_grid = np.where(plan.inside, 2.0 * sol.u_grid - w_grid, 0.0)
-    return new_grid, 2.0 * sol.u_gamma - w_gamma, sol.psi, sol.iters
+    c = np.mean(w_gamma)
+    f_grid = np.where(plan.inside, -kappa * (w_grid - c), 0.0)
+    sol = O.solve_neumann_on(plan, kappa, f_grid, -kappa * (w_gamma - c), np.zeros(plan.M), tol=tol, psi0=psi0)
+    new_grid = np.where(plan.inside, 2.0 * (c + sol.u_grid) - w_grid, 0.0)
+    return new_grid, 2.0 * (c + sol.u_gamma) - w_gamma, sol.psi, sol.iters
 
 
 @dataclasses.dataclass

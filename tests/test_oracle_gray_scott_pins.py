@@ -10,7 +10,14 @@ forms that do not come from the oracle:
 * with v = 0 the u-equation is linear (rate gamma/eps0) and commutes with the
   diffusion, so a Strang step multiplies u - 1 = c J_0(alpha r) by the CN factor
   times the square of the RK4 factor of a half step: this pins the order of the
-  sub-steps and their lengths.
+  sub-steps and their lengths;
+* the uniform state (u, v) = (1, 0) solves the whole system (zero reaction,
+  zero Laplacian, zero normal derivative), so the scheme must keep it to
+  rounding, and the Crank-Nicolson step is linear and keeps constants, so it
+  must commute with adding a constant to the state;
+* the maximum principle: Example 3's data has 0 <= v and u <= 1, and for
+  u <= 1 the u-reaction gamma (1 - u) - u v^2 <= gamma (1 - u) never pushes u
+  above 1, so u must stay at most 1 over the run.
 """
 import numpy as np
 import pytest
@@ -118,3 +125,49 @@ def test_gray_scott_state_stays_bounded_and_symmetric(plan128):
     assert np.all(st.v[ins] >= -1e-12) and np.all(st.v[ins] <= 1.0)
     assert np.max(np.abs(st.v - st.v[:, ::-1])) < 1e-8
     assert np.max(np.abs(st.u - st.u[:, ::-1])) < 1e-8
+
+
+def test_uniform_steady_state_is_kept_exactly(plan128):
+    """(1, 0) at Example 3's parameters, 128^2, dt = 1/8, T = 1 (kappa h^2 about 2
+    for u): every value stays 1 (u) and 0 (v) to rounding, on the grid and at
+    the samples."""
+    P = synth.GrayScottParams()
+    st = G.initial_state(plan128, lambda x, y: (np.ones_like(x), np.zeros_like(x)))
+    st = G.run(plan128, st, 0.125, 8, P, tol=1e-10)
+    ins = plan128.inside
+    assert np.max(np.abs(st.u[ins] - 1.0)) < 1e-12, np.max(np.abs(st.u[ins] - 1.0))
+    assert np.max(np.abs(st.u_gamma - 1.0)) < 1e-12
+    assert np.max(np.abs(st.v[ins])) < 1e-12 and np.max(np.abs(st.v_gamma)) < 1e-12
+    assert np.all(st.u[~ins] == 0.0)
+
+
+def test_diffusion_step_commutes_with_adding_a_constant(plan128):
+    """D(w + a) = D(w) + a on the grid in Omega and at the samples, for a smooth
+    non-constant w (a Neumann eigenmode plus a tilt) and a = 0.7."""
+    al = jnp_zeros(2, 1)[0] / R
+    X, Y = _grid(plan128)
+    w = lambda x, y: jv(2, al * np.hypot(x, y)) * np.cos(2 * np.arctan2(y, x)) + 0.1 * x
+    ins = plan128.inside
+    wg, wz = np.where(ins, w(X, Y), 0.0), w(plan128.xy[:, 0], plan128.xy[:, 1])
+    a = 0.7
+    g0, z0, _, _ = G.diffusion_step(plan128, wg, wz, 0.05, 0.25, tol=1e-13)
+    g1, z1, _, _ = G.diffusion_step(plan128, np.where(ins, wg + a, 0.0), wz + a, 0.05, 0.25, tol=1e-13)
+    assert np.max(np.abs(g1 - a - g0)[ins]) < 1e-10, np.max(np.abs(g1 - a - g0)[ins])
+    assert np.max(np.abs(z1 - a - z0)) < 1e-10
+    # the step did something (not the identity, not a constant)
+    assert np.max(np.abs(g0 - wg)[ins]) > 1e-3
+
+
+def test_example3_keeps_u_at_most_one_over_unit_time(plan128):
+    """Example 3's data and parameters at 128^2, 8 steps of dt = 1/8 (T = 1),
+    GMRES tol 1e-8: u <= 1 + 1e-8 and v >= -1e-12 everywhere, on the grid and
+    at the samples."""
+    P = synth.GrayScottParams()
+    st = G.initial_state(plan128, synth.gray_scott_initial)
+    st = G.run(plan128, st, 0.125, 8, P, tol=1e-8)
+    ins = plan128.inside
+    assert st.u[ins].max() <= 1.0 + 1e-8, st.u[ins].max()
+    assert st.u_gamma.max() <= 1.0 + 1e-8, st.u_gamma.max()
+    assert st.v[ins].min() >= -1e-12 and st.v_gamma.min() >= -1e-12
+    # the pattern evolved (not a frozen state)
+    assert st.u[ins].min() < 0.5 and st.v[ins].max() > 0.2
