@@ -241,8 +241,12 @@ kfbi_status kfbi_solve_neumann(kfbi_prob* prob, const double* f_grid, const doub
  * Omega and at the boundary samples, and D Crank-Nicolson as w <- 2 z - w, z the
  * solution of the Neumann problem Lap z - kappa z = -kappa w, d_n z = 0,
  * kappa = 2/(eps dt) (kfbi_solve_neumann, GMRES warm-started from the previous
- * step's density).  The state is a grid of (n+1)^2 values (zero outside Omega)
- * and the trace at the M boundary samples, per species. */
+ * step's density).  z is solved as c + z', c the mean of w's trace at the
+ * samples and z' the Neumann solution for the right-hand side -kappa (w - c):
+ * the same z, but the zero extension of the right-hand side outside Omega then
+ * jumps across Gamma by kappa (w - c) only, so a uniform state stays uniform.
+ * The state is a grid of (n+1)^2 values (zero outside Omega) and the trace at
+ * the M boundary samples, per species. */
 typedef struct kfbi_gs kfbi_gs;
 
 typedef struct {

@@ -11,6 +11,12 @@
 //    one Neumann solve per species, warm-started from the species' previous
 //    density.  The two species' solves are independent: each problem has its
 //    own stream and the solves overlap (solve_neumann_pair).
+//    The half step is solved as z = c + z', c the mean of w's trace at the
+//    samples: Lap z' - kappa z' = -kappa (w - c), d_n z' = 0.  A constant solves
+//    the Neumann problem exactly, so this is the same z; but the zero extension
+//    of the right-hand side outside Omega (the volume potential of the Sec. 2.2
+//    table) then jumps across Gamma by kappa (w - c), not kappa w, which at
+//    kappa h^2 of order one would otherwise lift a uniform state near Gamma.
 // Grid nodes outside Omega hold zero.
 #include <hip/hip_runtime.h>
 
@@ -55,34 +61,71 @@ struct GsState {
     int ng, M;
 };
 
-// R(dt/2), then the right-hand sides of the two half-step solves:
-// fu = -kappa_u u, fv = -kappa_v v (same layout as the state).
+constexpr int kMeanThreads = 256;
+
+// The means c_u, c_v of the two species' traces after R(dt/2): one workgroup
+// applies the reaction half step to the M trace values itself (the same
+// pointwise step k_gs_pre makes) and sums them in a fixed order.
+__global__ __launch_bounds__(kMeanThreads) void k_gs_trace_mean(GsState S, double dth, GsRates P,
+                                                                double* __restrict__ cmean) {
+    __shared__ double su[kMeanThreads], sv[kMeanThreads];
+    const int tid = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int t = tid; t < S.M; t += kMeanThreads) {
+        double u = S.u[S.ng + t], v = S.v[S.ng + t];
+        gs_rk4(u, v, dth, P);
+        a += u;
+        b += v;
+    }
+    su[tid] = a;
+    sv[tid] = b;
+    __syncthreads();
+    for (int w = kMeanThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+            su[tid] += su[tid + w];
+            sv[tid] += sv[tid + w];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        cmean[0] = su[0] / S.M;
+        cmean[1] = sv[0] / S.M;
+    }
+}
+
+// R(dt/2), then the right-hand sides of the two half-step solves for z' = z - c:
+// fu = -kappa_u (u - c_u), fv = -kappa_v (v - c_v) in Omega and at the samples,
+// zero at the grid nodes outside Omega (same layout as the state).
 __global__ __launch_bounds__(256) void k_gs_pre(GsState S, double* __restrict__ fu, double* __restrict__ fv,
-                                                double dth, double ku, double kv, GsRates P) {
+                                                double dth, double ku, double kv, GsRates P,
+                                                const double* __restrict__ cmean) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= S.ng + S.M) return;
-    double u = 0.0, v = 0.0;
+    double u = 0.0, v = 0.0, ru = 0.0, rv = 0.0;
     if (t >= S.ng || S.mask[t]) {
         u = S.u[t];
         v = S.v[t];
         gs_rk4(u, v, dth, P);
+        ru = -ku * (u - cmean[0]);
+        rv = -kv * (v - cmean[1]);
     }
     S.u[t] = u;
     S.v[t] = v;
-    fu[t] = -ku * u;
-    fv[t] = -kv * v;
+    fu[t] = ru;
+    fv[t] = rv;
 }
 
-// w <- 2 z - w for both species (z from the solves: grid zero outside Omega,
-// then the trace), then R(dt/2).
+// w <- 2 (c + z') - w for both species (z' from the solves: grid zero outside
+// Omega, then the trace), then R(dt/2).
 __global__ __launch_bounds__(256) void k_gs_post(GsState S, const double* __restrict__ zu,
-                                                 const double* __restrict__ zv, double dth, GsRates P) {
+                                                 const double* __restrict__ zv, double dth, GsRates P,
+                                                 const double* __restrict__ cmean) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= S.ng + S.M) return;
     double u = 0.0, v = 0.0;
     if (t >= S.ng || S.mask[t]) {
-        u = 2.0 * zu[t] - S.u[t];
-        v = 2.0 * zv[t] - S.v[t];
+        u = 2.0 * (cmean[0] + zu[t]) - S.u[t];
+        v = 2.0 * (cmean[1] + zv[t]) - S.v[t];
         gs_rk4(u, v, dth, P);
     }
     S.u[t] = u;
@@ -103,6 +146,7 @@ struct kfbi_gs {
     // device buffers; grid arrays are followed by the M trace values
     double *u = nullptr, *v = nullptr, *fu = nullptr, *fv = nullptr, *zu = nullptr, *zv = nullptr;
     double *psi_u = nullptr, *psi_v = nullptr, *gn = nullptr, *dn = nullptr;
+    double* cmean = nullptr;     // 2: the trace means c_u, c_v of the current step
     unsigned char* mask = nullptr;
     std::vector<void*> allocs;
     long long iters = 0;         // GMRES iterations of all solves so far
@@ -189,7 +233,7 @@ kfbi_status kfbi_gs_create(kfbi_ctx* ctx, const kfbi_gs_desc* d, kfbi_gs** out) 
         (st = gs_alloc(g, &g->fv, all)) || (st = gs_alloc(g, &g->zu, all)) || (st = gs_alloc(g, &g->zv, all)) ||
         (st = gs_alloc(g, &g->psi_u, g->M)) || (st = gs_alloc(g, &g->psi_v, g->M)) ||
         (st = gs_alloc(g, &g->gn, g->M)) || (st = gs_alloc(g, &g->dn, 2 * (size_t)g->M)) ||
-        (st = gs_alloc(g, &g->mask, g->ng)))
+        (st = gs_alloc(g, &g->cmean, 2)) || (st = gs_alloc(g, &g->mask, g->ng)))
         return fail(st);
     std::vector<unsigned char> mask(g->ng);
     kfbi_prob_mask(g->pu, mask.data());
@@ -271,7 +315,9 @@ kfbi_status kfbi_gs_step(kfbi_gs* g, int nsteps) {
     const NeumannIO iu{g->fu, g->fu + g->ng, g->gn, g->zu, g->zu + g->ng, g->dn, g->psi_u};
     const NeumannIO iv{g->fv, g->fv + g->ng, g->gn, g->zv, g->zv + g->ng, g->dn + g->M, g->psi_v};
     for (int k = 0; k < nsteps; ++k) {
-        HIP_TRY(klaunch(k_gs_pre, grid, block, 0, s, S, g->fu, g->fv, dth, g->ku, g->kv, P));
+        HIP_TRY(klaunch(k_gs_trace_mean, dim3(1), dim3(kMeanThreads), 0, s, S, dth, P, g->cmean));
+        HIP_TRY(klaunch(k_gs_pre, grid, block, 0, s, S, g->fu, g->fv, dth, g->ku, g->kv, P,
+                        (const double*)g->cmean));
         HIP_TRY(hipEventRecord(g->ev_pre, s));             // v's solve reads what k_gs_pre wrote
         HIP_TRY(hipStreamWaitEvent(s2, g->ev_pre, 0));
         int itu = 0, itv = 0;
@@ -279,7 +325,7 @@ kfbi_status kfbi_gs_step(kfbi_gs* g, int nsteps) {
         g->iters += itu + itv;
         HIP_TRY(hipEventRecord(g->ev_solved, s2));         // k_gs_post reads v's solution
         HIP_TRY(hipStreamWaitEvent(s, g->ev_solved, 0));
-        HIP_TRY(klaunch(k_gs_post, grid, block, 0, s, S, g->zu, g->zv, dth, P));
+        HIP_TRY(klaunch(k_gs_post, grid, block, 0, s, S, g->zu, g->zv, dth, P, (const double*)g->cmean));
         g->steps++;
     }
     HIP_TRY(hipStreamSynchronize(s));

@@ -78,8 +78,6 @@ def test_circle_solve_fp32_refined_vs_oracle(K, ctx, n, kappa):
     """Circle r = 0.8, M = N (samples about 2h apart), u = e^x sin y: the
     FP32-refined solve and the FP64 solve against the oracle at the full sizes
     (L-infinity, absolute)."""
-    if n == 4096 and kappa != 1.0:
-        pytest.skip("the 4096^2 oracle solve is run for kappa = 1 only (it takes minutes on the host)")
     p = synth.circle_problem(n=n, m=n, kappa=kappa)
     note(f"mixed-precision solve {p.name}")
     ref = O.solve_bvp(p.xy, p.n, LO, HI, p.kappa, p.f_grid, p.f_gamma, p.g, tol=1e-12)
