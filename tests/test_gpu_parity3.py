@@ -133,6 +133,32 @@ def test_solve_matches_oracle_and_converges(K, ctx, n):
     assert e < 2e-3
 
 
+def test_solve_matches_stored_oracle_at_128(K, ctx):
+    """The 128^3 solve against the oracle's, stored by
+    tests/golden/make_ellipsoid128.py (the oracle takes minutes there): the
+    trace at every control point and u at 20000 seeded nodes in Omega, to
+    relative 1e-10, both sides at tolerance 3e-12."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ellipsoid128_oracle.npz")
+    ref = np.load(path)
+    n = int(ref["n"])
+    pr = synth.ellipsoid_problem(n=n)
+    prob = K.Problem3(ctx, n, AXES, tol=float(ref["tol"]), max_iter=1500)
+    pts, _ = prob.points()
+    assert prob.M == ref["u_gamma"].shape[0]
+    fg, g = pr.boundary_data(pts)
+    note(f"3D solve {pr.name} against the stored oracle solve")
+    u, ug, phi, it, rel, conv = prob.solve(dev(pr.f_grid), dev(fg), dev(g))
+    u, ug = host(u), host(ug)
+    e_node = relerr(u.ravel()[ref["node"]], ref["u_node"])
+    e_gam = relerr(ug, ref["u_gamma"])
+    note(f"  iters gpu {it} ({rel:.2e}) oracle {int(ref['iters'])} ({float(ref['relres']):.2e}); "
+         f"relerr nodes {e_node:.2e} gamma {e_gam:.2e}")
+    assert conv
+    assert abs(it - int(ref["iters"])) <= max(2, int(ref["iters"]) // 50)
+    assert e_node < 1e-10 and e_gam < 1e-10
+
+
 def test_solve_converges_at_second_order_on_the_gpu(K, ctx):
     errs = []
     for n in (64, 128):

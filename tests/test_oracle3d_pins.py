@@ -163,3 +163,28 @@ def test_dirichlet_solve_converges_at_second_order():
         errs.append(e)
     assert errs[1] < errs[0] / 3.0, errs
     assert errs[1] < 5e-3, errs                        # |u| reaches e^2.1 on the ellipsoid
+
+
+def test_stored_128_solution_is_the_manufactured_one_to_second_order():
+    """The stored 128^3 oracle solve (tests/golden/make_ellipsoid128.py) is
+    pinned to the mathematics, not to the oracle: its trace and its sampled
+    node values are e^(x+y+z) up to the discretisation error at that grid
+    (the 64^3 error quartered, about 6e-5), its residual is below the stored
+    tolerance, and the sampled nodes lie in Omega."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ellipsoid128_oracle.npz")
+    ref = np.load(path)
+    n = int(ref["n"])
+    assert n == 128 and tuple(ref["axes"]) == AXES
+    assert float(ref["relres"]) < float(ref["tol"])
+    h = (HI - LO) / n
+    node = ref["node"]
+    i, j, k = node % (n + 1), (node // (n + 1)) % (n + 1), node // (n + 1) ** 2
+    x, y, z = LO + i * h, LO + j * h, LO + k * h
+    assert np.all(x * x / AXES[0] ** 2 + y * y / AXES[1] ** 2 + z * z / AXES[2] ** 2 < 1.0)
+    e_node = np.max(np.abs(ref["u_node"] - np.exp(x + y + z)))
+    plan = O3.build_plan(n, LO, HI, AXES)
+    q = plan.q_pos
+    e_gam = np.max(np.abs(ref["u_gamma"] - np.exp(q[:, 0] + q[:, 1] + q[:, 2])))
+    assert len(ref["u_gamma"]) == len(q)
+    assert e_node < 2e-4 and e_gam < 2e-4, (e_node, e_gam)
