@@ -124,25 +124,54 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def host_workers() -> int:
+    """Threads this process may use on the host: its CPU affinity, capped by
+    OMP_NUM_THREADS when that is set (the share of the machine it was given)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    return max(1, n)
+
+
+def _time_oracle_applies(plan, phi, kappa, seconds: float, workers: int):
+    """K_D applies of the oracle, back to back for about `seconds`, with scipy's
+    FFT given `workers` threads (the oracle's own code is unchanged)."""
+    from scipy import fft as sfft
+    from oracle import kfbi_oracle as O
+    with sfft.set_workers(workers):
+        O.apply_KD(plan, phi, kappa)                    # warm-up
+        t0 = time.perf_counter()
+        k = 0
+        while True:
+            O.apply_KD(plan, phi, kappa)
+            k += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return k, time.perf_counter() - t0
+
+
 def cpu_baseline(p, seconds: float):
-    """The oracle's K_D apply on the same workload, timed on the host cores."""
+    """The oracle's K_D apply on the same workload, timed on the host cores:
+    once with the FFTs on every thread the process may use (the reported
+    baseline), once on one thread."""
     from oracle import kfbi_oracle as O
     import synth
     plan = O.build_plan(p.xy, p.n, p.lo, p.hi)
     phi = synth.smooth_density(plan.M, 1234)
-    O.apply_KD(plan, phi, p.kappa)                      # warm-up
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        O.apply_KD(plan, phi, p.kappa)
-        k += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
     unknowns = (p.n - 1) ** 2
-    return {"value": unknowns * k / dt, "unit": "grid unknowns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} oracle K_D applies (scipy DST-I with workers=1, NumPy) on the same "
-                      f"{p.n}^2 star problem, {dt:.1f} s on {cpu_model()}"}
+    nw = host_workers()
+    legs = {}
+    for w in (nw, 1):
+        k, dt = _time_oracle_applies(plan, phi, p.kappa, seconds, w)
+        legs[w] = {"value": unknowns * k / dt, "applies": k, "seconds": dt}
+    top = legs[nw]
+    return {"value": top["value"], "unit": "grid unknowns/s", "cores": nw, "kind": "oracle",
+            "sample": f"{top['applies']} oracle K_D applies (scipy DST-I with workers={nw}, NumPy) on the same "
+                      f"{p.n}^2 star problem, {top['seconds']:.1f} s on {cpu_model()}",
+            "one_core": {"value": legs[1]["value"], "unit": "grid unknowns/s", "cores": 1,
+                         "sample": f"{legs[1]['applies']} applies with workers=1, {legs[1]['seconds']:.1f} s"}}
 
 
 def mixed_precision(ctx, n: int) -> dict:
@@ -495,7 +524,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=2048, help="grid intervals per axis")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--mixed", choices=["on", "off"], default="on")
     ap.add_argument("--convergence", choices=["on", "off"], default="on")
     ap.add_argument("--three-d", choices=["on", "off"], default="on")
@@ -527,7 +556,10 @@ def main():
     if args.mode == "copy":
         print(json.dumps(copy_calibration()), flush=True)
         return
-    ctx = kfbi.Context(0)
+    # one stream, current for torch and the library's: nothing to order between two
+    stream = torch.cuda.Stream(device=0)
+    torch.cuda.set_stream(stream)
+    ctx = kfbi.Context(0, stream=stream)
     if args.mode == "3d":
         print(json.dumps(three_d(ctx)), flush=True)
         return
@@ -549,17 +581,37 @@ def main():
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
     rhs = dev(p.g)
 
-    # warm-up (untimed): also captures the step graph
-    prob.gmres(rhs, tol=0.0, max_iter=max(args.warmup, 1))
-    torch.cuda.synchronize()
-
-    # timed region: graphed steps
+    # warm-up (untimed): also records the step graphs
+    phi = torch.zeros(prob.M, dtype=torch.float64, device="cuda:0")
+    prob.gmres(rhs, tol=0.0, max_iter=max(args.warmup, 1), out=phi)
+    # timed region: graphed steps from the zero initial guess (set before the clock starts)
+    phi.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, iters, applies, _, _ = prob.gmres(rhs, tol=0.0, max_iter=args.steps)
+    _, iters, applies, _, _ = prob.gmres(rhs, tol=0.0, max_iter=args.steps, out=phi)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     assert iters == args.steps
+
+    # the fixed cost of one kfbi_gmres call (start launch, graph launches, the
+    # final wait, the Python call), outside the timed region: medians of calls
+    # of 10 and 20 steps (11 and 21 applies, no restart), per step the difference
+    def call_us(k):
+        ts = []
+        for _ in range(7):
+            phi.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            prob.gmres(rhs, tol=0.0, max_iter=k, out=phi)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        return 1e6 * sorted(ts)[3]
+    t10, t20 = call_us(10), call_us(20)
+    marginal = (t20 - t10) / 10.0
+    per_call = {"overhead_us": t10 - 11.0 * marginal, "us_per_apply_marginal": marginal,
+                "call_10_steps_us": t10, "call_20_steps_us": t20,
+                "basis": "t(10 steps) - 11 x (t(20) - t(10))/10; a call of K steps makes K + 1 applies "
+                         "(the last one the true residual) below the restart length"}
 
     # instrumented region: the same steps launched one by one with HIP events per stage
     prob.set_timing(True)
@@ -632,6 +684,7 @@ def main():
                       "us_per_step_ungraphed": 1e6 * dt_ev / args.steps},
         "solve": {"ms": solve_ms, "gmres_iters": it, "relres": rel, "converged": conv,
                   "linf_err_vs_exact": float(err)},
+        "per_call": per_call,
     }
     if args.convergence == "on":
         out["convergence"] = convergence(ctx)

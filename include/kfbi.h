@@ -40,6 +40,14 @@
  * Errors: every call returns a kfbi_status; on error no output is written (for
  * enqueueing calls: nothing is enqueued) and kfbi_last_error() returns a
  * message for the calling thread.
+ *
+ * Non-finite data: the device checks what it computes from the caller's data.
+ * kfbi_apply, kfbi_apply_neumann and kfbi3_apply check the density first
+ * (and so wait for the check); the solves and outer iterations (GMRES,
+ * BiCGSTAB, Richardson, in every form) stop at the first residual or
+ * Arnoldi norm that comes out NaN or Inf -- a NaN or Inf anywhere in f inside
+ * Omega, f on Gamma, g or the initial density reaches it -- and return
+ * KFBI_ERR_NONFINITE with none of their outputs written.
  */
 #ifndef KFBI_H
 #define KFBI_H
@@ -123,6 +131,12 @@ kfbi_status kfbi_prob_mask(const kfbi_prob* prob, unsigned char* inside);
 kfbi_status kfbi_prob_crossings(const kfbi_prob* prob, int* axis, int* nodes, double* t, double* xy);
 /* host, I x 2: the irregular nodes (i, j) in the library's internal order. */
 kfbi_status kfbi_prob_irregular(const kfbi_prob* prob, int* ij);
+/* host, M x 2 each (either may be NULL): the control points where g, f on
+ * Gamma and the density live -- the samples as given, since Sec. 2.1 takes the
+ * density at the boundary points the curve is described by -- and the unit
+ * outward normal of the spline curve there (the normal of the jump formulas
+ * and of d_n v+; Neumann data are g_n = grad u . normal at these points). */
+kfbi_status kfbi_prob_points(const kfbi_prob* prob, double* xy, double* normal);
 
 /* ---------------------------------------------------------------- hot path */
 
@@ -130,7 +144,8 @@ kfbi_status kfbi_prob_irregular(const kfbi_prob* prob, int* ij);
  * F = 0 (Alg. 1 steps 4-6).  Jumps and corrections at the irregular nodes
  * (Alg. 2), a sine-transform solve along y with a tridiagonal solve along x
  * (Alg. 4) evaluated only where the interpolation needs it, and the
- * interpolation (Alg. 3).  phi, out: device, M doubles. */
+ * interpolation (Alg. 3).  phi, out: device, M doubles.  Waits for the check
+ * of phi (KFBI_ERR_NONFINITE, out untouched, if it holds a NaN or Inf). */
 kfbi_status kfbi_apply(kfbi_prob* prob, const double* phi, double* out);
 
 /* Full Dirichlet solve (Sec. 2.1): g^ = g - (Y f)^+, GMRES (Alg. 5) on
@@ -154,7 +169,8 @@ kfbi_status kfbi_solve(kfbi_prob* prob, const double* f_grid, const double* f_ga
  * guess in, iterate out.  Stops when the true relative residual drops below
  * tol, or after max_iter Arnoldi steps; tol <= 0 never stops early (fixed
  * work, for timing).  iters: Arnoldi steps made; applies: all K_D
- * applications (Arnoldi steps plus one residual check per restart cycle);
+ * applications (Arnoldi steps, one residual apply at the end of every cycle,
+ * and one at the start unless the initial guess is zero: K_D 0 = 0);
  * rel_res: last relative residual (true residual at cycle ends, Givens
  * estimate otherwise).  Host outputs may be NULL.  Synchronises. */
 kfbi_status kfbi_gmres(kfbi_prob* prob, const double* rhs, double* phi, double tol, int max_iter,
@@ -364,11 +380,14 @@ kfbi_status kfbi_batch_admit(kfbi_batch* batch, kfbi_prob* prob, const double* f
 /* Enqueue nsteps GMRES iterations of every live problem (no synchronisation). */
 kfbi_status kfbi_batch_step(kfbi_batch* batch, int nsteps);
 /* Synchronise and report per slot (host arrays of max_slots entries, any may be
- * NULL): state 1 converged, -1 iteration cap reached, 0 running, -2 empty slot;
- * Arnoldi steps made; last relative residual. */
+ * NULL): state 1 converged, -1 iteration cap reached, 0 running, -2 empty slot,
+ * -3 stopped on a NaN or Inf in the request's data; Arnoldi steps made; last
+ * relative residual. */
 kfbi_status kfbi_batch_poll(kfbi_batch* batch, int* state, int* iters, double* rel_res);
 /* Final solve u = W phi + Y f of a slot (outputs as in kfbi_solve) and release
- * the slot.  Enqueues; the outputs are ready after the next synchronisation. */
+ * the slot.  Enqueues; the outputs are ready after the next synchronisation.
+ * A slot the last poll reported as -3 is released with nothing written and
+ * KFBI_ERR_NONFINITE returned. */
 kfbi_status kfbi_batch_finish(kfbi_batch* batch, int slot, double* u_grid, double* u_gamma, double* phi);
 /* Live problems and the device bytes they hold. */
 kfbi_status kfbi_batch_info(const kfbi_batch* batch, int* live, size_t* bytes_in_use);

@@ -65,8 +65,11 @@ struct kfbi_prob {
     const double* b_fgam = nullptr;
     double* s2a = nullptr;       // M: spline second derivatives (density)
     double* s2b = nullptr;       // M: spline second derivatives (f on Gamma)
+    int* d_flag = nullptr;       // 1: the density checked by a kfbi_apply call holds a NaN or Inf
+    int h_flag = 0;              // its host copy
     GmresBufs gm{};
     GmresState st_host{};        // host copy of the GMRES state (stable address for async copies)
+    GmresState* st_pub = nullptr;   // pinned host mirror the device publishes the state to (gm.pub)
     // timing: a start and an end event for each of an apply's three launches,
     // read back by kfbi_apply_timing
     static constexpr int kMaxTimed = 4096;
@@ -76,9 +79,12 @@ struct kfbi_prob {
     double tuned_apply_us = 0, tuned_grid_us = 0;
     // a captured batch of GMRES steps (apply + Arnoldi update) per operator
     // (kOpD, kOpN), replayed per batch
-    static constexpr int kGraphSteps = 8;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    bool graph_failed[2] = {false, false};
+    // graphs of 32, 16, 8, 4, 2 and 1 steps (index k: kGraphSteps >> k
+    // steps), so a run launches exactly the steps it has left, in few graphs
+    static constexpr int kGraphSteps = 32;
+    static constexpr int kGraphSizes = 6;
+    hipGraphExec_t gexec[2][kGraphSizes] = {};
+    bool graph_failed[2][kGraphSizes] = {};
     // Richardson and BiCGSTAB (Table 2's alternatives): vectors, state, and a
     // graph of a batch of iterations for each
     IterBufs ib{};
@@ -115,13 +121,17 @@ kfbi_status upload(kfbi_prob* p, const T** out, const std::vector<T>& v) {
 void free_prob(kfbi_prob* p) {
     for (void* a : p->allocs) hipFree(a);
     p->allocs.clear();
+    if (p->st_pub) hipHostFree(p->st_pub);
+    p->st_pub = nullptr;
+    p->gm.pub = nullptr;
     for (auto& e : p->ev)
         if (e) hipEventDestroy(e);
     p->ev.clear();
-    for (auto& g : p->gexec) {
-        if (g) hipGraphExecDestroy(g);
-        g = nullptr;
-    }
+    for (auto& row : p->gexec)
+        for (auto& g : row) {
+            if (g) hipGraphExecDestroy(g);
+            g = nullptr;
+        }
     for (auto& g : p->iexec) {
         if (g) hipGraphExecDestroy(g);
         g = nullptr;
@@ -248,6 +258,20 @@ kfbi_status sparse_apply(kfbi_prob* p, int op, const double* phi, const double* 
     return KFBI_OK;
 }
 
+// K_D phi or K_N phi (op) of a caller's density, checked first: the apply's
+// launches skip when the check finds a NaN or Inf, so nothing is written, and
+// the call waits for the check's flag.
+kfbi_status checked_apply(kfbi_prob* p, int op, const double* phi, double* out) {
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(launch_nonfinite(p->M, phi, p->d_flag, s));
+    HIP_TRY(launch_spline(p->dp, phi, p->s2a, p->d_flag, s));
+    if (kfbi_status e = sparse_apply(p, op, phi, p->s2a, out, p->d_flag, nullptr, s)) return e;
+    HIP_TRY(hipMemcpyAsync(&p->h_flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (p->h_flag) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in the density");
+    return KFBI_OK;
+}
+
 // Restarted GMRES on K_D phi = ghat (ghat already in p->gm.ghat).  Steps are
 // enqueued in batches; with tol > 0 the host polls the device state after each
 // batch, with tol <= 0 the work is fixed and the host waits once at the end.
@@ -270,16 +294,16 @@ kfbi_status enqueue_steps(kfbi_prob* p, int op, int nsteps, hipStream_t s) {
     return KFBI_OK;
 }
 
-// Record kGraphSteps GMRES steps into a graph once per problem.  All launch
-// arguments are fixed device pointers and the steps read their parameters from
-// the device state, so one graph serves every call.  If capture is not possible
-// the steps are launched directly.
-void ensure_graph(kfbi_prob* p, int op) {
-    if (p->gexec[op] || p->graph_failed[op]) return;
+// Record kGraphSteps >> k GMRES steps into a graph once per problem.  All
+// launch arguments are fixed device pointers and the steps read their
+// parameters from the device state, so one graph serves every call.  If
+// recording is not possible the steps are launched directly.
+void ensure_graph(kfbi_prob* p, int op, int k) {
+    if (p->gexec[op][k] || p->graph_failed[op][k]) return;
     const bool timing = p->timing;
     p->timing = false;
-    p->graph_failed[op] = !record_graph(p->ctx->stream, &p->gexec[op], [&](hipStream_t s) {
-        return enqueue_steps(p, op, kfbi_prob::kGraphSteps, s);
+    p->graph_failed[op][k] = !record_graph(p->ctx->stream, &p->gexec[op][k], [&](hipStream_t s) {
+        return enqueue_steps(p, op, kfbi_prob::kGraphSteps >> k, s);
     });
     p->timing = timing;
 }
@@ -289,76 +313,89 @@ void ensure_graph(kfbi_prob* p, int op) {
 struct GmresRun {
     kfbi_prob* p = nullptr;
     int op = kOpD;
-    int max_steps = 0, steps = 0, batches = 0, poll_every = 1;
-    bool use_graph = false, finished = false;
+    int max_steps = 0, steps = 0;
+    bool use_graph = false, poll_each = true, extended = false, finished = false;
 };
 
-// Set up GMRES on K phi = ghat (K_D or K_N by op; ghat already in p->gm.ghat)
-// from phi_in: the state, the input's spline, the first step's corrections.
-kfbi_status gmres_start(kfbi_prob* p, int op, const double* phi_in, double tol, int max_iter, GmresRun* r) {
+// Set up GMRES on K phi = ghat (K_D or K_N by op) from phi_in: ghat <- rhs
+// (null: already in p->gm.ghat), the state, and the first K input with its
+// spline and corrections, in two launches (gm_start); xout (may be null)
+// receives the final iterate from the device.  The run takes at most max_iter
+// Arnoldi steps and one residual step per cycle end: those step slots are
+// launched.  A nonzero guess takes one residual step more, at the start; the
+// run finds that in its last poll and launches one more slot (gmres_more).
+kfbi_status gmres_start(kfbi_prob* p, int op, const double* rhs, const double* phi_in, double tol, int max_iter,
+                        double* xout, GmresRun* r) {
     hipStream_t s = p->ctx->stream;
-    const int M = p->M;
-    GmresBufs b = p->gm;
-    HIP_TRY(hipMemcpyAsync(b.phi, phi_in, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b.xcur, phi_in, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    GmresState& st0 = p->st_host;
-    st0 = GmresState{};
-    st0.first = 1;
-    st0.tol = tol;
-    st0.max_iter = max_iter;
-    st0.reorth = p->reorth;
-    HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
-    if (!p->timing) {                                  // the first step's corrections
-        JumpSrc js{b.xcur, b.s2cur, nullptr, nullptr, nullptr, nullptr};
-        HIP_TRY(launch_correct(op_view(p, op), js, nullptr, p->corr_il, nullptr, nullptr, s));
-    }
-    const int cycles = max_iter / std::max(1, p->restart) + 2;
+    const DevPlan d = op_view(p, op);
+    HIP_TRY(launch_gmres_start(&d, p->dp.taps, p->M, p->gm, rhs, phi_in, tol, max_iter, p->reorth, xout,
+                               p->timing ? nullptr : p->corr_il, s));
+    const int m = std::max(1, p->restart);
     *r = GmresRun{};
     r->p = p;
     r->op = op;
-    r->max_steps = max_iter + cycles;
+    r->max_steps = max_iter + (max_iter + m - 1) / m;
     r->use_graph = !p->timing;
-    if (r->use_graph) ensure_graph(p, op);
-    r->poll_every = tol > 0 ? 1 : (r->max_steps + kfbi_prob::kGraphSteps - 1) / kfbi_prob::kGraphSteps;
+    r->poll_each = tol > 0;
+    if (r->use_graph)                                   // recorded at the first run, not inside a later one
+        for (int k = 0; k < kfbi_prob::kGraphSizes; ++k) ensure_graph(p, op, k);
     return KFBI_OK;
 }
 
-// Enqueue the next batch of kGraphSteps steps (a replayed graph unless
-// per-launch timing is on); returns through *poll whether the state should be
-// read after it.
+// After the poll of the last slot: whether the run still needs its one extra
+// residual step (a nonzero initial guess); if so the slot is added.
+bool gmres_more(GmresRun& r) {
+    if (r.p->st_host.converged || r.extended) return false;
+    r.extended = true;
+    r.max_steps += 1;
+    return true;
+}
+
+// Enqueue the next batch of steps: kGraphSteps, or the largest power of two
+// not above what is left (a replayed graph unless per-launch timing is on);
+// returns through *poll whether the state should be read after it (every
+// batch when the run can stop early, else only after the last).
 kfbi_status gmres_batch(GmresRun& r, bool* poll) {
     kfbi_prob* p = r.p;
     hipStream_t s = p->ctx->stream;
-    if (r.use_graph && p->gexec[r.op]) {
-        HIP_TRY(hipGraphLaunch(p->gexec[r.op], s));
-    } else if (kfbi_status e = enqueue_steps(p, r.op, kfbi_prob::kGraphSteps, s)) {
+    const int left = r.max_steps - r.steps;
+    int k = 0;
+    while ((kfbi_prob::kGraphSteps >> k) > left && k + 1 < kfbi_prob::kGraphSizes) ++k;
+    const int n = kfbi_prob::kGraphSteps >> k;
+    if (r.use_graph) ensure_graph(p, r.op, k);
+    if (r.use_graph && p->gexec[r.op][k]) {
+        HIP_TRY(hipGraphLaunch(p->gexec[r.op][k], s));
+    } else if (kfbi_status e = enqueue_steps(p, r.op, n, s)) {
         return e;
     }
-    r.steps += kfbi_prob::kGraphSteps;
-    *poll = ++r.batches % r.poll_every == 0 || r.steps >= r.max_steps;
+    r.steps += n;
+    *poll = r.poll_each || r.steps >= r.max_steps;
     return KFBI_OK;
 }
 
-// Request the state into p->st_host (completes with the stream).
-kfbi_status gmres_request_state(GmresRun& r) {
-    HIP_TRY(hipMemcpyAsync(&r.p->st_host, r.p->gm.st, sizeof(GmresState), hipMemcpyDeviceToHost, r.p->ctx->stream));
+// Wait for the stream and take the state the device last published (every
+// residual step, a run's end and its start publish it) into p->st_host.
+kfbi_status gmres_read_state(kfbi_prob* p) {
+    HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+    p->st_host = *p->st_pub;
     return KFBI_OK;
 }
 
-// Restarted GMRES on K phi = ghat (K_D or K_N by op; ghat already in
-// p->gm.ghat).  Steps go in batches (a replayed graph unless per-launch timing
-// is on); with tol > 0 the host polls the device state after each batch, with
-// tol <= 0 the work is fixed and the host waits once at the end.
-kfbi_status run_gmres(kfbi_prob* p, int op, const double* phi_in, double tol, int max_iter, GmresState* out) {
+// Restarted GMRES on K phi = ghat (K_D or K_N by op; ghat <- rhs, or already
+// in p->gm.ghat when rhs is null).  Steps go in batches (a replayed graph
+// unless per-launch timing is on); with tol > 0 the host polls the device
+// state after each batch, with tol <= 0 the work is fixed and the host waits
+// once at the end.
+kfbi_status run_gmres(kfbi_prob* p, int op, const double* rhs, const double* phi_in, double tol, int max_iter,
+                      GmresState* out, double* x_out = nullptr) {
     GmresRun r;
-    if (kfbi_status e = gmres_start(p, op, phi_in, tol, max_iter, &r)) return e;
-    while (r.steps < r.max_steps) {
+    if (kfbi_status e = gmres_start(p, op, rhs, phi_in, tol, max_iter, x_out, &r)) return e;
+    for (;;) {
+        if (r.steps >= r.max_steps && !gmres_more(r)) break;
         bool poll = false;
         if (kfbi_status e = gmres_batch(r, &poll)) return e;
         if (poll) {
-            if (kfbi_status e = gmres_request_state(r)) return e;
-            HIP_TRY(hipStreamSynchronize(p->ctx->stream));
+            if (kfbi_status e = gmres_read_state(p)) return e;
             if (p->st_host.converged) break;
         }
     }
@@ -372,19 +409,18 @@ kfbi_status run_gmres(kfbi_prob* p, int op, const double* phi_in, double tol, in
 kfbi_status run_gmres_pair(kfbi_prob* pa, int opa, const double* xa, kfbi_prob* pb, int opb, const double* xb,
                            GmresState* outa, GmresState* outb) {
     GmresRun r[2];
-    if (kfbi_status e = gmres_start(pa, opa, xa, pa->tol, pa->max_iter, &r[0])) return e;
-    if (kfbi_status e = gmres_start(pb, opb, xb, pb->tol, pb->max_iter, &r[1])) return e;
+    if (kfbi_status e = gmres_start(pa, opa, nullptr, xa, pa->tol, pa->max_iter, nullptr, &r[0])) return e;
+    if (kfbi_status e = gmres_start(pb, opb, nullptr, xb, pb->tol, pb->max_iter, nullptr, &r[1])) return e;
     while (!(r[0].finished && r[1].finished)) {
         for (auto& q : r) {
             if (q.finished) continue;
             bool poll = false;
             if (kfbi_status e = gmres_batch(q, &poll)) return e;
-            if (kfbi_status e = gmres_request_state(q)) return e;
         }
         for (auto& q : r) {
             if (q.finished) continue;
-            HIP_TRY(hipStreamSynchronize(q.p->ctx->stream));
-            if (q.p->st_host.converged || q.steps >= q.max_steps) q.finished = true;
+            if (kfbi_status e = gmres_read_state(q.p)) return e;
+            if (q.p->st_host.converged || (q.steps >= q.max_steps && !gmres_more(q))) q.finished = true;
         }
     }
     *outa = pa->st_host;
@@ -400,15 +436,11 @@ kfbi_status gmres_call(kfbi_prob* p, int op, const double* rhs, double* x, doubl
     if (kfbi_status e = check_ptr(x, "x")) return e;
     if (max_iter <= 0) return set_err(KFBI_ERR_ARG, "max_iter must be positive");
     HIP_TRY(hipSetDevice(p->ctx->device));
-    hipStream_t s = p->ctx->stream;
-    HIP_TRY(hipMemcpyAsync(p->gm.ghat, rhs, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
     GmresState st{};
-    if (kfbi_status e = run_gmres(p, op, x, tol, max_iter, &st)) return e;
-    HIP_TRY(hipMemcpyAsync(x, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    if (kfbi_status e = run_gmres(p, op, rhs, x, tol, max_iter, &st, x)) return e;
+    if (st.converged == kGmNonfinite) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in rhs or the initial guess");
     if (iters) *iters = st.it;
-    // one residual apply per cycle start, one more for the final residual check
-    if (applies) *applies = st.it + st.cycles + (st.converged ? 1 : 0);
+    if (applies) *applies = st.it + st.res_applies;
     if (rel_res) *rel_res = st.relres;
     if (st.converged == 1) return KFBI_OK;
     return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");
@@ -494,6 +526,7 @@ kfbi_status run_iters(kfbi_prob* p, int method, const double* rhs, double* x, do
         st = st0;
         if (st.done) break;
     }
+    if (st.done == kIterNonfinite) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in rhs or the initial guess");
     if (method == kBicg) {                  // the true residual of the final iterate
         if (kfbi_status e = iter_apply(p, B.x, nullptr, s)) return e;
         HIP_TRY(launch_iter_step(kIterTrueRes, B, s));
@@ -547,6 +580,8 @@ kfbi_status solve_neumann_pair(kfbi_prob* pa, const NeumannIO& ia, kfbi_prob* pb
     if (kfbi_status e = neumann_prepare(pb, ib)) return e;
     GmresState sa{}, sb{};
     if (kfbi_status e = run_gmres_pair(pa, kOpN, ia.psi, pb, kOpN, ib.psi, &sa, &sb)) return e;
+    if (sa.converged == kGmNonfinite || sb.converged == kGmNonfinite)
+        return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in f, f_gamma, g_n or psi");
     if (kfbi_status e = neumann_finish(pa, ia)) return e;
     if (kfbi_status e = neumann_finish(pb, ib)) return e;
     if (iters_a) *iters_a = sa.it;
@@ -869,6 +904,7 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
     if ((st = dev_alloc(p, &p->corr, p->I)) || (st = dev_alloc(p, &p->corr_il, (size_t)dp.T * 64)) || (st = dev_alloc(p, &p->partial, (size_t)p->Gcap * M)) ||
         (st = dev_alloc(p, &p->R, (size_t)n * n)) || (st = dev_alloc(p, &p->A, (size_t)n * n)) ||
         (st = dev_alloc(p, &p->tmpM, M)) || (st = dev_alloc(p, &p->s2a, M)) || (st = dev_alloc(p, &p->s2b, M)) ||
+        (st = dev_alloc(p, &p->d_flag, 1)) ||
         (st = dev_alloc(p, &p->gm.s2cur, M)) || (st = dev_alloc(p, &p->gm.V, (size_t)(m + 1) * M)) ||
         (st = dev_alloc(p, &p->gm.H, (size_t)(m + 1) * m)) || (st = dev_alloc(p, &p->gm.cs, m)) ||
         (st = dev_alloc(p, &p->gm.sn, m)) || (st = dev_alloc(p, &p->gm.g, m + 1)) ||
@@ -887,6 +923,15 @@ kfbi_status kfbi_prob_create(kfbi_ctx* ctx, const kfbi_desc* d, kfbi_prob** out)
         ib.M = M;
     }
     HIP_TRY(hipMemset(p->gm.cnt, 0, sizeof(unsigned)));
+    // the state's host mirror: pinned, coherent host memory the device writes to
+    if (hipHostMalloc((void**)&p->st_pub, sizeof(GmresState), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
+        hipGetLastError();
+        p->st_pub = nullptr;
+        return fail(set_err(KFBI_ERR_OOM, "pinned host allocation of the GMRES state mirror failed"));
+    }
+    *p->st_pub = GmresState{};
+    p->gm.pub = p->st_pub;
     if (p->precision == KFBI_FP32_REFINED && (st = dev_alloc(p, &p->X32, (size_t)n * n))) return fail(st);
     if (p->refine >= 2 && (st = dev_alloc(p, &p->D, (size_t)n * n))) return fail(st);
     // pad slots of the interleaved corrections stay zero for the life of the problem
@@ -938,6 +983,21 @@ kfbi_status kfbi_prob_crossings(const kfbi_prob* p, int* axis, int* nodes, doubl
     return KFBI_OK;
 }
 
+kfbi_status kfbi_prob_points(const kfbi_prob* p, double* xy, double* normal) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    for (int k = 0; k < p->M; ++k) {
+        if (xy) {
+            xy[2 * k] = p->plan.px[k];
+            xy[2 * k + 1] = p->plan.py[k];
+        }
+        if (normal) {
+            normal[2 * k] = p->plan.z_geo[k].nx;
+            normal[2 * k + 1] = p->plan.z_geo[k].ny;
+        }
+    }
+    return KFBI_OK;
+}
+
 kfbi_status kfbi_prob_irregular(const kfbi_prob* p, int* ij) {
     if (!p || !ij) return set_err(KFBI_ERR_ARG, "NULL argument");
     for (int k = 0; k < p->I; ++k) {
@@ -952,8 +1012,7 @@ kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(phi, "phi")) return s;
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
-    HIP_TRY(launch_spline(p->dp, phi, p->s2a, nullptr, p->ctx->stream));
-    return sparse_apply(p, kOpD, phi, p->s2a, out, nullptr, nullptr, p->ctx->stream);
+    return checked_apply(p, kOpD, phi, out);
 }
 
 kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {
@@ -1022,7 +1081,8 @@ kfbi_status kfbi_solve(kfbi_prob* p, const double* f_grid, const double* f_gamma
     HIP_TRY(launch_axpby(M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
     // GMRES (Alg. 5): every step is one K_D apply plus one orthogonalisation
     GmresState st{};
-    if (kfbi_status e = run_gmres(p, kOpD, phi, p->tol, p->max_iter, &st)) return e;
+    if (kfbi_status e = run_gmres(p, kOpD, nullptr, phi, p->tol, p->max_iter, &st)) return e;
+    if (st.converged == kGmNonfinite) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in f, f_gamma, g or phi");
     // u = W phi + Y f
     JumpSrc jf{b.phi, nullptr, f_gamma, nullptr, nullptr, nullptr};
     if (kfbi_status e = dense_interface_solve(p, false, jf, f_grid, true, u_grid, true, u_gamma)) return e;
@@ -1096,8 +1156,7 @@ kfbi_status kfbi_apply_neumann(kfbi_prob* p, const double* psi, double* out) {
     if (kfbi_status s = check_ptr(psi, "psi")) return s;
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
-    HIP_TRY(launch_spline(p->dp, psi, p->s2a, nullptr, p->ctx->stream));
-    return sparse_apply(p, kOpN, psi, p->s2a, out, nullptr, nullptr, p->ctx->stream);
+    return checked_apply(p, kOpN, psi, out);
 }
 
 kfbi_status kfbi_interface_solve_neumann(kfbi_prob* p, const double* psi, const double* ftilde, const double* f_gamma,
@@ -1123,7 +1182,8 @@ kfbi_status kfbi_solve_neumann(kfbi_prob* p, const double* f_grid, const double*
     if (kfbi_status e = neumann_prepare(p, io)) return e;
     // GMRES on K_N psi = g^: every step is one K_N apply plus one orthogonalisation
     GmresState st{};
-    if (kfbi_status e = run_gmres(p, kOpN, psi, p->tol, p->max_iter, &st)) return e;
+    if (kfbi_status e = run_gmres(p, kOpN, nullptr, psi, p->tol, p->max_iter, &st)) return e;
+    if (st.converged == kGmNonfinite) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in f, f_gamma, g_n or psi");
     if (kfbi_status e = neumann_finish(p, io)) return e;
     HIP_TRY(hipStreamSynchronize(p->ctx->stream));
     if (iters) *iters = st.it;
@@ -1179,11 +1239,12 @@ bool tiles_valid(const kfbi_prob* p, int Rm, int B) {
 }
 
 void drop_graph(kfbi_prob* p) {
-    for (int op = 0; op < 2; ++op) {
-        if (p->gexec[op]) hipGraphExecDestroy(p->gexec[op]);
-        p->gexec[op] = nullptr;
-        p->graph_failed[op] = false;
-    }
+    for (int op = 0; op < 2; ++op)
+        for (int k = 0; k < kfbi_prob::kGraphSizes; ++k) {
+            if (p->gexec[op][k]) hipGraphExecDestroy(p->gexec[op][k]);
+            p->gexec[op][k] = nullptr;
+            p->graph_failed[op][k] = false;
+        }
 }
 
 // mean time in microseconds of `reps` runs of `body` (after one warm-up run)
@@ -1546,15 +1607,11 @@ kfbi_status kfbi_batch_admit(kfbi_batch* B, kfbi_prob* p, const double* f_grid, 
     if (kfbi_status e = dense_interface_solve(p, false, jy, f_grid, true, nullptr, false, p->tmpM)) return e;
     GmresBufs b = p->gm;
     HIP_TRY(launch_axpby(p->M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
-    HIP_TRY(launch_axpby(p->M, 0.0, b.ghat, 0.0, nullptr, b.phi, s));
-    HIP_TRY(launch_axpby(p->M, 0.0, b.ghat, 0.0, nullptr, b.xcur, s));
-    HIP_TRY(launch_spline(p->dp, b.xcur, b.s2cur, nullptr, s));
+    // the state and the first Arnoldi input (phi_0 = 0: the residual is g^);
+    // the batch's own correction stage makes its corrections
+    HIP_TRY(launch_gmres_start(nullptr, p->dp.taps, p->M, b, nullptr, nullptr, p->tol, p->max_iter, p->reorth,
+                               nullptr, nullptr, s));
     p->st_host = GmresState{};
-    p->st_host.first = 1;
-    p->st_host.tol = p->tol;
-    p->st_host.max_iter = p->max_iter;
-    p->st_host.reorth = p->reorth;
-    HIP_TRY(hipMemcpyAsync(b.st, &p->st_host, sizeof p->st_host, hipMemcpyHostToDevice, s));
     SlotDev& S = B->h_slots[free_slot];
     S.p = p->dp;
     S.b = b;
@@ -1598,7 +1655,7 @@ kfbi_status kfbi_batch_poll(kfbi_batch* B, int* state, int* iters, double* rel_r
     HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < B->max_slots; ++k) {
         const kfbi_prob* p = B->slot[k];
-        if (state) state[k] = p ? p->st_host.converged : -2;
+        if (state) state[k] = !p ? -2 : p->st_host.converged == kGmNonfinite ? -3 : p->st_host.converged;
         if (iters) iters[k] = p ? p->st_host.it : 0;
         if (rel_res) rel_res[k] = p ? p->st_host.relres : 0.0;
     }
@@ -1612,14 +1669,20 @@ kfbi_status kfbi_batch_finish(kfbi_batch* B, int slot, double* u_grid, double* u
     HIP_TRY(hipSetDevice(B->ctx->device));
     kfbi_prob* p = B->slot[slot];
     hipStream_t s = B->ctx->stream;
-    JumpSrc jf{p->gm.phi, nullptr, p->b_fgam, nullptr, nullptr, nullptr};
-    if (kfbi_status e = dense_interface_solve(p, false, jf, p->b_fgrid, true, u_grid, true, u_gamma)) return e;
-    HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // a slot that stopped on a NaN or Inf (as the last poll saw it) is released
+    // with nothing written
+    const bool bad = p->st_host.converged == kGmNonfinite;
+    if (!bad) {
+        JumpSrc jf{p->gm.phi, nullptr, p->b_fgam, nullptr, nullptr, nullptr};
+        if (kfbi_status e = dense_interface_solve(p, false, jf, p->b_fgrid, true, u_grid, true, u_gamma)) return e;
+        HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     B->used -= B->slot_bytes[slot];
     B->slot[slot] = nullptr;
     B->slot_bytes[slot] = 0;
     p->b_fgrid = p->b_fgam = nullptr;
-    return batch_rebuild(B);
+    if (kfbi_status e = batch_rebuild(B)) return e;
+    return bad ? set_err(KFBI_ERR_NONFINITE, "NaN or Inf in the slot's f, f_gamma or g") : KFBI_OK;
 }
 
 kfbi_status kfbi_batch_info(const kfbi_batch* B, int* live, size_t* bytes) {

@@ -29,6 +29,8 @@ struct kfbi_prob3 {
     double* J = nullptr;        // 10 M jumps
     double* tmpM = nullptr;     // M
     double* zeroM = nullptr;    // M zeros (the density of Y f)
+    int* d_flag = nullptr;      // 1: the density checked by kfbi3_apply holds a NaN or Inf
+    int h_flag = 0;
     int dstB = 16;
     GmresBufs gm{};
     GmresState st_host{};
@@ -104,30 +106,33 @@ kfbi_status enqueue_steps3(kfbi_prob3* p, int nsteps, hipStream_t s) {
 kfbi_status run_gmres3(kfbi_prob3* p, const double* phi_in, double tol, int max_iter, GmresState* out) {
     hipStream_t s = p->ctx->stream;
     GmresBufs b = p->gm;
-    HIP_TRY(hipMemcpyAsync(b.phi, phi_in, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(b.xcur, phi_in, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    GmresState& st0 = p->st_host;
-    st0 = GmresState{};
-    st0.first = 1;
-    st0.tol = tol;
-    st0.max_iter = max_iter;
-    st0.reorth = kGmReorthDefault;
-    HIP_TRY(hipMemcpyAsync(b.st, &st0, sizeof st0, hipMemcpyHostToDevice, s));
+    // the state and the first K_D input on the device (gm_start)
+    HIP_TRY(launch_gmres_start(nullptr, nullptr, p->M, b, nullptr, phi_in, tol, max_iter, kGmReorthDefault, nullptr,
+                               nullptr, s));
     if (!p->gexec && !p->graph_failed)
         p->graph_failed = !record_graph(s, &p->gexec,
                                         [&](hipStream_t st) { return enqueue_steps3(p, kfbi_prob3::kGraphSteps, st); });
-    const int cycles = max_iter / std::max(1, p->restart) + 2;
-    const int max_steps = max_iter + cycles;
+    // Arnoldi steps and one residual step per cycle end; a nonzero guess takes
+    // one residual step more, found in the last poll
+    const int m = std::max(1, p->restart);
+    int max_steps = max_iter + (max_iter + m - 1) / m;
+    bool extended = false;
     const int B = kfbi_prob3::kGraphSteps;
-    const int poll_every = tol > 0 ? 1 : (max_steps + B - 1) / B;
     GmresState& st = p->st_host;
-    for (int done = 0, nb = 0; done < max_steps; done += B) {
-        if (p->gexec) {
+    for (int done = 0;;) {
+        if (done >= max_steps) {
+            if (st.converged || extended) break;
+            extended = true;
+            max_steps += 1;
+        }
+        const int n = std::min(B, max_steps - done);
+        if (p->gexec && n == B) {
             HIP_TRY(hipGraphLaunch(p->gexec, s));
-        } else if (kfbi_status e = enqueue_steps3(p, B, s)) {
+        } else if (kfbi_status e = enqueue_steps3(p, n, s)) {
             return e;
         }
-        if (++nb % poll_every == 0 || done + B >= max_steps) {
+        done += n;
+        if (tol > 0 || done >= max_steps) {
             HIP_TRY(hipMemcpyAsync(&st, b.st, sizeof st, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             if (st.converged) break;
@@ -208,7 +213,7 @@ kfbi_status kfbi3_prob_create(kfbi_ctx* ctx, const kfbi_desc3* d, kfbi_prob3** o
     const int m = p->restart;
     GmresBufs& b = p->gm;
     if ((st = alloc3(p, &p->G, (size_t)N * N * N)) || (st = alloc3(p, &p->J, (size_t)kJump3 * M)) ||
-        (st = alloc3(p, &p->tmpM, M)) || (st = alloc3(p, &p->zeroM, M)) ||
+        (st = alloc3(p, &p->tmpM, M)) || (st = alloc3(p, &p->zeroM, M)) || (st = alloc3(p, &p->d_flag, 1)) ||
         (st = alloc3(p, &b.V, (size_t)(m + 1) * M)) || (st = alloc3(p, &b.H, (size_t)(m + 1) * m)) ||
         (st = alloc3(p, &b.cs, m)) || (st = alloc3(p, &b.sn, m)) || (st = alloc3(p, &b.g, m + 1)) ||
         (st = alloc3(p, &b.ghat, M)) || (st = alloc3(p, &b.phi, M)) || (st = alloc3(p, &b.xcur, M)) ||
@@ -277,6 +282,12 @@ kfbi_status kfbi3_apply(kfbi_prob3* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(phi, "phi")) return s;
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
+    // the density is checked first; with a NaN or Inf nothing is enqueued
+    hipStream_t s = p->ctx->stream;
+    HIP_TRY(launch_nonfinite(p->M, phi, p->d_flag, s));
+    HIP_TRY(hipMemcpyAsync(&p->h_flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (p->h_flag) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in the density");
     return interface3(p, phi, nullptr, nullptr, nullptr, false, out);
 }
 
@@ -303,6 +314,7 @@ kfbi_status kfbi3_solve(kfbi_prob3* p, const double* f_grid, const double* f_gam
     HIP_TRY(launch_axpby(M, 1.0, g, -1.0, p->tmpM, b.ghat, s));
     GmresState st{};
     if (kfbi_status e = run_gmres3(p, phi, p->tol, p->max_iter, &st)) return e;
+    if (st.converged == kGmNonfinite) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in f, f_gamma, g or phi");
     // u = W phi + Y f
     if (kfbi_status e = interface3(p, b.phi, f_grid, f_gamma, u_grid, true, u_gamma)) return e;
     HIP_TRY(hipMemcpyAsync(phi, b.phi, M * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -324,10 +336,11 @@ kfbi_status kfbi3_gmres(kfbi_prob3* p, const double* rhs, double* phi, double to
     HIP_TRY(hipMemcpyAsync(p->gm.ghat, rhs, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
     GmresState st{};
     if (kfbi_status e = run_gmres3(p, phi, tol, max_iter, &st)) return e;
+    if (st.converged == kGmNonfinite) return set_err(KFBI_ERR_NONFINITE, "NaN or Inf in rhs or the initial guess");
     HIP_TRY(hipMemcpyAsync(phi, p->gm.phi, p->M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (iters) *iters = st.it;
-    if (applies) *applies = st.it + st.cycles + (st.converged ? 1 : 0);
+    if (applies) *applies = st.it + st.res_applies;
     if (rel_res) *rel_res = st.relres;
     if (st.converged == 1) return KFBI_OK;
     return set_err(KFBI_NOT_CONVERGED, "GMRES reached the iteration cap");

@@ -31,6 +31,9 @@ constexpr int kGmHalo = kSplineK + 1;    // reach of the spline filter on each s
 
 enum GmKind { kGmNewCycle = 0, kGmNextVector = 1, kGmCycleEnd = 2, kGmDone = 3 };
 
+// GmresState::converged when a norm of the iteration came out NaN or Inf
+constexpr int kGmNonfinite = -2;
+
 __host__ __device__ inline int gm_chunks(int M) { return (M + kGmChunk - 1) / kGmChunk; }
 __host__ __device__ inline int gm_chunks64(int M) { return (M + 63) / 64; }
 // doubles of partial sums a problem needs: first-pass dots (m+1) x gc64, norms
@@ -72,6 +75,24 @@ __device__ __forceinline__ GmSnap gm_snap(const GmresState* st) {
     s.reorth = st->reorth;
     return s;
 }
+
+// The state, copied to the host-visible mirror (pinned host memory, null when
+// there is none) by the thread that just wrote it: the host reads the mirror
+// after a stream wait instead of copying the state back.
+__device__ __forceinline__ void gm_publish(const GmresBufs& b) {
+    if (b.pub) *b.pub = *b.st;
+}
+
+// What an emit launch takes from the state, given directly by the launch that
+// starts a run (which writes the state itself): the kind, the scale, the
+// source of the next input (x = xsrc * scale) and, when the run ends with
+// x = 0 right away, where that zero goes.
+struct EmitCtl {
+    int kind;
+    double scale;
+    const double* xsrc;
+    double* xzero;
+};
 
 // What the commit of an Arnoldi step reads besides the norms: the first-pass
 // coefficients, the previous rotations and g_j.  Every workgroup of the update
@@ -287,6 +308,14 @@ __device__ inline void gm_commit_residual(const GmresBufs& b, const GmSnap& s, d
     const double beta = sqrt(gm_block_sum(v, red));
     if (tid != 0) return;
     GmresState* st = b.st;
+    if (!isfinite(beta)) {                                 // NaN or Inf in the data: stop here
+        st->converged = kGmNonfinite;
+        st->mode = 2;
+        st->kind = kGmDone;
+        gm_publish(b);
+        return;
+    }
+    st->res_applies += 1;
     const double r0 = s.first ? beta : s.r0;
     const double rel = r0 > 0.0 ? beta / r0 : 0.0;
     const bool done = r0 == 0.0 || beta == 0.0 || rel < s.tol || s.it >= s.max_iter;
@@ -306,6 +335,7 @@ __device__ inline void gm_commit_residual(const GmresBufs& b, const GmSnap& s, d
         st->kind = kGmNewCycle;
         st->scale = 1.0 / beta;
     }
+    gm_publish(b);
 }
 
 // Commit of an Arnoldi step (mode 1), by one workgroup of kGmChunk threads:
@@ -347,32 +377,41 @@ __device__ inline void gm_commit_arnoldi(const GmresBufs& b, const GmSnap& s, co
         }
         for (int i = 0; i < j; ++i) col[i] = rot[i];
         const double den = hypot(a, hn);
-        const double cs = den > 0.0 ? a / den : 1.0;
-        const double sn = den > 0.0 ? hn / den : 0.0;
-        col[j] = den;
-        col[j + 1] = 0.0;
-        b.cs[j] = cs;
-        b.sn[j] = sn;
-        const double gj = ci.gj;
-        b.g[j + 1] = -sn * gj;
-        b.g[j] = cs * gj;
-        const int jn = j + 1, itn = s.it + 1;
-        const double est = fabs(sn * gj) / s.r0;
-        st->relres = est;
-        st->it = itn;
-        const bool end = est < s.tol || jn == m || itn >= s.max_iter || hn == 0.0;
-        s_end = end ? 1 : 0;
-        st->jn = jn;
-        if (end) {
-            st->mode = 0;
-            st->kind = kGmCycleEnd;
+        if (!isfinite(den) || !isfinite(ci.gj)) {         // NaN or Inf in the data: stop here
+            st->converged = kGmNonfinite;
+            st->mode = 2;
+            st->kind = kGmDone;
+            gm_publish(b);
+            s_end = -1;
         } else {
-            st->j = jn;
-            st->kind = kGmNextVector;
-            st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
+            const double cs = den > 0.0 ? a / den : 1.0;
+            const double sn = den > 0.0 ? hn / den : 0.0;
+            col[j] = den;
+            col[j + 1] = 0.0;
+            b.cs[j] = cs;
+            b.sn[j] = sn;
+            const double gj = ci.gj;
+            b.g[j + 1] = -sn * gj;
+            b.g[j] = cs * gj;
+            const int jn = j + 1, itn = s.it + 1;
+            const double est = fabs(sn * gj) / s.r0;
+            st->relres = est;
+            st->it = itn;
+            const bool end = est < s.tol || jn == m || itn >= s.max_iter || hn == 0.0;
+            s_end = end ? 1 : 0;
+            st->jn = jn;
+            if (end) {
+                st->mode = 0;
+                st->kind = kGmCycleEnd;
+            } else {
+                st->j = jn;
+                st->kind = kGmNextVector;
+                st->scale = hn > 0.0 ? 1.0 / hn : 0.0;
+            }
         }
     }
     __syncthreads();
+    if (s_end < 0) return;
     double* Hj = b.H + (size_t)j * (m + 1);
     if (tid <= j + 1) Hj[tid] = col[tid];
     if (!s_end) return;
@@ -521,12 +560,16 @@ __device__ __forceinline__ double gm_spline_s2(const double* __restrict__ taps, 
     return s;
 }
 
-__device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs& b, int M, int c) {
+// ctl: null in a GMRES step (everything from the state), else given by the
+// launch that starts the run.
+__device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs& b, int M, int c,
+                               const EmitCtl* ctl = nullptr) {
     constexpr int W = kGmChunk + 2 * kGmHalo;
     __shared__ double win[W];
     const int tid = threadIdx.x, c0 = c * kGmChunk;
     // z at this thread's window places is requested before the state is read:
     // it is the next input (scaled) unless the cycle has just ended
+    const double* zsrc = ctl ? ctl->xsrc : b.z;
     int ek[2];
     double zk[2];
 #pragma unroll
@@ -535,17 +578,26 @@ __device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs&
         int e = (c0 - kGmHalo + k) % M;
         if (e < 0) e += M;
         ek[r] = e;
-        zk[r] = k < W ? b.z[e] : 0.0;
+        zk[r] = k < W ? zsrc[e] : 0.0;
     }
     const GmresState* st = b.st;
-    const int kind = st->kind;
-    if (kind == kGmDone) return;
-    const double scale = st->scale;
-    const int jn = st->jn;
+    const int kind = ctl ? ctl->kind : st->kind;
+    if (kind == kGmDone) {                               // the run has ended: the iterate goes out
+        const int e = c0 + tid;
+        if (ctl) {
+            if (ctl->xzero && e < M) ctl->xzero[e] = 0.0;
+            return;
+        }
+        double* xo = st->xout;
+        if (xo && st->converged != kGmNonfinite && e < M) xo[e] = b.phi[e];
+        return;
+    }
+    const double scale = ctl ? ctl->scale : st->scale;
+    const int jn = ctl ? 0 : st->jn;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
         const int k = tid + r * kGmChunk;
-        if (k < W) win[k] = kind == kGmCycleEnd ? gm_next_x(b, M, kind, scale, jn, ek[r]) : zk[r] * scale;
+        if (k < W) win[k] = kind == kGmCycleEnd && !ctl ? gm_next_x(b, M, kind, scale, jn, ek[r]) : zk[r] * scale;
     }
     __syncthreads();
     const int e = c0 + tid;
@@ -564,7 +616,8 @@ __device__ inline void gm_emit(const double* __restrict__ taps, const GmresBufs&
 // second derivatives by the same filter, and the corrections by the same
 // arithmetic as a separate correction launch after gm_emit.  One workgroup of
 // kGmChunk threads; corr_il in the sparse-sum layout.
-__device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b, int cc, double* __restrict__ corr_il) {
+__device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b, int cc, double* __restrict__ corr_il,
+                                           const EmitCtl* ctl = nullptr) {
     __shared__ double xw[kCorrWindow];
     __shared__ double sw[kCorrWindow];
     const int M = p.M, tid = threadIdx.x;
@@ -587,7 +640,7 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
     // z at the thread's window place: the next input (scaled) unless the cycle
     // has just ended
     const int ew = (ch.z + tid) % M;
-    const double zw = tid < ch.w ? b.z[ew] : 0.0;
+    const double zw = tid < ch.w ? (ctl ? ctl->xsrc : b.z)[ew] : 0.0;
     const int ks[4] = {arm.x, arm.y, arm.z, arm.w};
     const double ds[4] = {dd.x, dd.y, dd.z, dd.w};
     PointGeom gs[4];
@@ -603,11 +656,11 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
         }
     }
     const GmresState* st = b.st;
-    const int kind = st->kind;
+    const int kind = ctl ? ctl->kind : st->kind;
     if (kind == kGmDone) return;
-    const double scale = st->scale;
-    const int jn = st->jn;
-    if (tid < ch.w) xw[tid] = kind == kGmCycleEnd ? gm_next_x(b, M, kind, scale, jn, ew) : zw * scale;
+    const double scale = ctl ? ctl->scale : st->scale;
+    const int jn = ctl ? 0 : st->jn;
+    if (tid < ch.w) xw[tid] = kind == kGmCycleEnd && !ctl ? gm_next_x(b, M, kind, scale, jn, ew) : zw * scale;
     __syncthreads();
     for (int w = kGmHalo + tid; w < ch.w - kGmHalo; w += kGmChunk) sw[w] = gm_spline_s2(p.taps, xw, w);
     __syncthreads();
@@ -658,6 +711,92 @@ __device__ inline void gm_emit_corrections(const DevPlan& p, const GmresBufs& b,
         acc -= sg * (jv + d * gv + 0.5 * d * d * hh);
     }
     corr_il[slot] = acc * p.inv_h2;
+}
+
+// The start of a GMRES run, one launch of kGmChunk-thread workgroups: the gc
+// emit workgroups, then (with p) one per correction chunk.  Every workgroup
+// first tests the initial guess phi_in (null: zero) for nonzero values and
+// sums |ghat|^2 (ghat <- rhs when rhs is given, else already in place) in one
+// fixed order, so all of them hold the same beta and know what the run does:
+//  - a zero guess has the residual ghat itself (K 0 = 0; Alg. 5 with x_0 = 0),
+//    so its first cycle starts here: V_0 = ghat / beta is the first K input;
+//  - any other guess makes phi_in the first K input, and the first step is a
+//    residual step;
+//  - beta = 0 (x = 0 solves it) or a NaN or Inf ends the run at once.
+// Workgroup 0 writes the whole state (nothing is uploaded from the host) and
+// publishes it; the emit workgroups copy phi_in and rhs into phi and ghat for
+// their chunk and write the first input with its spline second derivatives;
+// the correction workgroups make its corrections.  xout (may be null) is where
+// the emit launch of the step that ends the run copies the iterate.
+__device__ inline void gm_begin(const DevPlan* p, const double* __restrict__ taps, const GmresBufs& b, int M,
+                                const double* __restrict__ rhs, const double* __restrict__ phi_in, double tol,
+                                int max_iter, double reorth, double* xout, double* __restrict__ corr_il) {
+    __shared__ double red[kGmChunk / 64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c = blockIdx.x;
+    const double* gsrc = rhs ? rhs : b.ghat;
+    double ss = 0.0;
+    int nz = 0;
+    for (int e = tid; e < M; e += kGmChunk) {
+        const double gh = gsrc[e];
+        if (phi_in) nz |= phi_in[e] != 0.0;               // a NaN counts as nonzero
+        ss = fma(gh, gh, ss);
+    }
+    ss = wave_sum(ss);
+    if (lane == 0) red[wave] = ss;
+    const bool nonzero = __syncthreads_or(nz) != 0;
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kGmChunk / 64; ++w) t += red[w];  // fixed order
+    const double beta = sqrt(t);
+    EmitCtl ctl{kGmNewCycle, 1.0, gsrc, nullptr};
+    int converged = 0;
+    if (nonzero) {
+        ctl.kind = kGmCycleEnd;
+        ctl.xsrc = phi_in;
+    } else if (!isfinite(beta)) {
+        ctl.kind = kGmDone;
+        converged = kGmNonfinite;
+    } else if (beta == 0.0) {
+        ctl.kind = kGmDone;
+        ctl.xzero = xout;
+        converged = 1;
+    } else {
+        ctl.scale = 1.0 / beta;
+    }
+    if (c == 0) {
+        for (int k = 1 + tid; k <= b.m; k += kGmChunk) b.g[k] = 0.0;
+        if (tid == 0) {
+            GmresState* st = b.st;
+            b.g[0] = nonzero ? 0.0 : beta;
+            st->j = 0;
+            st->it = 0;
+            st->res_applies = 0;
+            st->tol = tol;
+            st->max_iter = max_iter;
+            st->reorth = reorth;
+            st->jn = 0;
+            st->xout = xout;
+            st->converged = converged;
+            st->kind = ctl.kind;
+            st->first = nonzero ? 1 : 0;
+            st->r0 = nonzero ? 0.0 : beta;
+            st->relres = converged == 1 ? 0.0 : 1.0;
+            st->scale = ctl.scale;
+            st->cycles = ctl.kind == kGmNewCycle ? 1 : 0;
+            st->mode = ctl.kind == kGmNewCycle ? 1 : ctl.kind == kGmCycleEnd ? 0 : 2;
+            gm_publish(b);
+        }
+    }
+    if (c < b.gc) {
+        const int e = c * kGmChunk + tid;
+        if (e < M) {
+            b.phi[e] = phi_in ? phi_in[e] : 0.0;
+            if (rhs) b.ghat[e] = rhs[e];
+        }
+        gm_emit(taps, b, M, c, &ctl);
+    } else {
+        gm_emit_corrections(*p, b, c - b.gc, corr_il, &ctl);
+    }
 }
 
 }  // namespace kfbi

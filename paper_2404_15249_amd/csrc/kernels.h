@@ -106,7 +106,7 @@ struct GmresState {
     int j;           // Arnoldi column inside the cycle
     int it;          // K_D applications made by the Arnoldi process
     int first;       // 1 until r0 is known
-    int converged;   // 1 converged, -1 iteration cap, 0 running
+    int converged;   // 1 converged, -1 iteration cap, -2 a NaN or Inf met (kGmNonfinite), 0 running
     int cycles;
     double r0;
     double relres;
@@ -114,9 +114,10 @@ struct GmresState {
     int max_iter;    // cap on Arnoldi steps
     int kind;        // what the last commit left for the emit launch (GmKind in gmres.h)
     int jn;          // columns of the cycle just finished (kGmCycleEnd)
-    int pad;
+    int res_applies; // K applications made for residuals (cycle starts and the final check)
     double scale;    // 1/beta (new cycle) or 1/h_{j+1,j} (next vector)
     double reorth;   // second Gram-Schmidt pass when |z| < reorth |w| (0: never, 1: always)
+    double* xout;    // where the emit launch of the finishing step copies the iterate (null: nowhere)
 };
 
 struct GmresBufs {
@@ -134,16 +135,20 @@ struct GmresBufs {
     double* part;    // gm_part_size(m, gc, gc64): per-chunk partial dots and norms
     double* y;       // m + 1: solution of the cycle's triangular system
     GmresState* st;  // state machine; also holds tol and max_iter so launches are call independent
+    GmresState* pub; // host-visible mirror of the state (pinned host memory; may be null)
     unsigned* cnt;   // chunks of the current update launch that have finished (0 between launches)
     int m;
     int gc;          // chunks of kGmChunk elements covering the M samples
     int gc64;        // chunks of 64 samples (the first Gram-Schmidt pass)
 };
 
+constexpr int kIterNonfinite = -2;
+
 // State of a Richardson or BiCGSTAB run (krylov.hip), in device memory.
 struct IterState {
     int it;          // Richardson: updates made; BiCGSTAB: iterations begun
-    int done;        // 0 running, 1 converged, -1 iteration cap (launches skip while nonzero)
+    int done;        // 0 running, 1 converged, -1 iteration cap or breakdown, -2 (kIterNonfinite)
+                     // a NaN or Inf met (launches skip while nonzero)
     int max_iter;
     int started;     // 1 once r0 is known
     int half;        // BiCGSTAB: 1 if it stopped half way through an iteration (one apply short)
@@ -210,6 +215,16 @@ hipError_t launch_residual(const DevPlan& p, const double* V, double* R, double*
 hipError_t launch_grid_out(const DevPlan& p, const double* V, bool mask, double* u, hipStream_t s);
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z,
                         hipStream_t s);
+// *flag = 1 if x[0..n) holds a NaN or Inf, else 0 (one workgroup; n up to a few 10^4)
+hipError_t launch_nonfinite(int n, const double* x, int* flag, hipStream_t s);
+// The start of a GMRES run (gm_begin in gmres.h), one launch: the state and
+// the first K input (its spline second derivatives with taps; with p and
+// corr_il also its corrections, in the sparse-sum layout).  rhs may be null
+// (ghat already in place); phi_in may be null (a zero guess); xout (may be
+// null) receives the iterate from the emit launch of the step that ends the run.
+hipError_t launch_gmres_start(const DevPlan* p, const double* taps, int M, GmresBufs b, const double* rhs,
+                              const double* phi_in, double tol, int max_iter, double reorth, double* xout,
+                              double* corr_il, hipStream_t s);
 // taps: the spline filter of the density (null: no spline, the surface problem)
 hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s);
 // default of GmresState::reorth (see gmres.h)

@@ -163,6 +163,19 @@ __global__ __launch_bounds__(256) void k_axpby(int n, double a, const double* __
     if (i < n) z[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }
 
+// flag <- 1 if any of x[0..n) is NaN or Inf, else 0: one workgroup, which
+// writes the flag whatever it finds (nothing to clear beforehand)
+__global__ __launch_bounds__(256) void k_nonfinite(int n, const double* __restrict__ x, int* __restrict__ flag) {
+    __shared__ int any;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    int bad = 0;
+    for (int i = threadIdx.x; i < n; i += 256) bad |= !isfinite(x[i]);
+    if (bad) any = 1;                                    // benign race: every writer stores 1
+    __syncthreads();
+    if (threadIdx.x == 0) *flag = any;
+}
+
 // ---------------------------------------------------------------- GMRES step (Alg. 5)
 
 // the apply's last launch inside GMRES: w at 64 samples, then the first pass
@@ -175,6 +188,11 @@ __global__ __launch_bounds__(1024) void k_reduce_gm(DevPlan p, JumpSrc js, const
     gm_dots1_64(b, p.M, blockIdx.x, red, &pre, mode, j);
 }
 __global__ __launch_bounds__(kGmChunk) void k_gm_upd1(GmresBufs b, int M) { gm_update1_commit(b, M, blockIdx.x); }
+__global__ __launch_bounds__(kGmChunk) void k_gm_begin(DevPlan p, int has_p, const double* taps, GmresBufs b, int M,
+                                                       const double* rhs, const double* phi_in, double tol,
+                                                       int max_iter, double reorth, double* xout, double* corr_il) {
+    gm_begin(has_p ? &p : nullptr, taps, b, M, rhs, phi_in, tol, max_iter, reorth, xout, corr_il);
+}
 __global__ __launch_bounds__(kGmChunk) void k_gm_emit(const double* taps, GmresBufs b, int M) {
     gm_emit(taps, b, M, blockIdx.x);
 }
@@ -307,10 +325,25 @@ hipError_t launch_axpby(int n, double a, const double* x, double b, const double
     return hipGetLastError();
 }
 
+hipError_t launch_nonfinite(int n, const double* x, int* flag, hipStream_t s) {
+    if (hipError_t e_ = klaunch(&k_nonfinite, dim3(1), dim3(256), 0, s, n, x, flag)) return e_;
+    return hipGetLastError();
+}
+
 hipError_t launch_gmres_step_corr(const DevPlan& p, GmresBufs b, double* corr_il, hipStream_t s) {
     const dim3 g(b.gc), t(kGmChunk);
     if (hipError_t e = klaunch(&k_gm_upd1, g, t, 0, s, b, p.M)) return e;
     return klaunch(&k_gm_emit_corr, dim3(b.gc + p.n_cc), t, 0, s, p, b, corr_il);
+}
+
+hipError_t launch_gmres_start(const DevPlan* p, const double* taps, int M, GmresBufs b, const double* rhs,
+                              const double* phi_in, double tol, int max_iter, double reorth, double* xout,
+                              double* corr_il, hipStream_t s) {
+    const bool corr = p && corr_il;
+    const DevPlan pv = corr ? *p : DevPlan{};
+    const int groups = b.gc + (corr ? p->n_cc : 0);
+    return klaunch(&k_gm_begin, dim3(groups), dim3(kGmChunk), 0, s, pv, corr ? 1 : 0, taps, b, M, rhs, phi_in, tol,
+                   max_iter, reorth, xout, corr ? corr_il : nullptr);
 }
 
 hipError_t launch_gmres_step(const double* taps, int M, GmresBufs b, hipStream_t s) {

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kIterThreads) void k_rich_step(IterBufs B) {
     if (it == 0 && !st->started) r0 = norm;
     const double rel = r0 > 0.0 ? norm / r0 : 0.0;
     int done = 0;
-    if (r0 == 0.0 || (it > 0 && rel < st->tol)) done = 1;
+    if (!isfinite(norm)) done = kIterNonfinite;
+    else if (r0 == 0.0 || (it > 0 && rel < st->tol)) done = 1;
     else if (it >= st->max_iter) done = -1;
     if (!done) {
         const double g = st->gamma;
@@ -100,7 +101,8 @@ __global__ __launch_bounds__(kIterThreads) void k_bicg_init(IterBufs B) {
         st->r0 = sqrt(nr[0]);
         st->rho = nr[0];
         st->relres = nr[0] > 0.0 ? 1.0 : 0.0;
-        if (nr[0] == 0.0) st->done = 1;
+        if (!isfinite(nr[0])) st->done = kIterNonfinite;
+        else if (nr[0] == 0.0) st->done = 1;
     }
 }
 
@@ -118,9 +120,9 @@ __global__ __launch_bounds__(kIterThreads) void k_bicg_half(IterBufs B) {
         d[0] = fma(B.rhat[i], v, d[0]);
     }
     block_sums(d, red);
-    if (d[0] == 0.0) {                                  // breakdown: r^ orthogonal to v
+    if (!isfinite(d[0]) || d[0] == 0.0) {               // NaN/Inf, or breakdown: r^ orthogonal to v
         __syncthreads();
-        if (threadIdx.x == 0) st->done = -1;
+        if (threadIdx.x == 0) st->done = isfinite(d[0]) ? -1 : kIterNonfinite;
         return;
     }
     const double alpha = st->rho / d[0];
@@ -163,9 +165,10 @@ __global__ __launch_bounds__(kIterThreads) void k_bicg_full(IterBufs B) {
         d[1] = fma(t, t, d[1]);
     }
     block_sums(d, red);
-    if (d[1] == 0.0 || d[0] == 0.0) {                   // breakdown: t = 0 or t orthogonal to s
+    const bool fin = isfinite(d[0]) && isfinite(d[1]);
+    if (!fin || d[1] == 0.0 || d[0] == 0.0) {           // NaN/Inf, or breakdown: t = 0 or t orthogonal to s
         __syncthreads();
-        if (threadIdx.x == 0) st->done = -1;
+        if (threadIdx.x == 0) st->done = fin ? -1 : kIterNonfinite;
         return;
     }
     const double omega = d[0] / d[1], alpha = st->alpha;
@@ -181,7 +184,8 @@ __global__ __launch_bounds__(kIterThreads) void k_bicg_full(IterBufs B) {
     block_sums(e, red);
     const double rel = sqrt(e[0]) / st->r0;
     int done = 0;
-    if (rel < st->tol) done = 1;
+    if (!isfinite(rel)) done = kIterNonfinite;
+    else if (rel < st->tol) done = 1;
     else if (st->it >= st->max_iter) done = -1;
     if (!done) {
         const double beta = (e[1] / st->rho) * (alpha / omega);

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as ct
 import os
+import threading
 
 import numpy as np
 import torch
@@ -24,6 +25,7 @@ OK = 0
 NOT_CONVERGED = 1
 ERR_GEOMETRY = -2
 ERR_BUDGET = -5
+ERR_NONFINITE = -6
 
 
 class KfbiError(RuntimeError):
@@ -34,6 +36,10 @@ class KfbiError(RuntimeError):
 
 class GeometryError(KfbiError):
     pass
+
+
+class NonfiniteError(KfbiError):
+    """A NaN or Inf in the data of a call (KFBI_ERR_NONFINITE); nothing was written."""
 
 
 class _Desc(ct.Structure):
@@ -79,6 +85,7 @@ _sigs = {
     "kfbi_prob_mask": [_vp, _vp],
     "kfbi_prob_crossings": [_vp, _vp, _vp, _vp, _vp],
     "kfbi_prob_irregular": [_vp, _vp],
+    "kfbi_prob_points": [_vp, _vp, _vp],
     "kfbi_apply": [_vp, _vp, _vp],
     "kfbi_solve": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
     "kfbi_gmres": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
@@ -150,6 +157,8 @@ def _check(status, allow=(OK,)):
     msg = _lib.kfbi_last_error().decode() or _lib.kfbi_status_str(status).decode()
     if status == ERR_GEOMETRY:
         raise GeometryError(status, msg)
+    if status == ERR_NONFINITE:
+        raise NonfiniteError(status, msg)
     raise KfbiError(status, msg)
 
 
@@ -170,22 +179,42 @@ class Context:
     By default the context owns a dedicated torch stream (default priority).
     Every call orders itself after the caller's current stream and makes the
     current stream wait for the library's work, so tensors flow between torch
-    and the library without explicit synchronisation.
+    and the library without explicit synchronisation.  A caller that makes the
+    context's stream its current torch stream (``torch.cuda.set_stream``) has
+    one stream, and the calls skip that ordering.
     """
 
     def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
         self.device = device
+        if stream is not None and stream.cuda_stream == 0:
+            # the C library reads a null stream as "make your own": the two would differ
+            raise ValueError("pass a created stream (torch.cuda.Stream), not the default stream")
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         h = _vp()
         _check(_lib.kfbi_ctx_create(device, _vp(self.stream.cuda_stream), ct.byref(h)))
         self._h = h
+        self._tls = threading.local()     # per-thread events, made once and reused
+
+    def _events(self):
+        ev = getattr(self._tls, "ev", None)
+        if ev is None:
+            ev = self._tls.ev = (torch.cuda.Event(), torch.cuda.Event())
+        return ev
 
     def __enter__(self):
-        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:   # nothing to order on one stream
+            ev = self._events()[0]
+            ev.record(cur)
+            self.stream.wait_event(ev)
         return self
 
     def __exit__(self, *exc):
-        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            ev = self._events()[1]
+            ev.record(self.stream)
+            cur.wait_event(ev)
         return False
 
     def sync(self):
@@ -256,6 +285,13 @@ class Problem:
         _check(_lib.kfbi_prob_irregular(self._h, _vp(ij.ctypes.data)))
         return ij
 
+    def points(self):
+        """The control points (M x 2) and the spline's unit outward normals there (M x 2)."""
+        xy = np.zeros((self.M, 2))
+        nrm = np.zeros((self.M, 2))
+        _check(_lib.kfbi_prob_points(self._h, _vp(xy.ctypes.data), _vp(nrm.ctypes.data)))
+        return xy, nrm
+
     # ---- device work
     def apply(self, phi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
@@ -313,10 +349,15 @@ class Problem:
                         allow=(OK, NOT_CONVERGED))
         return u, ug, phi, it.value, rel.value, st == OK
 
-    def gmres(self, rhs, phi0=None, tol=1e-10, max_iter=500):
-        """GMRES on ``K_D phi = rhs``; returns ``(phi, iters, applies, relres, converged)``."""
+    def gmres(self, rhs, phi0=None, tol=1e-10, max_iter=500, out=None):
+        """GMRES on ``K_D phi = rhs``; returns ``(phi, iters, applies, relres, converged)``.
+        ``out``: a device buffer holding the initial guess, overwritten with the
+        iterate (no copy is made); else the guess is ``phi0`` (copied) or zero."""
         dev = f"cuda:{self.ctx.device}"
-        phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
+        if out is not None:
+            phi = out
+        else:
+            phi = torch.zeros(self.M, dtype=torch.float64, device=dev) if phi0 is None else phi0.clone()
         it, ap, rel = ct.c_int(), ct.c_int(), ct.c_double()
         with self.ctx:
             st = _check(_lib.kfbi_gmres(self._h, _dptr(rhs, "rhs", self.M), _dptr(phi, "phi", self.M), float(tol),
@@ -654,7 +695,8 @@ class Batch:
             _check(_lib.kfbi_batch_step(self._h, int(nsteps)))
 
     def poll(self):
-        """``(state, iters, relres)`` per slot: state 1 converged, -1 cap, 0 running, -2 empty."""
+        """``(state, iters, relres)`` per slot: state 1 converged, -1 cap, 0 running, -2 empty,
+        -3 stopped on a NaN or Inf in the request's data."""
         state = np.zeros(self.max_slots, dtype=np.int32)
         iters = np.zeros(self.max_slots, dtype=np.int32)
         rel = np.zeros(self.max_slots)
@@ -669,9 +711,11 @@ class Batch:
         ug = torch.empty(prob.M, dtype=torch.float64, device=dev)
         phi = torch.empty(prob.M, dtype=torch.float64, device=dev)
         with self.ctx:
-            _check(_lib.kfbi_batch_finish(self._h, int(slot), _dptr(u, "u_grid"), _dptr(ug, "u_gamma"),
-                                          _dptr(phi, "phi")))
-        del self._held[slot]
+            st = _lib.kfbi_batch_finish(self._h, int(slot), _dptr(u, "u_grid"), _dptr(ug, "u_gamma"),
+                                        _dptr(phi, "phi"))
+        if st in (OK, ERR_NONFINITE):            # the slot is released either way
+            del self._held[slot]
+        _check(st)
         return u, ug, phi, prob
 
     def info(self):

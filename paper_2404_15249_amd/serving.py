@@ -228,7 +228,10 @@ class GpuExecutor:
         return {s: (int(st[s]), int(it[s]), float(rel[s])) for s in range(len(st)) if st[s] != -2}
 
     def finish(self, slot, hd):
-        u, ug, phi, prob = self.batch.finish(slot)
+        try:
+            u, ug, phi, prob = self.batch.finish(slot)
+        except self.kfbi.NonfiniteError:              # a NaN or Inf in the request: released, nothing written
+            return {"nonfinite": True, "under_resolved": bool(getattr(hd["spec"], "under_resolved", False))}
         if not self.check_error:
             return {"under_resolved": bool(getattr(hd["spec"], "under_resolved", False))}
         torch = self.torch

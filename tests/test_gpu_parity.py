@@ -212,6 +212,31 @@ def test_gmres_with_corrections_in_the_emit_launch(K, ctx, name):
     assert relerr(host(a), host(b)) < 1e-13
 
 
+@pytest.mark.parametrize("name", ["circle64", "star512"])
+def test_gmres_from_a_nonzero_guess_matches_oracle(K, ctx, name):
+    """GMRES warm-started from a smooth density (the first step is then a
+    residual apply) against the oracle's GMRES from the same guess, and the
+    count of K_D applications: Arnoldi steps plus one residual apply per cycle
+    end, plus the initial residual apply only for a nonzero guess."""
+    p = CASES[name]()
+    note(f"warm-started GMRES {name}")
+    prob = K.Problem(ctx, p.xy, p.n, p.kappa)
+    plan = O.build_plan(p.xy, p.n, LO, HI)
+    x0 = synth.smooth_density(prob.M, 99)
+    rhs = p.g
+    phi, it, ap, rel, conv = prob.gmres(dev(rhs), phi0=dev(x0), tol=1e-12)
+    ref, rit, rrel = O.gmres(lambda v: O.apply_KD(plan, v, p.kappa), rhs, tol=1e-13, x0=x0)
+    note(f"  gpu {it} iterations / {ap} applies ({rel:.2e}), oracle {rit} ({rrel:.2e})")
+    assert conv and abs(it - rit) <= 2
+    assert relerr(host(phi), ref) < 1e-10
+    # fixed work: 60 steps with restart 50 cross one restart
+    _, it0, ap0, _, _ = prob.gmres(dev(rhs), tol=0.0, max_iter=60)
+    _, it1, ap1, _, _ = prob.gmres(dev(rhs), phi0=dev(x0), tol=0.0, max_iter=60)
+    assert (it0, ap0) == (60, 62) and (it1, ap1) == (60, 63), (it0, ap0, it1, ap1)
+    _, it2, ap2, _, _ = prob.gmres(dev(rhs), tol=0.0, max_iter=20)
+    assert (it2, ap2) == (20, 21), (it2, ap2)
+
+
 @pytest.mark.parametrize("eta", [0.0, 1.0])
 def test_solve_with_and_without_the_second_gram_schmidt_pass(K, ctx, eta):
     """The second Gram-Schmidt pass, made on every step (eta = 1, by the
