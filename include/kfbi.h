@@ -148,6 +148,21 @@ kfbi_status kfbi_prob_points(const kfbi_prob* prob, double* xy, double* normal);
  * of phi (KFBI_ERR_NONFINITE, out untouched, if it holds a NaN or Inf). */
 kfbi_status kfbi_apply(kfbi_prob* prob, const double* phi, double* out);
 
+/* kfbi_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same kernels and the same result, with the apply's scratch (spline second
+ * derivatives, corrections, partial sums: 256 + 8 M + 512 T + 8 G M bytes,
+ * rounded up to 256-byte blocks) taken from a 32 MiB array of static device
+ * memory that each GPU holds for the life of the process, in place of the
+ * problem's workspace.  Allocates nothing and enqueues only: it does not wait,
+ * so a NaN or Inf in phi leaves out untouched but is not reported (kfbi_apply
+ * reports it).  KFBI_ERR_UNSUPPORTED, with nothing enqueued, when the problem
+ * needs more scratch than the array holds (the 2048^2 grid with 1024 samples
+ * needs about 2.1 MiB).  Every call on one GPU shares that GPU's array: calls
+ * that overlap on a GPU (on two streams, or from two threads) race, so
+ * serialise them.  phi, out: device, M doubles, as kfbi_apply. */
+kfbi_status kfbi_apply_noalloc(kfbi_prob* prob, const double* phi, double* out);
+
 /* Full Dirichlet solve (Sec. 2.1): g^ = g - (Y f)^+, GMRES (Alg. 5) on
  * K_D phi = g^ until the relative residual drops below tol, then u = W phi + Y f.
  *   f_grid : device grid, f at every node (values outside Omega are ignored)

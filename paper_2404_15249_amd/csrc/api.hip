@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <queue>
 #include <cstring>
 #include <new>
@@ -34,6 +35,40 @@ std::string& kfbi::last_error() {
     static thread_local std::string err;
     return err;
 }
+
+// ---------------------------------------------------------------- scratch of kfbi_apply_noalloc
+//
+// The entry point for callers that cannot allocate takes its scratch (the
+// spline second derivatives, corrections and partial sums of one K_D apply)
+// from this file-scope array instead of the problem's workspace.  Each device
+// holds its own copy for the life of the process; host code uses the address
+// hipGetSymbolAddress gives for it on that device (resolved once per device,
+// when a context is created there), never the array's name.
+constexpr size_t kNoAllocBytes = size_t(32) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// The scratch's address on `device` (the current device), resolved on first use.
+kfbi_status scratch_on(int device, void** out) {
+    if (device < 0 || device >= kMaxDevices) return kfbi::set_err(KFBI_ERR_UNSUPPORTED, "device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            hipGetLastError();
+            return kfbi::set_err(KFBI_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch[device] = ptr;
+    }
+    *out = g_scratch[device];
+    return KFBI_OK;
+}
+}  // namespace
 
 struct kfbi_prob {
     kfbi_ctx* ctx = nullptr;
@@ -624,6 +659,10 @@ kfbi_status kfbi_ctx_create(int device, void* hip_stream, kfbi_ctx** out) {
     c->device = device;
     c->lds_max = prop.sharedMemPerBlock;
     c->num_cu = prop.multiProcessorCount;
+    // the no-alloc scratch's address on this device, resolved here once; a
+    // failure only matters to kfbi_apply_noalloc, which reports it (and retries)
+    void* scr = nullptr;
+    if (scratch_on(device, &scr) != KFBI_OK) last_error().clear();
     if (hip_stream) {
         c->stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -1013,6 +1052,40 @@ kfbi_status kfbi_apply(kfbi_prob* p, const double* phi, double* out) {
     if (kfbi_status s = check_ptr(out, "out")) return s;
     HIP_TRY(hipSetDevice(p->ctx->device));
     return checked_apply(p, kOpD, phi, out);
+}
+
+kfbi_status kfbi_apply_noalloc(kfbi_prob* p, const double* phi, double* out) {
+    if (!p) return set_err(KFBI_ERR_ARG, "prob is NULL");
+    if (kfbi_status s = check_ptr(phi, "phi")) return s;
+    if (kfbi_status s = check_ptr(out, "out")) return s;
+    const int M = p->M;
+    const DevPlan d = op_view(p, kOpD);
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t off_s2 = 256, off_corr = off_s2 + up(sizeof(double) * M);
+    const size_t off_part = off_corr + up(sizeof(double) * (size_t)d.T * 64);
+    const size_t need = off_part + sizeof(double) * (size_t)p->G * M;
+    if (need > kNoAllocBytes)
+        return set_err(KFBI_ERR_UNSUPPORTED, "kfbi_apply_noalloc: the problem needs " + std::to_string(need) +
+                                                 " bytes of scratch, more than its " + std::to_string(kNoAllocBytes));
+    HIP_TRY(hipSetDevice(p->ctx->device));
+    void* base = nullptr;
+    if (kfbi_status e = scratch_on(p->ctx->device, &base)) return e;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    int* flag = reinterpret_cast<int*>(b);
+    double* s2 = reinterpret_cast<double*>(b + off_s2);
+    double* corr_il = reinterpret_cast<double*>(b + off_corr);
+    double* part = reinterpret_cast<double*>(b + off_part);
+    hipStream_t s = p->ctx->stream;
+    // the array keeps the last call's contents: the corrections' pad slots must
+    // be zero; the flag is written by its check whatever it finds
+    HIP_TRY(launch_fill((size_t)d.T * 64, 0.0, corr_il, s));
+    HIP_TRY(launch_nonfinite(M, phi, flag, s));
+    HIP_TRY(launch_spline(p->dp, phi, s2, flag, s));
+    const JumpSrc js{phi, s2, nullptr, nullptr, nullptr, nullptr};
+    HIP_TRY(launch_correct(d, js, nullptr, corr_il, nullptr, flag, s));
+    HIP_TRY(launch_modes(d, corr_il, part, p->Rm, flag, s));
+    HIP_TRY(launch_reduce_interp(d, js, part, p->G, out, flag, nullptr, s));
+    return KFBI_OK;
 }
 
 kfbi_status kfbi_correct(kfbi_prob* p, const double* phi, const double* f_gamma, double* corr) {

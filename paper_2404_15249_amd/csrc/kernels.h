@@ -215,6 +215,8 @@ hipError_t launch_residual(const DevPlan& p, const double* V, double* R, double*
 hipError_t launch_grid_out(const DevPlan& p, const double* V, bool mask, double* u, hipStream_t s);
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z,
                         hipStream_t s);
+// x[0..n) <- v (a kernel, so it may sit in a graph where a memset node may not)
+hipError_t launch_fill(size_t n, double v, double* x, hipStream_t s);
 // *flag = 1 if x[0..n) holds a NaN or Inf, else 0 (one workgroup; n up to a few 10^4)
 hipError_t launch_nonfinite(int n, const double* x, int* flag, hipStream_t s);
 // The start of a GMRES run (gm_begin in gmres.h), one launch: the state and

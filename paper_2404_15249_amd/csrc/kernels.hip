@@ -163,6 +163,11 @@ __global__ __launch_bounds__(256) void k_axpby(int n, double a, const double* __
     if (i < n) z[i] = a * x[i] + (y ? b * y[i] : 0.0);
 }
 
+__global__ __launch_bounds__(256) void k_fill(size_t n, double v, double* __restrict__ x) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
 // flag <- 1 if any of x[0..n) is NaN or Inf, else 0: one workgroup, which
 // writes the flag whatever it finds (nothing to clear beforehand)
 __global__ __launch_bounds__(256) void k_nonfinite(int n, const double* __restrict__ x, int* __restrict__ flag) {
@@ -322,6 +327,12 @@ hipError_t launch_grid_out(const DevPlan& p, const double* R, bool mask, double*
 hipError_t launch_axpby(int n, double a, const double* x, double b, const double* y, double* z, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (hipError_t e_ = klaunch(&k_axpby, dim3((n + 255) / 256), dim3(256), 0, s, n, a, x, b, y, z)) return e_;
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(size_t n, double v, double* x, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (hipError_t e_ = klaunch(&k_fill, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, v, x)) return e_;
     return hipGetLastError();
 }
 

@@ -87,6 +87,7 @@ _sigs = {
     "kfbi_prob_irregular": [_vp, _vp],
     "kfbi_prob_points": [_vp, _vp, _vp],
     "kfbi_apply": [_vp, _vp, _vp],
+    "kfbi_apply_noalloc": [_vp, _vp, _vp],
     "kfbi_solve": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
     "kfbi_gmres": [_vp, _vp, _vp, ct.c_double, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int),
                    ct.POINTER(ct.c_double)],
@@ -298,6 +299,13 @@ class Problem:
             out = torch.empty_like(phi)
         with self.ctx:
             _check(_lib.kfbi_apply(self._h, _dptr(phi, "phi", self.M), _dptr(out, "out", self.M)))
+        return out
+
+    def apply_noalloc(self, phi: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """``kfbi_apply_noalloc``: K_D phi into ``out`` with the library's static
+        scratch (no device allocation, no wait)."""
+        with self.ctx:
+            _check(_lib.kfbi_apply_noalloc(self._h, _dptr(phi, "phi", self.M), _dptr(out, "out", self.M)))
         return out
 
     def correct(self, phi, f_gamma=None, out=None):
