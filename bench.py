@@ -469,11 +469,12 @@ def gray_scott(ctx, grid_steps=((128, 8), (256, 16), (512, 32), (1024, 64)), T: 
             "rows": rows}
 
 
-def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0):
+def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_scale: float = 1.0, keep_ids=(),
+               label: str = ""):
     import synth
     from paper_2404_15249_amd.serving import GpuExecutor, Scheduler, summarize
     ex = GpuExecutor(ctx, max_slots=max_slots, m_max=8192, budget_bytes=0,
-                     make_spec=lambda r: synth.serving_spec(r.seed, r.n), tol=1e-10)
+                     make_spec=lambda r: synth.serving_spec(r.seed, r.n), tol=1e-10, keep_ids=keep_ids)
     sch = Scheduler(ex, int(budget_gib * (1 << 30)), max_slots, steps_per_poll=8, prepare_workers=8,
                     prepare_ahead=16, keep_results=True)
     recs, span = sch.run(reqs, time_scale=time_scale)
@@ -485,16 +486,68 @@ def run_stream(ctx, reqs, budget_gib: float = 64.0, max_slots: int = 32, time_sc
     out["resolved"] = len(solved) - len(flagged)
     out["peak_live"] = sch.peak_live
     out["peak_reserved_gib"] = sch.peak_reserved / (1 << 30)
+    # the byte model of a dense-formulation solve: (iterations + 2) applies of
+    # 48 B per grid unknown (three read+write passes), summed over the solves
+    model = sum((r.iters + 2) * 48.0 * (r.n - 1) ** 2 for r in solved)
+    out["byte_model_gbps"] = model / span / 1e9
+    out["byte_model_frac_of_hbm"] = model / span / HBM_PEAK_BYTES
     ex.batch.close()
+    kept = {r.rid: r.result for r in solved if r.result and "u_host" in r.result}
+    print(f"serving {label}: {len(solved)} solved in {span:.1f} s ({out['solves_per_s']:.1f}/s), "
+          f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+    return out, kept
+
+
+def oracle_check(kept, stream) -> dict:
+    """The served solutions of a seeded subsample against FP64 oracle solves of
+    the same requests: L-infinity over the grid nodes in Omega and the trace."""
+    import synth
+    from oracle import kfbi_oracle as O
+    rows = []
+    for rid in sorted(kept):
+        _, n, seed = stream[rid]
+        p = synth.serving_request(seed, n)
+        t0 = time.perf_counter()
+        ref = O.solve_bvp(p.xy, p.n, p.lo, p.hi, p.kappa, p.f_grid, p.f_gamma, p.g, tol=1e-12)
+        plan = O.build_plan(p.xy, p.n, p.lo, p.hi)
+        e_grid = float(np.max(np.abs(kept[rid]["u_host"] - ref.u_grid)[plan.inside]))
+        e_gam = float(np.max(np.abs(kept[rid]["u_gamma_host"] - ref.u_gamma)))
+        rows.append({"request": rid, "n": n, "linf_grid": e_grid, "linf_trace": e_gam,
+                     "oracle_s": time.perf_counter() - t0})
+        print(f"oracle check: request {rid} n={n}: Linf grid {e_grid:.2e} trace {e_gam:.2e}", file=sys.stderr,
+              flush=True)
+    worst = max([max(r["linf_grid"], r["linf_trace"]) for r in rows], default=0.0)
+    return {"requests": len(rows), "worst_linf": worst, "within_1e-6": worst <= 1e-6, "rows": rows}
+
+
+def oracle_subsample(stream, k: int, seed: int):
+    """A seeded choice of k resolved requests for the oracle check, weighted
+    toward the smaller grids the host solves quickly (at most one 2048^2)."""
+    import synth
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(len(stream))
+    quota = {256: (k + 2) // 3, 512: (k + 2) // 3, 1024: max(1, k // 5), 2048: 1}
+    out = []
+    for i in order:
+        _, n, s = stream[int(i)]
+        if quota.get(n, 0) > 0 and not synth.serving_spec(s, n).under_resolved:
+            quota[n] -= 1
+            out.append(int(i))
+        if len(out) >= k:
+            break
     return out
 
 
-def serving(ctx, n_requests: int, seed: int) -> dict:
-    """Saturation throughput, then Poisson arrivals at 50 % and 90 % of it."""
+def serving(ctx, n_requests: int, seed: int, oracle_requests: int = 0) -> dict:
+    """Saturation throughput, then Poisson arrivals at 50 % and 90 % of it;
+    with oracle_requests > 0 a seeded subsample of the saturation run is
+    checked against the FP64 oracle."""
     import synth
     from paper_2404_15249_amd.serving import Request
     stream = synth.serving_stream(n_requests, seed=seed, qps=1.0)
-    sat = run_stream(ctx, [Request(i, 0.0, n, s) for i, (_, n, s) in enumerate(stream)])
+    keep = oracle_subsample(stream, oracle_requests, seed + 1) if oracle_requests > 0 else ()
+    sat, kept = run_stream(ctx, [Request(i, 0.0, n, s) for i, (_, n, s) in enumerate(stream)], keep_ids=keep,
+                           label="saturation")
     rate = sat["solves_per_s"]
     res = {"requests": n_requests, "seed": seed, "sizes": "256/512/1024/2048 with p=.4/.3/.2/.1",
            "tol": 1e-10, "saturation": sat}
@@ -502,12 +555,15 @@ def serving(ctx, n_requests: int, seed: int) -> dict:
         qps = frac * rate
         # the stream's arrival times are drawn at 1 request/s: stretch them to the target rate
         reqs = [Request(i, t, n, s) for i, (t, n, s) in enumerate(stream)]
-        res[f"at_{int(frac * 100)}pct"] = dict(run_stream(ctx, reqs, time_scale=1.0 / qps), qps=qps)
+        r, _ = run_stream(ctx, reqs, time_scale=1.0 / qps, label=f"{int(frac * 100)}% load")
+        res[f"at_{int(frac * 100)}pct"] = dict(r, qps=qps)
+    if kept:
+        res["oracle_check"] = oracle_check(kept, stream)
     return res
 
 
 def serving_line(ctx, args) -> dict:
-    s = serving(ctx, args.serving_requests, args.serving_seed)
+    s = serving(ctx, args.serving_requests, args.serving_seed, args.oracle_requests)
     return {"metric": "solves/s (p99 latency beside)", "value": s["saturation"]["solves_per_s"],
             "unit": "solves/s", "n_gpus": 1, "steps": args.serving_requests, "warmup": 0,
             "ms_per_step": 1e3 / max(s["saturation"]["solves_per_s"], 1e-9), "higher_is_better": True,
@@ -533,6 +589,8 @@ def main():
     ap.add_argument("--iterations", choices=["on", "off"], default="on")
     ap.add_argument("--serving-requests", type=int, default=300)
     ap.add_argument("--serving-seed", type=int, default=2404)
+    ap.add_argument("--oracle-requests", type=int, default=0,
+                    help="--mode serving: served requests checked against the FP64 oracle")
     ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann", "gray_scott", "iterations"],
                     default="apply",
                     help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "

@@ -239,30 +239,62 @@ Plan build_plan(const double* xy, int m, int n, double lo, double hi) {
     };
     std::vector<int> hp = bucket(ch), vp = bucket(cv);
 
-    // classification along horizontal lines
+    // classification along horizontal lines: node x_i is in Omega when an odd
+    // number of the line's crossings lie strictly left of it, or when it lies
+    // within eps of a crossing.  Only the nodes between the first and the last
+    // crossing (and within eps of them) can be inside, so only those are visited.
     const int W = n + 1;
     P.inside.assign((size_t)W * W, 0);
+    int bi0 = n + 1, bi1 = -1, bj0 = n + 1, bj1 = -1;   // bounding box of the nodes in Omega
     for (int j = 0; j <= n; ++j) {
         const int b = hp[j], e = hp[j + 1];
         if ((e - b) % 2) fail("odd number of crossings on line y_%d", j);
         if (e == b) continue;
+        const int i_lo = std::max(0, (int)std::floor((ch[b].pos - eps - lo) / h) - 1);
+        const int i_hi = std::min(n, (int)std::ceil((ch[e - 1].pos + eps - lo) / h) + 1);
         int k = b;   // first crossing not left of the current node
-        for (int i = 0; i <= n; ++i) {
+        unsigned char* row = &P.inside[(size_t)j * W];
+        for (int i = i_lo; i <= i_hi; ++i) {
             const double x = lo + i * h;
             while (k < e && ch[k].pos < x) ++k;
             bool on = false;
             if (k < e && std::fabs(ch[k].pos - x) <= eps) on = true;
             if (k > b && std::fabs(ch[k - 1].pos - x) <= eps) on = true;
             const int left = k - b;
-            P.inside[(size_t)j * W + i] = (on || (left & 1)) ? 1 : 0;
+            row[i] = (on || (left & 1)) ? 1 : 0;
+            if (row[i]) {
+                bi0 = std::min(bi0, i);
+                bi1 = std::max(bi1, i);
+                bj0 = std::min(bj0, j);
+                bj1 = std::max(bj1, j);
+            }
         }
     }
+    // class changes can only sit on edges touching the box (rows and columns
+    // bj0-1 .. bj1+1 and bi0-1 .. bi1+1, clamped to the grid)
+    const int ei0 = std::max(0, bi0 - 1), ei1 = std::min(n, bi1 + 1);
+    const int ej0 = std::max(0, bj0 - 1), ej1 = std::min(n, bj1 + 1);
     auto in = [&](int i, int j) { return P.inside[(size_t)j * W + i] != 0; };
 
     // crossings that belong to edges whose end nodes differ
     for (int ax = 0; ax < 2; ++ax) {
         const std::vector<Crossing>& cs = ax == 0 ? ch : cv;
         const std::vector<int>& ptr = ax == 0 ? hp : vp;
+        // the edges whose end nodes differ, as (line, edge) in line then edge
+        // order; the mask is read row by row (vertical edges compare two rows)
+        std::vector<std::pair<int, int>> diff;
+        const unsigned char* msk = P.inside.data();
+        if (ax == 0) {
+            for (int j = ej0; j <= ej1; ++j)
+                for (int ed = ei0; ed < ei1; ++ed)
+                    if (msk[(size_t)j * W + ed] != msk[(size_t)j * W + ed + 1]) diff.push_back({j, ed});
+        } else {
+            for (int ed = ej0; ed < ej1; ++ed)
+                for (int i = ei0; i <= ei1; ++i)
+                    if (msk[(size_t)ed * W + i] != msk[(size_t)(ed + 1) * W + i]) diff.push_back({i, ed});
+            std::sort(diff.begin(), diff.end());
+        }
+        size_t dpos = 0;
         for (int line = 0; line <= n; ++line) {
             const int b = ptr[line], e = ptr[line + 1];
             auto cls = [&](int k) { return ax == 0 ? in(k, line) : in(line, k); };
@@ -277,8 +309,8 @@ Plan build_plan(const double* xy, int m, int n, double lo, double hi) {
                         fail("edge %d on line %d (axis %d) crossed twice", ed, line, ax);
                 }
             }
-            for (int ed = 0; ed < n; ++ed) {
-                if (cls(ed) == cls(ed + 1)) continue;
+            for (; dpos < diff.size() && diff[dpos].first == line; ++dpos) {
+                const int ed = diff[dpos].second;
                 const double a0 = lo + ed * h, a1 = lo + (ed + 1) * h;
                 int hit = -1, cnt = 0;
                 for (int k = b; k < e; ++k) {
@@ -306,8 +338,16 @@ Plan build_plan(const double* xy, int m, int n, double lo, double hi) {
     }
     const int Q = (int)P.q_axis.size();
 
-    // irregular nodes and their arms
-    std::vector<std::vector<std::pair<int, double>>> arms((size_t)W * W);
+    // irregular nodes and their arms: each crossing gives an arm to both end
+    // nodes of its edge; the arms are grouped by node, nodes ordered by column
+    // i then row j, a node's arms in crossing order
+    struct Arm {
+        long node;      // i W + j: column-major order
+        int q;
+        double d;
+    };
+    std::vector<Arm> arms;
+    arms.reserve(2 * (size_t)Q);
     for (int k = 0; k < Q; ++k) {
         const int ax = P.q_axis[k];
         const int* nd = &P.q_nodes[4 * k];
@@ -316,24 +356,25 @@ Plan build_plan(const double* xy, int m, int n, double lo, double hi) {
             const int mi = nd[2 * side], mj = nd[2 * side + 1];
             const int oi = nd[2 * (1 - side)], oj = nd[2 * (1 - side) + 1];
             const double other = lo + (ax == 0 ? oi : oj) * h;
-            arms[(size_t)mj * W + mi].push_back({k, other - qpos});
+            arms.push_back({(long)mi * W + mj, k, other - qpos});
         }
     }
+    std::stable_sort(arms.begin(), arms.end(), [](const Arm& a, const Arm& b) { return a.node < b.node; });
     P.col_ptr.assign(n + 2, 0);
-    for (int i = 0; i <= n; ++i) {
-        for (int j = 0; j <= n; ++j) {
-            const auto& a = arms[(size_t)j * W + i];
-            if (a.empty()) continue;
-            if (a.size() > 4) fail("node (%d,%d) has more than four arms", i, j);
-            P.irr_i.push_back(i);
-            P.irr_j.push_back(j);
-            P.irr_s.push_back(in(i, j) ? 1.0 : -1.0);
-            for (int s = 0; s < 4; ++s) {
-                P.arm_q.push_back(s < (int)a.size() ? a[s].first : -1);
-                P.arm_d.push_back(s < (int)a.size() ? a[s].second : 0.0);
-            }
-            P.col_ptr[i + 1]++;
+    for (size_t a0 = 0; a0 < arms.size();) {
+        size_t a1 = a0;
+        while (a1 < arms.size() && arms[a1].node == arms[a0].node) ++a1;
+        const int i = (int)(arms[a0].node / W), j = (int)(arms[a0].node % W);
+        if (a1 - a0 > 4) fail("node (%d,%d) has more than four arms", i, j);
+        P.irr_i.push_back(i);
+        P.irr_j.push_back(j);
+        P.irr_s.push_back(in(i, j) ? 1.0 : -1.0);
+        for (size_t s = 0; s < 4; ++s) {
+            P.arm_q.push_back(a0 + s < a1 ? arms[a0 + s].q : -1);
+            P.arm_d.push_back(a0 + s < a1 ? arms[a0 + s].d : 0.0);
         }
+        P.col_ptr[i + 1]++;
+        a0 = a1;
     }
     for (int i = 0; i <= n; ++i) P.col_ptr[i + 1] += P.col_ptr[i];
 

@@ -182,7 +182,7 @@ class GpuExecutor:
     """
 
     def __init__(self, ctx, max_slots: int, m_max: int, budget_bytes: int, make_spec, tol: float = 1e-10,
-                 restart: int = 50, check_error: bool = False):
+                 restart: int = 50, check_error: bool = False, keep_ids=()):
         import torch
         from . import kfbi
         self.torch = torch
@@ -192,6 +192,7 @@ class GpuExecutor:
         self.make_spec = make_spec
         self.tol, self.restart = tol, restart
         self.check_error = check_error
+        self.keep_ids = set(keep_ids)       # requests whose solution is copied to the host
         self._m_cache = {}
         self.request_errors = (kfbi.GeometryError,)
 
@@ -215,7 +216,7 @@ class GpuExecutor:
         fg = sp.sol_torch.f(zx, zy, sp.kappa).contiguous()
         g = sp.sol_torch.u(zx, zy).contiguous()
         torch.cuda.current_stream(self.ctx.device).synchronize()
-        return {"prob": prob, "f": f, "fg": fg, "g": g, "spec": sp}
+        return {"prob": prob, "f": f, "fg": fg, "g": g, "spec": sp, "rid": r.rid}
 
     def admit(self, hd):
         return self.batch.admit(hd["prob"], hd["f"], hd["fg"], hd["g"])
@@ -232,6 +233,9 @@ class GpuExecutor:
             u, ug, phi, prob = self.batch.finish(slot)
         except self.kfbi.NonfiniteError:              # a NaN or Inf in the request: released, nothing written
             return {"nonfinite": True, "under_resolved": bool(getattr(hd["spec"], "under_resolved", False))}
+        if hd.get("rid") in self.keep_ids:
+            return {"under_resolved": bool(getattr(hd["spec"], "under_resolved", False)),
+                    "u_host": u.cpu().numpy(), "u_gamma_host": ug.cpu().numpy()}
         if not self.check_error:
             return {"under_resolved": bool(getattr(hd["spec"], "under_resolved", False))}
         torch = self.torch
