@@ -36,18 +36,23 @@ def common_flags():
 
 
 def spilling_kernels(remarks: str) -> list:
-    """Kernels whose resource-usage remarks report VGPR spills to scratch memory."""
+    """Kernels whose resource-usage remarks report VGPR spills or any other use
+    of scratch (private) memory: a stack object a kernel never touches still
+    makes every dispatch reserve scratch."""
     out, name = [], None
     for line in remarks.splitlines():
         m = re.search(r"Function Name: (\S+)", line)
         if m:
             name = m.group(1)
             continue
+        if name is None:
+            continue
         m = re.search(r"VGPRs Spill: (\d+)", line)
-        if m and name is not None:
-            if int(m.group(1)) > 0:
-                out.append((name, int(m.group(1))))
-            name = None
+        if m and int(m.group(1)) > 0:
+            out.append((name, "VGPRs Spill", int(m.group(1))))
+        m = re.search(r"ScratchSize \[bytes/lane\]: (\d+)", line)
+        if m and int(m.group(1)) > 0:
+            out.append((name, "ScratchSize", int(m.group(1))))
     return out
 
 
@@ -60,10 +65,10 @@ def _compile(src: str, build_dir: str) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compiling {src} failed:\n{r.stdout}\n{r.stderr}")
-    # every kernel must keep its registers: a VGPR spill to scratch is a build error
+    # every kernel must keep its registers and use no scratch memory: a build error otherwise
     spills = spilling_kernels(r.stderr)
     if spills:
-        raise RuntimeError(f"{src}: kernels spill registers to scratch memory: {spills}")
+        raise RuntimeError(f"{src}: kernels use scratch memory: {spills}")
     return obj
 
 

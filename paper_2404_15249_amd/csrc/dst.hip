@@ -63,6 +63,31 @@ __device__ __forceinline__ void twiddle(const double* sq, int k, int N, double& 
     wi = -sinpi_n(sq, (2 * k) & mask2, N);
 }
 
+// Passes s and s+1 of the decimation-in-time FFT on four points at distance h
+// (a radix-4 step): with k = pos N / (4h) the table gives W = W_N^k; pass s
+// combines (a, b) and (c, d) with W^2, pass s+1 combines (a, c) with W and
+// (b, d) with W_N^{k + N/4} = -i W.  In place.
+template <class T>
+__device__ __forceinline__ void radix4_step(const double* sq, int tw, int N, cpx<T>& a, cpx<T>& bb, cpx<T>& c,
+                                            cpx<T>& d) {
+    double dr, di;
+    twiddle(sq, tw, N, dr, di);
+    const T w2r = (T)dr, w2i = (T)di;
+    const T w1r = (T)(dr * dr - di * di), w1i = (T)(2.0 * dr * di);
+    // pass s: (a, b) and (c, d) with W^2
+    const T tbr = w1r * bb.x - w1i * bb.y, tbi = w1r * bb.y + w1i * bb.x;
+    const T tdr = w1r * d.x - w1i * d.y, tdi = w1r * d.y + w1i * d.x;
+    const cpx<T> a1{a.x + tbr, a.y + tbi}, b1{a.x - tbr, a.y - tbi};
+    const cpx<T> c1{c.x + tdr, c.y + tdi}, d1{c.x - tdr, c.y - tdi};
+    // pass s + 1: (a, c) with W and (b, d) with -i W
+    const T tcr = w2r * c1.x - w2i * c1.y, tci = w2r * c1.y + w2i * c1.x;
+    const T ter = w2i * d1.x + w2r * d1.y, tei = w2i * d1.y - w2r * d1.x;
+    a = cpx<T>{a1.x + tcr, a1.y + tci};
+    c = cpx<T>{a1.x - tcr, a1.y - tci};
+    bb = cpx<T>{b1.x + ter, b1.y + tei};
+    d = cpx<T>{b1.x - ter, b1.y - tei};
+}
+
 // Rows are ld elements apart; blockIdx.y selects a slice of `slice` elements
 // (several independent N-row arrays, as the planes of a 3D grid).
 template <class T, class Tin, class Tout, int B>
@@ -89,57 +114,76 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     const int tile = (G & 7) ? (int)blockIdx.x : ((int)blockIdx.x & 7) * (G >> 3) + ((int)blockIdx.x >> 3);
     const int col0 = tile * B;
     for (int k = tid; k <= N / 2; k += NTH) sq[k] = sinq[k];
-    // load: columns (2p, 2p+1) of row r -> z[p][r + 1]; the batch's loads are
-    // all issued before any is stored, so their latencies overlap
-    for (int base = 0; base < N * P; base += NTH * kLoadBatch) {
-        Vin v[kLoadBatch];
+    // load and pre-process in one pass: item (j, p), j = 1 .. N/2, loads x_j
+    // (row j-1) and x_{N-j} (row N-j-1) of column pair p, forms y_j and y_{N-j}
+    // and stores them at their bit-reversed places, the order the
+    // decimation-in-time passes read (so no reversal pass); x_0 = x_N = 0 gives
+    // y_0 = 0.  A batch's loads are all issued before any is used.
+    const int lh = log2N - 1;                                // log2 (N/2)
+    constexpr int LB = kLoadBatch / 2;
+    const int items = P << lh;
+    for (int base = 0; base < items; base += NTH * LB) {
+        Vin va[LB], vb[LB];
+        double sv[LB];
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) {
+        for (int u = 0; u < LB; ++u) {
             const int idx = base + u * NTH + tid;
-            const int r = idx >> LP, p = idx & (P - 1);
-            if (idx < N * P && r + 1 < N) v[u] = *reinterpret_cast<const Vin*>(in + (size_t)r * ld + col0 + 2 * p);
+            const int j = (idx >> LP) + 1, p = idx & (P - 1);
+            if (idx < items) {
+                va[u] = *reinterpret_cast<const Vin*>(in + (size_t)(j - 1) * ld + col0 + 2 * p);
+                if (j < N / 2) vb[u] = *reinterpret_cast<const Vin*>(in + (size_t)(N - j - 1) * ld + col0 + 2 * p);
+                sv[u] = sinq[j];
+            }
         }
 #pragma unroll
-        for (int u = 0; u < kLoadBatch; ++u) {
+        for (int u = 0; u < LB; ++u) {
             const int idx = base + u * NTH + tid;
-            const int r = idx >> LP, p = idx & (P - 1);
-            if (idx < N * P && r + 1 < N) z[p * NS + zs(r + 1)] = cpx<T>{(T)v[u].x, (T)v[u].y};
+            const int j = (idx >> LP) + 1, p = idx & (P - 1);
+            if (idx >= items) continue;
+            cpx<T>* zp = z + p * NS;
+            const T ax = (T)va[u].x, ay = (T)va[u].y;
+            if (j == N / 2) {
+                zp[zs(bitrev(j, log2N))] = cpx<T>{ax * T(2), ay * T(2)};
+            } else {
+                const T bx = (T)vb[u].x, by = (T)vb[u].y;
+                const T sj = (T)sv[u];
+                zp[zs(bitrev(j, log2N))] = cpx<T>{sj * (ax + bx) + T(0.5) * (ax - bx), sj * (ay + by) + T(0.5) * (ay - by)};
+                zp[zs(bitrev(N - j, log2N))] =
+                    cpx<T>{sj * (bx + ax) + T(0.5) * (bx - ax), sj * (by + ay) + T(0.5) * (by - ay)};
+            }
         }
     }
     if (tid < P) z[tid * NS + zs(0)] = cpx<T>{T(0), T(0)};
     __syncthreads();
-    // pre-process pairs (j, N - j)
-    const int lh = log2N - 1;                                // log2 (N/2)
-    for (int idx = tid; idx < (P << lh); idx += NTH) {
-        const int p = idx >> lh, j = (idx & (N / 2 - 1)) + 1;        // 1 .. N/2
-        cpx<T>* zp = z + p * NS;
-        if (j == N / 2) {
-            zp[zs(j)].x *= T(2);
-            zp[zs(j)].y *= T(2);
-        } else {
-            const cpx<T> a = zp[zs(j)], b = zp[zs(N - j)];
-            const T s = (T)sq[j];
-            zp[zs(j)] = cpx<T>{s * (a.x + b.x) + T(0.5) * (a.x - b.x), s * (a.y + b.y) + T(0.5) * (a.y - b.y)};
-            zp[zs(N - j)] = cpx<T>{s * (b.x + a.x) + T(0.5) * (b.x - a.x), s * (b.y + a.y) + T(0.5) * (b.y - a.y)};
-        }
-    }
-    __syncthreads();
-    // in-place FFT, decimation in time: bit reversal, then the passes
-    for (int idx = tid; idx < (P << log2N); idx += NTH) {
-        const int p = idx >> log2N, j = idx & (N - 1);
-        const int rj = bitrev(j, log2N);
-        if (j < rj) {
-            cpx<T>* zp = z + p * NS;
-            const cpx<T> t = zp[zs(j)];
-            zp[zs(j)] = zp[zs(rj)];
-            zp[zs(rj)] = t;
-        }
-    }
-    __syncthreads();
-    // passes s and s+1 together as one radix-4 step.  With h = 2^(s-1) and
-    // k = pos N / (4h), pass s uses W_N^{2k} = W^2 and pass s+1 uses W = W_N^k
-    // and W_N^{k + N/4} = -i W: one table lookup per four points.
+    // passes s .. s+3 together as one radix-16 step (h = 2^(s-1), 16 points
+    // at distance h held in registers): two radix-4 steps, the first on the
+    // four groups of four consecutive points (passes s, s+1: one twiddle for
+    // all four), the second across the groups (passes s+2, s+3: distance 4h,
+    // the twiddle of each point's own position); one LDS round trip for four
+    // passes.  Then radix-4 steps (passes s, s+1) while two passes are left.
     int s = 1;
+    const int lx = log2N - 4;                                // log2 (N/16)
+    for (; s + 3 <= log2N; s += 4) {
+        const int h = 1 << (s - 1);
+        for (int idx = tid; idx < (P << lx); idx += NTH) {
+            const int p = idx >> lx, b = idx & (N / 16 - 1);
+            const int pos = b & (h - 1), grp = b >> (s - 1);
+            const int i0 = grp * 16 * h + pos;
+            cpx<T>* zp = z + p * NS;
+            cpx<T> x[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) x[q] = zp[zs(i0 + q * h)];
+            const int tw1 = pos << (log2N - s - 1);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) radix4_step(sq, tw1, N, x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                radix4_step(sq, (pos + q * h) << (log2N - s - 3), N, x[q], x[q + 4], x[q + 8], x[q + 12]);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) zp[zs(i0 + q * h)] = x[q];
+        }
+        __syncthreads();
+    }
     const int lq = log2N - 2;                                // log2 (N/4)
     for (; s + 1 <= log2N; s += 2) {
         const int h = 1 << (s - 1);
@@ -148,23 +192,12 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int pos = b & (h - 1), grp = b >> (s - 1);
             const int i0 = grp * 4 * h + pos;
             cpx<T>* zp = z + p * NS;
-            const cpx<T> a = zp[zs(i0)], bb = zp[zs(i0 + h)], c = zp[zs(i0 + 2 * h)], d = zp[zs(i0 + 3 * h)];
-            double dr, di;
-            twiddle(sq, pos << (log2N - s - 1), N, dr, di);
-            const T w2r = (T)dr, w2i = (T)di;
-            const T w1r = (T)(dr * dr - di * di), w1i = (T)(2.0 * dr * di);
-            // pass s: (a, b) and (c, d) with W^2
-            const T tbr = w1r * bb.x - w1i * bb.y, tbi = w1r * bb.y + w1i * bb.x;
-            const T tdr = w1r * d.x - w1i * d.y, tdi = w1r * d.y + w1i * d.x;
-            const cpx<T> a1{a.x + tbr, a.y + tbi}, b1{a.x - tbr, a.y - tbi};
-            const cpx<T> c1{c.x + tdr, c.y + tdi}, d1{c.x - tdr, c.y - tdi};
-            // pass s + 1: (a, c) with W and (b, d) with -i W
-            const T tcr = w2r * c1.x - w2i * c1.y, tci = w2r * c1.y + w2i * c1.x;
-            const T ter = w2i * d1.x + w2r * d1.y, tei = w2i * d1.y - w2r * d1.x;
-            zp[zs(i0)] = cpx<T>{a1.x + tcr, a1.y + tci};
-            zp[zs(i0 + 2 * h)] = cpx<T>{a1.x - tcr, a1.y - tci};
-            zp[zs(i0 + h)] = cpx<T>{b1.x + ter, b1.y + tei};
-            zp[zs(i0 + 3 * h)] = cpx<T>{b1.x - ter, b1.y - tei};
+            cpx<T> a = zp[zs(i0)], bb = zp[zs(i0 + h)], c = zp[zs(i0 + 2 * h)], d = zp[zs(i0 + 3 * h)];
+            radix4_step(sq, pos << (log2N - s - 1), N, a, bb, c, d);
+            zp[zs(i0)] = a;
+            zp[zs(i0 + h)] = bb;
+            zp[zs(i0 + 2 * h)] = c;
+            zp[zs(i0 + 3 * h)] = d;
         }
         __syncthreads();
     }

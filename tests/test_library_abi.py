@@ -99,4 +99,19 @@ def test_build_flags_register_spills():
             "a.hip:9:1: remark: Function Name: k_two [-Rpass]\n"
             "a.hip:9:1: remark:     ScratchSize [bytes/lane]: 48 [-Rpass]\n"
             "a.hip:9:1: remark:     VGPRs Spill: 10 [-Rpass]\n")
-    assert spilling_kernels(text) == [("k_two", 10)]
+    assert spilling_kernels(text) == [("k_two", "ScratchSize", 48), ("k_two", "VGPRs Spill", 10)]
+
+
+def test_build_rejects_spills_and_scratch():
+    """The build's check of the compiler's resource remarks: a VGPR spill or any
+    nonzero scratch size fails it; clean kernels pass."""
+    from paper_2404_15249_amd import build
+    clean = ("x.hip:1:1: remark: Function Name: k_a\nx.hip:1:1: remark:     VGPRs Spill: 0\n"
+             "x.hip:1:1: remark:     ScratchSize [bytes/lane]: 0\n")
+    stack = ("x.hip:1:1: remark: Function Name: k_b\nx.hip:1:1: remark:     VGPRs Spill: 0\n"
+             "x.hip:1:1: remark:     ScratchSize [bytes/lane]: 24\n")
+    spill = ("x.hip:1:1: remark: Function Name: k_c\nx.hip:1:1: remark:     VGPRs Spill: 3\n"
+             "x.hip:1:1: remark:     ScratchSize [bytes/lane]: 12\n")
+    assert build.spilling_kernels(clean) == []
+    assert build.spilling_kernels(stack) == [("k_b", "ScratchSize", 24)]
+    assert [k[:2] for k in build.spilling_kernels(clean + spill)] == [("k_c", "VGPRs Spill"), ("k_c", "ScratchSize")]
