@@ -125,6 +125,18 @@ __device__ __forceinline__ void radix4_step(const double* sq, int tw, int N, cpx
     d = cpx<T>{b1.x - ter, b1.y - tei};
 }
 
+// Pass s' on two points at distance 2^(s'-1): b <- a - W b, a <- a + W b with
+// W = W_N^tw.  In place.
+template <class T>
+__device__ __forceinline__ void radix2_step(const double* sq, int tw, int N, cpx<T>& a, cpx<T>& b) {
+    double dr, di;
+    twiddle(sq, tw, N, dr, di);
+    const T wr = (T)dr, wi = (T)di;
+    const T tr = wr * b.x - wi * b.y, ti = wr * b.y + wi * b.x;
+    b = cpx<T>{a.x - tr, a.y - ti};
+    a = cpx<T>{a.x + tr, a.y + ti};
+}
+
 // Rows are ld elements apart; blockIdx.y selects a slice of `slice` elements
 // (several independent N-row arrays, as the planes of a 3D grid).
 template <class T, class Tin, class Tout, int B>
@@ -212,7 +224,8 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     // four groups of four consecutive points (passes s, s+1: one twiddle for
     // all four), the second across the groups (passes s+2, s+3: distance 4h,
     // the twiddle of each point's own position); one LDS round trip for four
-    // passes.  Then radix-4 steps (passes s, s+1) while two passes are left.
+    // passes.  What is left after them: three passes as one radix-8 step, else
+    // radix-4 steps and a last radix-2 pass.
     int s = 1;
     const int lx = log2N - 4;                                // log2 (N/16)
     for (; s + 3 <= log2N; s += 4) {
@@ -236,6 +249,30 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         }
         __syncthreads();
     }
+    // three passes left: one radix-8 step (a radix-4 step on each half, then
+    // pass s+2 at distance 4h, twiddle W_N^{(pos + q h) N / (8h)} for point q)
+    if (s + 2 == log2N) {
+        const int h = 1 << (s - 1);
+        const int l8 = log2N - 3;                            // log2 (N/8)
+        for (int idx = tid; idx < (P << l8); idx += NTH) {
+            const int p = idx >> l8, b = idx & (N / 8 - 1);
+            const int pos = b & (h - 1), grp = b >> (s - 1);
+            const int i0 = grp * 8 * h + pos;
+            cpx<T>* zp = z + p * NS;
+            cpx<T> x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = zp[zs<T>(i0 + q * h)];
+            const int tw1 = pos << (log2N - s - 1);
+            radix4_step(sq, tw1, N, x[0], x[1], x[2], x[3]);
+            radix4_step(sq, tw1, N, x[4], x[5], x[6], x[7]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) radix2_step(sq, (pos + q * h) << (log2N - s - 2), N, x[q], x[q + 4]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) zp[zs<T>(i0 + q * h)] = x[q];
+        }
+        __syncthreads();
+        s += 3;
+    }
     const int lq = log2N - 2;                                // log2 (N/4)
     for (; s + 1 <= log2N; s += 2) {
         const int h = 1 << (s - 1);
@@ -253,36 +290,24 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         }
         __syncthreads();
     }
-    if (s == log2N) {                                        // odd log2 N: one radix-2 pass left
+    if (s == log2N) {                                        // one radix-2 pass left
         const int half = 1 << (s - 1);
         for (int idx = tid; idx < (P << lh); idx += NTH) {
             const int p = idx >> lh, pos = idx & (N / 2 - 1);
-            const int i1 = pos, i2 = pos + half;
-            double dr, di;
-            twiddle(sq, pos, N, dr, di);
-            const T wr = (T)dr, wi = (T)di;
             cpx<T>* zp = z + p * NS;
-            const cpx<T> a = zp[zs<T>(i1)], c = zp[zs<T>(i2)];
-            const T tr = wr * c.x - wi * c.y, ti = wr * c.y + wi * c.x;
-            zp[zs<T>(i1)] = cpx<T>{a.x + tr, a.y + ti};
-            zp[zs<T>(i2)] = cpx<T>{a.x - tr, a.y - ti};
+            cpx<T> a = zp[zs<T>(pos)], c = zp[zs<T>(pos + half)];
+            radix2_step(sq, pos, N, a, c);
+            zp[zs<T>(pos)] = a;
+            zp[zs<T>(pos + half)] = c;
         }
         __syncthreads();
     }
-    // separate the two columns: slot k <- (R_a, R_b), slot N-k <- (-I_a, -I_b) = X_2k
-    for (int idx = tid; idx < (P << lh); idx += NTH) {
-        const int p = idx >> lh, k = idx & (N / 2 - 1);
-        cpx<T>* zp = z + p * NS;
-        const cpx<T> Zk = zp[zs<T>(k)], Zn = zp[zs<T>((N - k) & (N - 1))];
-        const T ra = T(0.5) * (Zk.x + Zn.x), ia = T(0.5) * (Zk.y - Zn.y);
-        const T rb = T(0.5) * (Zk.y + Zn.y), ib = -T(0.5) * (Zk.x - Zn.x);
-        zp[zs<T>(k)] = cpx<T>{ra, rb};
-        if (k > 0) zp[zs<T>(N - k)] = cpx<T>{-ia, -ib};
-    }
-    __syncthreads();
-    // odd outputs: X_{2k+1} = R_0/2 + R_1 + ... + R_k, both columns of a pair
-    // at once (slot k holds (R_a, R_b)).  TPP threads per pair own V
-    // consecutive k each: a running sum over the thread's values, an
+    // separate the two columns and sum the odd outputs.  From Z_k and
+    // Z_{N-k}: (R_a, R_b) = (Re, Im) of (Z_k + conj Z_{N-k}) / 2 and
+    // (I_a, I_b) = (Im, -Re) of (Z_k - conj Z_{N-k}) / 2; X_{2k} = -I_k goes
+    // to slot N-k at once (only the thread owning k reads that slot), and
+    // X_{2k+1} = R_0/2 + R_1 + ... + R_k to slot k.  TPP threads per pair own
+    // V consecutive k each: a running sum over the thread's values, an
     // inclusive scan of the thread totals across the wavefront, then the
     // totals of the pair's earlier wavefronts, added in wavefront order
     // (through LDS, in the place of the sine table, which is no longer read).
@@ -301,10 +326,14 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             for (int e = 0; e < VMAX; ++e) {
                 if (e < V) {
                     const int k = t * V + e;
-                    const cpx<T> c = z[p * NS + zs<T>(k)];
+                    cpx<T>* zp = z + p * NS;
+                    const cpx<T> Zk = zp[zs<T>(k)], Zn = zp[zs<T>((N - k) & (N - 1))];
+                    const T Ra = T(0.5) * (Zk.x + Zn.x), Ia = T(0.5) * (Zk.y - Zn.y);
+                    const T Rb = T(0.5) * (Zk.y + Zn.y), Ib = -T(0.5) * (Zk.x - Zn.x);
+                    if (k > 0) zp[zs<T>(N - k)] = cpx<T>{-Ia, -Ib};
                     const double h = k == 0 ? 0.5 : 1.0;
-                    ta += h * (double)c.x;
-                    tb += h * (double)c.y;
+                    ta += h * (double)Ra;
+                    tb += h * (double)Rb;
                     ra[e] = ta;
                     rb[e] = tb;
                 }
