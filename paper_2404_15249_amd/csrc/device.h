@@ -538,20 +538,26 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
                     cvn[q] = corr[(size_t)(t0 + kSlots + q) * 64 + lane];
                 }
             }
+            // sin((l0 + r) t), t = pi j / N, for r = 0 .. R-1: two table values,
+            // then s_{r+1} = 2 cos t s_r - s_{r-1}.  The group's table values are
+            // read before any of its sums is stored, so their latencies overlap
+            double s0[kSlots], s1[kSlots], c2[kSlots];
 #pragma unroll
             for (int q = 0; q < kSlots; ++q) {
-                // sin((l0 + r) t), t = pi j / N, for r = 0 .. R-1: two table
-                // values, then s_{r+1} = 2 cos t s_r - s_{r-1}
                 const int j = pk[q] & 0xfff;
                 const int m0 = (int)(__umul24((unsigned)j, (unsigned)l0) & mask2);
-                double sp = sinpi_n(sq, m0, N);
-                double sc = R > 1 ? sinpi_n(sq, (m0 + j) & mask2, N) : 0.0;
-                const double c2 = R > 2 ? 2.0 * sinpi_n(sq, (j + half) & mask2, N) : 0.0;
+                s0[q] = sinpi_n(sq, m0, N);
+                s1[q] = R > 1 ? sinpi_n(sq, (m0 + j) & mask2, N) : 0.0;
+                c2[q] = R > 2 ? 2.0 * sinpi_n(sq, (j + half) & mask2, N) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < kSlots; ++q) {
+                double sp = s0[q], sc = s1[q];
                 acc[0] = fma(cv[q], sp, acc[0]);
                 if (R > 1) acc[1] = fma(cv[q], sc, acc[1]);
 #pragma unroll
                 for (int r = 2; r < R; ++r) {
-                    const double sn = fma(c2, sc, -sp);
+                    const double sn = fma(c2[q], sc, -sp);
                     acc[r] = fma(cv[q], sn, acc[r]);
                     sp = sc;
                     sc = sn;
@@ -560,11 +566,16 @@ __device__ __forceinline__ void modes_round(const DevPlan& p, const double* __re
                     const int dest = (pk[q] >> 16) & 0x7fff;
                     double* to = dest < kExtraFlag ? L.xs + dest : L.ex + (dest - kExtraFlag);
                     const int stride = dest < kExtraFlag ? XS : kMaxExtra;
+                    if (nact == R) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        if (r < nact) to[r * stride] = acc[r];
-                        acc[r] = 0.0;
+                        for (int r = 0; r < R; ++r) to[r * stride] = acc[r];
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            if (r < nact) to[r * stride] = acc[r];
                     }
+#pragma unroll
+                    for (int r = 0; r < R; ++r) acc[r] = 0.0;
                 }
             }
             if (more) {
