@@ -221,6 +221,45 @@ def mixed_precision(ctx, n: int) -> dict:
     return res
 
 
+def dense_solves(ctx, n: int, calls: int = 20) -> dict:
+    """The dense path alone: interface solves (volume potential form: right-hand
+    side with its corrections, the grid solve, interpolation at the samples) of
+    the circle problem (r = 0.8, M = N, kappa = 1) with FP64 and with FP32 grid
+    solves (0 and 1 refinement steps), timed with events on the library's stream.
+    One FP64 grid solve is two column sine transforms (``k_dst_cols``, in place)
+    around the row solves; each transform reads N - 1 rows and writes N rows of
+    N doubles."""
+    import torch
+    import synth
+    from paper_2404_15249_amd import kfbi
+    p = synth.circle_problem(n=n, m=n, kappa=1.0)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda:0")
+    f, fg = dev(p.f_grid), dev(p.f_gamma)
+    res = {"mode": "dense", "workload": f"circle r=0.8, {n}x{n} grid, M={n}, kappa=1: interface solves",
+           "grid": n, "calls": calls, "transform_bytes_per_launch": 8 * (2 * n - 1) * n}
+    base = None
+    for name, prec, rs in (("fp64", "fp64", 1), ("fp32_refine0", "fp32", 0), ("fp32_refine1", "fp32", 1)):
+        prob = kfbi.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-12, precision=prec, refine_steps=rs)
+        zero = torch.zeros(prob.M, dtype=torch.float64, device="cuda:0")
+        _, vz = prob.interface_solve(zero, f, fg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(calls):
+            prob.interface_solve(zero, f, fg)
+        e1.record()
+        torch.cuda.synchronize()
+        entry = {"interface_solve_us": 1e3 * e0.elapsed_time(e1) / calls, "dst_tile": prob.tiles()["dst_cols"]}
+        v = vz.cpu().numpy()
+        if base is None:
+            base = v
+        else:
+            entry["linf_diff_vs_fp64_at_samples"] = float(np.max(np.abs(v - base)))
+        res[name] = entry
+        prob.close()
+    return res
+
+
 def convergence(ctx, sizes=(512, 1024, 2048)) -> dict:
     """Full FP64 solves of the star workload (kappa = 1, M = N/2,
     u = sin(pi x) cos(pi y) + x^2) at several grids: L-infinity error against the
@@ -591,10 +630,11 @@ def main():
     ap.add_argument("--serving-seed", type=int, default=2404)
     ap.add_argument("--oracle-requests", type=int, default=0,
                     help="--mode serving: served requests checked against the FP64 oracle")
-    ap.add_argument("--mode", choices=["apply", "serving", "copy", "3d", "neumann", "gray_scott", "iterations"],
+    ap.add_argument("--mode", choices=["apply", "serving", "copy", "dense", "3d", "neumann", "gray_scott", "iterations"],
                     default="apply",
                     help="serving: only the request stream (metric solves/s), e.g. with --serving-requests 10000; "
                          "copy: a 256 MiB device copy to calibrate the HBM byte counters; "
+                         "dense: only the dense path (interface solves at --n, --steps calls); "
                          "3d: only the ellipsoid section; neumann: only the Neumann section; "
                          "gray_scott: only the Gray-Scott section; iterations: only Table 2's comparison")
     args = ap.parse_args()
@@ -618,6 +658,9 @@ def main():
     stream = torch.cuda.Stream(device=0)
     torch.cuda.set_stream(stream)
     ctx = kfbi.Context(0, stream=stream)
+    if args.mode == "dense":
+        print(json.dumps(dense_solves(ctx, args.n, calls=min(args.steps, 50))), flush=True)
+        return
     if args.mode == "3d":
         print(json.dumps(three_d(ctx)), flush=True)
         return

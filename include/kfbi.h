@@ -347,7 +347,7 @@ kfbi_status kfbi_interface_solve_jumps(kfbi_prob* prob, const double* jq, const 
 typedef struct {
     int modes_per_group;  /* sparse fast solve: sine modes per workgroup, 1/2/4/8/16 */
     int modes_groups;     /* sparse fast solve: workgroups, ceil((n-1) / modes_per_group) (output only) */
-    int dst_cols;         /* column sine transforms: columns per workgroup, 4/8/16 */
+    int dst_cols;         /* column sine transforms: columns per workgroup, 4/8/16 (32/64 in FP64) */
     double apply_us;      /* autotune output: mean K_D apply time with this shape */
     double grid_solve_us; /* autotune output: mean dense grid solve time (transforms + row solves) */
 } kfbi_tiles;

@@ -17,6 +17,8 @@
 // come from the quarter-period sine table.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.h"
 #include "graph.h"
 #include "kernels.h"
@@ -57,10 +59,24 @@ __device__ __forceinline__ int zs(int i) {
     return i ^ ((i >> 5) & 15) ^ (((i >> 8) & 1) << 4);
 }
 
+// Slot of element i of pair p.  With 8 or more pairs (16-byte pairs only) a
+// wavefront of the early passes spans several pairs, so the pair index joins
+// the XOR: lanes of different pairs with the same element land apart.
+template <class T, int P>
+__device__ __forceinline__ int zsp(int p, int i) {
+    if constexpr (sizeof(T) == 8 && P >= 8) return i ^ (((i >> 4) ^ p) & 15);
+    return zs<T>(i);
+}
+
 // pair stride N + pad: the load and write phases interleave the P pairs
-// across lanes, so successive pairs start a 1/P bank row apart
+// across lanes, so successive pairs start a 1/P bank row apart (with 8 or
+// more pairs the XOR above spreads them instead)
 template <class T, int B>
-constexpr int pair_pad() { return (sizeof(T) == 8 ? 16 : 32) / (B / 2); }
+constexpr int pair_pad() {
+    constexpr int P = B / 2;
+    if constexpr (sizeof(T) == 8) return P <= 4 ? 16 / P : P == 8 ? 8 : 0;
+    return 32 / P;
+}
 
 // the quarter-period sine table with one skip every 32 entries: the twiddle
 // lookups of a pass at a power-of-two stride spread over the banks
@@ -148,7 +164,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     out += blockIdx.y * slice;
     extern __shared__ double smem_d[];
     constexpr int P = B / 2;                                 // column pairs
-    constexpr int LP = B == 4 ? 1 : B == 8 ? 2 : 3;          // log2 P
+    constexpr int LP = B == 4 ? 1 : B == 8 ? 2 : B == 16 ? 3 : B == 32 ? 4 : 5;   // log2 P
     constexpr int NTH = kDstThreads;
     using Vin = typename pair_of<Tin>::type;
     using Vout = typename pair_of<Tout>::type;
@@ -207,17 +223,17 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             cpx<T>* zp = z + p * NS;
             const T ax = (T)va[u].x, ay = (T)va[u].y;
             if (i == 1) {
-                zp[zs<T>(1)] = cpx<T>{ax * T(2), ay * T(2)};
+                zp[zsp<T, P>(p, 1)] = cpx<T>{ax * T(2), ay * T(2)};
             } else {
                 const T bx = (T)vb[u].x, by = (T)vb[u].y;
                 const T sj = (T)sv[u];
-                zp[zs<T>(i)] = cpx<T>{sj * (ax + bx) + T(0.5) * (ax - bx), sj * (ay + by) + T(0.5) * (ay - by)};
-                zp[zs<T>(i ^ (lo - 1))] =
+                zp[zsp<T, P>(p, i)] = cpx<T>{sj * (ax + bx) + T(0.5) * (ax - bx), sj * (ay + by) + T(0.5) * (ay - by)};
+                zp[zsp<T, P>(p, i ^ (lo - 1))] =
                     cpx<T>{sj * (bx + ax) + T(0.5) * (bx - ax), sj * (by + ay) + T(0.5) * (by - ay)};
             }
         }
     }
-    if (tid < P) z[tid * NS + zs<T>(0)] = cpx<T>{T(0), T(0)};
+    if (tid < P) z[tid * NS + zsp<T, P>(tid, 0)] = cpx<T>{T(0), T(0)};
     __syncthreads();
     // passes s .. s+3 together as one radix-16 step (h = 2^(s-1), 16 points
     // at distance h held in registers): two radix-4 steps, the first on the
@@ -237,7 +253,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             cpx<T>* zp = z + p * NS;
             cpx<T> x[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) x[q] = zp[zs<T>(i0 + q * h)];
+            for (int q = 0; q < 16; ++q) x[q] = zp[zsp<T, P>(p, i0 + q * h)];
             const int tw1 = pos << (log2N - s - 1);
 #pragma unroll
             for (int t = 0; t < 4; ++t) radix4_step(sq, tw1, N, x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]);
@@ -245,7 +261,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             for (int q = 0; q < 4; ++q)
                 radix4_step(sq, (pos + q * h) << (log2N - s - 3), N, x[q], x[q + 4], x[q + 8], x[q + 12]);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) zp[zs<T>(i0 + q * h)] = x[q];
+            for (int q = 0; q < 16; ++q) zp[zsp<T, P>(p, i0 + q * h)] = x[q];
         }
         __syncthreads();
     }
@@ -261,14 +277,14 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             cpx<T>* zp = z + p * NS;
             cpx<T> x[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = zp[zs<T>(i0 + q * h)];
+            for (int q = 0; q < 8; ++q) x[q] = zp[zsp<T, P>(p, i0 + q * h)];
             const int tw1 = pos << (log2N - s - 1);
             radix4_step(sq, tw1, N, x[0], x[1], x[2], x[3]);
             radix4_step(sq, tw1, N, x[4], x[5], x[6], x[7]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) radix2_step(sq, (pos + q * h) << (log2N - s - 2), N, x[q], x[q + 4]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) zp[zs<T>(i0 + q * h)] = x[q];
+            for (int q = 0; q < 8; ++q) zp[zsp<T, P>(p, i0 + q * h)] = x[q];
         }
         __syncthreads();
         s += 3;
@@ -281,12 +297,12 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int pos = b & (h - 1), grp = b >> (s - 1);
             const int i0 = grp * 4 * h + pos;
             cpx<T>* zp = z + p * NS;
-            cpx<T> a = zp[zs<T>(i0)], bb = zp[zs<T>(i0 + h)], c = zp[zs<T>(i0 + 2 * h)], d = zp[zs<T>(i0 + 3 * h)];
+            cpx<T> a = zp[zsp<T, P>(p, i0)], bb = zp[zsp<T, P>(p, i0 + h)], c = zp[zsp<T, P>(p, i0 + 2 * h)], d = zp[zsp<T, P>(p, i0 + 3 * h)];
             radix4_step(sq, pos << (log2N - s - 1), N, a, bb, c, d);
-            zp[zs<T>(i0)] = a;
-            zp[zs<T>(i0 + h)] = bb;
-            zp[zs<T>(i0 + 2 * h)] = c;
-            zp[zs<T>(i0 + 3 * h)] = d;
+            zp[zsp<T, P>(p, i0)] = a;
+            zp[zsp<T, P>(p, i0 + h)] = bb;
+            zp[zsp<T, P>(p, i0 + 2 * h)] = c;
+            zp[zsp<T, P>(p, i0 + 3 * h)] = d;
         }
         __syncthreads();
     }
@@ -295,10 +311,10 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         for (int idx = tid; idx < (P << lh); idx += NTH) {
             const int p = idx >> lh, pos = idx & (N / 2 - 1);
             cpx<T>* zp = z + p * NS;
-            cpx<T> a = zp[zs<T>(pos)], c = zp[zs<T>(pos + half)];
+            cpx<T> a = zp[zsp<T, P>(p, pos)], c = zp[zsp<T, P>(p, pos + half)];
             radix2_step(sq, pos, N, a, c);
-            zp[zs<T>(pos)] = a;
-            zp[zs<T>(pos + half)] = c;
+            zp[zsp<T, P>(p, pos)] = a;
+            zp[zsp<T, P>(p, pos + half)] = c;
         }
         __syncthreads();
     }
@@ -327,10 +343,10 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
                 if (e < V) {
                     const int k = t * V + e;
                     cpx<T>* zp = z + p * NS;
-                    const cpx<T> Zk = zp[zs<T>(k)], Zn = zp[zs<T>((N - k) & (N - 1))];
+                    const cpx<T> Zk = zp[zsp<T, P>(p, k)], Zn = zp[zsp<T, P>(p, (N - k) & (N - 1))];
                     const T Ra = T(0.5) * (Zk.x + Zn.x), Ia = T(0.5) * (Zk.y - Zn.y);
                     const T Rb = T(0.5) * (Zk.y + Zn.y), Ib = -T(0.5) * (Zk.x - Zn.x);
-                    if (k > 0) zp[zs<T>(N - k)] = cpx<T>{-Ia, -Ib};
+                    if (k > 0) zp[zsp<T, P>(p, N - k)] = cpx<T>{-Ia, -Ib};
                     const double h = k == 0 ? 0.5 : 1.0;
                     ta += h * (double)Ra;
                     tb += h * (double)Rb;
@@ -368,7 +384,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             for (int e = 0; e < VMAX; ++e) {
                 if (e < V) {
                     const int k = t * V + e;
-                    z[p * NS + zs<T>(k)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
+                    z[p * NS + zsp<T, P>(p, k)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
                 }
             }
         }
@@ -384,7 +400,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int l = r + 1;
             vx[u] = vy[u] = 0.0;
             if (idx < N * P && l < N) {
-                const cpx<T> e = z[p * NS + zs<T>((l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
+                const cpx<T> e = z[p * NS + zsp<T, P>(p, (l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
                 vx[u] = alpha * (double)e.x;
                 vy[u] = alpha * (double)e.y;
             }
@@ -443,7 +459,13 @@ hipError_t dst_dispatch(const Lines& g, const Tin* in, Tout* out, double alpha, 
     switch (B) {
         case 4: return dst_launch<T, Tin, Tout, 4>(g, in, out, alpha, acc, s);
         case 8: return dst_launch<T, Tin, Tout, 8>(g, in, out, alpha, acc, s);
-        default: return dst_launch<T, Tin, Tout, 16>(g, in, out, alpha, acc, s);
+        case 16: return dst_launch<T, Tin, Tout, 16>(g, in, out, alpha, acc, s);
+        default:
+            if constexpr (sizeof(T) == 8) {                  // wide tiles: 16-byte pairs only
+                if (B == 32) return dst_launch<T, Tin, Tout, 32>(g, in, out, alpha, acc, s);
+                return dst_launch<T, Tin, Tout, 64>(g, in, out, alpha, acc, s);
+            }
+            return hipErrorInvalidValue;
     }
 }
 
@@ -452,24 +474,30 @@ Lines grid2(const DevPlan& p) { return Lines{p.N, p.log2N, p.sinq, p.N, 1, 0, nu
 }  // namespace
 
 size_t dst_lds_bytes(int N, int B, size_t cpx_bytes) {
-    const int pad = (cpx_bytes == 16 ? 16 : 32) / (B / 2);   // pair_pad
+    const int pad = cpx_bytes == 16 ? (B == 4 ? pair_pad<double, 4>() : B == 8 ? pair_pad<double, 8>()
+                                       : B == 16 ? pair_pad<double, 16>() : pair_pad<double, 32>())
+                                     : 32 / (B / 2);
+    static_assert(pair_pad<double, 32>() == pair_pad<double, 64>(), "one pad for the wide tiles");
     return sizeof(double) * (size_t)dst_table_len(N) + cpx_bytes * (size_t)(B / 2) * (N + pad);
 }
 
 bool dst_tile_ok(int N, int B, size_t cpx_bytes, size_t lds_max) {
-    // 256 / B threads per column share a scan of N / 2 values with wavefront shuffles
-    if (B != 4 && B != 8 && B != 16) return false;
-    if (N % B || 256 / B > 64 || (N / 2) < 256 / B) return false;
+    if (B < 4 || B > 64 || (B & (B - 1))) return false;
+    if (B > 16 && cpx_bytes != 16) return false;             // wide tiles: 16-byte pairs only
+    if (N < 32 || (N & (N - 1)) || N % B || N / 2 < 256 / B) return false;
+    const int P = B / 2;
+    if ((N / 2) / std::min(kDstThreads / P, N / 2) > 8) return false;   // the scan's values per thread
     return dst_lds_bytes(N, B, cpx_bytes) <= lds_max;
 }
 
 int dst_default_tile(int N, size_t cpx_bytes, size_t lds_max, long lines, int min_groups) {
     // the widest valid tile that still gives min_groups workgroups (wider
-    // tiles read longer row segments, more workgroups fill the chip); else the
-    // narrowest valid one
-    for (int B : {16, 8, 4})
+    // tiles read longer row segments and keep more of a workgroup's threads
+    // busy in the passes; more workgroups fill the chip); else the narrowest
+    // valid one
+    for (int B : {64, 32, 16, 8, 4})
         if (dst_tile_ok(N, B, cpx_bytes, lds_max) && lines / B >= min_groups) return B;
-    for (int B : {4, 8, 16})
+    for (int B : {4, 8, 16, 32, 64})
         if (dst_tile_ok(N, B, cpx_bytes, lds_max)) return B;
     return 0;
 }

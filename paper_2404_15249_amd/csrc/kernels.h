@@ -188,7 +188,7 @@ hipError_t launch_fill_rhs(const DevPlan& p, const double* f, bool mask, double*
 // column sine transforms (dst.hip): FP64, and FP32 arithmetic reading an FP64
 // grid into FP32 storage or reading FP32 storage into an FP64 grid (written or
 // accumulated)
-// B: columns per workgroup (4, 8 or 16; see dst_tile_ok)
+// B: columns per workgroup (4, 8 or 16; 32 or 64 with FP64 pairs; see dst_tile_ok)
 hipError_t launch_dst_cols(const DevPlan& p, const double* in, double* out, double alpha, bool acc, int B,
                            hipStream_t s);
 hipError_t launch_dst_cols_f32(const DevPlan& p, const double* in, float* out, double alpha, int B, hipStream_t s);

@@ -72,19 +72,24 @@ def test_every_transform_tile_matches_oracle(K, ctx, precision):
     ref[1:n, 1:n] = O.dst_solve(rhs[1:n, 1:n], (HI - LO) / n, 1.0)
     t = prob.tiles()
     tol = 1e-12 if precision == "fp64" else 1e-10
-    for b in (4, 8, 16):
+    tried = []
+    for b in (4, 8, 16, 32, 64):
         try:
             prob.set_tiles(t["modes_per_group"], b)
         except K.KfbiError:
             continue
         assert relerr(host(prob.fast_solve(dev(rhs))), ref) < tol, b
+        tried.append(b)
+    # 16-byte pairs (FP64) also take the wide tiles of 32 and 64 columns
+    assert tried == ([4, 8, 16, 32, 64] if precision == "fp64" else [4, 8, 16]), tried
 
 
 def test_invalid_shapes_are_refused(K, ctx):
     p = synth.circle_problem(n=64, m=128)
     prob = K.Problem(ctx, p.xy, p.n, p.kappa)
     t = prob.tiles()
-    for bad in [(3, 8), (0, 8), (32, 8), (t["modes_per_group"], 2), (t["modes_per_group"], 32)]:
+    for bad in [(3, 8), (0, 8), (32, 8), (t["modes_per_group"], 2), (t["modes_per_group"], 12),
+                (t["modes_per_group"], 128)]:
         with pytest.raises(K.KfbiError):
             prob.set_tiles(*bad)
     assert prob.tiles()["modes_per_group"] == t["modes_per_group"]
