@@ -68,6 +68,17 @@ __device__ __forceinline__ int zsp(int p, int i) {
     return zs<T>(i);
 }
 
+// Slot of point i0 + q h of pair p in a pass at stride h, from a = its slot for
+// q = 0.  The passes run at h = 1, 16 or a multiple of 256 with i0 free of the
+// bits of q h, so i0 + q h = i0 ^ q h, and the 16-byte pairs' swizzle then moves
+// the slot by q h, plus q when h = 16 (bits 4-7 of the element index change with
+// q).  One XOR per point instead of the swizzle's arithmetic.
+template <class T, int P>
+__device__ __forceinline__ int pass_slot(int a, int p, int i0, int q, int h) {
+    if constexpr (sizeof(T) == 8) return a ^ (q * h) ^ (h == 16 ? q : 0);
+    return zsp<T, P>(p, i0 + q * h);
+}
+
 // pair stride N + pad: the load and write phases interleave the P pairs
 // across lanes, so successive pairs start a 1/P bank row apart (with 8 or
 // more pairs the XOR above spreads them instead)
@@ -78,13 +89,14 @@ constexpr int pair_pad() {
     return 32 / P;
 }
 
-// the quarter-period sine table with one skip every 32 entries: the twiddle
-// lookups of a pass at a power-of-two stride spread over the banks
-__device__ __forceinline__ int tws(int m) { return m + (m >> 5); }
+// The twiddle table: W_N^k = (cos 2 pi k/N, -sin 2 pi k/N) for 0 <= k < N/4, one
+// 16-byte entry each, entry k at slot k ^ ((k >> 4 ^ k >> 8) & 15) (a
+// permutation inside each aligned block of 16) so that the reads of every pass
+// at its power-of-two strides land on distinct banks.
+__device__ __forceinline__ int tws(int k) { return k ^ (((k >> 4) ^ (k >> 8)) & 15); }
 
-// doubles of LDS the table takes (entries 0 .. tws(N/2)), even so that the
-// pair arrays after it stay 16-byte aligned
-__host__ __device__ constexpr int dst_table_len(int N) { return (N / 2 + ((N / 2) >> 5) + 2) & ~1; }
+// doubles of LDS the table takes (N/4 pairs); the pair arrays follow it
+__host__ __device__ constexpr int dst_table_len(int N) { return N / 2; }
 
 // two adjacent columns of one row travel as one vector load or store
 template <class T>
@@ -101,19 +113,17 @@ struct pair_of<float> {
 constexpr int kDstThreads = 1024;   // 16 wavefronts per workgroup: the LDS tile limits a CU to one
 constexpr int kLoadBatch = 8;       // vector loads in flight per thread
 
-// sin(pi m / N) for 0 <= m < 2N from the skewed quarter-period table
-__device__ __forceinline__ double sinpi_tw(const double* sq, int m, int N) {
-    const double sgn = (m & N) ? -1.0 : 1.0;
-    m &= N - 1;
-    m = min(m, N - m);
-    return sgn * sq[tws(m)];
-}
-
-// W_N^k = e^{-2 pi i k / N} for 0 <= k < N, from the quarter-period table
-__device__ __forceinline__ void twiddle(const double* sq, int k, int N, double& wr, double& wi) {
-    const int mask2 = 2 * N - 1;
-    wr = sinpi_tw(sq, (2 * k + N / 2) & mask2, N);
-    wi = -sinpi_tw(sq, (2 * k) & mask2, N);
+// W_N^k for 0 <= k < N/2 from the table: W_N^{k + N/4} = -i W_N^k
+__device__ __forceinline__ void twiddle(const cpx<double>* tw, int k, int N, double& wr, double& wi) {
+    const int q = N / 4;
+    const cpx<double> w = tw[tws(k & (q - 1))];
+    if (k & q) {
+        wr = w.y;
+        wi = -w.x;
+    } else {
+        wr = w.x;
+        wi = w.y;
+    }
 }
 
 // Passes s and s+1 of the decimation-in-time FFT on four points at distance h
@@ -121,7 +131,7 @@ __device__ __forceinline__ void twiddle(const double* sq, int k, int N, double& 
 // combines (a, b) and (c, d) with W^2, pass s+1 combines (a, c) with W and
 // (b, d) with W_N^{k + N/4} = -i W.  In place.
 template <class T>
-__device__ __forceinline__ void radix4_step(const double* sq, int tw, int N, cpx<T>& a, cpx<T>& bb, cpx<T>& c,
+__device__ __forceinline__ void radix4_step(const cpx<double>* sq, int tw, int N, cpx<T>& a, cpx<T>& bb, cpx<T>& c,
                                             cpx<T>& d) {
     double dr, di;
     twiddle(sq, tw, N, dr, di);
@@ -144,7 +154,7 @@ __device__ __forceinline__ void radix4_step(const double* sq, int tw, int N, cpx
 // Pass s' on two points at distance 2^(s'-1): b <- a - W b, a <- a + W b with
 // W = W_N^tw.  In place.
 template <class T>
-__device__ __forceinline__ void radix2_step(const double* sq, int tw, int N, cpx<T>& a, cpx<T>& b) {
+__device__ __forceinline__ void radix2_step(const cpx<double>* sq, int tw, int N, cpx<T>& a, cpx<T>& b) {
     double dr, di;
     twiddle(sq, tw, N, dr, di);
     const T wr = (T)dr, wi = (T)di;
@@ -169,7 +179,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     using Vin = typename pair_of<Tin>::type;
     using Vout = typename pair_of<Tout>::type;
     const int NS = N + pair_pad<T, B>();                     // pair stride
-    double* sq = smem_d;                                     // skewed table
+    cpx<double>* sq = reinterpret_cast<cpx<double>*>(smem_d);   // twiddle table
     cpx<T>* z = reinterpret_cast<cpx<T>*>(smem_d + dst_table_len(N));   // P x NS
     const int tid = threadIdx.x;
     // XCD-aware tile order: consecutive workgroups go round-robin over the 8
@@ -178,7 +188,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     const int G = gridDim.x;
     const int tile = (G & 7) ? (int)blockIdx.x : ((int)blockIdx.x & 7) * (G >> 3) + ((int)blockIdx.x >> 3);
     const int col0 = tile * B;
-    for (int k = tid; k <= N / 2; k += NTH) sq[tws(k)] = sinq[k];
+    for (int k = tid; k < N / 4; k += NTH) sq[tws(k)] = cpx<double>{sinq[N / 2 - 2 * k], -sinq[2 * k]};
     // load and pre-process in one pass.  With rev the log2 N-bit reversal, the
     // passes read y_j at place rev(j); y_j and y_{N-j} need x_j (row j-1) and
     // x_{N-j} (row N-j-1).  Item q = 0 .. N/2-1 of column pair p takes the
@@ -252,8 +262,9 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int i0 = grp * 16 * h + pos;
             cpx<T>* zp = z + p * NS;
             cpx<T> x[16];
+            const int a0 = zsp<T, P>(p, i0);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) x[q] = zp[zsp<T, P>(p, i0 + q * h)];
+            for (int q = 0; q < 16; ++q) x[q] = zp[pass_slot<T, P>(a0, p, i0, q, h)];
             const int tw1 = pos << (log2N - s - 1);
 #pragma unroll
             for (int t = 0; t < 4; ++t) radix4_step(sq, tw1, N, x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]);
@@ -261,7 +272,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             for (int q = 0; q < 4; ++q)
                 radix4_step(sq, (pos + q * h) << (log2N - s - 3), N, x[q], x[q + 4], x[q + 8], x[q + 12]);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) zp[zsp<T, P>(p, i0 + q * h)] = x[q];
+            for (int q = 0; q < 16; ++q) zp[pass_slot<T, P>(a0, p, i0, q, h)] = x[q];
         }
         __syncthreads();
     }
@@ -276,15 +287,16 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int i0 = grp * 8 * h + pos;
             cpx<T>* zp = z + p * NS;
             cpx<T> x[8];
+            const int a0 = zsp<T, P>(p, i0);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) x[q] = zp[zsp<T, P>(p, i0 + q * h)];
+            for (int q = 0; q < 8; ++q) x[q] = zp[pass_slot<T, P>(a0, p, i0, q, h)];
             const int tw1 = pos << (log2N - s - 1);
             radix4_step(sq, tw1, N, x[0], x[1], x[2], x[3]);
             radix4_step(sq, tw1, N, x[4], x[5], x[6], x[7]);
 #pragma unroll
             for (int q = 0; q < 4; ++q) radix2_step(sq, (pos + q * h) << (log2N - s - 2), N, x[q], x[q + 4]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) zp[zsp<T, P>(p, i0 + q * h)] = x[q];
+            for (int q = 0; q < 8; ++q) zp[pass_slot<T, P>(a0, p, i0, q, h)] = x[q];
         }
         __syncthreads();
         s += 3;
@@ -297,12 +309,15 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int pos = b & (h - 1), grp = b >> (s - 1);
             const int i0 = grp * 4 * h + pos;
             cpx<T>* zp = z + p * NS;
-            cpx<T> a = zp[zsp<T, P>(p, i0)], bb = zp[zsp<T, P>(p, i0 + h)], c = zp[zsp<T, P>(p, i0 + 2 * h)], d = zp[zsp<T, P>(p, i0 + 3 * h)];
+            const int a0 = zsp<T, P>(p, i0);
+            const int s1 = pass_slot<T, P>(a0, p, i0, 1, h), s2 = pass_slot<T, P>(a0, p, i0, 2, h),
+                      s3 = pass_slot<T, P>(a0, p, i0, 3, h);
+            cpx<T> a = zp[a0], bb = zp[s1], c = zp[s2], d = zp[s3];
             radix4_step(sq, pos << (log2N - s - 1), N, a, bb, c, d);
-            zp[zsp<T, P>(p, i0)] = a;
-            zp[zsp<T, P>(p, i0 + h)] = bb;
-            zp[zsp<T, P>(p, i0 + 2 * h)] = c;
-            zp[zsp<T, P>(p, i0 + 3 * h)] = d;
+            zp[a0] = a;
+            zp[s1] = bb;
+            zp[s2] = c;
+            zp[s3] = d;
         }
         __syncthreads();
     }
@@ -311,10 +326,11 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         for (int idx = tid; idx < (P << lh); idx += NTH) {
             const int p = idx >> lh, pos = idx & (N / 2 - 1);
             cpx<T>* zp = z + p * NS;
-            cpx<T> a = zp[zsp<T, P>(p, pos)], c = zp[zsp<T, P>(p, pos + half)];
+            const int a0 = zsp<T, P>(p, pos), s1 = pass_slot<T, P>(a0, p, pos, 1, half);
+            cpx<T> a = zp[a0], c = zp[s1];
             radix2_step(sq, pos, N, a, c);
-            zp[zsp<T, P>(p, pos)] = a;
-            zp[zsp<T, P>(p, pos + half)] = c;
+            zp[a0] = a;
+            zp[s1] = c;
         }
         __syncthreads();
     }
