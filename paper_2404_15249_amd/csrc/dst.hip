@@ -353,16 +353,27 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         const int p = tid >> lT, t = tid & (TPP - 1), tw = t & (W - 1);
         double ra[VMAX], rb[VMAX];
         double ta = 0.0, tb = 0.0;
+        // slots of k = t V + e and of its partner N - k: t V and N - (t+1) V are
+        // multiples of V <= 8, so with 16-byte pairs the slot moves by e (by V - e
+        // from the partners' block; e = 0 has the next block's first element)
+        const int ak = zsp<T, P>(p, t * V), an = zsp<T, P>(p, (N - (t + 1) * V) & (N - 1)),
+                  a0n = zsp<T, P>(p, (N - t * V) & (N - 1));
+        auto slot_k = [&](int e) { return sizeof(T) == 8 ? ak ^ e : zsp<T, P>(p, t * V + e); };
+        auto slot_n = [&](int e) {
+            if constexpr (sizeof(T) == 8) return e == 0 ? a0n : an ^ (V - e);
+            return zsp<T, P>(p, (N - t * V - e) & (N - 1));
+        };
         if (p < P) {
 #pragma unroll
             for (int e = 0; e < VMAX; ++e) {
                 if (e < V) {
                     const int k = t * V + e;
                     cpx<T>* zp = z + p * NS;
-                    const cpx<T> Zk = zp[zsp<T, P>(p, k)], Zn = zp[zsp<T, P>(p, (N - k) & (N - 1))];
+                    const int sk = slot_k(e), sn = slot_n(e);
+                    const cpx<T> Zk = zp[sk], Zn = zp[sn];
                     const T Ra = T(0.5) * (Zk.x + Zn.x), Ia = T(0.5) * (Zk.y - Zn.y);
                     const T Rb = T(0.5) * (Zk.y + Zn.y), Ib = -T(0.5) * (Zk.x - Zn.x);
-                    if (k > 0) zp[zsp<T, P>(p, N - k)] = cpx<T>{-Ia, -Ib};
+                    if (k > 0) zp[sn] = cpx<T>{-Ia, -Ib};
                     const double h = k == 0 ? 0.5 : 1.0;
                     ta += h * (double)Ra;
                     tb += h * (double)Rb;
@@ -397,12 +408,8 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         }
         if (p < P) {
 #pragma unroll
-            for (int e = 0; e < VMAX; ++e) {
-                if (e < V) {
-                    const int k = t * V + e;
-                    z[p * NS + zsp<T, P>(p, k)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
-                }
-            }
+            for (int e = 0; e < VMAX; ++e)
+                if (e < V) z[p * NS + slot_k(e)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
         }
     }
     __syncthreads();
