@@ -372,7 +372,7 @@ kfbi_status kfbi_prob_set_tiles(kfbi_prob* prob, const kfbi_tiles* tiles);
  * every stage of an iteration (correction, sparse fast solve, interpolation,
  * Gram-Schmidt/Givens) is one persistent launch over a device-resident work
  * list of all live problems, replayed as a captured graph.  Problems may have
- * different grids (n <= 2048) and sample counts (m <= m_max); a problem's
+ * different grids (n <= 4096) and sample counts (m <= m_max); a problem's
  * arithmetic is split into the same blocks whatever else is in the batch, so
  * its result is the same alone and in the mix.  hbm_budget bounds the device
  * bytes of the admitted problems (0: no bound).  For callers that serve solve

@@ -7,10 +7,11 @@
 
 namespace kfbi {
 
-constexpr int kBatchNmax = 2048;    // largest grid a batch serves
+constexpr int kBatchNmax = 4096;    // largest grid a batch serves
 // LDS of the batched fast solve holds this many doubles of mode solutions
-// (and, after them, kMaxModesPerGroup x kMaxExtra sums of extra pieces)
-constexpr int kBatchXs = 8 * (kBatchNmax + 64);
+// (and, after them, kMaxModesPerGroup x kMaxExtra sums of extra pieces):
+// eight padded modes of the 2048^2 grid, four of the 4096^2 grid
+constexpr int kBatchXs = 8 * (2048 + 64);
 
 // Modes per workgroup of a batched problem with grid N: the largest power of two
 // up to kMaxModesPerGroup whose padded solutions fit kBatchXs.

@@ -62,7 +62,8 @@ __global__ __launch_bounds__(kModeWaves * 64) void k_modes_b(const SlotDev* __re
             case 256: modes_item<4>(p, S.corr_il, item.y, L, S.partial); break;
             case 512: modes_item<8>(p, S.corr_il, item.y, L, S.partial); break;
             case 1024: modes_item<16>(p, S.corr_il, item.y, L, S.partial); break;
-            default: modes_item<32>(p, S.corr_il, item.y, L, S.partial); break;
+            case 2048: modes_item<32>(p, S.corr_il, item.y, L, S.partial); break;
+            default: modes_item<64>(p, S.corr_il, item.y, L, S.partial); break;
         }
     }
 }

@@ -112,6 +112,28 @@ def test_alone_and_in_the_mix_are_bitwise_equal(K, ctx):
         assert alone[4] == mixed[k][4]
 
 
+def test_large_grids_in_a_batch(K, ctx):
+    """The 2048^2 and 4096^2 grids (the largest a batch serves: four modes per
+    workgroup at 4096^2) beside a small problem: each matches its single-problem
+    solve, and the 4096^2 member is bitwise the same alone and in the mix."""
+    problems = [synth.star_problem(n=4096, kappa=1.0), synth.circle_problem(n=2048, m=1024, kappa=1.0),
+                synth.circle_problem(n=64, m=128)]
+    mixed = run_batch(K, ctx, problems, tol=1e-10)
+    for p, (u, ug, phi, st, it, rel) in zip(problems, mixed):
+        note(f"{p.name}: state {st} iters {it} relres {rel:.3e}")
+        assert st == 1, (p.name, it, rel)
+        prob = K.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-10)
+        u1, ug1, phi1, it1, rel1, conv1 = prob.solve(dev(p.f_grid), dev(p.f_gamma), dev(p.g))
+        note(f"  single: iters {it1} relres {rel1:.3e}")
+        assert conv1 and abs(it1 - it) <= 1, p.name
+        assert relerr(phi, host(phi1)) < 1e-9, p.name
+        assert relerr(u, host(u1)) < 1e-9, p.name
+        prob.close()
+    alone = run_batch(K, ctx, [problems[0]], tol=1e-10)[0]
+    for a, b in zip(alone[:3], mixed[0][:3]):
+        assert np.array_equal(a, b)
+
+
 def test_budget_admission(K, ctx):
     p1, p2 = synth.star_problem(n=256, kappa=1.0), synth.circle_problem(n=256, m=512)
     a = K.Problem(ctx, p1.xy, p1.n, p1.kappa)
