@@ -84,6 +84,19 @@ def test_every_transform_tile_matches_oracle(K, ctx, precision):
     assert tried == ([4, 8, 16, 32, 64] if precision == "fp64" else [4, 8, 16]), tried
 
 
+@pytest.mark.parametrize("n", [64, 128])
+def test_short_columns_fast_solve_matches_oracle(K, ctx, n):
+    """Grids of 64 rows take the transform with one wavefront per column pair
+    (128 the tiled one): both against the oracle's DST-I solve."""
+    prob = K.Problem(ctx, synth.circle_points(2 * n, 0.8), n, 1.0)
+    print(f"short columns n={n}", flush=True)
+    rng = np.random.default_rng(n)
+    rhs = rng.standard_normal((n + 1, n + 1))
+    ref = np.zeros_like(rhs)
+    ref[1:n, 1:n] = O.dst_solve(rhs[1:n, 1:n], (HI - LO) / n, 1.0)
+    assert relerr(host(prob.fast_solve(dev(rhs))), ref) < 1e-12
+
+
 def test_invalid_shapes_are_refused(K, ctx):
     p = synth.circle_problem(n=64, m=128)
     prob = K.Problem(ctx, p.xy, p.n, p.kappa)
