@@ -244,6 +244,38 @@ struct GmUpdIn {
     double w;
     double h, cs, sn, g;
 };
+// Chunk counts up to which one thread adds a row of partials (or the chunk
+// norms) itself; above them (the surface problem's long vectors) the
+// workgroup's threads split the work, so the chain of dependent loads stays short.
+constexpr int kGmSerialSums = 32;
+
+// h_i = the sum of row i of the nco chunk partials, i < m, for many chunks:
+// kGmChunk / m threads per row, each adding every (kGmChunk / m)-th chunk in
+// order, then the parts added in order.  Returns h_tid for tid < m; the same
+// order in every workgroup, so they all agree.  Called by the whole workgroup.
+__device__ inline double gm_dots_spread(const double* d1, int m, int nco) {
+    __shared__ double part[kGmChunk];
+    const int tid = threadIdx.x, P = kGmChunk / m;
+    double s = 0.0;
+    if (tid < m * P) {
+        const int i = tid / P, r = tid - i * P;
+        const double* row = d1 + (size_t)i * nco;
+        for (int c0 = r; c0 < nco; c0 += 16 * P) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = c0 + u * P < nco ? row[c0 + u * P] : 0.0;   // issued together
+#pragma unroll
+            for (int u = 0; u < 16; ++u) s += v[u];
+        }
+    }
+    part[tid] = s;
+    __syncthreads();
+    double h = 0.0;
+    if (tid < m)
+        for (int r = 0; r < P; ++r) h += part[tid * P + r];
+    return h;
+}
+
 __device__ __forceinline__ GmUpdIn gm_update_loads(const GmresBufs& b, int M, int c) {
     const int tid = threadIdx.x, m = b.m, nco = b.gc64;
     const GmPart q = gm_part(b);
@@ -256,10 +288,16 @@ __device__ __forceinline__ GmUpdIn gm_update_loads(const GmresBufs& b, int M, in
         u.cs = b.cs[tid];
         u.sn = b.sn[tid];
         u.g = b.g[tid];
-        double sum = 0.0;
+    }
+    if (nco <= kGmSerialSums) {
+        if (tid < m) {
+            double sum = 0.0;
 #pragma unroll 16
-        for (int cc = 0; cc < nco; ++cc) sum += q.d1[(size_t)tid * nco + cc];   // loads issued together
-        u.h = sum;
+            for (int cc = 0; cc < nco; ++cc) sum += q.d1[(size_t)tid * nco + cc];   // loads issued together
+            u.h = sum;
+        }
+    } else {
+        u.h = gm_dots_spread(q.d1, m, nco);
     }
     return u;
 }
@@ -512,16 +550,30 @@ __device__ inline void gm_update1_commit(const GmresBufs& b, int M, int c) {
         return;
     }
     for (int i = threadIdx.x; i < kMaxRestart + 2; i += kGmChunk) h2s[i] = 0.0;
-    if (threadIdx.x == 0) {
-        const GmPart q = gm_part(b);
-        double zz = 0.0, ww = 0.0;
+    if (b.gc <= kGmSerialSums) {
+        if (threadIdx.x == 0) {
+            const GmPart q = gm_part(b);
+            double zz = 0.0, ww = 0.0;
 #pragma unroll 8
-        for (int cc = 0; cc < b.gc; ++cc) {                // fixed order
-            zz += q.nrm[cc];
-            ww += q.nrmw[cc];
+            for (int cc = 0; cc < b.gc; ++cc) {            // fixed order
+                zz += q.nrm[cc];
+                ww += q.nrmw[cc];
+            }
+            s_second = zz < s.reorth * s.reorth * ww;
+            s_zz = zz;
         }
-        s_second = zz < s.reorth * s.reorth * ww;
-        s_zz = zz;
+    } else {                                               // many chunks: every thread, then a block sum
+        const GmPart q = gm_part(b);
+        double a = 0.0, w = 0.0;
+        for (int cc = threadIdx.x; cc < b.gc; cc += kGmChunk) {
+            a += q.nrm[cc];
+            w += q.nrmw[cc];
+        }
+        const double zz = gm_block_sum(a, red), ww = gm_block_sum(w, red);
+        if (threadIdx.x == 0) {
+            s_second = zz < s.reorth * s.reorth * ww;
+            s_zz = zz;
+        }
     }
     __syncthreads();
     const double zz = s_second ? gm_second_pass(b, M, s.j, h2s, red) : s_zz;
