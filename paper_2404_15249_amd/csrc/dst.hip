@@ -474,14 +474,19 @@ __global__ __launch_bounds__(kShortThreads) void k_dst_short(const double* __res
     constexpr int LOG2N = NP == 1 ? 6 : NP == 2 ? 7 : 8;
     constexpr int KT = NP >= 2 ? NP / 2 : 1;                 // values of k per lane
     if (skip && *skip) return;
-    in += blockIdx.y * slice;
-    out += blockIdx.y * slice;
+    // tiles of eight columns (64 bytes of a row, half a cache line), in all
+    // slices: consecutive workgroups go round-robin over the 8 XCDs, so each
+    // XCD takes a contiguous range of the flattened (slice, tile) order and
+    // neighbouring tiles share their lines in its L2
+    const int Gx = gridDim.x, Gt = Gx * gridDim.y;
+    int lin = (int)blockIdx.x + (int)blockIdx.y * Gx;
+    if ((Gt & 7) == 0) lin = (lin & 7) * (Gt >> 3) + (lin >> 3);
+    const int tile = lin % Gx;
+    in += (size_t)(lin / Gx) * slice;
+    out += (size_t)(lin / Gx) * slice;
     __shared__ cpx<double> tw[N / 4];
     const int tid = threadIdx.x, L = tid & 63;
     for (int k = tid; k < N / 4; k += kShortThreads) tw[k] = cpx<double>{sinq[N / 2 - 2 * k], -sinq[2 * k]};
-    // tiles of eight columns, each XCD a contiguous range of them
-    const int G = gridDim.x;
-    const int tile = (G & 7) ? (int)blockIdx.x : ((int)blockIdx.x & 7) * (G >> 3) + ((int)blockIdx.x >> 3);
     const int col = 8 * tile + 2 * (tid >> 6);
     // load and pre-process: y_j = sin(pi j/N)(x_j + x_{N-j}) + (x_j - x_{N-j})/2, y_0 = 0
     cpx<double> v[NP];
