@@ -348,7 +348,7 @@ void ensure_graph(kfbi_prob* p, int op, int k) {
 struct GmresRun {
     kfbi_prob* p = nullptr;
     int op = kOpD;
-    int max_steps = 0, steps = 0;
+    int max_steps = 0, steps = 0, batches = 0;
     bool use_graph = false, poll_each = true, extended = false, finished = false;
 };
 
@@ -389,13 +389,17 @@ bool gmres_more(GmresRun& r) {
 // Enqueue the next batch of steps: kGraphSteps, or the largest power of two
 // not above what is left (a replayed graph unless per-launch timing is on);
 // returns through *poll whether the state should be read after it (every
-// batch when the run can stop early, else only after the last).
+// batch when the run can stop early, else only after the last).  A run that
+// can stop early takes batches of 8, 16, then 32 steps: the steps launched
+// after the device has converged return at once but still cost their
+// launches (about 7 us a step), a poll costs about three of them.
 kfbi_status gmres_batch(GmresRun& r, bool* poll) {
     kfbi_prob* p = r.p;
     hipStream_t s = p->ctx->stream;
-    const int left = r.max_steps - r.steps;
+    const int cap = r.poll_each ? std::min(kfbi_prob::kGraphSteps, 8 << std::min(r.batches, 4)) : kfbi_prob::kGraphSteps;
+    const int want = std::min(r.max_steps - r.steps, cap);
     int k = 0;
-    while ((kfbi_prob::kGraphSteps >> k) > left && k + 1 < kfbi_prob::kGraphSizes) ++k;
+    while ((kfbi_prob::kGraphSteps >> k) > want && k + 1 < kfbi_prob::kGraphSizes) ++k;
     const int n = kfbi_prob::kGraphSteps >> k;
     if (r.use_graph) ensure_graph(p, r.op, k);
     if (r.use_graph && p->gexec[r.op][k]) {
@@ -404,6 +408,7 @@ kfbi_status gmres_batch(GmresRun& r, bool* poll) {
         return e;
     }
     r.steps += n;
+    r.batches += 1;
     *poll = r.poll_each || r.steps >= r.max_steps;
     return KFBI_OK;
 }
