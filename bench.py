@@ -734,14 +734,20 @@ def main():
     fl = modes_flops(p.n, prob.I, prob.M)
     achieved = fl / (tim["modes_us"] * 1e-6) / 1e12
 
-    # one full Dirichlet solve of the same problem (volume potential, GMRES to 1e-10, final solve)
+    # full Dirichlet solves of the same problem (volume potential, GMRES to 1e-10,
+    # final solve), the data already on the device: the median of five after two
     prob_s = kfbi.Problem(ctx, p.xy, p.n, p.kappa, tol=1e-10)
-    prob_s.solve(dev(p.f_grid), dev(p.f_gamma), dev(p.g))
-    torch.cuda.synchronize()
-    ts = time.perf_counter()
-    u, ug, phi, it, rel, conv = prob_s.solve(dev(p.f_grid), dev(p.f_gamma), dev(p.g))
-    torch.cuda.synchronize()
-    solve_ms = 1e3 * (time.perf_counter() - ts)
+    fs, fgs, gs = dev(p.f_grid), dev(p.f_gamma), dev(p.g)
+    for _ in range(2):
+        prob_s.solve(fs, fgs, gs)
+    solve_ts = []
+    for _ in range(5):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        u, ug, phi, it, rel, conv = prob_s.solve(fs, fgs, gs)
+        torch.cuda.synchronize()
+        solve_ts.append(1e3 * (time.perf_counter() - ts))
+    solve_ms = sorted(solve_ts)[2]
     c = p.lo + np.arange(p.n + 1) * p.h
     X, Y = np.meshgrid(c, c, indexing="xy")
     mask = prob_s.mask()
