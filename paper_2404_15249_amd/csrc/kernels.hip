@@ -112,19 +112,42 @@ __global__ __launch_bounds__(256) void k_fill_rhs(DevPlan p, const double* __res
 }
 
 // One wavefront per sine mode l (row l-1 of A): the tridiagonal solve along x,
-// in FP64 whatever the storage type T.
+// in FP64 whatever the storage type T.  The solve wants each lane's C
+// consecutive values in registers; the row goes through LDS so that the global
+// loads and stores stay coalesced (lane-consecutive), one skipped slot per C
+// values keeping the lanes' chunk reads on distinct banks.  Rows per
+// workgroup: 4 up to C = 16, 2 at C = 32, 1 at C = 64 (33.8 KB of LDS).
+template <int C>
+constexpr int rows_per_group() { return C <= 16 ? 4 : C == 32 ? 2 : 1; }
+
 template <int C, class T>
-__global__ __launch_bounds__(256) void k_rows_solve(DevPlan p, T* __restrict__ A) {
-    const int lane = threadIdx.x & 63;
-    const int l = blockIdx.x * 4 + (threadIdx.x >> 6) + 1;
-    if (l > p.n) return;
+__global__ __launch_bounds__(64 * rows_per_group<C>()) void k_rows_solve(DevPlan p, T* __restrict__ A) {
+    constexpr int RPW = rows_per_group<C>(), W = 64 * C, WP = W + 64;
+    __shared__ double rs[RPW][WP];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int l = blockIdx.x * RPW + w + 1;
+    const bool live = l <= p.n;                          // the barriers below are the workgroup's
     T* row = A + (size_t)(l - 1) * p.N;
+    double* r = rs[w];
+    auto pad = [](int e) { return e + e / C; };
+    if (live) {
+#pragma unroll 8
+        for (int c = 0; c < C; ++c) r[pad(c * 64 + lane)] = (double)row[c * 64 + lane] * p.h2;
+    }
+    __syncthreads();
     double e[C];
+    if (live) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) e[c] = (double)row[lane * C + c] * p.h2;
-    mode_solve<C>(e, p.modes[l], lane, p.N);
+        for (int c = 0; c < C; ++c) e[c] = r[pad(lane * C + c)];
+        mode_solve<C>(e, p.modes[l], lane, p.N);
 #pragma unroll
-    for (int c = 0; c < C; ++c) row[lane * C + c] = (T)e[c];
+        for (int c = 0; c < C; ++c) r[pad(lane * C + c)] = e[c];
+    }
+    __syncthreads();
+    if (live) {
+#pragma unroll 8
+        for (int c = 0; c < C; ++c) row[c * 64 + lane] = (T)r[pad(c * 64 + lane)];
+    }
 }
 
 // R <- R - ((V_E + V_W + V_N + V_S - 4 V) / h^2 - kappa V) at the interior nodes
@@ -240,7 +263,9 @@ hipError_t modes_dispatch_r(const DevPlan& p, const double* corr, double* partia
 
 template <int C, class T>
 hipError_t rows_dispatch(const DevPlan& p, T* A, hipStream_t s) {
-    if (hipError_t e_ = klaunch(&k_rows_solve<C, T>, dim3((p.n + 3) / 4), dim3(256), 0, s, p, A)) return e_;
+    constexpr int RPW = rows_per_group<C>();
+    if (hipError_t e_ = klaunch(&k_rows_solve<C, T>, dim3((p.n + RPW - 1) / RPW), dim3(64 * RPW), 0, s, p, A))
+        return e_;
     return hipGetLastError();
 }
 
