@@ -34,6 +34,12 @@ struct alignas(2 * sizeof(T)) cpx {
     T x, y;
 };
 
+// a compile-time int passed as an argument (selects a generic lambda's body)
+template <int V>
+struct IntConst {
+    static constexpr int value = V;
+};
+
 __device__ __forceinline__ int bitrev(int v, int bits) { return (int)(__brev((unsigned)v) >> (32 - bits)); }
 
 // LDS banks on gfx950: 64 four-byte banks.  A 16-byte access serves the
@@ -131,10 +137,7 @@ __device__ __forceinline__ void twiddle(const cpx<double>* tw, int k, int N, dou
 // combines (a, b) and (c, d) with W^2, pass s+1 combines (a, c) with W and
 // (b, d) with W_N^{k + N/4} = -i W.  In place.
 template <class T>
-__device__ __forceinline__ void radix4_step(const cpx<double>* sq, int tw, int N, cpx<T>& a, cpx<T>& bb, cpx<T>& c,
-                                            cpx<T>& d) {
-    double dr, di;
-    twiddle(sq, tw, N, dr, di);
+__device__ __forceinline__ void radix4_step(double dr, double di, cpx<T>& a, cpx<T>& bb, cpx<T>& c, cpx<T>& d) {
     const T w2r = (T)dr, w2i = (T)di;
     const T w1r = (T)(dr * dr - di * di), w1i = (T)(2.0 * dr * di);
     // pass s: (a, b) and (c, d) with W^2
@@ -151,16 +154,30 @@ __device__ __forceinline__ void radix4_step(const cpx<double>* sq, int tw, int N
     d = cpx<T>{b1.x - ter, b1.y - tei};
 }
 
+// the same with the twiddle read from the table
+template <class T>
+__device__ __forceinline__ void radix4_step(const cpx<double>* sq, int tw, int N, cpx<T>& a, cpx<T>& bb, cpx<T>& c,
+                                            cpx<T>& d) {
+    double dr, di;
+    twiddle(sq, tw, N, dr, di);
+    radix4_step(dr, di, a, bb, c, d);
+}
+
 // Pass s' on two points at distance 2^(s'-1): b <- a - W b, a <- a + W b with
 // W = W_N^tw.  In place.
 template <class T>
-__device__ __forceinline__ void radix2_step(const cpx<double>* sq, int tw, int N, cpx<T>& a, cpx<T>& b) {
-    double dr, di;
-    twiddle(sq, tw, N, dr, di);
+__device__ __forceinline__ void radix2_step(double dr, double di, cpx<T>& a, cpx<T>& b) {
     const T wr = (T)dr, wi = (T)di;
     const T tr = wr * b.x - wi * b.y, ti = wr * b.y + wi * b.x;
     b = cpx<T>{a.x - tr, a.y - ti};
     a = cpx<T>{a.x + tr, a.y + ti};
+}
+
+template <class T>
+__device__ __forceinline__ void radix2_step(const cpx<double>* sq, int tw, int N, cpx<T>& a, cpx<T>& b) {
+    double dr, di;
+    twiddle(sq, tw, N, dr, di);
+    radix2_step(dr, di, a, b);
 }
 
 // Rows are ld elements apart; blockIdx.y selects a slice of `slice` elements
@@ -198,7 +215,13 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     // reversed, so the items meet every pair {j, N - j} once (i = 1 is
     // j = N/2, its own partner) and a wavefront's stores run through
     // consecutive places, ascending and descending.  x_0 = x_N = 0 gives
-    // y_0 = 0.  A batch's loads are all issued before any is used.
+    // y_0 = 0.  A batch's loads are all issued before any is used, and every
+    // path uses every loaded value (no load is left outstanding into the
+    // next batch, so the compiler need not wait between one item's loads and
+    // the next's): i = 1 (j = N/2) reads its one row twice and the table's
+    // sin(pi/2) = 1, which gives 2 x_j through the general formula, stored at
+    // place 1 twice; threads past the last item redo it (the same values to
+    // the same places).
     const int lh = log2N - 1;                                // log2 (N/2)
     constexpr int LB = kLoadBatch / 2;
     const int items = P << lh;
@@ -212,35 +235,28 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         double sv[LB];
 #pragma unroll
         for (int u = 0; u < LB; ++u) {
-            const int idx = base + u * NTH + tid;
+            const int idx = min(base + u * NTH + tid, items - 1);
             const int p = idx & (P - 1);
-            if (idx < items) {
-                int lo;
-                const int i = place(idx >> LP, lo);
-                const int j = bitrev(i, log2N);
-                va[u] = *reinterpret_cast<const Vin*>(in + (size_t)(j - 1) * ld + col0 + 2 * p);
-                if (i != 1) vb[u] = *reinterpret_cast<const Vin*>(in + (size_t)(N - j - 1) * ld + col0 + 2 * p);
-                sv[u] = sinq[min(j, N - j)];
-            }
+            int lo;
+            const int i = place(idx >> LP, lo);
+            const int j = bitrev(i, log2N);
+            va[u] = *reinterpret_cast<const Vin*>(in + (size_t)(j - 1) * ld + col0 + 2 * p);
+            vb[u] = *reinterpret_cast<const Vin*>(in + (size_t)(N - j - 1) * ld + col0 + 2 * p);
+            sv[u] = sinq[min(j, N - j)];
         }
 #pragma unroll
         for (int u = 0; u < LB; ++u) {
-            const int idx = base + u * NTH + tid;
-            if (idx >= items) continue;
+            const int idx = min(base + u * NTH + tid, items - 1);
             const int p = idx & (P - 1);
             int lo;
             const int i = place(idx >> LP, lo);
             cpx<T>* zp = z + p * NS;
             const T ax = (T)va[u].x, ay = (T)va[u].y;
-            if (i == 1) {
-                zp[zsp<T, P>(p, 1)] = cpx<T>{ax * T(2), ay * T(2)};
-            } else {
-                const T bx = (T)vb[u].x, by = (T)vb[u].y;
-                const T sj = (T)sv[u];
-                zp[zsp<T, P>(p, i)] = cpx<T>{sj * (ax + bx) + T(0.5) * (ax - bx), sj * (ay + by) + T(0.5) * (ay - by)};
-                zp[zsp<T, P>(p, i ^ (lo - 1))] =
-                    cpx<T>{sj * (bx + ax) + T(0.5) * (bx - ax), sj * (by + ay) + T(0.5) * (by - ay)};
-            }
+            const T bx = (T)vb[u].x, by = (T)vb[u].y;
+            const T sj = (T)sv[u];
+            zp[zsp<T, P>(p, i)] = cpx<T>{sj * (ax + bx) + T(0.5) * (ax - bx), sj * (ay + by) + T(0.5) * (ay - by)};
+            zp[zsp<T, P>(p, i ^ (lo - 1))] =
+                cpx<T>{sj * (bx + ax) + T(0.5) * (bx - ax), sj * (by + ay) + T(0.5) * (by - ay)};
         }
     }
     if (tid < P) z[tid * NS + zsp<T, P>(tid, 0)] = cpx<T>{T(0), T(0)};
@@ -265,12 +281,15 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int a0 = zsp<T, P>(p, i0);
 #pragma unroll
             for (int q = 0; q < 16; ++q) x[q] = zp[pass_slot<T, P>(a0, p, i0, q, h)];
-            const int tw1 = pos << (log2N - s - 1);
+            // the five twiddles are read before any is used
+            double w1r, w1i, w2r[4], w2i[4];
+            twiddle(sq, pos << (log2N - s - 1), N, w1r, w1i);
 #pragma unroll
-            for (int t = 0; t < 4; ++t) radix4_step(sq, tw1, N, x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]);
+            for (int q = 0; q < 4; ++q) twiddle(sq, (pos + q * h) << (log2N - s - 3), N, w2r[q], w2i[q]);
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                radix4_step(sq, (pos + q * h) << (log2N - s - 3), N, x[q], x[q + 4], x[q + 8], x[q + 12]);
+            for (int t = 0; t < 4; ++t) radix4_step(w1r, w1i, x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) radix4_step(w2r[q], w2i[q], x[q], x[q + 4], x[q + 8], x[q + 12]);
 #pragma unroll
             for (int q = 0; q < 16; ++q) zp[pass_slot<T, P>(a0, p, i0, q, h)] = x[q];
         }
@@ -290,11 +309,15 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             const int a0 = zsp<T, P>(p, i0);
 #pragma unroll
             for (int q = 0; q < 8; ++q) x[q] = zp[pass_slot<T, P>(a0, p, i0, q, h)];
-            const int tw1 = pos << (log2N - s - 1);
-            radix4_step(sq, tw1, N, x[0], x[1], x[2], x[3]);
-            radix4_step(sq, tw1, N, x[4], x[5], x[6], x[7]);
+            // the five twiddles are read before any is used
+            double w1r, w1i, w2r[4], w2i[4];
+            twiddle(sq, pos << (log2N - s - 1), N, w1r, w1i);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) radix2_step(sq, (pos + q * h) << (log2N - s - 2), N, x[q], x[q + 4]);
+            for (int q = 0; q < 4; ++q) twiddle(sq, (pos + q * h) << (log2N - s - 2), N, w2r[q], w2i[q]);
+            radix4_step(w1r, w1i, x[0], x[1], x[2], x[3]);
+            radix4_step(w1r, w1i, x[4], x[5], x[6], x[7]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) radix2_step(w2r[q], w2i[q], x[q], x[q + 4]);
 #pragma unroll
             for (int q = 0; q < 8; ++q) zp[pass_slot<T, P>(a0, p, i0, q, h)] = x[q];
         }
@@ -343,15 +366,16 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     // inclusive scan of the thread totals across the wavefront, then the
     // totals of the pair's earlier wavefronts, added in wavefront order
     // (through LDS, in the place of the sine table, which is no longer read).
-    // Sums are carried in FP64 whatever the storage type.
-    {
-        constexpr int VMAX = 8;                              // V <= 8 for every tile that fits the LDS
-        const int TPP = min(NTH / P, N / 2);                 // a power of two
-        const int lT = 31 - __clz(TPP);
-        const int V = (N / 2) >> lT;
+    // Sums are carried in FP64 whatever the storage type.  V is a template
+    // constant of the body (1, 2, 4 or 8 for every tile that fits the LDS), so
+    // a thread's 2V reads are all issued before the first is used.
+    const int TPP = min(NTH / P, N / 2);                     // a power of two
+    const int lT = 31 - __clz(TPP);
+    auto separate = [&](auto vc) {
+        constexpr int V = decltype(vc)::value;
         const int W = min(TPP, 64);                          // scan width inside a wavefront
         const int p = tid >> lT, t = tid & (TPP - 1), tw = t & (W - 1);
-        double ra[VMAX], rb[VMAX];
+        double ra[V], rb[V];
         double ta = 0.0, tb = 0.0;
         // slots of k = t V + e and of its partner N - k: t V and N - (t+1) V are
         // multiples of V <= 8, so with 16-byte pairs the slot moves by e (by V - e
@@ -363,23 +387,25 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             if constexpr (sizeof(T) == 8) return e == 0 ? a0n : an ^ (V - e);
             return zsp<T, P>(p, (N - t * V - e) & (N - 1));
         };
+        cpx<T>* zp = z + p * NS;
         if (p < P) {
+            cpx<T> Zk[V], Zn[V];
 #pragma unroll
-            for (int e = 0; e < VMAX; ++e) {
-                if (e < V) {
-                    const int k = t * V + e;
-                    cpx<T>* zp = z + p * NS;
-                    const int sk = slot_k(e), sn = slot_n(e);
-                    const cpx<T> Zk = zp[sk], Zn = zp[sn];
-                    const T Ra = T(0.5) * (Zk.x + Zn.x), Ia = T(0.5) * (Zk.y - Zn.y);
-                    const T Rb = T(0.5) * (Zk.y + Zn.y), Ib = -T(0.5) * (Zk.x - Zn.x);
-                    if (k > 0) zp[sn] = cpx<T>{-Ia, -Ib};
-                    const double h = k == 0 ? 0.5 : 1.0;
-                    ta += h * (double)Ra;
-                    tb += h * (double)Rb;
-                    ra[e] = ta;
-                    rb[e] = tb;
-                }
+            for (int e = 0; e < V; ++e) {
+                Zk[e] = zp[slot_k(e)];
+                Zn[e] = zp[slot_n(e)];
+            }
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int k = t * V + e;
+                const T Ra = T(0.5) * (Zk[e].x + Zn[e].x), Ia = T(0.5) * (Zk[e].y - Zn[e].y);
+                const T Rb = T(0.5) * (Zk[e].y + Zn[e].y), Ib = -T(0.5) * (Zk[e].x - Zn[e].x);
+                if (k > 0) zp[slot_n(e)] = cpx<T>{-Ia, -Ib};
+                const double h = k == 0 ? 0.5 : 1.0;
+                ta += h * (double)Ra;
+                tb += h * (double)Rb;
+                ra[e] = ta;
+                rb[e] = tb;
             }
         }
         for (int o = 1; o < W; o <<= 1) {
@@ -392,15 +418,25 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         double ea = __shfl_up(ta, 1, W), eb = __shfl_up(tb, 1, W);
         if (tw == 0) ea = eb = 0.0;
         if (TPP > 64) {
-            const int nw = TPP >> 6;                         // wavefronts per pair
+            const int nw = TPP >> 6;                         // wavefronts per pair (<= 16)
             double2* tot = reinterpret_cast<double2*>(smem_d);
             if (p < P && (t & 63) == 63) tot[p * nw + (t >> 6)] = make_double2(ta, tb);
             __syncthreads();
             if (p < P) {
+                // the earlier wavefronts' totals in order; four reads issued
+                // together (clamped to the pair's entries), the later ones skipped
+                const int wt = t >> 6;
                 double ba = 0.0, bb = 0.0;
-                for (int w = 0; w < (t >> 6); ++w) {
-                    ba += tot[p * nw + w].x;
-                    bb += tot[p * nw + w].y;
+                for (int w0 = 0; w0 < nw; w0 += 4) {
+                    double2 tv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) tv[u] = tot[p * nw + min(w0 + u, nw - 1)];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (w0 + u < wt) {
+                            ba += tv[u].x;
+                            bb += tv[u].y;
+                        }
                 }
                 ea += ba;
                 eb += bb;
@@ -408,33 +444,43 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
         }
         if (p < P) {
 #pragma unroll
-            for (int e = 0; e < VMAX; ++e)
-                if (e < V) z[p * NS + slot_k(e)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
+            for (int e = 0; e < V; ++e) zp[slot_k(e)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
         }
+    };
+    switch ((N / 2) >> lT) {
+        case 1: separate(IntConst<1>{}); break;
+        case 2: separate(IntConst<2>{}); break;
+        case 4: separate(IntConst<4>{}); break;
+        default: separate(IntConst<8>{}); break;
     }
     __syncthreads();
     // write: X_l to row l-1 (odd l from slot (l-1)/2, even l from slot N - l/2); row N-1 is the pad
+    // (every thread reads LDS and, when accumulating, loads the old values at a
+    // valid place: clamped past the tile's last element, only the stores are
+    // guarded, so the reads of a batch issue together)
     for (int base = 0; base < N * P; base += NTH * kLoadBatch) {
         double vx[kLoadBatch], vy[kLoadBatch];
+        cpx<T> ev[kLoadBatch];
 #pragma unroll
         for (int u = 0; u < kLoadBatch; ++u) {
-            const int idx = base + u * NTH + tid;
+            const int idx = min(base + u * NTH + tid, N * P - 1);
             const int r = idx >> LP, p = idx & (P - 1);
-            const int l = r + 1;
-            vx[u] = vy[u] = 0.0;
-            if (idx < N * P && l < N) {
-                const cpx<T> e = z[p * NS + zsp<T, P>(p, (l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
-                vx[u] = alpha * (double)e.x;
-                vy[u] = alpha * (double)e.y;
-            }
+            const int l = r + 1;                             // l = N: slot N/2, not used
+            ev[u] = z[p * NS + zsp<T, P>(p, (l & 1) ? (l - 1) >> 1 : N - (l >> 1))];
+        }
+#pragma unroll
+        for (int u = 0; u < kLoadBatch; ++u) {
+            const int l = (min(base + u * NTH + tid, N * P - 1) >> LP) + 1;
+            vx[u] = l < N ? alpha * (double)ev[u].x : 0.0;
+            vy[u] = l < N ? alpha * (double)ev[u].y : 0.0;
         }
         if (accumulate) {
             Vout old[kLoadBatch];
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
-                const int idx = base + u * NTH + tid;
+                const int idx = min(base + u * NTH + tid, N * P - 1);
                 const int r = idx >> LP, p = idx & (P - 1);
-                if (idx < N * P) old[u] = *reinterpret_cast<const Vout*>(out + (size_t)r * ld + col0 + 2 * p);
+                old[u] = *reinterpret_cast<const Vout*>(out + (size_t)r * ld + col0 + 2 * p);
             }
 #pragma unroll
             for (int u = 0; u < kLoadBatch; ++u) {
