@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
             for (int e = 0; e < V; ++e) zp[slot_k(e)] = cpx<T>{(T)(ea + ra[e]), (T)(eb + rb[e])};
         }
     };
-    switch ((N / 2) >> lT) {
+    switch ((N / 2) >> lT) {                                 // dst_tile_ok admits V <= 8 only
         case 1: separate(IntConst<1>{}); break;
         case 2: separate(IntConst<2>{}); break;
         case 4: separate(IntConst<4>{}); break;

@@ -60,9 +60,11 @@ def test_curves_and_surfaces_under_sanitizers(driver):
         q, i = map(int, got.split()[1:])
         plan = O.build_plan(xy, n, synth.BOX_LO, synth.BOX_HI)
         assert (q, i) == (len(plan.q_axis), len(plan.irr)), (n, q, i, len(plan.q_axis), len(plan.irr))
-    # the circle of the first workload: the survey's brute-force counts
+    # the circle r = 0.8 on the 64^2 grid: 172 crossings, 244 irregular nodes (the counts a
+    # brute-force scan of the grid edges gives, pinned in the oracle's tests too)
     assert out[0] == "ok 172 244"
-    # the ellipsoid at 64^3 and 128^3: the survey's counts (control points = crossings)
+    # the ellipsoid (0.9, 0.7, 0.5) at 64^3 and 128^3: control points (= grid-edge crossings)
+    # and irregular nodes, as the oracle's 3D pins count them
     assert out[-2:] == ["ok 6394 7352", "ok 25514 29360"]
 
 
