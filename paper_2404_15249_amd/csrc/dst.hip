@@ -163,6 +163,18 @@ __device__ __forceinline__ void radix4_step(const cpx<double>* sq, int tw, int N
     radix4_step(dr, di, a, bb, c, d);
 }
 
+// The radix-4 step with W = 1 (the first passes, h = 1): additions only
+// (pass s + 1 multiplies (b, d) by -i)
+template <class T>
+__device__ __forceinline__ void radix4_unit(cpx<T>& a, cpx<T>& bb, cpx<T>& c, cpx<T>& d) {
+    const cpx<T> a1{a.x + bb.x, a.y + bb.y}, b1{a.x - bb.x, a.y - bb.y};
+    const cpx<T> c1{c.x + d.x, c.y + d.y}, d1{c.x - d.x, c.y - d.y};
+    a = cpx<T>{a1.x + c1.x, a1.y + c1.y};
+    c = cpx<T>{a1.x - c1.x, a1.y - c1.y};
+    bb = cpx<T>{b1.x + d1.y, b1.y - d1.x};
+    d = cpx<T>{b1.x - d1.y, b1.y + d1.x};
+}
+
 // Pass s' on two points at distance 2^(s'-1): b <- a - W b, a <- a + W b with
 // W = W_N^tw.  In place.
 template <class T>
@@ -268,8 +280,28 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     // the twiddle of each point's own position); one LDS round trip for four
     // passes.  What is left after them: three passes as one radix-8 step, else
     // radix-4 steps and a last radix-2 pass.
-    int s = 1;
     const int lx = log2N - 4;                                // log2 (N/16)
+    // passes 1 .. 4 (h = 1, N >= 32 always has them): the first radix-4
+    // steps' twiddle is W^0 = 1, so they are additions only; the second
+    // stage's are W_N^{q N/16}, the same for every item
+    {
+        for (int idx = tid; idx < (P << lx); idx += NTH) {
+            const int p = idx >> lx, i0 = (idx & (N / 16 - 1)) * 16;
+            cpx<T>* zp = z + p * NS;
+            cpx<T> x[16];
+            const int a0 = zsp<T, P>(p, i0);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) x[q] = zp[pass_slot<T, P>(a0, p, i0, q, 1)];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) radix4_unit(x[4 * t], x[4 * t + 1], x[4 * t + 2], x[4 * t + 3]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) radix4_step(sq, q << lx, N, x[q], x[q + 4], x[q + 8], x[q + 12]);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) zp[pass_slot<T, P>(a0, p, i0, q, 1)] = x[q];
+        }
+        __syncthreads();
+    }
+    int s = 5;
     for (; s + 3 <= log2N; s += 4) {
         const int h = 1 << (s - 1);
         for (int idx = tid; idx < (P << lx); idx += NTH) {
