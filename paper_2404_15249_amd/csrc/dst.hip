@@ -175,6 +175,27 @@ __device__ __forceinline__ void radix4_unit(cpx<T>& a, cpx<T>& bb, cpx<T>& c, cp
     d = cpx<T>{b1.x - d1.y, b1.y + d1.x};
 }
 
+// Inclusive sums over aligned groups of W consecutive lanes (W = 16, 32 or
+// 64): four DPP row shifts inside each row of 16 lanes, then the row totals
+// read as scalars and added in row order.
+__device__ __forceinline__ double group_scan(double v, int W, int lane) {
+    v += dpp_f64<kDppRowShr1>(v);
+    v += dpp_f64<kDppRowShr1 + 1>(v);
+    v += dpp_f64<kDppRowShr1 + 3>(v);
+    v += dpp_f64<kDppRowShr1 + 7>(v);
+    if (W > 16) {
+        const double r0 = readlane_f64(v, 15), r1 = readlane_f64(v, 31), r2 = readlane_f64(v, 47);
+        const int row = lane >> 4;
+        double before;
+        if (W == 32)
+            before = row == 1 ? r0 : row == 3 ? r2 : 0.0;
+        else
+            before = row == 1 ? r0 : row == 2 ? r0 + r1 : row == 3 ? (r0 + r1) + r2 : 0.0;
+        v += before;
+    }
+    return v;
+}
+
 // Pass s' on two points at distance 2^(s'-1): b <- a - W b, a <- a + W b with
 // W = W_N^tw.  In place.
 template <class T>
@@ -395,7 +416,7 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     // to slot N-k at once (only the thread owning k reads that slot), and
     // X_{2k+1} = R_0/2 + R_1 + ... + R_k to slot k.  TPP threads per pair own
     // V consecutive k each: a running sum over the thread's values, an
-    // inclusive scan of the thread totals across the wavefront, then the
+    // inclusive scan of the thread totals across the wavefront (DPP), then the
     // totals of the pair's earlier wavefronts, added in wavefront order
     // (through LDS, in the place of the sine table, which is no longer read).
     // Sums are carried in FP64 whatever the storage type.  V is a template
@@ -440,14 +461,9 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
                 rb[e] = tb;
             }
         }
-        for (int o = 1; o < W; o <<= 1) {
-            const double ua = __shfl_up(ta, o, W), ub = __shfl_up(tb, o, W);
-            if (tw >= o) {
-                ta += ua;
-                tb += ub;
-            }
-        }
-        double ea = __shfl_up(ta, 1, W), eb = __shfl_up(tb, 1, W);
+        ta = group_scan(ta, W, tid & 63);
+        tb = group_scan(tb, W, tid & 63);
+        double ea = dpp_f64<kDppWaveShr1>(ta), eb = dpp_f64<kDppWaveShr1>(tb);   // the lane below's
         if (tw == 0) ea = eb = 0.0;
         if (TPP > 64) {
             const int nw = TPP >> 6;                         // wavefronts per pair (<= 16)
@@ -649,18 +665,10 @@ __global__ __launch_bounds__(kShortThreads) void k_dst_short(const double* __res
     double ca = 0.0, cb = 0.0;
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const double ua = __shfl_up(pa[t], o, 64), ub = __shfl_up(pb[t], o, 64);
-            if (L >= o) {
-                pa[t] += ua;
-                pb[t] += ub;
-            }
-        }
-        pa[t] += ca;
-        pb[t] += cb;
-        ca = __shfl(pa[t], 63, 64);
-        cb = __shfl(pb[t], 63, 64);
+        pa[t] = group_scan(pa[t], 64, L) + ca;
+        pb[t] = group_scan(pb[t], 64, L) + cb;
+        ca = readlane_f64(pa[t], 63);
+        cb = readlane_f64(pb[t], 63);
     }
     // write: X_{2k+1} to row 2k, X_{2k} = -I_k to row 2k-1, the pad row N-1 zero
     auto put = [&](int row, double a, double b) {
