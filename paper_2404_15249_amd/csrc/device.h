@@ -143,6 +143,21 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
     return __hiloint2double(hi, lo);
 }
 
+// The sum over the wavefront, the same in every lane: the partner lane of each
+// step differs in one more bit of the lane index (DPP quad swaps for bits 0
+// and 1, the half-row and row mirrors, lane ^ 7 and lane ^ 15, for bits 2 and
+// 3), so every lane holds its row's sum after four steps; the four row sums
+// are then read as scalars.  Each step adds the same two values in either
+// partner, so all lanes agree to the bit.
+constexpr int kDppQuadSwap1 = 0xB1, kDppQuadSwap2 = 0x4E, kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
+__device__ __forceinline__ double wave_allsum(double v) {
+    v += dpp_f64<kDppQuadSwap1>(v);
+    v += dpp_f64<kDppQuadSwap2>(v);
+    v += dpp_f64<kDppRowHalfMirror>(v);
+    v += dpp_f64<kDppRowMirror>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // base^k for 0 <= k < 256 by repeated squaring (eight fixed steps)
 __device__ __forceinline__ double pow_u8(double base, int k) {
     double res = 1.0;
@@ -342,8 +357,7 @@ __device__ __forceinline__ void stencil_nodes(const DevPlan& p, int cp, int (&ni
 
 __device__ inline double block_sum(double v, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_allsum(v);
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();

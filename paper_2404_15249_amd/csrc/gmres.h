@@ -104,16 +104,11 @@ struct GmCommitIn {
     double gj;
 };
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
+__device__ __forceinline__ double wave_sum(double v) { return wave_allsum(v); }
 
 __device__ inline double gm_block_sum(double v, double* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    v = wave_allsum(v);
     __syncthreads();
     if (lane == 0) red[wave] = v;
     __syncthreads();
