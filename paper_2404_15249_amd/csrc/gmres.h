@@ -459,7 +459,7 @@ __device__ inline void gm_commit_arnoldi(const GmresBufs& b, const GmSnap& s, co
         double gk = lane < jn ? b.g[lane] : 0.0;
         double yk = 0.0;
         for (int i = jn - 1; i >= 0; --i) {
-            const double yi = __shfl(gk, i, 64) / Hs[i * (m + 1) + i];
+            const double yi = readlane_f64(gk, i) / Hs[i * (m + 1) + i];   // i is the same in every lane
             if (lane == i) yk = yi;
             if (lane < i) gk -= Hs[i * (m + 1) + lane] * yi;
         }
