@@ -548,6 +548,38 @@ __global__ __launch_bounds__(kDstThreads) void k_dst_cols(int N, int log2N, cons
     }
 }
 
+// The value of lane ^ s (s = 1, 2, 4, 8, 16 or 32; every lane active) without
+// a round trip through LDS: DPP quad swaps for 1 and 2, the row shifts left
+// and right by 4 (each lane takes the one that stays in its half-row) for 4,
+// the row rotation by 8 for 8, and gfx950's permlane swaps for 16 (odd rows
+// take the first result, even rows the second) and 32 (the upper half the
+// first, the lower half the second).
+constexpr int kDppRowRor8 = 0x128;                           // rotate right by 8 inside each row of 16 lanes
+__device__ __forceinline__ int lane_xor_i32(int v, int s, int lane) {
+    switch (s) {
+        case 1: return __builtin_amdgcn_update_dpp(0, v, kDppQuadSwap1, 0xf, 0xf, false);
+        case 2: return __builtin_amdgcn_update_dpp(0, v, kDppQuadSwap2, 0xf, 0xf, false);
+        case 4: {
+            const int l = __builtin_amdgcn_update_dpp(0, v, kDppRowShl1 + 3, 0xf, 0xf, false);
+            const int r = __builtin_amdgcn_update_dpp(0, v, kDppRowShr1 + 3, 0xf, 0xf, false);
+            return (lane & 4) ? r : l;
+        }
+        case 8: return __builtin_amdgcn_update_dpp(0, v, kDppRowRor8, 0xf, 0xf, false);
+        case 16: {
+            const auto p = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+            return (int)((lane & 16) ? p[0] : p[1]);
+        }
+        default: {
+            const auto p = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+            return (int)((lane & 32) ? p[0] : p[1]);
+        }
+    }
+}
+
+__device__ __forceinline__ double lane_xor(double v, int s, int lane) {
+    return __hiloint2double(lane_xor_i32(__double2hiint(v), s, lane), lane_xor_i32(__double2loint(v), s, lane));
+}
+
 // Column sine transforms of short columns, N = 64 NP (NP = 1, 2 or 4; the
 // dispatch uses NP = 1): one wavefront per column pair, in registers, with the same DST-I through one
 // complex FFT per pair as above.  Lane L holds the points L + 64 r (r < NP).
@@ -633,7 +665,7 @@ __global__ __launch_bounds__(kShortThreads) void k_dst_short(const double* __res
         const cpx<double> w = twid((L & (s - 1)) * (N / (2 * s)));
 #pragma unroll
         for (int r = 0; r < NP; ++r) {
-            const cpx<double> o{__shfl_xor(v[r].x, s, 64), __shfl_xor(v[r].y, s, 64)};
+            const cpx<double> o{lane_xor(v[r].x, s, L), lane_xor(v[r].y, s, L)};
             v[r] = up ? cmul(cpx<double>{o.x - v[r].x, o.y - v[r].y}, w) : cpx<double>{v[r].x + o.x, v[r].y + o.y};
         }
     }
