@@ -585,12 +585,16 @@ __device__ __forceinline__ double gm_next_x(const GmresBufs& b, int M, int kind,
     if (kind == kGmCycleEnd) {
         double x = b.phi[e];
         for (int i0 = 0; i0 < jn; i0 += 8) {
-            double vv[8];
+            double vv[8], yy[8];                         // the coefficients with the basis values
 #pragma unroll
-            for (int u = 0; u < 8; ++u) vv[u] = i0 + u < jn ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+            for (int u = 0; u < 8; ++u) {
+                const bool in = i0 + u < jn;
+                vv[u] = in ? b.V[(size_t)(i0 + u) * M + e] : 0.0;
+                yy[u] = in ? b.y[i0 + u] : 0.0;
+            }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
-                if (i0 + u < jn) x = fma(b.y[i0 + u], vv[u], x);
+                if (i0 + u < jn) x = fma(yy[u], vv[u], x);
         }
         return x;
     }
